@@ -1,0 +1,857 @@
+// C ABI and host driver: problem set-up (validation, sorting, workspace) and
+// the Levenberg-Marquardt loop of Alg. 1 (one partition) inside the
+// trust-region wrapper of the supplementary Sec. C.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ba.h"
+#include "ba_internal.h"
+
+using namespace ba;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct DevAlloc {
+    std::vector<void*> ptrs;
+    int64_t bytes = 0;
+    hipError_t err = hipSuccess;
+    template <typename T>
+    T* get(int64_t count)
+    {
+        if (err != hipSuccess) return nullptr;
+        if (count <= 0) count = 1;
+        void* p = nullptr;
+        const size_t sz = (size_t)count * sizeof(T);
+        err = hipMalloc(&p, sz);
+        if (err != hipSuccess) return nullptr;
+        ptrs.push_back(p);
+        bytes += (int64_t)sz;
+        return (T*)p;
+    }
+    void release()
+    {
+        for (void* p : ptrs) (void)hipFree(p);
+        ptrs.clear();
+        bytes = 0;
+    }
+};
+
+}  // namespace
+
+struct ba_problem {
+    int32_t m = 0, n = 0;
+    int64_t N = 0;
+    ba_options opt{};
+    hipStream_t stream = nullptr;
+    std::string last_error;
+    std::vector<int32_t> old_of_new, new_of_old;
+
+    DevAlloc mem;
+    // state (internal camera order)
+    double *cams = nullptr, *pts = nullptr, *cams_t = nullptr, *pts_t = nullptr;
+    CamK<double>*ck64 = nullptr, *ck64_t = nullptr;
+    CamK<float>* ck32 = nullptr;
+    int32_t* d_old_of_new = nullptr;
+    PointMajor pm{};
+    CameraMajor cm{};
+    // blocks
+    void* hcp = nullptr;   // [27][N] of T
+    void* hpp = nullptr;   // [n][6] of T
+    void* cinv = nullptr;  // [n][6] of T
+    double* wpt = nullptr; // [n][3]
+    double *hcc = nullptr, *vcam = nullptr, *bd = nullptr, *lfac = nullptr, *dcam = nullptr;
+    // PCG
+    double *g = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *cacc = nullptr;
+    void* pT = nullptr;
+    double* dp = nullptr;
+    double *partials = nullptr, *sums = nullptr;
+    PcgScalars* sc = nullptr;
+    int32_t* flag = nullptr;
+    // pinned host scratch
+    double* h_scalars = nullptr;
+    bool is_f32() const { return opt.precision == BA_FP32_MIXED; }
+};
+
+#define BA_TRY(prob, expr)                                                                    \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) {                                                              \
+            (prob)->last_error = std::string(#expr) + ": " + hipGetErrorString(e_);         \
+            return BA_EDEVICE;                                                               \
+        }                                                                                    \
+    } while (0)
+
+static bool finite_all(const double* a, int64_t len)
+{
+    for (int64_t t = 0; t < len; ++t)
+        if (!std::isfinite(a[t])) return false;
+    return true;
+}
+
+static ba_status check_options(const ba_options* o, std::string& msg)
+{
+    if (o->struct_size != sizeof(ba_options)) {
+        msg = "ba_options.struct_size mismatch";
+        return BA_EINVAL;
+    }
+    if (o->precision != BA_FP64 && o->precision != BA_FP32_MIXED) {
+        msg = "unknown precision";
+        return BA_EINVAL;
+    }
+    if (o->damping != BA_DAMP_MARQUARDT && o->damping != BA_DAMP_IDENTITY) {
+        msg = "unknown damping";
+        return BA_EINVAL;
+    }
+    if (o->max_lm_iters < 0 || o->max_pcg_iters < 0 || o->pcg_fixed_iters < 0 || !std::isfinite(o->pcg_rtol) ||
+        !(o->lambda_init > 0.0) || !std::isfinite(o->lambda_init) || !std::isfinite(o->min_relative_decrease) ||
+        !std::isfinite(o->huber_delta)) {
+        msg = "invalid option value";
+        return BA_EINVAL;
+    }
+    if (o->pcg_schedule)
+        for (int32_t t = 0; t < o->max_lm_iters; ++t)
+            if (o->pcg_schedule[t] < 0) {
+                msg = "negative pcg_schedule entry";
+                return BA_EINVAL;
+            }
+    return BA_OK;
+}
+
+extern "C" {
+
+ba_status ba_options_default(ba_options* opt)
+{
+    if (!opt) return BA_EINVAL;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->struct_size = sizeof(ba_options);
+    opt->precision = BA_FP64;
+    opt->damping = BA_DAMP_MARQUARDT;
+    opt->huber_delta = 0.0;
+    opt->max_lm_iters = 10;
+    opt->max_pcg_iters = 50;
+    opt->pcg_rtol = 1e-8;
+    opt->pcg_fixed_iters = 0;
+    opt->pcg_schedule = nullptr;
+    opt->lambda_init = 1e-4;
+    opt->min_relative_decrease = 1e-3;
+    opt->time_kernels = 0;
+    return BA_OK;
+}
+
+const char* ba_status_str(ba_status s)
+{
+    switch (s) {
+    case BA_OK: return "BA_OK";
+    case BA_EINVAL: return "BA_EINVAL";
+    case BA_ENOMEM: return "BA_ENOMEM";
+    case BA_EDEVICE: return "BA_EDEVICE";
+    case BA_ENUMERIC: return "BA_ENUMERIC";
+    }
+    return "BA_UNKNOWN";
+}
+
+const char* ba_last_error(const ba_problem* prob)
+{
+    if (!prob) return g_create_error.c_str();
+    return prob->last_error.c_str();
+}
+
+void ba_destroy(ba_problem* prob)
+{
+    if (!prob) return;
+    if (prob->stream) (void)hipStreamSynchronize(prob->stream);
+    else (void)hipDeviceSynchronize();
+    prob->mem.release();
+    if (prob->h_scalars) (void)hipHostFree(prob->h_scalars);
+    delete prob;
+}
+
+ba_status ba_memory_bytes(const ba_problem* prob, int64_t* bytes)
+{
+    if (!prob || !bytes) return BA_EINVAL;
+    *bytes = prob->mem.bytes;
+    return BA_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ set-up
+static ba_status upload_state(ba_problem* P, const double* cameras, const double* points)
+{
+    const int32_t m = P->m, n = P->n;
+    if (cameras) {
+        std::vector<double> c((size_t)9 * m);
+        for (int32_t j = 0; j < m; ++j)
+            std::memcpy(&c[(size_t)9 * j], cameras + (size_t)9 * P->old_of_new[j], 9 * sizeof(double));
+        BA_TRY(P, hipMemcpyAsync(P->cams, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice, P->stream));
+        BA_TRY(P, launch_camera_constants_f64(m, P->cams, P->ck64, P->stream));
+        BA_TRY(P, hipStreamSynchronize(P->stream));
+    }
+    if (points && n > 0) {
+        BA_TRY(P, hipMemcpyAsync(P->pts, points, (size_t)3 * n * sizeof(double), hipMemcpyHostToDevice, P->stream));
+        BA_TRY(P, hipStreamSynchronize(P->stream));
+    }
+    return BA_OK;
+}
+
+extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* cameras, const double* points,
+                               const int32_t* obs_camera, const int32_t* obs_point, const double* obs_uv,
+                               const ba_options* opt_in, void* hip_stream, ba_problem** out)
+{
+    g_create_error.clear();
+    if (!out) {
+        g_create_error = "out is NULL";
+        return BA_EINVAL;
+    }
+    *out = nullptr;
+    ba_options opt;
+    if (opt_in) opt = *opt_in;
+    else ba_options_default(&opt);
+    std::string msg;
+    if (check_options(&opt, msg) != BA_OK) {
+        g_create_error = msg;
+        return BA_EINVAL;
+    }
+    if (m < 1 || n < 0 || N < 0 || N >= ((int64_t)1 << 31)) {
+        g_create_error = "invalid counts";
+        return BA_EINVAL;
+    }
+    if (!cameras || (n > 0 && !points) || (N > 0 && (!obs_camera || !obs_point || !obs_uv))) {
+        g_create_error = "NULL input array";
+        return BA_EINVAL;
+    }
+    if (!finite_all(cameras, 9 * (int64_t)m) || (n > 0 && !finite_all(points, 3 * (int64_t)n)) ||
+        (N > 0 && !finite_all(obs_uv, 2 * N))) {
+        g_create_error = "non-finite input";
+        return BA_EINVAL;
+    }
+    for (int64_t k = 0; k < N; ++k)
+        if (obs_camera[k] < 0 || obs_camera[k] >= m || obs_point[k] < 0 || obs_point[k] >= n) {
+            g_create_error = "observation index out of range at " + std::to_string(k);
+            return BA_EINVAL;
+        }
+
+    ba_problem* P = new (std::nothrow) ba_problem();
+    if (!P) {
+        g_create_error = "host allocation failed";
+        return BA_ENOMEM;
+    }
+    P->m = m;
+    P->n = n;
+    P->N = N;
+    P->opt = opt;
+    P->opt.pcg_schedule = nullptr;  // a create-time schedule pointer is not retained
+    P->stream = (hipStream_t)hip_stream;
+
+    // Cameras relabelled by popularity (most observed first), ties by id.
+    std::vector<int64_t> ccount(m, 0);
+    for (int64_t k = 0; k < N; ++k) ccount[obs_camera[k]]++;
+    P->old_of_new.resize(m);
+    P->new_of_old.resize(m);
+    for (int32_t j = 0; j < m; ++j) P->old_of_new[j] = j;
+    std::stable_sort(P->old_of_new.begin(), P->old_of_new.end(),
+                     [&](int32_t a, int32_t b) { return ccount[a] > ccount[b]; });
+    for (int32_t j = 0; j < m; ++j) P->new_of_old[P->old_of_new[j]] = j;
+
+    // Point-major order: counting sort by point, then by camera within a point.
+    std::vector<int64_t> poff((size_t)n + 1, 0);
+    for (int64_t k = 0; k < N; ++k) poff[(size_t)obs_point[k] + 1]++;
+    for (int32_t i = 0; i < n; ++i) poff[(size_t)i + 1] += poff[i];
+    std::vector<int32_t> pm_order((size_t)N);
+    {
+        std::vector<int64_t> fill(poff.begin(), poff.end() - 1);
+        for (int64_t k = 0; k < N; ++k) pm_order[(size_t)fill[obs_point[k]]++] = (int32_t)k;
+    }
+    std::vector<int32_t> h_pm_cam((size_t)N), h_pm_pt((size_t)N);
+    for (int32_t i = 0; i < n; ++i) {
+        auto b = pm_order.begin() + poff[i], e = pm_order.begin() + poff[(size_t)i + 1];
+        std::stable_sort(b, e, [&](int32_t u, int32_t v) {
+            return P->new_of_old[obs_camera[u]] < P->new_of_old[obs_camera[v]];
+        });
+    }
+    std::vector<double> h_uvx((size_t)N), h_uvy((size_t)N);
+    for (int64_t t = 0; t < N; ++t) {
+        const int32_t k = pm_order[(size_t)t];
+        h_pm_cam[(size_t)t] = P->new_of_old[obs_camera[k]];
+        h_pm_pt[(size_t)t] = obs_point[k];
+        h_uvx[(size_t)t] = obs_uv[2 * (int64_t)k];
+        h_uvy[(size_t)t] = obs_uv[2 * (int64_t)k + 1];
+    }
+    // Point-aligned tiles of <= kTile observations; a longer point is a tile alone.
+    std::vector<int32_t> tiles;
+    tiles.push_back(0);
+    {
+        int64_t cur = 0;  // start of the open tile
+        for (int32_t i = 0; i < n; ++i) {
+            const int64_t a = poff[i], b = poff[(size_t)i + 1];
+            if (b == a) continue;
+            if (b - cur > kTile && a > cur) {
+                tiles.push_back((int32_t)a);
+                cur = a;
+            }
+            if (b - a > kTile) {  // long point: its own tile
+                tiles.push_back((int32_t)b);
+                cur = b;
+            }
+        }
+        if (cur < N) tiles.push_back((int32_t)N);
+    }
+    P->pm.num_tiles = (int32_t)tiles.size() - 1;
+
+    // Camera-major order: stable counting sort of the point-major stream by camera.
+    std::vector<int64_t> coff((size_t)m + 1, 0);
+    for (int64_t t = 0; t < N; ++t) coff[(size_t)h_pm_cam[(size_t)t] + 1]++;
+    for (int32_t j = 0; j < m; ++j) coff[(size_t)j + 1] += coff[j];
+    std::vector<int32_t> h_cm_cam((size_t)N), h_cm_pt((size_t)N);
+    std::vector<double> h_cm_uvx((size_t)N), h_cm_uvy((size_t)N);
+    {
+        std::vector<int64_t> fill(coff.begin(), coff.end() - 1);
+        for (int64_t t = 0; t < N; ++t) {
+            const int32_t j = h_pm_cam[(size_t)t];
+            const int64_t d = fill[j]++;
+            h_cm_cam[(size_t)d] = j;
+            h_cm_pt[(size_t)d] = h_pm_pt[(size_t)t];
+            h_cm_uvx[(size_t)d] = h_uvx[(size_t)t];
+            h_cm_uvy[(size_t)d] = h_uvy[(size_t)t];
+        }
+    }
+    // Wave chunks and their partial-sum slots: one slot per (chunk, camera run).
+    const int32_t num_chunks = (int32_t)((N + kCmChunk - 1) / kCmChunk);
+    std::vector<int32_t> chunk_slot((size_t)num_chunks + 1, 0);
+    std::vector<int32_t> slots_per_cam((size_t)m, 0);
+    {
+        int32_t slot = 0;
+        for (int32_t c = 0; c < num_chunks; ++c) {
+            chunk_slot[c] = slot;
+            const int64_t s = (int64_t)c * kCmChunk, e = std::min<int64_t>(N, s + kCmChunk);
+            for (int64_t t = s; t < e; ++t)
+                if (t == s || h_cm_cam[(size_t)t] != h_cm_cam[(size_t)t - 1]) {
+                    slots_per_cam[h_cm_cam[(size_t)t]]++;
+                    ++slot;
+                }
+        }
+        chunk_slot[num_chunks] = slot;
+        P->cm.num_slots = slot;
+    }
+    std::vector<int32_t> cam_slot((size_t)m + 1, 0);
+    for (int32_t j = 0; j < m; ++j) cam_slot[(size_t)j + 1] = cam_slot[j] + slots_per_cam[j];
+    P->cm.num_chunks = num_chunks;
+
+    // Workspace: everything the solve needs, sized once.
+    DevAlloc& A = P->mem;
+    const size_t tsz = P->is_f32() ? sizeof(float) : sizeof(double);
+    P->cams = A.get<double>(9 * (int64_t)m);
+    P->cams_t = A.get<double>(9 * (int64_t)m);
+    P->pts = A.get<double>(3 * (int64_t)n);
+    P->pts_t = A.get<double>(3 * (int64_t)n);
+    P->ck64 = A.get<CamK<double>>(m);
+    P->ck64_t = A.get<CamK<double>>(m);
+    P->ck32 = A.get<CamK<float>>(m);
+    P->d_old_of_new = A.get<int32_t>(m);
+    P->pm.cam = A.get<int32_t>(N);
+    P->pm.pt = A.get<int32_t>(N);
+    P->pm.uvx = A.get<double>(N);
+    P->pm.uvy = A.get<double>(N);
+    P->pm.tile = A.get<int32_t>((int64_t)tiles.size());
+    P->cm.cam = A.get<int32_t>(N);
+    P->cm.pt = A.get<int32_t>(N);
+    P->cm.uvx = A.get<double>(N);
+    P->cm.uvy = A.get<double>(N);
+    P->cm.chunk_slot = A.get<int32_t>((int64_t)num_chunks + 1);
+    P->cm.cam_slot = A.get<int32_t>((int64_t)m + 1);
+    P->cm.slots = A.get<double>((int64_t)P->cm.num_slots * kCamSlotWords);
+    P->hcp = A.get<char>(27 * N * (int64_t)tsz);
+    P->hpp = A.get<char>(6 * (int64_t)n * (int64_t)tsz);
+    P->cinv = A.get<char>(6 * (int64_t)n * (int64_t)tsz);
+    P->wpt = A.get<double>(3 * (int64_t)n);
+    P->hcc = A.get<double>(81 * (int64_t)m);
+    P->vcam = A.get<double>(9 * (int64_t)m);
+    P->bd = A.get<double>(81 * (int64_t)m);
+    P->lfac = A.get<double>(45 * (int64_t)m);
+    P->dcam = A.get<double>(9 * (int64_t)m);
+    for (double** v : {&P->g, &P->x, &P->r, &P->z, &P->p, &P->q, &P->cacc}) *v = A.get<double>(9 * (int64_t)m);
+    P->pT = A.get<char>(9 * (int64_t)m * (int64_t)tsz);
+    P->dp = A.get<double>(3 * (int64_t)n);
+    P->partials = A.get<double>(2 * 2048);
+    P->sums = A.get<double>(8);
+    P->sc = A.get<PcgScalars>(1);
+    P->flag = A.get<int32_t>(1);
+    if (A.err != hipSuccess) {
+        g_create_error = std::string("device allocation failed: ") + hipGetErrorString(A.err);
+        const bool oom = A.err == hipErrorOutOfMemory || A.err == hipErrorMemoryAllocation;
+        A.release();
+        delete P;
+        return oom ? BA_ENOMEM : BA_EDEVICE;
+    }
+    if (hipHostMalloc((void**)&P->h_scalars, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        g_create_error = "pinned host allocation failed";
+        A.release();
+        delete P;
+        return BA_ENOMEM;
+    }
+    auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+        if (bytes == 0) return hipSuccess;
+        return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+    };
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = up(P->d_old_of_new, P->old_of_new.data(), sizeof(int32_t) * m);
+    if (e == hipSuccess) e = up(P->pm.cam, h_pm_cam.data(), sizeof(int32_t) * N);
+    if (e == hipSuccess) e = up(P->pm.pt, h_pm_pt.data(), sizeof(int32_t) * N);
+    if (e == hipSuccess) e = up(P->pm.uvx, h_uvx.data(), sizeof(double) * N);
+    if (e == hipSuccess) e = up(P->pm.uvy, h_uvy.data(), sizeof(double) * N);
+    if (e == hipSuccess) e = up(P->pm.tile, tiles.data(), sizeof(int32_t) * tiles.size());
+    if (e == hipSuccess) e = up(P->cm.cam, h_cm_cam.data(), sizeof(int32_t) * N);
+    if (e == hipSuccess) e = up(P->cm.pt, h_cm_pt.data(), sizeof(int32_t) * N);
+    if (e == hipSuccess) e = up(P->cm.uvx, h_cm_uvx.data(), sizeof(double) * N);
+    if (e == hipSuccess) e = up(P->cm.uvy, h_cm_uvy.data(), sizeof(double) * N);
+    if (e == hipSuccess) e = up(P->cm.chunk_slot, chunk_slot.data(), sizeof(int32_t) * chunk_slot.size());
+    if (e == hipSuccess) e = up(P->cm.cam_slot, cam_slot.data(), sizeof(int32_t) * cam_slot.size());
+    if (e == hipSuccess) e = hipMemset(P->hpp, 0, 6 * (size_t)(n > 0 ? n : 1) * tsz);
+    if (e == hipSuccess) e = hipMemset(P->wpt, 0, 3 * (size_t)(n > 0 ? n : 1) * sizeof(double));
+    if (e == hipSuccess) e = hipMemset(P->sc, 0, sizeof(PcgScalars));
+    if (e == hipSuccess) e = hipMemset(P->flag, 0, sizeof(int32_t));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        g_create_error = std::string("device upload failed: ") + hipGetErrorString(e);
+        ba_destroy(P);
+        return BA_EDEVICE;
+    }
+    ba_status st = upload_state(P, cameras, points);
+    if (st != BA_OK) {
+        g_create_error = P->last_error;
+        ba_destroy(P);
+        return st;
+    }
+    *out = P;
+    return BA_OK;
+}
+
+extern "C" ba_status ba_set_params(ba_problem* P, const double* cameras, const double* points)
+{
+    if (!P) return BA_EINVAL;
+    if ((cameras && !finite_all(cameras, 9 * (int64_t)P->m)) || (points && !finite_all(points, 3 * (int64_t)P->n))) {
+        P->last_error = "non-finite parameters";
+        return BA_EINVAL;
+    }
+    return upload_state(P, cameras, points);
+}
+
+extern "C" ba_status ba_get_params(const ba_problem* Pc, double* cameras, double* points)
+{
+    if (!Pc) return BA_EINVAL;
+    ba_problem* P = const_cast<ba_problem*>(Pc);
+    BA_TRY(P, hipStreamSynchronize(P->stream));
+    if (cameras) {
+        std::vector<double> c((size_t)9 * P->m);
+        BA_TRY(P, hipMemcpy(c.data(), P->cams, c.size() * sizeof(double), hipMemcpyDeviceToHost));
+        for (int32_t j = 0; j < P->m; ++j)
+            std::memcpy(cameras + (size_t)9 * P->old_of_new[j], &c[(size_t)9 * j], 9 * sizeof(double));
+    }
+    if (points && P->n > 0)
+        BA_TRY(P, hipMemcpy(points, P->pts, (size_t)3 * P->n * sizeof(double), hipMemcpyDeviceToHost));
+    return BA_OK;
+}
+
+// ------------------------------------------------------------- helpers
+static ba_status read_scalars(ba_problem* P, const void* dev, size_t bytes)
+{
+    BA_TRY(P, hipMemcpyAsync(P->h_scalars, dev, bytes, hipMemcpyDeviceToHost, P->stream));
+    BA_TRY(P, hipStreamSynchronize(P->stream));
+    return BA_OK;
+}
+
+// F at (pts, ck) summed in FP64 into P->sums[0]
+template <typename T>
+static ba_status cost_into_sums(ba_problem* P, const double* pts, const CamK<T>* ck, hipStream_t s)
+{
+    int32_t nb = 0;
+    if (P->N == 0) {
+        BA_TRY(P, launch_zero(P->sums, 1, s));
+        return BA_OK;
+    }
+    BA_TRY(P, launch_cost_t<T>(P->pm, P->N, pts, ck, P->opt.huber_delta, P->partials, &nb, s));
+    BA_TRY(P, launch_sum_partials(P->partials, nb, 1, 1, P->sums, s));
+    return BA_OK;
+}
+
+template <typename T>
+static ba_status build_system(ba_problem* P)
+{
+    hipStream_t s = P->stream;
+    const CamK<T>* ck;
+    if constexpr (sizeof(T) == 4) {
+        BA_TRY(P, launch_camera_constants_f32(P->m, P->cams, P->ck32, s));
+        ck = (const CamK<T>*)P->ck32;
+    } else {
+        ck = (const CamK<T>*)P->ck64;
+    }
+    BA_TRY(P, launch_build_points<T>(P->pm, P->N, P->pts, ck, P->opt.huber_delta, false, (T*)P->hcp, (T*)P->hpp,
+                                     P->wpt, s));
+    BA_TRY(P, launch_build_cameras<T>(P->cm, P->m, P->N, P->pts, ck, P->opt.huber_delta, false, P->hcc, P->vcam, s));
+    return BA_OK;
+}
+
+struct PcgTimer {
+    std::vector<hipEvent_t> ev;
+    size_t used = 0;
+    ~PcgTimer()
+    {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+    hipError_t next(hipEvent_t* a, hipEvent_t* b)
+    {
+        while (ev.size() < used + 2) {
+            hipEvent_t e;
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+            ev.push_back(e);
+        }
+        *a = ev[used];
+        *b = ev[used + 1];
+        used += 2;
+        return hipSuccess;
+    }
+};
+
+// PCG on the reduced camera system (Alg. 2, one partition); dc = x.
+template <typename T>
+static ba_status run_pcg(ba_problem* P, const ba_options& o, int32_t fixed, int32_t* iters, PcgTimer* tm,
+                         double* matvec_ms, int64_t* launches)
+{
+    hipStream_t s = P->stream;
+    const int32_t m = P->m;
+    int32_t nb = 0;
+    // b = v - E C^-1 w; x = 0; r = b
+    BA_TRY(P, launch_zero(P->cacc, 9 * (int64_t)m, s));
+    BA_TRY(P, launch_schur_tiles<T>(1, P->pm, P->N, (const T*)P->hcp, (const T*)P->cinv, P->wpt, nullptr, P->cacc,
+                                    nullptr, s));
+    BA_TRY(P, launch_rhs_combine(m, P->vcam, P->cacc, P->g, P->x, P->r, P->partials, &nb, s));
+    BA_TRY(P, launch_sum_partials(P->partials, nb, 1, 1, P->sums, s));
+    BA_TRY(P, launch_pcg_finish_scalars(P->sc, P->sums, 0, s));
+    int32_t it = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> marks;
+    while (true) {
+        if (fixed > 0) {
+            if (it >= fixed) break;
+        } else {
+            ba_status st = read_scalars(P, P->sc, sizeof(PcgScalars));
+            if (st != BA_OK) return st;
+            const PcgScalars* h = (const PcgScalars*)P->h_scalars;
+            if (h->breakdown) break;
+            if (std::sqrt(h->rr) <= o.pcg_rtol * std::sqrt(h->bb) || it >= o.max_pcg_iters) break;
+        }
+        BA_TRY(P, launch_pcg_precond(m, P->lfac, P->r, P->z, P->partials, &nb, P->sc, s));
+        BA_TRY(P, launch_sum_partials(P->partials, nb, 2, 2, P->sums, s));
+        BA_TRY(P, launch_pcg_finish_scalars(P->sc, P->sums, 1, s));
+        BA_TRY(P, launch_pcg_direction<T>(m, it == 0, P->z, P->p, (T*)P->pT, P->sc, s));
+        BA_TRY(P, launch_zero(P->cacc, 9 * (int64_t)m, s));
+        hipEvent_t ea = nullptr, eb = nullptr;
+        if (tm) {
+            BA_TRY(P, tm->next(&ea, &eb));
+            BA_TRY(P, hipEventRecord(ea, s));
+        }
+        BA_TRY(P, launch_schur_tiles<T>(0, P->pm, P->N, (const T*)P->hcp, (const T*)P->cinv, P->wpt,
+                                        (const T*)P->pT, P->cacc, nullptr, s));
+        if (tm) {
+            BA_TRY(P, hipEventRecord(eb, s));
+            marks.emplace_back(ea, eb);
+        }
+        BA_TRY(P, launch_matvec_combine(m, P->bd, P->p, P->cacc, P->q, P->partials, &nb, P->sc, s));
+        BA_TRY(P, launch_sum_partials(P->partials, nb, 1, 1, P->sums, s));
+        BA_TRY(P, launch_pcg_finish_scalars(P->sc, P->sums, 2, s));
+        BA_TRY(P, launch_pcg_update(m, P->p, P->q, P->x, P->r, P->partials, &nb, P->sc, s));
+        BA_TRY(P, launch_sum_partials(P->partials, nb, 1, 1, P->sums, s));
+        BA_TRY(P, launch_pcg_finish_scalars(P->sc, P->sums, 3, s));
+        ++it;
+    }
+    *iters = it;
+    ba_status st = read_scalars(P, P->sc, sizeof(PcgScalars));
+    if (st != BA_OK) return st;
+    if (((const PcgScalars*)P->h_scalars)->breakdown) {
+        P->last_error = "PCG breakdown: p^T q <= 0 or non-finite";
+        return BA_ENUMERIC;
+    }
+    for (auto& pr : marks) {
+        float ms = 0.0f;
+        BA_TRY(P, hipEventElapsedTime(&ms, pr.first, pr.second));
+        *matvec_ms += ms;
+        *launches += 1;
+    }
+    if (tm) tm->used = 0;
+    return BA_OK;
+}
+
+template <typename T>
+static ba_status lm_solve_t(ba_problem* P, const ba_options& o, ba_report* rep)
+{
+    using clock = std::chrono::steady_clock;
+    hipStream_t s = P->stream;
+    const int32_t m = P->m, n = P->n;
+    const auto t_start = clock::now();
+    ba_status st;
+    BA_TRY(P, hipStreamSynchronize(s));
+    if ((st = cost_into_sums<double>(P, P->pts, P->ck64, s)) != BA_OK) return st;
+    if ((st = read_scalars(P, P->sums, sizeof(double))) != BA_OK) return st;
+    double F = P->h_scalars[0];
+    double lambda = o.lambda_init, nu = 2.0;
+    bool need_build = true;
+    double pcg_ms = 0.0, matvec_ms = 0.0;
+    int64_t pcg_total = 0, launches = 0;
+    PcgTimer timer;
+    if (rep) {
+        rep->initial_cost = F;
+        rep->iters_run = 0;
+    }
+    int32_t it = 0;
+    ba_status result = BA_OK;
+    for (it = 0; it < o.max_lm_iters; ++it) {
+        const auto t_it = clock::now();
+        if (need_build) {
+            if ((st = build_system<T>(P)) != BA_OK) return st;
+            need_build = false;
+        }
+        BA_TRY(P, launch_damp_cameras(m, P->hcc, lambda, o.damping, P->bd, P->lfac, P->dcam, P->flag, s));
+        BA_TRY(P, launch_damp_points<T>(n, (const T*)P->hpp, lambda, o.damping, (T*)P->cinv, P->flag, s));
+        BA_TRY(P, hipMemcpyAsync(P->h_scalars, P->flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        BA_TRY(P, hipStreamSynchronize(s));
+        if (*(int32_t*)P->h_scalars != 0) {
+            BA_TRY(P, hipMemsetAsync(P->flag, 0, sizeof(int32_t), s));
+            P->last_error = "damped block not positive definite";
+            result = BA_ENUMERIC;
+            break;
+        }
+        const int32_t fixed = o.pcg_schedule ? o.pcg_schedule[it] : o.pcg_fixed_iters;
+        int32_t npcg = 0;
+        const auto t_pcg = clock::now();
+        st = run_pcg<T>(P, o, fixed, &npcg, o.time_kernels ? &timer : nullptr, &matvec_ms, &launches);
+        pcg_ms += std::chrono::duration<double, std::milli>(clock::now() - t_pcg).count();
+        pcg_total += npcg;
+        if (st != BA_OK) {
+            if (rep && rep->pcg_iters && it < rep->capacity) rep->pcg_iters[it] = npcg;
+            result = st;
+            break;
+        }
+        // dp = C~^-1 (w - E^T dc); trial state; F(x + dx); predicted decrease
+        BA_TRY(P, launch_pcg_direction<T>(m, true, P->x, P->p, (T*)P->pT, P->sc, s));
+        BA_TRY(P, launch_schur_tiles<T>(2, P->pm, P->N, (const T*)P->hcp, (const T*)P->cinv, P->wpt,
+                                        (const T*)P->pT, nullptr, P->dp, s));
+        BA_TRY(P, launch_trial_state(m, n, P->cams, P->x, P->pts, P->dp, P->cams_t, P->pts_t, s));
+        BA_TRY(P, launch_camera_constants_f64(m, P->cams_t, P->ck64_t, s));
+        if ((st = cost_into_sums<double>(P, P->pts_t, P->ck64_t, s)) != BA_OK) return st;
+        int32_t nb = 0;
+        BA_TRY(P, launch_pred<T>(m, n, P->x, P->dcam, P->vcam, P->dp, (const T*)P->hpp, P->wpt, lambda, o.damping,
+                                 P->partials, &nb, s));
+        BA_TRY(P, launch_sum_partials(P->partials, nb, 2, 2, P->sums + 1, s));
+        if ((st = read_scalars(P, P->sums, 3 * sizeof(double))) != BA_OK) return st;
+        const double Ft = P->h_scalars[0];
+        const double pred = 0.5 * (P->h_scalars[1] + P->h_scalars[2]);
+        const double gain = (F - Ft) / pred;
+        const bool acc = pred > 0.0 && std::isfinite(Ft) && gain > o.min_relative_decrease;
+        if (rep) {
+            if (it < rep->capacity) {
+                if (rep->lambda) rep->lambda[it] = lambda;
+                if (rep->trial_cost) rep->trial_cost[it] = Ft;
+                if (rep->pred) rep->pred[it] = pred;
+                if (rep->pcg_iters) rep->pcg_iters[it] = npcg;
+                if (rep->accepted) rep->accepted[it] = acc ? 1 : 0;
+            }
+        }
+        if (acc) {
+            std::swap(P->cams, P->cams_t);
+            std::swap(P->pts, P->pts_t);
+            std::swap(P->ck64, P->ck64_t);
+            F = Ft;
+            const double t = 2.0 * gain - 1.0;
+            const double f = 1.0 - t * t * t;
+            lambda *= (f > 1.0 / 3.0 ? f : 1.0 / 3.0);
+            nu = 2.0;
+            need_build = true;
+        } else {
+            lambda *= nu;
+            nu *= 2.0;
+        }
+        if (rep && it < rep->capacity) {
+            if (rep->cost) rep->cost[it] = F;
+            if (rep->ms) rep->ms[it] = std::chrono::duration<double, std::milli>(clock::now() - t_it).count();
+        }
+        if (lambda > 1e32) {  // no further progress possible: normal end
+            ++it;
+            break;
+        }
+    }
+    if (rep) {
+        rep->iters_run = it;
+        rep->final_cost = F;
+        rep->total_ms = std::chrono::duration<double, std::milli>(clock::now() - t_start).count();
+        rep->pcg_ms = pcg_ms;
+        rep->pcg_iters_total = pcg_total;
+        rep->matvec_ms = matvec_ms;
+        rep->matvec_launches = launches;
+    }
+    return result;
+}
+
+extern "C" ba_status ba_lm_solve(ba_problem* P, const ba_options* opt, ba_report* rep)
+{
+    if (!P) return BA_EINVAL;
+    ba_options o = opt ? *opt : P->opt;
+    std::string msg;
+    if (check_options(&o, msg) != BA_OK) {
+        P->last_error = msg;
+        return BA_EINVAL;
+    }
+    if (o.precision != P->opt.precision) {
+        P->last_error = "precision differs from the create-time precision";
+        return BA_EINVAL;
+    }
+    if (rep && rep->capacity < 0) {
+        P->last_error = "negative report capacity";
+        return BA_EINVAL;
+    }
+    const double delta_saved = P->opt.huber_delta;
+    P->opt.huber_delta = o.huber_delta;
+    ba_status st = P->is_f32() ? lm_solve_t<float>(P, o, rep) : lm_solve_t<double>(P, o, rep);
+    P->opt.huber_delta = delta_saved;
+    return st;
+}
+
+// --------------------------------------------------- cost and gradients
+template <typename T>
+static ba_status grad_into(ba_problem* P, const double* pts, const CamK<T>* ck, hipStream_t s)
+{
+    BA_TRY(P, launch_build_points<T>(P->pm, P->N, pts, ck, P->opt.huber_delta, true, nullptr, nullptr, P->wpt, s));
+    BA_TRY(P, launch_build_cameras<T>(P->cm, P->m, P->N, pts, ck, P->opt.huber_delta, true, nullptr, P->vcam, s));
+    return BA_OK;
+}
+
+extern "C" ba_status ba_eval_cost_grad(ba_problem* P, double* cost, double* grad_cameras, double* grad_points)
+{
+    if (!P) return BA_EINVAL;
+    hipStream_t s = P->stream;
+    ba_status st;
+    if (cost) {
+        if ((st = cost_into_sums<double>(P, P->pts, P->ck64, s)) != BA_OK) return st;
+        if ((st = read_scalars(P, P->sums, sizeof(double))) != BA_OK) return st;
+        *cost = P->h_scalars[0];
+    }
+    if (grad_cameras || grad_points) {
+        if ((st = grad_into<double>(P, P->pts, P->ck64, s)) != BA_OK) return st;
+        // gradients land in cams_t / pts_t (caller order), then to the host
+        BA_TRY(P, launch_scatter_grad(P->m, P->n, 0, 1.0, P->vcam, P->wpt, P->d_old_of_new,
+                                      grad_cameras ? (void*)P->cams_t : nullptr,
+                                      grad_points ? (void*)P->pts_t : nullptr, s));
+        BA_TRY(P, hipStreamSynchronize(s));
+        if (grad_cameras)
+            BA_TRY(P, hipMemcpy(grad_cameras, P->cams_t, sizeof(double) * 9 * (size_t)P->m, hipMemcpyDeviceToHost));
+        if (grad_points && P->n > 0)
+            BA_TRY(P, hipMemcpy(grad_points, P->pts_t, sizeof(double) * 3 * (size_t)P->n, hipMemcpyDeviceToHost));
+    }
+    return BA_OK;
+}
+
+template <typename T>
+static ba_status device_form(ba_problem* P, int32_t dtype, const void* d_cams, const void* d_pts, bool backward,
+                             double gout, void* d_cost, void* d_gc, void* d_gp, hipStream_t s)
+{
+    BA_TRY(P, launch_gather_cameras(P->m, dtype, d_cams, P->d_old_of_new, P->cams_t, s));
+    BA_TRY(P, launch_convert_points(P->n, dtype, d_pts, P->pts_t, s));
+    const CamK<T>* ck;
+    if constexpr (sizeof(T) == 4) {
+        BA_TRY(P, launch_camera_constants_f32(P->m, P->cams_t, P->ck32, s));
+        ck = (const CamK<T>*)P->ck32;
+    } else {
+        BA_TRY(P, launch_camera_constants_f64(P->m, P->cams_t, P->ck64_t, s));
+        ck = (const CamK<T>*)P->ck64_t;
+    }
+    ba_status st;
+    if (!backward) {
+        if ((st = cost_into_sums<T>(P, P->pts_t, ck, s)) != BA_OK) return st;
+        BA_TRY(P, launch_store_cost(P->sums, (double*)d_cost, s));
+        return BA_OK;
+    }
+    if ((st = grad_into<T>(P, P->pts_t, ck, s)) != BA_OK) return st;
+    BA_TRY(P, launch_scatter_grad(P->m, P->n, dtype, gout, P->vcam, P->wpt, P->d_old_of_new, d_gc, d_gp, s));
+    return BA_OK;
+}
+
+extern "C" ba_status ba_cost_fwd_device(ba_problem* P, int32_t dtype, const void* d_cams, const void* d_pts,
+                                        void* d_cost_f64, void* hip_stream)
+{
+    if (!P || (dtype != 0 && dtype != 1) || !d_cams || (P->n > 0 && !d_pts) || !d_cost_f64) {
+        if (P) P->last_error = "invalid argument";
+        return BA_EINVAL;
+    }
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : P->stream;
+    return dtype == 0 ? device_form<double>(P, dtype, d_cams, d_pts, false, 0.0, d_cost_f64, nullptr, nullptr, s)
+                      : device_form<float>(P, dtype, d_cams, d_pts, false, 0.0, d_cost_f64, nullptr, nullptr, s);
+}
+
+extern "C" ba_status ba_cost_bwd_device(ba_problem* P, int32_t dtype, const void* d_cams, const void* d_pts,
+                                        double gout, void* d_grad_cams, void* d_grad_pts, void* hip_stream)
+{
+    if (!P || (dtype != 0 && dtype != 1) || !d_cams || (P->n > 0 && !d_pts) || !std::isfinite(gout)) {
+        if (P) P->last_error = "invalid argument";
+        return BA_EINVAL;
+    }
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : P->stream;
+    return dtype == 0
+               ? device_form<double>(P, dtype, d_cams, d_pts, true, gout, nullptr, d_grad_cams, d_grad_pts, s)
+               : device_form<float>(P, dtype, d_cams, d_pts, true, gout, nullptr, d_grad_cams, d_grad_pts, s);
+}
+
+// ------------------------------------------------ reduced-system operator
+template <typename T>
+static ba_status schur_matvec_t(ba_problem* P, double lambda, int32_t damping, const double* x, double* q)
+{
+    hipStream_t s = P->stream;
+    const int32_t m = P->m, n = P->n;
+    ba_status st;
+    if ((st = build_system<T>(P)) != BA_OK) return st;
+    BA_TRY(P, launch_damp_cameras(m, P->hcc, lambda, damping, P->bd, P->lfac, P->dcam, P->flag, s));
+    BA_TRY(P, launch_damp_points<T>(n, (const T*)P->hpp, lambda, damping, (T*)P->cinv, P->flag, s));
+    std::vector<double> xi((size_t)9 * m), qi((size_t)9 * m);
+    for (int32_t j = 0; j < m; ++j)
+        std::memcpy(&xi[(size_t)9 * j], x + (size_t)9 * P->old_of_new[j], 9 * sizeof(double));
+    BA_TRY(P, hipMemcpyAsync(P->x, xi.data(), xi.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    BA_TRY(P, launch_zero(P->sums, 1, s));
+    BA_TRY(P, launch_pcg_finish_scalars(P->sc, P->sums, 0, s));
+    BA_TRY(P, launch_pcg_direction<T>(m, true, P->x, P->p, (T*)P->pT, P->sc, s));
+    BA_TRY(P, launch_zero(P->cacc, 9 * (int64_t)m, s));
+    BA_TRY(P, launch_schur_tiles<T>(0, P->pm, P->N, (const T*)P->hcp, (const T*)P->cinv, P->wpt, (const T*)P->pT,
+                                    P->cacc, nullptr, s));
+    int32_t nb = 0;
+    BA_TRY(P, launch_matvec_combine(m, P->bd, P->p, P->cacc, P->q, P->partials, &nb, P->sc, s));
+    BA_TRY(P, hipMemcpyAsync(qi.data(), P->q, qi.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    BA_TRY(P, hipMemcpyAsync(P->h_scalars, P->flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    BA_TRY(P, hipStreamSynchronize(s));
+    if (*(int32_t*)P->h_scalars != 0) {
+        BA_TRY(P, hipMemset(P->flag, 0, sizeof(int32_t)));
+        P->last_error = "damped block not positive definite";
+        return BA_ENUMERIC;
+    }
+    for (int32_t j = 0; j < m; ++j)
+        std::memcpy(q + (size_t)9 * P->old_of_new[j], &qi[(size_t)9 * j], 9 * sizeof(double));
+    return BA_OK;
+}
+
+extern "C" ba_status ba_schur_matvec(ba_problem* P, double lambda, int32_t damping, const double* x, double* q)
+{
+    if (!P) return BA_EINVAL;
+    if (!x || !q || !(lambda >= 0.0) || !std::isfinite(lambda) ||
+        (damping != BA_DAMP_MARQUARDT && damping != BA_DAMP_IDENTITY) || !finite_all(x, 9 * (int64_t)P->m)) {
+        P->last_error = "invalid argument";
+        return BA_EINVAL;
+    }
+    return P->is_f32() ? schur_matvec_t<float>(P, lambda, damping, x, q)
+                       : schur_matvec_t<double>(P, lambda, damping, x, q);
+}

@@ -1,0 +1,372 @@
+// Residual, Jacobian and Schur block assembly (Alg. 1: residual/Jacobian and
+// Hessian/constant-vector steps; Sec. 3 Eq. schur_complement), and the FP64
+// cost F = 1/2 sum rho(|e|^2) (Sec. 3 Eq. obj with a Huber loss).
+//
+// Two passes over the observations, each with its own sorted copy of the
+// index and pixel streams:
+//   * point-major (k_build_points): one workgroup per point-aligned tile of
+//     <= 256 observations, one lane per observation.  Writes the coupling
+//     block E_k = w J_c^T J_p of every observation as 27 coalesced streams
+//     [27][N], and reduces the point blocks C_i = sum w J_p^T J_p and
+//     w_i = -sum w J_p^T e over the point's contiguous segment in LDS.
+//   * camera-major (k_build_cameras): one wavefront per contiguous chunk of
+//     2048 observations sorted by camera.  Lanes accumulate the camera terms
+//     B_j = sum w J_c^T J_c and v_j = -sum w J_c^T e in registers while the
+//     camera does not change and flush a wavefront-reduced partial sum into a
+//     slot when it does; slots of one camera are contiguous and are summed in
+//     a fixed order by k_reduce_slots, so the result is deterministic.  This
+//     balances the Zipf-skewed camera segments (the most-seen camera holds
+//     about 60% of all points) over the whole chip, as the paper's equal-edge
+//     partition (Sec. 4.1) does over GPUs.
+#include "ba_internal.h"
+
+namespace ba {
+
+// ------------------------------------------------------- camera constants
+template <typename T>
+__global__ void k_camera_constants(int32_t m, const double* __restrict__ cams, CamK<T>* __restrict__ out)
+{
+    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    CamK<T> k;
+    camera_constants<T>(cams + 9 * (int64_t)j, k);
+    out[j] = k;
+}
+
+hipError_t launch_camera_constants_f64(int32_t m, const double* cams, CamK<double>* out, hipStream_t s)
+{
+    if (m > 0) hipLaunchKernelGGL(k_camera_constants<double>, dim3((m + 127) / 128), dim3(128), 0, s, m, cams, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_camera_constants_f32(int32_t m, const double* cams, CamK<float>* out, hipStream_t s)
+{
+    if (m > 0) hipLaunchKernelGGL(k_camera_constants<float>, dim3((m + 127) / 128), dim3(128), 0, s, m, cams, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------ point-major build
+// Terms of one observation for its point: C (upper 6) and w (3).
+template <typename T>
+__device__ __forceinline__ void point_terms(const T Jp[6], T e0, T e1, T wt, double out[9])
+{
+    out[0] = (double)(wt * (Jp[0] * Jp[0] + Jp[3] * Jp[3]));
+    out[1] = (double)(wt * (Jp[0] * Jp[1] + Jp[3] * Jp[4]));
+    out[2] = (double)(wt * (Jp[0] * Jp[2] + Jp[3] * Jp[5]));
+    out[3] = (double)(wt * (Jp[1] * Jp[1] + Jp[4] * Jp[4]));
+    out[4] = (double)(wt * (Jp[1] * Jp[2] + Jp[4] * Jp[5]));
+    out[5] = (double)(wt * (Jp[2] * Jp[2] + Jp[5] * Jp[5]));
+    out[6] = (double)(-wt * (Jp[0] * e0 + Jp[3] * e1));
+    out[7] = (double)(-wt * (Jp[1] * e0 + Jp[4] * e1));
+    out[8] = (double)(-wt * (Jp[2] * e0 + Jp[5] * e1));
+}
+
+template <typename T>
+__device__ __forceinline__ void observation(int64_t k, const int32_t* __restrict__ cam, const int32_t* __restrict__ pt,
+                                            const double* __restrict__ uvx, const double* __restrict__ uvy,
+                                            const double* __restrict__ pts, const CamK<T>* __restrict__ ck,
+                                            T delta, T& e0, T& e1, T& wt, T Jc[18], T Jp[6], int32_t& i)
+{
+    const int32_t j = cam[k];
+    i = pt[k];
+    const CamK<T> kk = ck[j];
+    const T X0 = (T)pts[3 * (int64_t)i], X1 = (T)pts[3 * (int64_t)i + 1], X2 = (T)pts[3 * (int64_t)i + 2];
+    residual_jacobian<T>(kk, X0, X1, X2, (T)uvx[k], (T)uvy[k], e0, e1, Jc, Jp);
+    wt = huber_weight<T>(e0 * e0 + e1 * e1, delta);
+}
+
+template <typename T>
+__device__ __forceinline__ void store_coupling(int64_t k, int64_t N, const T Jc[18], const T Jp[6], T wt,
+                                               T* __restrict__ hcp)
+{
+#pragma unroll
+    for (int a = 0; a < 9; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            hcp[(int64_t)(a * 3 + b) * N + k] = wt * (Jc[a] * Jp[b] + Jc[9 + a] * Jp[3 + b]);
+}
+
+template <typename T, bool GRAD_ONLY>
+__global__ __launch_bounds__(kTile) void k_build_points(
+    const int32_t* __restrict__ tile, const int32_t* __restrict__ cam, const int32_t* __restrict__ pt,
+    const double* __restrict__ uvx, const double* __restrict__ uvy, const double* __restrict__ pts,
+    const CamK<T>* __restrict__ ck, T delta, int64_t N, T* __restrict__ hcp, T* __restrict__ hpp,
+    double* __restrict__ wpt)
+{
+    __shared__ double sh[9][kTile];
+    __shared__ int32_t shpt[kTile];
+    const int tid = threadIdx.x;
+    const int32_t s = tile[blockIdx.x], e = tile[blockIdx.x + 1];
+    const int32_t len = e - s;
+    if (len <= kTile) {
+        const bool valid = tid < len;
+        int32_t i = -1;
+        if (valid) {
+            const int64_t k = s + tid;
+            T e0, e1, wt, Jc[18], Jp[6];
+            observation<T>(k, cam, pt, uvx, uvy, pts, ck, delta, e0, e1, wt, Jc, Jp, i);
+            if (!GRAD_ONLY) store_coupling<T>(k, N, Jc, Jp, wt, hcp);
+            double t[9];
+            point_terms<T>(Jp, e0, e1, wt, t);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) sh[q][tid] = t[q];
+        }
+        shpt[tid] = i;
+        __syncthreads();
+        if (valid && (tid == 0 || shpt[tid - 1] != i)) {
+            double acc[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) acc[q] = 0.0;
+            for (int u = tid; u < len && shpt[u] == i; ++u)
+#pragma unroll
+                for (int q = 0; q < 9; ++q) acc[q] += sh[q][u];
+            if (!GRAD_ONLY)
+#pragma unroll
+                for (int q = 0; q < 6; ++q) hpp[6 * (int64_t)i + q] = (T)acc[q];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) wpt[3 * (int64_t)i + q] = acc[6 + q];
+        }
+    } else {
+        // one point with more than kTile observations: chunked, fixed-order reduction
+        double acc[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) acc[q] = 0.0;
+        int32_t i = pt[s];
+        for (int32_t base = s; base < e; base += kTile) {
+            const int64_t k = base + tid;
+            if (k < e) {
+                T e0, e1, wt, Jc[18], Jp[6];
+                int32_t ii;
+                observation<T>(k, cam, pt, uvx, uvy, pts, ck, delta, e0, e1, wt, Jc, Jp, ii);
+                if (!GRAD_ONLY) store_coupling<T>(k, N, Jc, Jp, wt, hcp);
+                double t[9];
+                point_terms<T>(Jp, e0, e1, wt, t);
+#pragma unroll
+                for (int q = 0; q < 9; ++q) acc[q] += t[q];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 9; ++q) sh[q][tid] = acc[q];
+        __syncthreads();
+        for (int stride = kTile / 2; stride > 0; stride >>= 1) {
+            if (tid < stride)
+#pragma unroll
+                for (int q = 0; q < 9; ++q) sh[q][tid] += sh[q][tid + stride];
+            __syncthreads();
+        }
+        if (tid == 0) {
+            if (!GRAD_ONLY)
+#pragma unroll
+                for (int q = 0; q < 6; ++q) hpp[6 * (int64_t)i + q] = (T)sh[q][0];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) wpt[3 * (int64_t)i + q] = sh[6 + q][0];
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_build_points(const PointMajor& pm, int64_t N, const double* pts, const CamK<T>* ck,
+                               double delta, bool grad_only, T* hcp, T* hpp, double* wpt, hipStream_t s)
+{
+    if (pm.num_tiles <= 0) return hipGetLastError();
+    if (grad_only)
+        hipLaunchKernelGGL((k_build_points<T, true>), dim3(pm.num_tiles), dim3(kTile), 0, s, pm.tile, pm.cam,
+                           pm.pt, pm.uvx, pm.uvy, pts, ck, (T)delta, N, hcp, hpp, wpt);
+    else
+        hipLaunchKernelGGL((k_build_points<T, false>), dim3(pm.num_tiles), dim3(kTile), 0, s, pm.tile, pm.cam,
+                           pm.pt, pm.uvx, pm.uvy, pts, ck, (T)delta, N, hcp, hpp, wpt);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------- camera-major build
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <bool GRAD_ONLY>
+__device__ __forceinline__ void flush_slot(double* acc, double* __restrict__ slots, int32_t slot, int lane)
+{
+    constexpr int W = GRAD_ONLY ? 9 : kCamSlotWords;
+    for (int q = 0; q < W; ++q) {
+        const double v = wave_sum(acc[q]);
+        if (lane == 0) slots[(int64_t)slot * kCamSlotWords + q] = v;
+        acc[q] = 0.0;
+    }
+}
+
+template <typename T, bool GRAD_ONLY>
+__global__ __launch_bounds__(256) void k_build_cameras(
+    int64_t N, int32_t num_chunks, const int32_t* __restrict__ cam, const int32_t* __restrict__ pt,
+    const double* __restrict__ uvx, const double* __restrict__ uvy, const double* __restrict__ pts,
+    const CamK<T>* __restrict__ ck, T delta, const int32_t* __restrict__ chunk_slot, double* __restrict__ slots)
+{
+    constexpr int W = GRAD_ONLY ? 9 : kCamSlotWords;
+    const int lane = threadIdx.x & 63;
+    const int32_t chunk = (int32_t)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
+    if (chunk >= num_chunks) return;  // whole wavefront leaves together
+    const int64_t start = (int64_t)chunk * kCmChunk;
+    const int64_t end = start + kCmChunk < N ? start + kCmChunk : N;
+    int32_t slot = chunk_slot[chunk];
+    int32_t cur = cam[start];
+    double acc[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) acc[q] = 0.0;
+    for (int row = 0; row < kCmRows; ++row) {
+        const int64_t k = start + (int64_t)row * 64 + lane;
+        if (start + (int64_t)row * 64 >= end) break;
+        const bool valid = k < end;
+        T e0 = 0, e1 = 0, wt = 0, Jc[18], Jp[6];
+        int32_t j = 0x7fffffff;
+        if (valid) {
+            int32_t i;
+            j = cam[k];
+            observation<T>(k, cam, pt, uvx, uvy, pts, ck, delta, e0, e1, wt, Jc, Jp, i);
+        }
+        while (true) {
+            if (valid && j == cur) {
+                int q = 0;
+                if (!GRAD_ONLY) {
+#pragma unroll
+                    for (int a = 0; a < 9; ++a)
+#pragma unroll
+                        for (int b = a; b < 9; ++b)
+                            acc[q++] += (double)(wt * (Jc[a] * Jc[b] + Jc[9 + a] * Jc[9 + b]));
+                }
+#pragma unroll
+                for (int a = 0; a < 9; ++a) acc[q++] += (double)(-wt * (Jc[a] * e0 + Jc[9 + a] * e1));
+            }
+            // lanes not yet consumed hold larger camera ids (the chunk is sorted)
+            const uint64_t more = __ballot(valid && j > cur);
+            if (more == 0) break;
+            flush_slot<GRAD_ONLY>(acc, slots, slot, lane);
+            ++slot;
+            const int first = __ffsll((unsigned long long)more) - 1;
+            cur = __shfl(j, first, 64);  // strictly larger: the loop ends
+        }
+    }
+    flush_slot<GRAD_ONLY>(acc, slots, slot, lane);
+}
+
+// One wavefront per camera sums its slots in order (deterministic).
+template <bool GRAD_ONLY>
+__global__ __launch_bounds__(256) void k_reduce_slots(int32_t m, const int32_t* __restrict__ cam_slot,
+                                                      const double* __restrict__ slots, double* __restrict__ hcc,
+                                                      double* __restrict__ vcam)
+{
+    const int lane = threadIdx.x & 63;
+    const int32_t j = (int32_t)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
+    if (j >= m) return;
+    const int32_t s0 = cam_slot[j], s1 = cam_slot[j + 1];
+    const int q = GRAD_ONLY ? 45 + lane : lane;
+    if (q >= kCamSlotWords) return;
+    double acc = 0.0;
+    const int col = GRAD_ONLY ? lane : q;
+    for (int32_t sl = s0; sl < s1; ++sl) acc += slots[(int64_t)sl * kCamSlotWords + col];
+    if (q < 45) {
+        // upper-triangle index q -> (a, b), a <= b
+        int a = 0, rem = q;
+        while (rem >= 9 - a) {
+            rem -= 9 - a;
+            ++a;
+        }
+        const int b = a + rem;
+        hcc[81 * (int64_t)j + a * 9 + b] = acc;
+        hcc[81 * (int64_t)j + b * 9 + a] = acc;
+    } else {
+        vcam[9 * (int64_t)j + (q - 45)] = acc;
+    }
+}
+
+template <typename T>
+hipError_t launch_build_cameras(const CameraMajor& cm, int32_t m, int64_t N, const double* pts, const CamK<T>* ck,
+                                double delta, bool grad_only, double* hcc, double* vcam, hipStream_t s)
+{
+    if (cm.num_chunks > 0) {
+        const int blocks = (cm.num_chunks + 3) / 4;
+        if (grad_only)
+            hipLaunchKernelGGL((k_build_cameras<T, true>), dim3(blocks), dim3(256), 0, s, N, cm.num_chunks, cm.cam,
+                               cm.pt, cm.uvx, cm.uvy, pts, ck, (T)delta, cm.chunk_slot, cm.slots);
+        else
+            hipLaunchKernelGGL((k_build_cameras<T, false>), dim3(blocks), dim3(256), 0, s, N, cm.num_chunks,
+                               cm.cam, cm.pt, cm.uvx, cm.uvy, pts, ck, (T)delta, cm.chunk_slot, cm.slots);
+    }
+    const int blocks = (m + 3) / 4;
+    if (m > 0) {
+        if (grad_only)
+            hipLaunchKernelGGL((k_reduce_slots<true>), dim3(blocks), dim3(256), 0, s, m, cm.cam_slot, cm.slots, hcc,
+                               vcam);
+        else
+            hipLaunchKernelGGL((k_reduce_slots<false>), dim3(blocks), dim3(256), 0, s, m, cm.cam_slot, cm.slots, hcc,
+                               vcam);
+    }
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------- FP64 cost
+template <typename T>
+__global__ __launch_bounds__(kRedBlock) void k_cost(int64_t N, const int32_t* __restrict__ cam,
+                                                    const int32_t* __restrict__ pt, const double* __restrict__ uvx,
+                                                    const double* __restrict__ uvy, const double* __restrict__ pts,
+                                                    const CamK<T>* __restrict__ ck, T delta,
+                                                    double* __restrict__ partials)
+{
+    __shared__ double sh[kRedBlock / 64];
+    double acc = 0.0;
+    for (int64_t k = blockIdx.x * (int64_t)kRedBlock + threadIdx.x; k < N; k += (int64_t)gridDim.x * kRedBlock) {
+        const int32_t j = cam[k], i = pt[k];
+        const CamK<T> kk = ck[j];
+        T e0, e1;
+        residual<T>(kk, (T)pts[3 * (int64_t)i], (T)pts[3 * (int64_t)i + 1], (T)pts[3 * (int64_t)i + 2], (T)uvx[k],
+                    (T)uvy[k], e0, e1);
+        acc += 0.5 * (double)huber_rho<T>(e0 * e0 + e1 * e1, delta);
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kRedBlock / 64; ++w) t += sh[w];
+        partials[blockIdx.x] = t;
+    }
+}
+
+int32_t reduce_blocks(int64_t count)
+{
+    int64_t b = (count + kRedBlock - 1) / kRedBlock;
+    if (b > 2048) b = 2048;
+    if (b < 1) b = 1;
+    return (int32_t)b;
+}
+
+template <typename T>
+hipError_t launch_cost_t(const PointMajor& pm, int64_t N, const double* pts, const CamK<T>* ck, double delta,
+                         double* partials, int32_t* nblocks, hipStream_t s)
+{
+    const int32_t b = reduce_blocks(N);
+    *nblocks = b;
+    hipLaunchKernelGGL((k_cost<T>), dim3(b), dim3(kRedBlock), 0, s, N, pm.cam, pm.pt, pm.uvx, pm.uvy, pts, ck,
+                       (T)delta, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_cost(const PointMajor& pm, int64_t N, const double* pts, const CamK<double>* ck, double delta,
+                       double* partials, int32_t* nblocks, hipStream_t s)
+{
+    return launch_cost_t<double>(pm, N, pts, ck, delta, partials, nblocks, s);
+}
+
+template hipError_t launch_build_points<double>(const PointMajor&, int64_t, const double*, const CamK<double>*,
+                                                double, bool, double*, double*, double*, hipStream_t);
+template hipError_t launch_build_points<float>(const PointMajor&, int64_t, const double*, const CamK<float>*,
+                                               double, bool, float*, float*, double*, hipStream_t);
+template hipError_t launch_build_cameras<double>(const CameraMajor&, int32_t, int64_t, const double*,
+                                                 const CamK<double>*, double, bool, double*, double*, hipStream_t);
+template hipError_t launch_build_cameras<float>(const CameraMajor&, int32_t, int64_t, const double*,
+                                                const CamK<float>*, double, bool, double*, double*, hipStream_t);
+template hipError_t launch_cost_t<float>(const PointMajor&, int64_t, const double*, const CamK<float>*, double,
+                                         double*, int32_t*, hipStream_t);
+
+}  // namespace ba

@@ -1,0 +1,154 @@
+// Camera model and its analytic Jacobian, shared by every kernel.
+//
+// Camera parameters (BAL convention of the paper's datasets, Sec. 6 dataset
+// table): w (angle-axis, 3), t (3), f, k1, k2.
+//   P = R(w) X + t,  p = -(Px, Py) / Pz,  d = 1 + k1 |p|^2 + k2 |p|^4,
+//   u = f d p,  e = u - uv.
+// Rotation: R(w) = cos(th) I + sin(th) [k]x + (1 - cos(th)) k k^T with
+// th = |w|, k = w / th; when th^2 <= DBL_EPSILON the first-order form
+// R = I + [w]x is used.
+//
+// Jacobian (the paper's analytic "-m" variant, Sec. 6):
+//   de/dp   = f (d I + 2 (k1 + 2 k2 |p|^2) p p^T)          (2x2)
+//   dp/dP   = -(1/Pz) [[1, 0, px], [0, 1, py]]             (2x3)
+//   de/dP   = de/dp dp/dP;   de/dt = de/dP;   de/dX = de/dP R
+//   de/dw   = de/dP (-[R X]x) J_l(w), J_l the left Jacobian of SO(3):
+//             J_l = I + (1 - cos th)/th^2 [w]x + (th - sin th)/th^3 [w]x^2
+//             (first-order branch: de/dw = de/dP (-[X]x))
+//   de/df = d p,  de/dk1 = f |p|^2 p,  de/dk2 = f |p|^4 p.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <float.h>
+#include <stdint.h>
+
+namespace ba {
+
+// Per-camera constants, computed once per state from the FP64 parameters.
+template <typename T>
+struct CamK {
+    T R[9];   // row-major rotation
+    T t[3];
+    T f, k1, k2;
+    T Jl[9];  // left Jacobian of SO(3) at w; identity in the first-order branch
+    T small;  // 1 in the first-order branch (use X instead of R X for de/dw)
+    T pad[2];
+};
+
+template <typename T>
+__host__ __device__ inline void camera_constants(const double* c, CamK<T>& k)
+{
+    const double w0 = c[0], w1 = c[1], w2 = c[2];
+    const double th2 = w0 * w0 + w1 * w1 + w2 * w2;
+    double R[9], J[9], small;
+    if (th2 > DBL_EPSILON) {
+        const double th = sqrt(th2);
+        const double s = sin(th), co = cos(th);
+        const double a0 = w0 / th, a1 = w1 / th, a2 = w2 / th;
+        const double omc = 1.0 - co;
+        R[0] = co + omc * a0 * a0;      R[1] = -s * a2 + omc * a0 * a1; R[2] = s * a1 + omc * a0 * a2;
+        R[3] = s * a2 + omc * a1 * a0;  R[4] = co + omc * a1 * a1;      R[5] = -s * a0 + omc * a1 * a2;
+        R[6] = -s * a1 + omc * a2 * a0; R[7] = s * a0 + omc * a2 * a1;  R[8] = co + omc * a2 * a2;
+        const double c1 = omc / th2, c2 = (th - s) / (th2 * th);
+        // [w]x^2 = w w^T - th^2 I
+        const double W[9] = {0.0, -w2, w1, w2, 0.0, -w0, -w1, w0, 0.0};
+        const double ww[9] = {w0 * w0 - th2, w0 * w1, w0 * w2, w1 * w0, w1 * w1 - th2,
+                              w1 * w2, w2 * w0, w2 * w1, w2 * w2 - th2};
+        for (int q = 0; q < 9; ++q) J[q] = ((q % 4) == 0 ? 1.0 : 0.0) + c1 * W[q] + c2 * ww[q];
+        small = 0.0;
+    } else {
+        R[0] = 1.0; R[1] = -w2; R[2] = w1;
+        R[3] = w2;  R[4] = 1.0; R[5] = -w0;
+        R[6] = -w1; R[7] = w0;  R[8] = 1.0;
+        for (int q = 0; q < 9; ++q) J[q] = (q % 4) == 0 ? 1.0 : 0.0;
+        small = 1.0;
+    }
+    for (int q = 0; q < 9; ++q) {
+        k.R[q] = (T)R[q];
+        k.Jl[q] = (T)J[q];
+    }
+    k.t[0] = (T)c[3];
+    k.t[1] = (T)c[4];
+    k.t[2] = (T)c[5];
+    k.f = (T)c[6];
+    k.k1 = (T)c[7];
+    k.k2 = (T)c[8];
+    k.small = (T)small;
+    k.pad[0] = k.pad[1] = (T)0;
+}
+
+// Residual only.
+template <typename T>
+__device__ __forceinline__ void residual(const CamK<T>& k, T X0, T X1, T X2, T u, T v, T& e0, T& e1)
+{
+    const T P0 = k.R[0] * X0 + k.R[1] * X1 + k.R[2] * X2 + k.t[0];
+    const T P1 = k.R[3] * X0 + k.R[4] * X1 + k.R[5] * X2 + k.t[1];
+    const T P2 = k.R[6] * X0 + k.R[7] * X1 + k.R[8] * X2 + k.t[2];
+    const T px = -(P0 / P2), py = -(P1 / P2);
+    const T r2 = px * px + py * py;
+    const T fd = k.f * ((T)1 + k.k1 * r2 + k.k2 * (r2 * r2));
+    e0 = fd * px - u;
+    e1 = fd * py - v;
+}
+
+// Residual and Jacobians: Jc row-major 2x9, Jp row-major 2x3.
+template <typename T>
+__device__ __forceinline__ void residual_jacobian(const CamK<T>& k, T X0, T X1, T X2, T u, T v,
+                                                  T& e0, T& e1, T Jc[18], T Jp[6])
+{
+    const T RX0 = k.R[0] * X0 + k.R[1] * X1 + k.R[2] * X2;
+    const T RX1 = k.R[3] * X0 + k.R[4] * X1 + k.R[5] * X2;
+    const T RX2 = k.R[6] * X0 + k.R[7] * X1 + k.R[8] * X2;
+    const T P0 = RX0 + k.t[0], P1 = RX1 + k.t[1], P2 = RX2 + k.t[2];
+    const T iz = (T)1 / P2;
+    const T px = -(P0 * iz), py = -(P1 * iz);
+    const T r2 = px * px + py * py;
+    const T d = (T)1 + k.k1 * r2 + k.k2 * (r2 * r2);
+    const T fd = k.f * d;
+    e0 = fd * px - u;
+    e1 = fd * py - v;
+    const T g = (T)2 * k.f * (k.k1 + (T)2 * k.k2 * r2);
+    const T A00 = fd + g * px * px, A01 = g * px * py, A11 = fd + g * py * py;
+    // de/dP rows
+    const T D00 = -iz * A00, D01 = -iz * A01, D02 = -iz * (A00 * px + A01 * py);
+    const T D10 = -iz * A01, D11 = -iz * A11, D12 = -iz * (A01 * px + A11 * py);
+    // lever arm for de/dw: R X (or X in the first-order branch)
+    const bool sm = k.small != (T)0;
+    const T a0 = sm ? X0 : RX0, a1 = sm ? X1 : RX1, a2 = sm ? X2 : RX2;
+    // y_r = a x D_r  (row r of de/dP (-[a]x)), then de/dw_r = y_r J_l
+    const T y00 = a1 * D02 - a2 * D01, y01 = a2 * D00 - a0 * D02, y02 = a0 * D01 - a1 * D00;
+    const T y10 = a1 * D12 - a2 * D11, y11 = a2 * D10 - a0 * D12, y12 = a0 * D11 - a1 * D10;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        Jc[c] = y00 * k.Jl[c] + y01 * k.Jl[3 + c] + y02 * k.Jl[6 + c];
+        Jc[9 + c] = y10 * k.Jl[c] + y11 * k.Jl[3 + c] + y12 * k.Jl[6 + c];
+        Jp[c] = D00 * k.R[c] + D01 * k.R[3 + c] + D02 * k.R[6 + c];
+        Jp[3 + c] = D10 * k.R[c] + D11 * k.R[3 + c] + D12 * k.R[6 + c];
+    }
+    Jc[3] = D00; Jc[4] = D01; Jc[5] = D02;
+    Jc[12] = D10; Jc[13] = D11; Jc[14] = D12;
+    Jc[6] = d * px;
+    Jc[15] = d * py;
+    const T fr2 = k.f * r2;
+    Jc[7] = fr2 * px;
+    Jc[16] = fr2 * py;
+    Jc[8] = fr2 * r2 * px;
+    Jc[17] = fr2 * r2 * py;
+}
+
+// Huber on the 2-D residual norm, s = |e|^2: rho(s) = s for s <= delta^2,
+// else 2 delta sqrt(s) - delta^2; delta <= 0 is the squared loss.  The
+// IRLS weight is rho'(s).
+template <typename T>
+__device__ __forceinline__ T huber_rho(T s, T delta)
+{
+    return (delta <= (T)0 || s <= delta * delta) ? s : (T)2 * delta * sqrt(s) - delta * delta;
+}
+
+template <typename T>
+__device__ __forceinline__ T huber_weight(T s, T delta)
+{
+    return (delta <= (T)0 || s <= delta * delta) ? (T)1 : delta / sqrt(s);
+}
+
+}  // namespace ba

@@ -1,0 +1,437 @@
+// Camera-sized vector work of the PCG loop (Alg. 2 with one partition) and
+// the small per-iteration kernels of the LM loop (trial state, predicted
+// decrease, parameter gathers).  All vectors and scalars are FP64.  Every
+// reduction writes per-block partial sums that k_sum_partials adds in a fixed
+// order, so results do not depend on scheduling.
+//
+// PCG (Alg. 2, with the printed index slips read as: the beta branch runs for
+// n >= 1, p^n = z^n + beta p^{n-1}, r^{n+1} = r^n - alpha q^n):
+//   z = M^-1 r (M = blockdiag of the damped camera blocks B~_j, through their
+//   Cholesky factors), rho = r^T z, p = z + beta p, q = S p,
+//   alpha = rho / p^T q, x += alpha p, r -= alpha q.
+#include "ba_internal.h"
+
+namespace ba {
+
+__device__ __forceinline__ double wave_sum64(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Block sum of up to two values into partials[blockIdx * 2 + {0,1}].
+template <int NV>
+__device__ __forceinline__ void block_partials(double v0, double v1, double* __restrict__ partials)
+{
+    __shared__ double sh[2][kRedBlock / 64];
+    v0 = wave_sum64(v0);
+    if (NV > 1) v1 = wave_sum64(v1);
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][threadIdx.x >> 6] = v0;
+        sh[1][threadIdx.x >> 6] = v1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int w = 0; w < kRedBlock / 64; ++w) {
+            a += sh[0][w];
+            b += sh[1][w];
+        }
+        partials[(int64_t)blockIdx.x * NV] = a;
+        if (NV > 1) partials[(int64_t)blockIdx.x * NV + 1] = b;
+    }
+}
+
+__global__ void k_zero(double* __restrict__ p, int64_t count)
+{
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x)
+        p[t] = 0.0;
+}
+
+hipError_t launch_zero(double* p, int64_t count, hipStream_t s)
+{
+    if (count > 0) {
+        int64_t b = (count + 255) / 256;
+        if (b > 4096) b = 4096;
+        hipLaunchKernelGGL(k_zero, dim3((unsigned)b), dim3(256), 0, s, p, count);
+    }
+    return hipGetLastError();
+}
+
+// Sums `count` rows of `stride` doubles column-wise (ncols <= stride) in a
+// fixed order; one block.
+__global__ __launch_bounds__(kRedBlock) void k_sum_partials(const double* __restrict__ partials, int32_t count,
+                                                            int32_t stride, int32_t ncols, double* __restrict__ out)
+{
+    __shared__ double sh[kRedBlock / 64];
+    for (int c = 0; c < ncols; ++c) {
+        double acc = 0.0;
+        for (int32_t t = threadIdx.x; t < count; t += kRedBlock) acc += partials[(int64_t)t * stride + c];
+        acc = wave_sum64(acc);
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int w = 0; w < kRedBlock / 64; ++w) t += sh[w];
+            out[c] = t;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_sum_partials(const double* partials, int32_t count, int32_t stride, int32_t ncols, double* out,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kRedBlock), 0, s, partials, count, stride, ncols, out);
+    return hipGetLastError();
+}
+
+// g = v - c; x = 0; r = g; partial ||g||^2
+__global__ __launch_bounds__(kRedBlock) void k_rhs_combine(int64_t len, const double* __restrict__ vcam,
+                                                           const double* __restrict__ cacc, double* __restrict__ g,
+                                                           double* __restrict__ x, double* __restrict__ r,
+                                                           double* __restrict__ partials)
+{
+    double acc = 0.0;
+    for (int64_t t = blockIdx.x * (int64_t)kRedBlock + threadIdx.x; t < len; t += (int64_t)gridDim.x * kRedBlock) {
+        const double v = vcam[t] - cacc[t];
+        g[t] = v;
+        r[t] = v;
+        x[t] = 0.0;
+        acc += v * v;
+    }
+    block_partials<1>(acc, 0.0, partials);
+}
+
+hipError_t launch_rhs_combine(int32_t m, const double* vcam, const double* cacc, double* g, double* x, double* r,
+                              double* partials, int32_t* nblocks, hipStream_t s)
+{
+    const int64_t len = 9 * (int64_t)m;
+    const int32_t b = reduce_blocks(len);
+    *nblocks = b;
+    hipLaunchKernelGGL(k_rhs_combine, dim3(b), dim3(kRedBlock), 0, s, len, vcam, cacc, g, x, r, partials);
+    return hipGetLastError();
+}
+
+__host__ __device__ constexpr int tri2(int r, int c) { return r * (r + 1) / 2 + c; }
+
+// z_j = (L L^T)^-1 r_j per camera; partials: r^T z and ||r||^2
+__global__ __launch_bounds__(kRedBlock) void k_pcg_precond(int32_t m, const double* __restrict__ lfac,
+                                                           const double* __restrict__ r, double* __restrict__ z,
+                                                           double* __restrict__ partials,
+                                                           const PcgScalars* __restrict__ sc)
+{
+    double rz = 0.0, rr = 0.0;
+    if (!sc->breakdown) {
+        for (int32_t j = blockIdx.x * kRedBlock + threadIdx.x; j < m; j += gridDim.x * kRedBlock) {
+            const double* L = lfac + 45 * (int64_t)j;
+            double rj[9], y[9];
+            for (int a = 0; a < 9; ++a) rj[a] = r[9 * (int64_t)j + a];
+            for (int a = 0; a < 9; ++a) {
+                double v = rj[a];
+                for (int t = 0; t < a; ++t) v -= L[tri2(a, t)] * y[t];
+                y[a] = v / L[tri2(a, a)];
+            }
+            for (int a = 8; a >= 0; --a) {
+                double v = y[a];
+                for (int t = a + 1; t < 9; ++t) v -= L[tri2(t, a)] * y[t];
+                y[a] = v / L[tri2(a, a)];
+            }
+            for (int a = 0; a < 9; ++a) {
+                z[9 * (int64_t)j + a] = y[a];
+                rz += rj[a] * y[a];
+                rr += rj[a] * rj[a];
+            }
+        }
+    }
+    block_partials<2>(rz, rr, partials);
+}
+
+hipError_t launch_pcg_precond(int32_t m, const double* lfac, const double* r, double* z, double* partials,
+                              int32_t* nblocks, const PcgScalars* sc, hipStream_t s)
+{
+    const int32_t b = reduce_blocks(m);
+    *nblocks = b;
+    hipLaunchKernelGGL(k_pcg_precond, dim3(b), dim3(kRedBlock), 0, s, m, lfac, r, z, partials, sc);
+    return hipGetLastError();
+}
+
+// p = z (first) or z + beta p, beta = rho / rho_prev; pT = (T) p
+template <typename T>
+__global__ void k_pcg_direction(int64_t len, int first, const double* __restrict__ z, double* __restrict__ p,
+                                T* __restrict__ pT, PcgScalars* __restrict__ sc)
+{
+    if (sc->breakdown) return;
+    const double beta = first ? 0.0 : sc->rho / sc->rho_prev;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < len; t += (int64_t)gridDim.x * blockDim.x) {
+        const double v = first ? z[t] : z[t] + beta * p[t];
+        p[t] = v;
+        pT[t] = (T)v;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->beta = beta;
+}
+
+template <typename T>
+hipError_t launch_pcg_direction(int32_t m, bool first, const double* z, double* p, T* pT, PcgScalars* sc,
+                                hipStream_t s)
+{
+    const int64_t len = 9 * (int64_t)m;
+    int64_t b = (len + 255) / 256;
+    if (b > 1024) b = 1024;
+    hipLaunchKernelGGL((k_pcg_direction<T>), dim3((unsigned)b), dim3(256), 0, s, len, first ? 1 : 0, z, p, pT, sc);
+    return hipGetLastError();
+}
+
+// q = B~ p - c; partial p^T q
+__global__ __launch_bounds__(kRedBlock) void k_matvec_combine(int32_t m, const double* __restrict__ bd,
+                                                              const double* __restrict__ p,
+                                                              const double* __restrict__ cacc, double* __restrict__ q,
+                                                              double* __restrict__ partials,
+                                                              const PcgScalars* __restrict__ sc)
+{
+    double acc = 0.0;
+    if (!sc->breakdown) {
+        const int64_t len = 9 * (int64_t)m;
+        for (int64_t t = blockIdx.x * (int64_t)kRedBlock + threadIdx.x; t < len; t += (int64_t)gridDim.x * kRedBlock) {
+            const int64_t j = t / 9;
+            const int a = (int)(t - 9 * j);
+            const double* B = bd + 81 * j + 9 * a;
+            const double* pj = p + 9 * j;
+            double v = 0.0;
+            for (int c = 0; c < 9; ++c) v += B[c] * pj[c];
+            v -= cacc[t];
+            q[t] = v;
+            acc += p[t] * v;
+        }
+    }
+    block_partials<1>(acc, 0.0, partials);
+}
+
+hipError_t launch_matvec_combine(int32_t m, const double* bd, const double* p, const double* cacc, double* q,
+                                 double* partials, int32_t* nblocks, const PcgScalars* sc, hipStream_t s)
+{
+    const int32_t b = reduce_blocks(9 * (int64_t)m);
+    *nblocks = b;
+    hipLaunchKernelGGL(k_matvec_combine, dim3(b), dim3(kRedBlock), 0, s, m, bd, p, cacc, q, partials, sc);
+    return hipGetLastError();
+}
+
+// alpha = rho / pq; x += alpha p; r -= alpha q; partial ||r||^2
+__global__ __launch_bounds__(kRedBlock) void k_pcg_update(int64_t len, const double* __restrict__ p,
+                                                          const double* __restrict__ q, double* __restrict__ x,
+                                                          double* __restrict__ r, double* __restrict__ partials,
+                                                          const PcgScalars* __restrict__ sc)
+{
+    double acc = 0.0;
+    if (!sc->breakdown) {
+        const double alpha = sc->rho / sc->pq;
+        for (int64_t t = blockIdx.x * (int64_t)kRedBlock + threadIdx.x; t < len; t += (int64_t)gridDim.x * kRedBlock) {
+            x[t] += alpha * p[t];
+            const double rn = r[t] - alpha * q[t];
+            r[t] = rn;
+            acc += rn * rn;
+        }
+    }
+    block_partials<1>(acc, 0.0, partials);
+}
+
+hipError_t launch_pcg_update(int32_t m, const double* p, const double* q, double* x, double* r, double* partials,
+                             int32_t* nblocks, PcgScalars* sc, hipStream_t s)
+{
+    const int64_t len = 9 * (int64_t)m;
+    const int32_t b = reduce_blocks(len);
+    *nblocks = b;
+    hipLaunchKernelGGL(k_pcg_update, dim3(b), dim3(kRedBlock), 0, s, len, p, q, x, r, partials, sc);
+    return hipGetLastError();
+}
+
+// Moves reduced sums into the scalar block.
+//   which 0: sums[0] = ||b||^2              -> bb, rr
+//   which 1: sums[0] = r^T z, sums[1] = ||r||^2 -> rho (rr unchanged)
+//   which 2: sums[0] = p^T q                -> pq; breakdown if <= 0 or non-finite
+//   which 3: sums[0] = ||r||^2 after update -> rr; rho_prev = rho
+__global__ void k_finish_scalars(PcgScalars* __restrict__ sc, const double* __restrict__ sums, int which)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (which == 0) {
+        sc->bb = sums[0];
+        sc->rr = sums[0];
+        sc->breakdown = 0;
+        sc->rho = sc->rho_prev = sc->pq = 0.0;
+    } else if (sc->breakdown) {
+        return;
+    } else if (which == 1) {
+        sc->rho = sums[0];
+    } else if (which == 2) {
+        const double pq = sums[0];
+        sc->pq = pq;
+        if (!(pq > 0.0) || !isfinite(pq)) sc->breakdown = 1;
+        else sc->alpha = sc->rho / pq;
+    } else {
+        sc->rr = sums[0];
+        sc->rho_prev = sc->rho;
+    }
+}
+
+hipError_t launch_pcg_finish_scalars(PcgScalars* sc, const double* sums, int which, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finish_scalars, dim3(1), dim3(64), 0, s, sc, sums, which);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ LM helpers
+__global__ void k_trial_state(int64_t lc, int64_t lp, const double* __restrict__ cams, const double* __restrict__ dc,
+                              const double* __restrict__ pts, const double* __restrict__ dp,
+                              double* __restrict__ cams_t, double* __restrict__ pts_t)
+{
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < lc + lp; t += (int64_t)gridDim.x * blockDim.x) {
+        if (t < lc) cams_t[t] = cams[t] + dc[t];
+        else pts_t[t - lc] = pts[t - lc] + dp[t - lc];
+    }
+}
+
+hipError_t launch_trial_state(int32_t m, int32_t n, const double* cams, const double* dc, const double* pts,
+                              const double* dp, double* cams_t, double* pts_t, hipStream_t s)
+{
+    const int64_t lc = 9 * (int64_t)m, lp = 3 * (int64_t)n;
+    int64_t b = (lc + lp + 255) / 256;
+    if (b > 8192) b = 8192;
+    if (b < 1) b = 1;
+    hipLaunchKernelGGL(k_trial_state, dim3((unsigned)b), dim3(256), 0, s, lc, lp, cams, dc, pts, dp, cams_t, pts_t);
+    return hipGetLastError();
+}
+
+__device__ __forceinline__ double clamp_d(double h) { return h < 1e-6 ? 1e-6 : (h > 1e32 ? 1e32 : h); }
+
+// pred terms: dc^T (lambda D_c dc + v) over cameras, dp^T (lambda D_p dp + w) over points
+template <typename T>
+__global__ __launch_bounds__(kRedBlock) void k_pred(int64_t lc, int64_t lp, const double* __restrict__ dc,
+                                                    const double* __restrict__ dcam, const double* __restrict__ vcam,
+                                                    const double* __restrict__ dp, const T* __restrict__ hpp,
+                                                    const double* __restrict__ wpt, double lambda, int32_t damping,
+                                                    double* __restrict__ partials)
+{
+    double a = 0.0, b = 0.0;
+    for (int64_t t = blockIdx.x * (int64_t)kRedBlock + threadIdx.x; t < lc + lp; t += (int64_t)gridDim.x * kRedBlock) {
+        if (t < lc) {
+            a += dc[t] * (lambda * dcam[t] * dc[t] + vcam[t]);
+        } else {
+            const int64_t u = t - lc;
+            const int64_t i = u / 3;
+            const int c = (int)(u - 3 * i);
+            const int dpos = c == 0 ? 0 : (c == 1 ? 3 : 5);
+            const double D = damping == 0 ? clamp_d((double)hpp[6 * i + dpos]) : 1.0;
+            b += dp[u] * (lambda * D * dp[u] + wpt[u]);
+        }
+    }
+    block_partials<2>(a, b, partials);
+}
+
+template <typename T>
+hipError_t launch_pred(int32_t m, int32_t n, const double* dc, const double* dcam, const double* vcam,
+                       const double* dp, const T* hpp, const double* wpt, double lambda, int32_t damping,
+                       double* partials, int32_t* nblocks, hipStream_t s)
+{
+    const int64_t lc = 9 * (int64_t)m, lp = 3 * (int64_t)n;
+    const int32_t b = reduce_blocks(lc + lp);
+    *nblocks = b;
+    hipLaunchKernelGGL((k_pred<T>), dim3(b), dim3(kRedBlock), 0, s, lc, lp, dc, dcam, vcam, dp, hpp, wpt, lambda,
+                       damping, partials);
+    return hipGetLastError();
+}
+
+// ------------------------------------------- caller order <-> internal
+__global__ void k_gather_cameras(int32_t m, int dtype, const void* __restrict__ src,
+                                 const int32_t* __restrict__ old_of_new, double* __restrict__ dst)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= 9 * (int64_t)m) return;
+    const int64_t j = t / 9;
+    const int a = (int)(t - 9 * j);
+    const int64_t o = 9 * (int64_t)old_of_new[j] + a;
+    dst[t] = dtype == 0 ? ((const double*)src)[o] : (double)((const float*)src)[o];
+}
+
+hipError_t launch_gather_cameras(int32_t m, int dtype, const void* src, const int32_t* old_of_new, double* dst,
+                                 hipStream_t s)
+{
+    const int64_t len = 9 * (int64_t)m;
+    if (len > 0)
+        hipLaunchKernelGGL(k_gather_cameras, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, m, dtype, src,
+                           old_of_new, dst);
+    return hipGetLastError();
+}
+
+__global__ void k_convert_points(int64_t len, int dtype, const void* __restrict__ src, double* __restrict__ dst)
+{
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < len; t += (int64_t)gridDim.x * blockDim.x)
+        dst[t] = dtype == 0 ? ((const double*)src)[t] : (double)((const float*)src)[t];
+}
+
+hipError_t launch_convert_points(int32_t n, int dtype, const void* src, double* dst, hipStream_t s)
+{
+    const int64_t len = 3 * (int64_t)n;
+    int64_t b = (len + 255) / 256;
+    if (b > 8192) b = 8192;
+    if (len > 0) hipLaunchKernelGGL(k_convert_points, dim3((unsigned)b), dim3(256), 0, s, len, dtype, src, dst);
+    return hipGetLastError();
+}
+
+// grad = -scale * [v; w] scattered to caller order (v, w hold -J^T W e)
+__global__ void k_scatter_grad(int64_t lc, int64_t lp, int dtype, double scale, const double* __restrict__ vcam,
+                               const double* __restrict__ wpt, const int32_t* __restrict__ old_of_new,
+                               void* __restrict__ gcam, void* __restrict__ gpt)
+{
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < lc + lp; t += (int64_t)gridDim.x * blockDim.x) {
+        if (t < lc) {
+            if (!gcam) continue;
+            const int64_t j = t / 9;
+            const int a = (int)(t - 9 * j);
+            const int64_t o = 9 * (int64_t)old_of_new[j] + a;
+            const double v = -scale * vcam[t];
+            if (dtype == 0) ((double*)gcam)[o] = v;
+            else ((float*)gcam)[o] = (float)v;
+        } else {
+            if (!gpt) continue;
+            const int64_t u = t - lc;
+            const double v = -scale * wpt[u];
+            if (dtype == 0) ((double*)gpt)[u] = v;
+            else ((float*)gpt)[u] = (float)v;
+        }
+    }
+}
+
+hipError_t launch_scatter_grad(int32_t m, int32_t n, int dtype, double scale, const double* vcam, const double* wpt,
+                               const int32_t* old_of_new, void* gcam, void* gpt, hipStream_t s)
+{
+    const int64_t lc = 9 * (int64_t)m, lp = 3 * (int64_t)n;
+    int64_t b = (lc + lp + 255) / 256;
+    if (b > 8192) b = 8192;
+    if (b < 1) b = 1;
+    hipLaunchKernelGGL(k_scatter_grad, dim3((unsigned)b), dim3(256), 0, s, lc, lp, dtype, scale, vcam, wpt,
+                       old_of_new, gcam, gpt);
+    return hipGetLastError();
+}
+
+__global__ void k_store_cost(const double* __restrict__ sum, double* __restrict__ out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = sum[0];
+}
+
+hipError_t launch_store_cost(const double* sum, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_store_cost, dim3(1), dim3(64), 0, s, sum, out);
+    return hipGetLastError();
+}
+
+template hipError_t launch_pcg_direction<double>(int32_t, bool, const double*, double*, double*, PcgScalars*,
+                                                 hipStream_t);
+template hipError_t launch_pcg_direction<float>(int32_t, bool, const double*, double*, float*, PcgScalars*,
+                                                hipStream_t);
+template hipError_t launch_pred<double>(int32_t, int32_t, const double*, const double*, const double*, const double*,
+                                        const double*, const double*, double, int32_t, double*, int32_t*, hipStream_t);
+template hipError_t launch_pred<float>(int32_t, int32_t, const double*, const double*, const double*, const double*,
+                                       const float*, const double*, double, int32_t, double*, int32_t*, hipStream_t);
+
+}  // namespace ba

@@ -1,0 +1,312 @@
+// Damping, block inverses and the implicit Schur products.
+//
+//   * k_damp_cameras: B~_j = B_j + lambda D_j and its Cholesky factor, FP64
+//     (the block-Jacobi preconditioner of Alg. 2 and the B x term of Alg. 3).
+//   * k_damp_points:  C~_i = C_i + lambda D_i and its explicit inverse (Alg. 3
+//     b = C^-1 a, Eq. schur_x_p), one lane per point.
+//   * k_schur_tiles: the observation pass of Alg. 3 (DSE) with one partition,
+//     and its two relatives, over point-aligned tiles of <= 256 observations:
+//       mode 0  c = E C~^-1 E^T x   (a = E^T x per point, b = C~^-1 a,
+//                                    then c_j += E_k b per observation)
+//       mode 1  c = E C~^-1 w       (reduced right-hand side, Eq. schur_x_c)
+//       mode 2  dp = C~^-1 (w - E^T x)   (back-substitution, Eq. schur_x_p)
+//     E is read as 27 coalesced streams.  The per-point sums a_i run over the
+//     point's contiguous segment in LDS; each observation then scatters its
+//     nine-word camera contribution with a hardware float atomic add.
+// Damping (Reading of Sec. 3 and supplementary Sec. C): D = clamp(diag, 1e-6,
+// 1e32) (Marquardt, Ceres-like) or D = I (as printed in Sec. 3).
+#include "ba_internal.h"
+
+namespace ba {
+
+__device__ __forceinline__ double clamp_diag(double h)
+{
+    return h < 1e-6 ? 1e-6 : (h > 1e32 ? 1e32 : h);
+}
+
+// packed lower-triangular index (r >= c)
+__host__ __device__ constexpr int tri(int r, int c) { return r * (r + 1) / 2 + c; }
+
+__global__ void k_damp_cameras(int32_t m, const double* __restrict__ hcc, double lambda, int32_t damping,
+                               double* __restrict__ bd, double* __restrict__ lfac, double* __restrict__ dcam,
+                               int32_t* __restrict__ flag)
+{
+    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const double* H = hcc + 81 * (int64_t)j;
+    double L[45];
+    for (int r = 0; r < 9; ++r)
+        for (int c = 0; c <= r; ++c) L[tri(r, c)] = H[r * 9 + c];
+    for (int a = 0; a < 9; ++a) {
+        const double D = damping == 0 ? clamp_diag(H[a * 10]) : 1.0;
+        dcam[9 * (int64_t)j + a] = D;
+        L[tri(a, a)] += lambda * D;
+    }
+    for (int r = 0; r < 9; ++r)
+        for (int c = 0; c < 9; ++c) {
+            const double v = r >= c ? L[tri(r, c)] : L[tri(c, r)];
+            bd[81 * (int64_t)j + r * 9 + c] = v;
+        }
+    bool ok = true;
+    for (int c = 0; c < 9; ++c) {
+        double sd = L[tri(c, c)];
+        for (int t = 0; t < c; ++t) sd -= L[tri(c, t)] * L[tri(c, t)];
+        if (!(sd > 0.0)) {
+            ok = false;
+            sd = 1.0;
+        }
+        const double d = sqrt(sd);
+        L[tri(c, c)] = d;
+        for (int r = c + 1; r < 9; ++r) {
+            double x = L[tri(r, c)];
+            for (int t = 0; t < c; ++t) x -= L[tri(r, t)] * L[tri(c, t)];
+            L[tri(r, c)] = x / d;
+        }
+    }
+    for (int q = 0; q < 45; ++q) lfac[45 * (int64_t)j + q] = L[q];
+    if (!ok) atomicOr(flag, 1);
+}
+
+hipError_t launch_damp_cameras(int32_t m, const double* hcc, double lambda, int32_t damping, double* bd,
+                               double* lfac, double* dcam, int32_t* flag, hipStream_t s)
+{
+    if (m > 0)
+        hipLaunchKernelGGL(k_damp_cameras, dim3((m + 63) / 64), dim3(64), 0, s, m, hcc, lambda, damping, bd, lfac,
+                           dcam, flag);
+    return hipGetLastError();
+}
+
+// C~ = C + lambda D, inverse through its Cholesky factor; packed symmetric
+// order (00, 01, 02, 11, 12, 22).
+template <typename T>
+__global__ void k_damp_points(int32_t n, const T* __restrict__ hpp, double lambda, int32_t damping,
+                              T* __restrict__ cinv, int32_t* __restrict__ flag)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const T* h = hpp + 6 * (int64_t)i;
+    T a00 = h[0], a01 = h[1], a02 = h[2], a11 = h[3], a12 = h[4], a22 = h[5];
+    const T lam = (T)lambda;
+    if (damping == 0) {
+        a00 += lam * (T)clamp_diag((double)a00);
+        a11 += lam * (T)clamp_diag((double)a11);
+        a22 += lam * (T)clamp_diag((double)a22);
+    } else {
+        a00 += lam;
+        a11 += lam;
+        a22 += lam;
+    }
+    bool ok = a00 > (T)0;
+    const T l00 = sqrt(ok ? a00 : (T)1);
+    const T l10 = a01 / l00, l20 = a02 / l00;
+    T s11 = a11 - l10 * l10;
+    ok = ok && s11 > (T)0;
+    const T l11 = sqrt(s11 > (T)0 ? s11 : (T)1);
+    const T l21 = (a12 - l20 * l10) / l11;
+    T s22 = a22 - l20 * l20 - l21 * l21;
+    ok = ok && s22 > (T)0;
+    const T l22 = sqrt(s22 > (T)0 ? s22 : (T)1);
+    const T m00 = (T)1 / l00, m11 = (T)1 / l11, m22 = (T)1 / l22;
+    const T m10 = -l10 * m00 * m11;
+    const T m21 = -l21 * m11 * m22;
+    const T m20 = -(l20 * m00 + l21 * m10) * m22;
+    T* o = cinv + 6 * (int64_t)i;
+    o[0] = m00 * m00 + m10 * m10 + m20 * m20;
+    o[1] = m10 * m11 + m20 * m21;
+    o[2] = m20 * m22;
+    o[3] = m11 * m11 + m21 * m21;
+    o[4] = m21 * m22;
+    o[5] = m22 * m22;
+    if (!ok) atomicOr(flag, 2);
+}
+
+template <typename T>
+hipError_t launch_damp_points(int32_t n, const T* hpp, double lambda, int32_t damping, T* cinv, int32_t* flag,
+                              hipStream_t s)
+{
+    if (n > 0)
+        hipLaunchKernelGGL((k_damp_points<T>), dim3((n + 255) / 256), dim3(256), 0, s, n, hpp, lambda, damping, cinv,
+                           flag);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------- Schur tiles
+template <typename T>
+__device__ __forceinline__ void sym3_apply(const T* __restrict__ ci, T a0, T a1, T a2, T& b0, T& b1, T& b2)
+{
+    const T c00 = ci[0], c01 = ci[1], c02 = ci[2], c11 = ci[3], c12 = ci[4], c22 = ci[5];
+    b0 = c00 * a0 + c01 * a1 + c02 * a2;
+    b1 = c01 * a0 + c11 * a1 + c12 * a2;
+    b2 = c02 * a0 + c12 * a1 + c22 * a2;
+}
+
+__device__ __forceinline__ void atomic_add_f64(double* p, double v) { unsafeAtomicAdd(p, v); }
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kTile) void k_schur_tiles(const int32_t* __restrict__ tile,
+                                                       const int32_t* __restrict__ cam,
+                                                       const int32_t* __restrict__ pt, int64_t N,
+                                                       const T* __restrict__ hcp, const T* __restrict__ cinv,
+                                                       const double* __restrict__ wpt, const T* __restrict__ xcam,
+                                                       double* __restrict__ cacc, double* __restrict__ dp)
+{
+    __shared__ T sha[3][kTile];
+    __shared__ T shb[3][kTile];
+    __shared__ int32_t shpt[kTile];
+    const int tid = threadIdx.x;
+    const int32_t s = tile[blockIdx.x], e = tile[blockIdx.x + 1];
+    const int32_t len = e - s;
+    if (len <= kTile) {
+        const bool valid = tid < len;
+        const int64_t k = s + tid;
+        int32_t i = -1, j = 0;
+        T h[27];
+        if (valid) {
+            j = cam[k];
+            i = pt[k];
+#pragma unroll
+            for (int q = 0; q < 27; ++q) h[q] = hcp[(int64_t)q * N + k];
+            if (MODE != 1) {
+                T x[9];
+#pragma unroll
+                for (int a = 0; a < 9; ++a) x[a] = xcam[9 * (int64_t)j + a];
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    T acc = 0;
+#pragma unroll
+                    for (int a = 0; a < 9; ++a) acc += h[a * 3 + b] * x[a];
+                    sha[b][tid] = acc;
+                }
+            }
+        }
+        shpt[tid] = i;
+        __syncthreads();
+        if (valid && (tid == 0 || shpt[tid - 1] != i)) {
+            T b0, b1, b2;
+            const T* ci = cinv + 6 * (int64_t)i;
+            if (MODE == 1) {
+                sym3_apply<T>(ci, (T)wpt[3 * (int64_t)i], (T)wpt[3 * (int64_t)i + 1], (T)wpt[3 * (int64_t)i + 2],
+                              b0, b1, b2);
+            } else {
+                T a0 = 0, a1 = 0, a2 = 0;
+                for (int u = tid; u < len && shpt[u] == i; ++u) {
+                    a0 += sha[0][u];
+                    a1 += sha[1][u];
+                    a2 += sha[2][u];
+                }
+                if (MODE == 2) {
+                    a0 = (T)wpt[3 * (int64_t)i] - a0;
+                    a1 = (T)wpt[3 * (int64_t)i + 1] - a1;
+                    a2 = (T)wpt[3 * (int64_t)i + 2] - a2;
+                }
+                sym3_apply<T>(ci, a0, a1, a2, b0, b1, b2);
+            }
+            if (MODE == 2) {
+                dp[3 * (int64_t)i] = (double)b0;
+                dp[3 * (int64_t)i + 1] = (double)b1;
+                dp[3 * (int64_t)i + 2] = (double)b2;
+            } else {
+                shb[0][tid] = b0;
+                shb[1][tid] = b1;
+                shb[2][tid] = b2;
+            }
+        }
+        if (MODE == 2) return;
+        __syncthreads();
+        if (valid) {
+            int hd = tid;
+            while (hd > 0 && shpt[hd - 1] == i) --hd;
+            const T b0 = shb[0][hd], b1 = shb[1][hd], b2 = shb[2][hd];
+#pragma unroll
+            for (int a = 0; a < 9; ++a)
+                atomic_add_f64(cacc + 9 * (int64_t)j + a, (double)(h[a * 3] * b0 + h[a * 3 + 1] * b1 + h[a * 3 + 2] * b2));
+        }
+    } else {
+        // one point with more than kTile observations
+        const int32_t i = pt[s];
+        T a0 = 0, a1 = 0, a2 = 0;
+        if (MODE != 1) {
+            for (int32_t base = s; base < e; base += kTile) {
+                const int64_t k = base + tid;
+                if (k < e) {
+                    const int32_t j = cam[k];
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) {
+                        T acc = 0;
+#pragma unroll
+                        for (int a = 0; a < 9; ++a) acc += hcp[(int64_t)(a * 3 + b) * N + k] * xcam[9 * (int64_t)j + a];
+                        if (b == 0) a0 += acc;
+                        if (b == 1) a1 += acc;
+                        if (b == 2) a2 += acc;
+                    }
+                }
+            }
+            sha[0][tid] = a0;
+            sha[1][tid] = a1;
+            sha[2][tid] = a2;
+            __syncthreads();
+            for (int stride = kTile / 2; stride > 0; stride >>= 1) {
+                if (tid < stride)
+                    for (int b = 0; b < 3; ++b) sha[b][tid] += sha[b][tid + stride];
+                __syncthreads();
+            }
+        }
+        if (tid == 0) {
+            const T* ci = cinv + 6 * (int64_t)i;
+            T b0, b1, b2;
+            if (MODE == 1) {
+                sym3_apply<T>(ci, (T)wpt[3 * (int64_t)i], (T)wpt[3 * (int64_t)i + 1], (T)wpt[3 * (int64_t)i + 2],
+                              b0, b1, b2);
+            } else if (MODE == 2) {
+                sym3_apply<T>(ci, (T)wpt[3 * (int64_t)i] - sha[0][0], (T)wpt[3 * (int64_t)i + 1] - sha[1][0],
+                              (T)wpt[3 * (int64_t)i + 2] - sha[2][0], b0, b1, b2);
+                dp[3 * (int64_t)i] = (double)b0;
+                dp[3 * (int64_t)i + 1] = (double)b1;
+                dp[3 * (int64_t)i + 2] = (double)b2;
+            } else {
+                sym3_apply<T>(ci, sha[0][0], sha[1][0], sha[2][0], b0, b1, b2);
+            }
+            shb[0][0] = b0;
+            shb[1][0] = b1;
+            shb[2][0] = b2;
+        }
+        if (MODE == 2) return;
+        __syncthreads();
+        const T b0 = shb[0][0], b1 = shb[1][0], b2 = shb[2][0];
+        for (int32_t base = s; base < e; base += kTile) {
+            const int64_t k = base + tid;
+            if (k < e) {
+                const int32_t j = cam[k];
+#pragma unroll
+                for (int a = 0; a < 9; ++a)
+                    atomic_add_f64(cacc + 9 * (int64_t)j + a,
+                                   (double)(hcp[(int64_t)(a * 3) * N + k] * b0 + hcp[(int64_t)(a * 3 + 1) * N + k] * b1 +
+                                            hcp[(int64_t)(a * 3 + 2) * N + k] * b2));
+            }
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_schur_tiles(int mode, const PointMajor& pm, int64_t N, const T* hcp, const T* cinv,
+                              const double* wpt, const T* xcam, double* cacc, double* dp, hipStream_t s)
+{
+    if (pm.num_tiles <= 0) return hipGetLastError();
+    const dim3 g(pm.num_tiles), b(kTile);
+    if (mode == 0)
+        hipLaunchKernelGGL((k_schur_tiles<T, 0>), g, b, 0, s, pm.tile, pm.cam, pm.pt, N, hcp, cinv, wpt, xcam, cacc, dp);
+    else if (mode == 1)
+        hipLaunchKernelGGL((k_schur_tiles<T, 1>), g, b, 0, s, pm.tile, pm.cam, pm.pt, N, hcp, cinv, wpt, xcam, cacc, dp);
+    else
+        hipLaunchKernelGGL((k_schur_tiles<T, 2>), g, b, 0, s, pm.tile, pm.cam, pm.pt, N, hcp, cinv, wpt, xcam, cacc, dp);
+    return hipGetLastError();
+}
+
+template hipError_t launch_damp_points<double>(int32_t, const double*, double, int32_t, double*, int32_t*, hipStream_t);
+template hipError_t launch_damp_points<float>(int32_t, const float*, double, int32_t, float*, int32_t*, hipStream_t);
+template hipError_t launch_schur_tiles<double>(int, const PointMajor&, int64_t, const double*, const double*,
+                                               const double*, const double*, double*, double*, hipStream_t);
+template hipError_t launch_schur_tiles<float>(int, const PointMajor&, int64_t, const float*, const float*,
+                                              const double*, const float*, double*, double*, hipStream_t);
+
+}  // namespace ba

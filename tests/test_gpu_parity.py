@@ -1,0 +1,163 @@
+"""HIP path vs the FP64 CPU oracle, element by element, through the C ABI.
+
+Tolerances: the FP64 path matches the oracle's per-iteration cost to relative
+1e-9 with the PCG iteration counts matched (the oracle runs first with its
+rtol and the GPU replays its counts); cost, gradient and Schur products agree
+to near round-off (1e-12 .. 1e-10 relative, the spread of summation order over
+a few thousand terms).  The FP32-mixed path must reach a final cost within
+relative 1e-4 of the oracle's.
+"""
+import numpy as np
+import pytest
+
+from helpers import rel_err, small_zipf, with_edge_cases
+from oracle import oracle as orc
+from paper_2112_01349_amd import FP32_MIXED, FP64, Problem, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def make(prob_or_arrays, precision=FP64, **opts):
+    if isinstance(prob_or_arrays, tuple):
+        cams, pts, oc, op, uv = prob_or_arrays[:5]
+    else:
+        p = prob_or_arrays
+        cams, pts, oc, op, uv = p.cameras0, p.points0, p.obs_camera, p.obs_point, p.obs_uv
+    return Problem(cams, pts, oc, op, uv, precision=precision, **opts), (cams, pts, oc, op, uv)
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return synth.generate("tiny", seed=0)
+
+
+@pytest.mark.parametrize("delta", [0.0, 1.0])
+def test_cost_and_gradient(tiny, delta):
+    src = tiny if delta == 0.0 else small_zipf()
+    prob, (cams, pts, oc, op, uv) = make(src, huber_delta=delta)
+    F, gc, gp = prob.eval_cost_grad()
+    Fo, gco, gpo = orc.gradient(cams, pts, oc, op, uv, delta)
+    assert abs(F - Fo) <= 1e-13 * abs(Fo)
+    assert rel_err(gc, gco) <= 1e-10
+    assert rel_err(gp, gpo) <= 1e-10
+    c2, p2 = prob.get_params()
+    np.testing.assert_array_equal(c2, cams)
+    np.testing.assert_array_equal(p2, pts)
+
+
+@pytest.mark.parametrize("damping", [0, 1])
+def test_schur_matvec(tiny, damping):
+    prob, (cams, pts, oc, op, uv) = make(tiny)
+    lam = 1e-3
+    A = orc.assemble(cams, pts, oc, op, uv)
+    Bd, Cd, Dc, Dp = orc.damp(A["B"], A["C"], lam, damping)
+    Ci = orc.invert_points(Cd)
+    x = np.random.default_rng(4).normal(size=(len(cams), 9))
+    ref = orc.schur_matvec(oc, op, Bd, A["E"], Ci, x)
+    q = prob.schur_matvec(x, lam, damping)
+    assert rel_err(q, ref) <= 1e-11
+
+
+def test_edge_cases_cost_gradient_matvec():
+    arrays = with_edge_cases(small_zipf(seed=7))
+    cams, pts, oc, op, uv, info = arrays
+    prob, _ = make(arrays, huber_delta=1.0)
+    F, gc, gp = prob.eval_cost_grad()
+    Fo, gco, gpo = orc.gradient(cams, pts, oc, op, uv, 1.0)
+    assert abs(F - Fo) <= 1e-13 * abs(Fo)
+    assert rel_err(gc, gco) <= 1e-10 and rel_err(gp, gpo) <= 1e-10
+    assert np.all(gc[info["unseen_camera"]] == 0.0) and np.all(gp[info["unseen_point"]] == 0.0)
+    lam = 1e-2
+    A = orc.assemble(cams, pts, oc, op, uv, 1.0)
+    Bd, Cd, Dc, Dp = orc.damp(A["B"], A["C"], lam, 0)
+    Ci = orc.invert_points(Cd)
+    x = np.random.default_rng(5).normal(size=(len(cams), 9))
+    ref = orc.schur_matvec(oc, op, Bd, A["E"], Ci, x)
+    assert rel_err(prob.schur_matvec(x, lam), ref) <= 1e-10
+
+
+def lm_pair(src, delta=0.0, iters=10, max_pcg=50, rtol=1e-8, edge=False):
+    arrays = src if isinstance(src, tuple) else None
+    if arrays is None:
+        arrays = (src.cameras0, src.points0, src.obs_camera, src.obs_point, src.obs_uv)
+    cams, pts, oc, op, uv = arrays[:5]
+    oc_, op_, tr, rc = orc.lm_solve(cams, pts, oc, op, uv, huber_delta=delta, max_lm_iters=iters,
+                                    max_pcg_iters=max_pcg, pcg_rtol=rtol)
+    assert rc == 0
+    prob, _ = make(arrays[:5], huber_delta=delta)
+    gpu = prob.lm_solve(max_lm_iters=iters, pcg_schedule=tr["pcg_iters"], max_pcg_iters=max_pcg,
+                        pcg_rtol=rtol)
+    return tr, gpu, prob, (oc_, op_)
+
+
+def assert_traces_match(tr, gpu, tol=1e-9, decisive=1e-10):
+    """Per-iteration trial and accepted costs agree to `tol`.  Accept/reject
+    decisions (and so lambda) must agree while the oracle's cost change is
+    above round-off (|F - F_trial| > decisive * F); once the solve has
+    converged the gain ratio is a ratio of rounding errors and either
+    decision is correct."""
+    assert gpu["status"] == 0
+    assert gpu["iters_run"] == tr["iters_run"]
+    assert abs(gpu["initial_cost"] - tr["initial_cost"]) <= 1e-13 * tr["initial_cost"]
+    np.testing.assert_array_equal(gpu["pcg_iters"], tr["pcg_iters"])
+    prev = tr["initial_cost"]
+    same_path = True
+    for k in range(tr["iters_run"]):
+        assert abs(gpu["trial_cost"][k] - tr["trial_cost"][k]) <= tol * abs(tr["trial_cost"][k]), k
+        assert abs(gpu["cost"][k] - tr["cost"][k]) <= tol * abs(tr["cost"][k]), k
+        if abs(prev - tr["trial_cost"][k]) > decisive * prev and same_path:
+            assert gpu["accepted"][k] == tr["accepted"][k], k
+            assert abs(gpu["lambda"][k] - tr["lambda"][k]) <= 1e-6 * tr["lambda"][k], k
+        else:
+            same_path = False
+        prev = tr["cost"][k]
+
+
+def test_lm_trace_fp64_tiny(tiny):
+    tr, gpu, prob, (co, po) = lm_pair(tiny)
+    assert_traces_match(tr, gpu)
+    c, p = prob.get_params()
+    assert rel_err(c, co) <= 1e-6 and rel_err(p, po) <= 1e-6
+
+
+def test_lm_trace_fp64_huber_edge_cases():
+    arrays = with_edge_cases(small_zipf(seed=11, m=20, n=400, N=2400))
+    tr, gpu, prob, _ = lm_pair(arrays, delta=1.0, iters=8, max_pcg=60, rtol=1e-8)
+    assert_traces_match(tr, gpu)
+
+
+def test_lm_rtol_mode_agrees(tiny):
+    cams, pts, oc, op, uv = tiny.cameras0, tiny.points0, tiny.obs_camera, tiny.obs_point, tiny.obs_uv
+    _, _, tr, rc = orc.lm_solve(cams, pts, oc, op, uv, max_lm_iters=10, max_pcg_iters=50, pcg_rtol=1e-8)
+    prob, _ = make(tiny)
+    gpu = prob.lm_solve(max_lm_iters=10, max_pcg_iters=50, pcg_rtol=1e-8)
+    # decisions above round-off agree; PCG counts differ by at most one
+    prev = tr["initial_cost"]
+    for k in range(10):
+        if abs(prev - tr["trial_cost"][k]) <= 1e-10 * prev:
+            break
+        assert gpu["accepted"][k] == tr["accepted"][k], k
+        assert abs(int(gpu["pcg_iters"][k]) - int(tr["pcg_iters"][k])) <= 1, k
+        prev = tr["cost"][k]
+    assert abs(gpu["final_cost"] - tr["final_cost"]) <= 1e-9 * tr["final_cost"]
+
+
+def test_mixed_precision_reaches_oracle_cost(tiny):
+    cams, pts, oc, op, uv = tiny.cameras0, tiny.points0, tiny.obs_camera, tiny.obs_point, tiny.obs_uv
+    _, _, tr, rc = orc.lm_solve(cams, pts, oc, op, uv, max_lm_iters=10, max_pcg_iters=50, pcg_rtol=1e-8)
+    prob, _ = make(tiny, precision=FP32_MIXED)
+    gpu = prob.lm_solve(max_lm_iters=10, max_pcg_iters=50, pcg_rtol=1e-8)
+    assert gpu["status"] == 0
+    assert np.all(np.diff(np.concatenate([[gpu["initial_cost"]], gpu["cost"]])) <= 0)
+    assert gpu["final_cost"] <= tr["final_cost"] * (1 + 1e-4)
+
+
+def test_lm_monotone_and_state_consistent(tiny):
+    prob, _ = make(tiny)
+    gpu = prob.lm_solve(max_lm_iters=6, max_pcg_iters=50, pcg_rtol=1e-8)
+    costs = np.concatenate([[gpu["initial_cost"]], gpu["cost"]])
+    assert np.all(np.diff(costs) <= 0)
+    assert abs(prob.cost() - gpu["final_cost"]) <= 1e-13 * gpu["final_cost"]
+    c, p = prob.get_params()
+    assert abs(orc.cost(c, p, tiny.obs_camera, tiny.obs_point, tiny.obs_uv) - gpu["final_cost"]) \
+        <= 1e-12 * gpu["final_cost"]

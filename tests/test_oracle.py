@@ -16,6 +16,7 @@ import scipy.linalg
 import scipy.sparse.linalg
 from scipy.spatial.transform import Rotation
 
+from helpers import small_zipf
 from oracle import oracle as orc
 from paper_2112_01349_amd import synth
 
@@ -25,16 +26,6 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 @pytest.fixture(scope="module")
 def tiny():
     return synth.generate("tiny", seed=0)
-
-
-def small_zipf(seed=1, m=12, n=150, N=700, outliers=0.05):
-    """A small problem with the Zipf/outlier structure of the large workloads."""
-    cfg = dict(m=m, n=n, N=N, vmax=8, half=50.0, ring=150.0, outliers=outliers)
-    synth.CONFIGS["_small"] = cfg
-    try:
-        return synth.generate("_small", seed=seed)
-    finally:
-        del synth.CONFIGS["_small"]
 
 
 def skew(w):
