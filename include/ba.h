@@ -96,6 +96,8 @@ typedef struct {
     int64_t pcg_iters_total;       /* Schur matvecs executed */
     double matvec_ms;              /* sum of timed matvec kernel durations (time_kernels) */
     int64_t matvec_launches;       /* number of timed matvec launches (time_kernels) */
+    double schur_hot_ms;           /* of matvec_ms: the point-major pass over all
+                                      observations (time_kernels) */
 } ba_report;
 
 /* Fills *opt with defaults: FP64, Marquardt damping, squared loss, 10 LM

@@ -64,6 +64,7 @@ struct ba_problem {
     int32_t* d_old_of_new = nullptr;
     PointMajor pm{};
     CameraMajor cm{};
+    SchurPlan sp{};
     // blocks
     void* hcp = nullptr;   // [27][N] of T
     void* hpp = nullptr;   // [n][6] of T
@@ -186,6 +187,32 @@ ba_status ba_memory_bytes(const ba_problem* prob, int64_t* bytes)
 }  // extern "C"
 
 // ------------------------------------------------------------------ set-up
+// Partial-sum slots of a camera-sorted stream cut into wave chunks of
+// kCmChunk: one slot per (chunk, camera run); a camera's slots are
+// contiguous.  Returns the slot count.
+static int32_t plan_slots(const std::vector<int32_t>& cam_sorted, int32_t m, std::vector<int32_t>& chunk_slot,
+                          std::vector<int32_t>& cam_slot)
+{
+    const int64_t len = (int64_t)cam_sorted.size();
+    const int32_t num_chunks = (int32_t)((len + kCmChunk - 1) / kCmChunk);
+    chunk_slot.assign((size_t)num_chunks + 1, 0);
+    std::vector<int32_t> per_cam((size_t)m, 0);
+    int32_t slot = 0;
+    for (int32_t c = 0; c < num_chunks; ++c) {
+        chunk_slot[c] = slot;
+        const int64_t s = (int64_t)c * kCmChunk, e = std::min<int64_t>(len, s + kCmChunk);
+        for (int64_t t = s; t < e; ++t)
+            if (t == s || cam_sorted[(size_t)t] != cam_sorted[(size_t)t - 1]) {
+                per_cam[cam_sorted[(size_t)t]]++;
+                ++slot;
+            }
+    }
+    chunk_slot[num_chunks] = slot;
+    cam_slot.assign((size_t)m + 1, 0);
+    for (int32_t j = 0; j < m; ++j) cam_slot[(size_t)j + 1] = cam_slot[j] + per_cam[j];
+    return slot;
+}
+
 static ba_status upload_state(ba_problem* P, const double* cameras, const double* points)
 {
     const int32_t m = P->m, n = P->n;
@@ -312,7 +339,7 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     std::vector<int64_t> coff((size_t)m + 1, 0);
     for (int64_t t = 0; t < N; ++t) coff[(size_t)h_pm_cam[(size_t)t] + 1]++;
     for (int32_t j = 0; j < m; ++j) coff[(size_t)j + 1] += coff[j];
-    std::vector<int32_t> h_cm_cam((size_t)N), h_cm_pt((size_t)N);
+    std::vector<int32_t> h_cm_cam((size_t)N), h_cm_pt((size_t)N), h_cm_src((size_t)N);
     std::vector<double> h_cm_uvx((size_t)N), h_cm_uvy((size_t)N);
     {
         std::vector<int64_t> fill(coff.begin(), coff.end() - 1);
@@ -321,31 +348,80 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
             const int64_t d = fill[j]++;
             h_cm_cam[(size_t)d] = j;
             h_cm_pt[(size_t)d] = h_pm_pt[(size_t)t];
+            h_cm_src[(size_t)d] = (int32_t)t;
             h_cm_uvx[(size_t)d] = h_uvx[(size_t)t];
             h_cm_uvy[(size_t)d] = h_uvy[(size_t)t];
         }
     }
-    // Wave chunks and their partial-sum slots: one slot per (chunk, camera run).
-    const int32_t num_chunks = (int32_t)((N + kCmChunk - 1) / kCmChunk);
-    std::vector<int32_t> chunk_slot((size_t)num_chunks + 1, 0);
-    std::vector<int32_t> slots_per_cam((size_t)m, 0);
-    {
-        int32_t slot = 0;
-        for (int32_t c = 0; c < num_chunks; ++c) {
-            chunk_slot[c] = slot;
-            const int64_t s = (int64_t)c * kCmChunk, e = std::min<int64_t>(N, s + kCmChunk);
-            for (int64_t t = s; t < e; ++t)
-                if (t == s || h_cm_cam[(size_t)t] != h_cm_cam[(size_t)t - 1]) {
-                    slots_per_cam[h_cm_cam[(size_t)t]]++;
-                    ++slot;
-                }
-        }
-        chunk_slot[num_chunks] = slot;
-        P->cm.num_slots = slot;
-    }
-    std::vector<int32_t> cam_slot((size_t)m + 1, 0);
-    for (int32_t j = 0; j < m; ++j) cam_slot[(size_t)j + 1] = cam_slot[j] + slots_per_cam[j];
+    std::vector<int32_t> chunk_slot, cam_slot;
+    P->cm.num_slots = plan_slots(h_cm_cam, m, chunk_slot, cam_slot);
+    const int32_t num_chunks = (int32_t)chunk_slot.size() - 1;
     P->cm.num_chunks = num_chunks;
+
+    // Schur-product schedule: hot cameras held in LDS, persistent workgroups
+    // over short tiles, long tiles apart, cold observations camera-major.
+    int dev = 0, cus = 0, lds_limit = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+        g_create_error = "cannot query the HIP device";
+        delete P;
+        return BA_EDEVICE;
+    }
+    SchurPlan& sp = P->sp;
+    {
+        int32_t kmax = P->is_f32() ? hot_max_cameras<float>((size_t)lds_limit)
+                                   : hot_max_cameras<double>((size_t)lds_limit);
+        if (const char* env = std::getenv("BA_HOT_CAMERAS")) kmax = std::min(kmax, std::max(0, std::atoi(env)));
+        sp.K = std::max(0, std::min(m, kmax));
+    }
+    std::vector<int32_t> short_idx, long_idx;
+    std::vector<uint8_t> tile_is_long(tiles.size() > 1 ? tiles.size() - 1 : 0, 0);
+    int64_t short_obs = 0;
+    for (size_t t = 0; t + 1 < tiles.size(); ++t) {
+        const int32_t len = tiles[t + 1] - tiles[t];
+        if (len > kTile) {
+            long_idx.push_back((int32_t)t);
+            tile_is_long[t] = 1;
+        } else {
+            short_idx.push_back((int32_t)t);
+            short_obs += len;
+        }
+    }
+    sp.num_short = (int32_t)short_idx.size();
+    sp.num_long = (int32_t)long_idx.size();
+    sp.num_wg = std::min<int32_t>(std::max(1, cus), std::max<int32_t>(1, sp.num_short));
+    if (sp.num_short == 0) sp.num_wg = 0;
+    std::vector<int32_t> wg_range((size_t)sp.num_wg + 1, 0);
+    {
+        int64_t acc = 0;
+        int32_t w = 1;
+        for (int32_t u = 0; u < sp.num_short && w < sp.num_wg; ++u) {
+            const int32_t t = short_idx[(size_t)u];
+            acc += tiles[(size_t)t + 1] - tiles[t];
+            if (acc * sp.num_wg >= short_obs * w) wg_range[(size_t)w++] = u + 1;
+        }
+        for (; w <= sp.num_wg; ++w) wg_range[(size_t)w] = sp.num_short;
+    }
+    // cold stream: observations of short tiles on cameras >= K, camera-major
+    std::vector<uint8_t> obs_long((size_t)N, 0);
+    for (int32_t t : long_idx)
+        for (int32_t k = tiles[t]; k < tiles[(size_t)t + 1]; ++k) obs_long[(size_t)k] = 1;
+    std::vector<int32_t> cold_pos((size_t)N, -1), h_cold_cam, h_cold_pt;
+    std::vector<uint8_t> has_cold((size_t)(n > 0 ? n : 1), 0);
+    for (int64_t d = 0; d < N; ++d) {
+        const int32_t t = h_cm_src[(size_t)d];
+        if (h_cm_cam[(size_t)d] >= sp.K && !obs_long[(size_t)t]) {
+            cold_pos[(size_t)t] = (int32_t)h_cold_cam.size();
+            h_cold_cam.push_back(h_cm_cam[(size_t)d]);
+            h_cold_pt.push_back(h_cm_pt[(size_t)d]);
+            has_cold[(size_t)h_cm_pt[(size_t)d]] = 1;
+        }
+    }
+    sp.cold.N = (int64_t)h_cold_cam.size();
+    std::vector<int32_t> cold_chunk_slot, cold_cam_slot;
+    sp.cold.num_slots = plan_slots(h_cold_cam, m, cold_chunk_slot, cold_cam_slot);
+    sp.cold.num_chunks = (int32_t)cold_chunk_slot.size() - 1;
 
     // Workspace: everything the solve needs, sized once.
     DevAlloc& A = P->mem;
@@ -381,6 +457,20 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     P->dcam = A.get<double>(9 * (int64_t)m);
     for (double** v : {&P->g, &P->x, &P->r, &P->z, &P->p, &P->q, &P->cacc}) *v = A.get<double>(9 * (int64_t)m);
     P->pT = A.get<char>(9 * (int64_t)m * (int64_t)tsz);
+    sp.short_idx = A.get<int32_t>(sp.num_short);
+    sp.long_idx = A.get<int32_t>(sp.num_long);
+    sp.wg_range = A.get<int32_t>((int64_t)sp.num_wg + 1);
+    sp.has_cold = A.get<uint8_t>(n);
+    sp.cold_pos = A.get<int32_t>(N);
+    sp.hot_part = A.get<char>((int64_t)sp.num_wg * sp.K * 9 * (int64_t)tsz);
+    sp.bcold = A.get<char>(3 * (int64_t)n * (int64_t)tsz);
+    sp.c_long = A.get<double>(9 * (int64_t)m);
+    sp.cold.cam = A.get<int32_t>(sp.cold.N);
+    sp.cold.pt = A.get<int32_t>(sp.cold.N);
+    sp.cold.hcp = A.get<char>(27 * sp.cold.N * (int64_t)tsz);
+    sp.cold.chunk_slot = A.get<int32_t>((int64_t)sp.cold.num_chunks + 1);
+    sp.cold.cam_slot = A.get<int32_t>((int64_t)m + 1);
+    sp.cold.slots = A.get<double>((int64_t)sp.cold.num_slots * 9);
     P->dp = A.get<double>(3 * (int64_t)n);
     P->partials = A.get<double>(2 * 2048);
     P->sums = A.get<double>(8);
@@ -416,6 +506,17 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     if (e == hipSuccess) e = up(P->cm.uvy, h_cm_uvy.data(), sizeof(double) * N);
     if (e == hipSuccess) e = up(P->cm.chunk_slot, chunk_slot.data(), sizeof(int32_t) * chunk_slot.size());
     if (e == hipSuccess) e = up(P->cm.cam_slot, cam_slot.data(), sizeof(int32_t) * cam_slot.size());
+    if (e == hipSuccess) e = up(sp.short_idx, short_idx.data(), sizeof(int32_t) * short_idx.size());
+    if (e == hipSuccess) e = up(sp.long_idx, long_idx.data(), sizeof(int32_t) * long_idx.size());
+    if (e == hipSuccess) e = up(sp.wg_range, wg_range.data(), sizeof(int32_t) * wg_range.size());
+    if (e == hipSuccess) e = up(sp.has_cold, has_cold.data(), (size_t)n);
+    if (e == hipSuccess) e = up(sp.cold_pos, cold_pos.data(), sizeof(int32_t) * N);
+    if (e == hipSuccess) e = up(sp.cold.cam, h_cold_cam.data(), sizeof(int32_t) * h_cold_cam.size());
+    if (e == hipSuccess) e = up(sp.cold.pt, h_cold_pt.data(), sizeof(int32_t) * h_cold_pt.size());
+    if (e == hipSuccess) e = up(sp.cold.chunk_slot, cold_chunk_slot.data(), sizeof(int32_t) * cold_chunk_slot.size());
+    if (e == hipSuccess) e = up(sp.cold.cam_slot, cold_cam_slot.data(), sizeof(int32_t) * cold_cam_slot.size());
+    if (e == hipSuccess)
+        e = P->is_f32() ? prepare_schur_kernels<float>(sp.K) : prepare_schur_kernels<double>(sp.K);
     if (e == hipSuccess) e = hipMemset(P->hpp, 0, 6 * (size_t)(n > 0 ? n : 1) * tsz);
     if (e == hipSuccess) e = hipMemset(P->wpt, 0, 3 * (size_t)(n > 0 ? n : 1) * sizeof(double));
     if (e == hipSuccess) e = hipMemset(P->sc, 0, sizeof(PcgScalars));
@@ -496,7 +597,7 @@ static ba_status build_system(ba_problem* P)
         ck = (const CamK<T>*)P->ck64;
     }
     BA_TRY(P, launch_build_points<T>(P->pm, P->N, P->pts, ck, P->opt.huber_delta, false, (T*)P->hcp, (T*)P->hpp,
-                                     P->wpt, s));
+                                     P->wpt, P->sp.cold_pos, P->sp.cold.N, (T*)P->sp.cold.hcp, s));
     BA_TRY(P, launch_build_cameras<T>(P->cm, P->m, P->N, P->pts, ck, P->opt.huber_delta, false, P->hcc, P->vcam, s));
     return BA_OK;
 }
@@ -526,20 +627,19 @@ struct PcgTimer {
 // PCG on the reduced camera system (Alg. 2, one partition); dc = x.
 template <typename T>
 static ba_status run_pcg(ba_problem* P, const ba_options& o, int32_t fixed, int32_t* iters, PcgTimer* tm,
-                         double* matvec_ms, int64_t* launches)
+                         double* matvec_ms, double* hot_ms, int64_t* launches)
 {
     hipStream_t s = P->stream;
     const int32_t m = P->m;
     int32_t nb = 0;
     // b = v - E C^-1 w; x = 0; r = b
-    BA_TRY(P, launch_zero(P->cacc, 9 * (int64_t)m, s));
-    BA_TRY(P, launch_schur_tiles<T>(1, P->pm, P->N, (const T*)P->hcp, (const T*)P->cinv, P->wpt, nullptr, P->cacc,
-                                    nullptr, s));
-    BA_TRY(P, launch_rhs_combine(m, P->vcam, P->cacc, P->g, P->x, P->r, P->partials, &nb, s));
+    BA_TRY(P, launch_schur_product<T>(1, P->sp, P->pm, P->N, (const T*)P->hcp, (const T*)P->cinv, P->wpt, nullptr, m,
+                                      P->bd, nullptr, P->vcam, P->g, P->x, P->r, P->partials, &nb, P->sc, nullptr,
+                                      nullptr, s));
     BA_TRY(P, launch_sum_partials(P->partials, nb, 1, 1, P->sums, s));
     BA_TRY(P, launch_pcg_finish_scalars(P->sc, P->sums, 0, s));
     int32_t it = 0;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> marks;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> marks, hot_marks;
     while (true) {
         if (fixed > 0) {
             if (it >= fixed) break;
@@ -554,19 +654,20 @@ static ba_status run_pcg(ba_problem* P, const ba_options& o, int32_t fixed, int3
         BA_TRY(P, launch_sum_partials(P->partials, nb, 2, 2, P->sums, s));
         BA_TRY(P, launch_pcg_finish_scalars(P->sc, P->sums, 1, s));
         BA_TRY(P, launch_pcg_direction<T>(m, it == 0, P->z, P->p, (T*)P->pT, P->sc, s));
-        BA_TRY(P, launch_zero(P->cacc, 9 * (int64_t)m, s));
-        hipEvent_t ea = nullptr, eb = nullptr;
+        hipEvent_t ea = nullptr, eb = nullptr, ha = nullptr, hb = nullptr;
         if (tm) {
             BA_TRY(P, tm->next(&ea, &eb));
+            BA_TRY(P, tm->next(&ha, &hb));
             BA_TRY(P, hipEventRecord(ea, s));
         }
-        BA_TRY(P, launch_schur_tiles<T>(0, P->pm, P->N, (const T*)P->hcp, (const T*)P->cinv, P->wpt,
-                                        (const T*)P->pT, P->cacc, nullptr, s));
+        BA_TRY(P, launch_schur_product<T>(0, P->sp, P->pm, P->N, (const T*)P->hcp, (const T*)P->cinv, P->wpt,
+                                          (const T*)P->pT, m, P->bd, P->p, nullptr, P->q, nullptr, nullptr,
+                                          P->partials, &nb, P->sc, ha, hb, s));
         if (tm) {
             BA_TRY(P, hipEventRecord(eb, s));
             marks.emplace_back(ea, eb);
+            hot_marks.emplace_back(ha, hb);
         }
-        BA_TRY(P, launch_matvec_combine(m, P->bd, P->p, P->cacc, P->q, P->partials, &nb, P->sc, s));
         BA_TRY(P, launch_sum_partials(P->partials, nb, 1, 1, P->sums, s));
         BA_TRY(P, launch_pcg_finish_scalars(P->sc, P->sums, 2, s));
         BA_TRY(P, launch_pcg_update(m, P->p, P->q, P->x, P->r, P->partials, &nb, P->sc, s));
@@ -587,6 +688,11 @@ static ba_status run_pcg(ba_problem* P, const ba_options& o, int32_t fixed, int3
         *matvec_ms += ms;
         *launches += 1;
     }
+    for (auto& pr : hot_marks) {
+        float ms = 0.0f;
+        BA_TRY(P, hipEventElapsedTime(&ms, pr.first, pr.second));
+        *hot_ms += ms;
+    }
     if (tm) tm->used = 0;
     return BA_OK;
 }
@@ -605,7 +711,7 @@ static ba_status lm_solve_t(ba_problem* P, const ba_options& o, ba_report* rep)
     double F = P->h_scalars[0];
     double lambda = o.lambda_init, nu = 2.0;
     bool need_build = true;
-    double pcg_ms = 0.0, matvec_ms = 0.0;
+    double pcg_ms = 0.0, matvec_ms = 0.0, hot_ms = 0.0;
     int64_t pcg_total = 0, launches = 0;
     PcgTimer timer;
     if (rep) {
@@ -633,7 +739,7 @@ static ba_status lm_solve_t(ba_problem* P, const ba_options& o, ba_report* rep)
         const int32_t fixed = o.pcg_schedule ? o.pcg_schedule[it] : o.pcg_fixed_iters;
         int32_t npcg = 0;
         const auto t_pcg = clock::now();
-        st = run_pcg<T>(P, o, fixed, &npcg, o.time_kernels ? &timer : nullptr, &matvec_ms, &launches);
+        st = run_pcg<T>(P, o, fixed, &npcg, o.time_kernels ? &timer : nullptr, &matvec_ms, &hot_ms, &launches);
         pcg_ms += std::chrono::duration<double, std::milli>(clock::now() - t_pcg).count();
         pcg_total += npcg;
         if (st != BA_OK) {
@@ -643,7 +749,7 @@ static ba_status lm_solve_t(ba_problem* P, const ba_options& o, ba_report* rep)
         }
         // dp = C~^-1 (w - E^T dc); trial state; F(x + dx); predicted decrease
         BA_TRY(P, launch_pcg_direction<T>(m, true, P->x, P->p, (T*)P->pT, P->sc, s));
-        BA_TRY(P, launch_schur_tiles<T>(2, P->pm, P->N, (const T*)P->hcp, (const T*)P->cinv, P->wpt,
+        BA_TRY(P, launch_schur_tiles<T>(2, P->pm, nullptr, 0, P->N, (const T*)P->hcp, (const T*)P->cinv, P->wpt,
                                         (const T*)P->pT, nullptr, P->dp, s));
         BA_TRY(P, launch_trial_state(m, n, P->cams, P->x, P->pts, P->dp, P->cams_t, P->pts_t, s));
         BA_TRY(P, launch_camera_constants_f64(m, P->cams_t, P->ck64_t, s));
@@ -697,6 +803,7 @@ static ba_status lm_solve_t(ba_problem* P, const ba_options& o, ba_report* rep)
         rep->pcg_iters_total = pcg_total;
         rep->matvec_ms = matvec_ms;
         rep->matvec_launches = launches;
+        rep->schur_hot_ms = hot_ms;
     }
     return result;
 }
@@ -729,7 +836,8 @@ extern "C" ba_status ba_lm_solve(ba_problem* P, const ba_options* opt, ba_report
 template <typename T>
 static ba_status grad_into(ba_problem* P, const double* pts, const CamK<T>* ck, hipStream_t s)
 {
-    BA_TRY(P, launch_build_points<T>(P->pm, P->N, pts, ck, P->opt.huber_delta, true, nullptr, nullptr, P->wpt, s));
+    BA_TRY(P, launch_build_points<T>(P->pm, P->N, pts, ck, P->opt.huber_delta, true, nullptr, nullptr, P->wpt,
+                                     nullptr, 0, nullptr, s));
     BA_TRY(P, launch_build_cameras<T>(P->cm, P->m, P->N, pts, ck, P->opt.huber_delta, true, nullptr, P->vcam, s));
     return BA_OK;
 }
@@ -826,11 +934,10 @@ static ba_status schur_matvec_t(ba_problem* P, double lambda, int32_t damping, c
     BA_TRY(P, launch_zero(P->sums, 1, s));
     BA_TRY(P, launch_pcg_finish_scalars(P->sc, P->sums, 0, s));
     BA_TRY(P, launch_pcg_direction<T>(m, true, P->x, P->p, (T*)P->pT, P->sc, s));
-    BA_TRY(P, launch_zero(P->cacc, 9 * (int64_t)m, s));
-    BA_TRY(P, launch_schur_tiles<T>(0, P->pm, P->N, (const T*)P->hcp, (const T*)P->cinv, P->wpt, (const T*)P->pT,
-                                    P->cacc, nullptr, s));
     int32_t nb = 0;
-    BA_TRY(P, launch_matvec_combine(m, P->bd, P->p, P->cacc, P->q, P->partials, &nb, P->sc, s));
+    BA_TRY(P, launch_schur_product<T>(0, P->sp, P->pm, P->N, (const T*)P->hcp, (const T*)P->cinv, P->wpt,
+                                      (const T*)P->pT, m, P->bd, P->p, nullptr, P->q, nullptr, nullptr, P->partials,
+                                      &nb, P->sc, nullptr, nullptr, s));
     BA_TRY(P, hipMemcpyAsync(qi.data(), P->q, qi.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     BA_TRY(P, hipMemcpyAsync(P->h_scalars, P->flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     BA_TRY(P, hipStreamSynchronize(s));

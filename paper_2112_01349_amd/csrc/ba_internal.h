@@ -50,14 +50,58 @@ struct CameraMajor {
     double* slots;        // [num_slots][54]
 };
 
+// Workgroup shape of the hot-camera Schur pass: tiles in flight per workgroup.
+template <typename T>
+struct HotGroups;
+template <>
+struct HotGroups<float> {
+    static constexpr int value = 4;
+};
+template <>
+struct HotGroups<double> {
+    static constexpr int value = 2;
+};
+
+// Observations on cameras outside the hot set, in camera-major order.
+struct ColdStream {
+    int64_t N = 0;
+    int32_t* cam = nullptr;         // [N]
+    int32_t* pt = nullptr;          // [N]
+    void* hcp = nullptr;            // [27][N] of T
+    int32_t* chunk_slot = nullptr;  // [num_chunks + 1]
+    int32_t* cam_slot = nullptr;    // [m + 1]
+    int32_t num_chunks = 0;
+    int32_t num_slots = 0;
+    double* slots = nullptr;        // [num_slots][9]
+};
+
+// Schedule of the implicit Schur product (see matvec.hip).
+struct SchurPlan {
+    int32_t K = 0;                  // hot cameras: internal ids [0, K)
+    int32_t num_wg = 0;             // persistent workgroups of the hot pass
+    int32_t num_short = 0, num_long = 0;
+    int32_t* short_idx = nullptr;   // [num_short] tiles of <= kTile observations
+    int32_t* long_idx = nullptr;    // [num_long] single-point tiles longer than kTile
+    int32_t* wg_range = nullptr;    // [num_wg + 1] ranges of short_idx per workgroup
+    uint8_t* has_cold = nullptr;    // [n] point has an observation in the cold stream
+    int32_t* cold_pos = nullptr;    // [N] point-major observation -> cold index or -1
+    void* hot_part = nullptr;       // [num_wg][K][9] of T
+    void* bcold = nullptr;          // [n][3] of T
+    double* c_long = nullptr;       // [m][9]
+    ColdStream cold;
+};
+
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `s` and return hipGetLastError().
 hipError_t launch_camera_constants_f64(int32_t m, const double* cams, CamK<double>* out, hipStream_t s);
 hipError_t launch_camera_constants_f32(int32_t m, const double* cams, CamK<float>* out, hipStream_t s);
 
+// cold_pos / chcp (nullable): observations with cold_pos[k] >= 0 also write
+// their coupling block to chcp[q * Nc + cold_pos[k]].
 template <typename T>
 hipError_t launch_build_points(const PointMajor& pm, int64_t N, const double* pts, const CamK<T>* ck,
-                               double delta, bool grad_only, T* hcp, T* hpp, double* wpt, hipStream_t s);
+                               double delta, bool grad_only, T* hcp, T* hpp, double* wpt,
+                               const int32_t* cold_pos, int64_t Nc, T* chcp, hipStream_t s);
 template <typename T>
 hipError_t launch_build_cameras(const CameraMajor& cm, int32_t m, int64_t N, const double* pts,
                                 const CamK<T>* ck, double delta, bool grad_only, double* hcc,
@@ -72,9 +116,27 @@ hipError_t launch_damp_points(int32_t n, const T* hpp, double lambda, int32_t da
 // mode 0: c = E C^-1 E^T x    (implicit Schur product without the B term)
 // mode 1: c = E C^-1 w        (reduced right-hand side)
 // mode 2: dp = C^-1 (w - E^T x)  (back-substitution)
+// tile_list (nullable = every tile) selects the tiles; count = its length.
 template <typename T>
-hipError_t launch_schur_tiles(int mode, const PointMajor& pm, int64_t N, const T* hcp, const T* cinv,
-                              const double* wpt, const T* xcam, double* cacc, double* dp, hipStream_t s);
+hipError_t launch_schur_tiles(int mode, const PointMajor& pm, const int32_t* tile_list, int32_t count, int64_t N,
+                              const T* hcp, const T* cinv, const double* wpt, const T* xcam, double* cacc,
+                              double* dp, hipStream_t s);
+
+// Full implicit Schur product (mode 0: out = q = B~ x - E C~^-1 E^T x with
+// partial p^T q; mode 1: out = g = v - E C~^-1 w, r = g, x = 0, partial
+// ||g||^2).  xcam: x in T (mode 0); pvec: x in FP64 (mode 0).
+template <typename T>
+hipError_t launch_schur_product(int mode, const SchurPlan& sp, const PointMajor& pm, int64_t N, const T* hcp,
+                                const T* cinv, const double* wpt, const T* xcam, int32_t m, const double* bd,
+                                const double* pvec, const double* vcam, double* out, double* xvec, double* rvec,
+                                double* partials, int32_t* nblocks, const PcgScalars* sc, hipEvent_t hot_begin,
+                                hipEvent_t hot_end, hipStream_t s);
+template <typename T>
+size_t hot_lds_bytes(int32_t K);
+template <typename T>
+int32_t hot_max_cameras(size_t lds_limit);
+template <typename T>
+hipError_t prepare_schur_kernels(int32_t K);
 
 hipError_t launch_zero(double* p, int64_t count, hipStream_t s);
 hipError_t launch_rhs_combine(int32_t m, const double* vcam, const double* cacc, double* g, double* x,

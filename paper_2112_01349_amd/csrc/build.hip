@@ -91,7 +91,7 @@ __global__ __launch_bounds__(kTile) void k_build_points(
     const int32_t* __restrict__ tile, const int32_t* __restrict__ cam, const int32_t* __restrict__ pt,
     const double* __restrict__ uvx, const double* __restrict__ uvy, const double* __restrict__ pts,
     const CamK<T>* __restrict__ ck, T delta, int64_t N, T* __restrict__ hcp, T* __restrict__ hpp,
-    double* __restrict__ wpt)
+    double* __restrict__ wpt, const int32_t* __restrict__ cold_pos, int64_t Nc, T* __restrict__ chcp)
 {
     __shared__ double sh[9][kTile];
     __shared__ int32_t shpt[kTile];
@@ -105,7 +105,13 @@ __global__ __launch_bounds__(kTile) void k_build_points(
             const int64_t k = s + tid;
             T e0, e1, wt, Jc[18], Jp[6];
             observation<T>(k, cam, pt, uvx, uvy, pts, ck, delta, e0, e1, wt, Jc, Jp, i);
-            if (!GRAD_ONLY) store_coupling<T>(k, N, Jc, Jp, wt, hcp);
+            if (!GRAD_ONLY) {
+                store_coupling<T>(k, N, Jc, Jp, wt, hcp);
+                if (cold_pos) {
+                    const int32_t c = cold_pos[k];
+                    if (c >= 0) store_coupling<T>(c, Nc, Jc, Jp, wt, chcp);
+                }
+            }
             double t[9];
             point_terms<T>(Jp, e0, e1, wt, t);
 #pragma unroll
@@ -166,15 +172,17 @@ __global__ __launch_bounds__(kTile) void k_build_points(
 
 template <typename T>
 hipError_t launch_build_points(const PointMajor& pm, int64_t N, const double* pts, const CamK<T>* ck,
-                               double delta, bool grad_only, T* hcp, T* hpp, double* wpt, hipStream_t s)
+                               double delta, bool grad_only, T* hcp, T* hpp, double* wpt,
+                               const int32_t* cold_pos, int64_t Nc, T* chcp, hipStream_t s)
 {
     if (pm.num_tiles <= 0) return hipGetLastError();
     if (grad_only)
         hipLaunchKernelGGL((k_build_points<T, true>), dim3(pm.num_tiles), dim3(kTile), 0, s, pm.tile, pm.cam,
-                           pm.pt, pm.uvx, pm.uvy, pts, ck, (T)delta, N, hcp, hpp, wpt);
+                           pm.pt, pm.uvx, pm.uvy, pts, ck, (T)delta, N, hcp, hpp, wpt, nullptr, (int64_t)0,
+                           (T*)nullptr);
     else
         hipLaunchKernelGGL((k_build_points<T, false>), dim3(pm.num_tiles), dim3(kTile), 0, s, pm.tile, pm.cam,
-                           pm.pt, pm.uvx, pm.uvy, pts, ck, (T)delta, N, hcp, hpp, wpt);
+                           pm.pt, pm.uvx, pm.uvy, pts, ck, (T)delta, N, hcp, hpp, wpt, cold_pos, Nc, chcp);
     return hipGetLastError();
 }
 
@@ -359,9 +367,11 @@ hipError_t launch_cost(const PointMajor& pm, int64_t N, const double* pts, const
 }
 
 template hipError_t launch_build_points<double>(const PointMajor&, int64_t, const double*, const CamK<double>*,
-                                                double, bool, double*, double*, double*, hipStream_t);
+                                                double, bool, double*, double*, double*, const int32_t*, int64_t,
+                                                double*, hipStream_t);
 template hipError_t launch_build_points<float>(const PointMajor&, int64_t, const double*, const CamK<float>*,
-                                               double, bool, float*, float*, double*, hipStream_t);
+                                               double, bool, float*, float*, double*, const int32_t*, int64_t,
+                                               float*, hipStream_t);
 template hipError_t launch_build_cameras<double>(const CameraMajor&, int32_t, int64_t, const double*,
                                                  const CamK<double>*, double, bool, double*, double*, hipStream_t);
 template hipError_t launch_build_cameras<float>(const CameraMajor&, int32_t, int64_t, const double*,

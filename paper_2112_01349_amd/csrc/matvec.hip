@@ -1,0 +1,361 @@
+// Implicit Schur product of Alg. 3 (DSE) with one partition, and the reduced
+// right-hand side of Eq. schur_x_c that shares its second half:
+//   mode 0:  c = E C~^-1 E^T x,  then q = B~ x - c   (and p^T q)
+//   mode 1:  c = E C~^-1 w,      then g = v - c      (r = g, x = 0, ||g||^2)
+//
+// E is held as one 9x3 block per observation (27 coalesced streams) in
+// point-major order.  Per point i, a_i = sum_k E_k^T x_j(k) needs all of the
+// point's observations before b_i = C~_i^-1 a_i, and then every observation
+// adds E_k b_i into its camera.  The camera side is Zipf-skewed (the most
+// seen camera is in ~60% of the points), so the scatter is organised by
+// camera popularity (cameras are relabelled most-observed first):
+//
+//   pass 1 (k_schur_hot): persistent workgroups, one per CU, stream
+//     point-aligned tiles of <= 256 observations (several tiles in flight
+//     per workgroup, the next round's blocks prefetched into registers).
+//     a_i and b_i are reduced in LDS; contributions to the K hottest
+//     cameras accumulate in a per-workgroup LDS copy of their 9-vectors
+//     (K sized to fill the 160 KB LDS), written out once at the end.
+//     b_i of points that also have observations on colder cameras is stored.
+//   pass 2 (k_schur_cold): the observations on cameras >= K, from their own
+//     camera-major copy of E, gather b_i and are reduced per camera by
+//     wavefront chunks into fixed partial-sum slots (no atomics).
+//   epilogue (k_schur_epilogue): per camera entry, sums the workgroup
+//     partials (hot) or the slots (cold) in a fixed order and forms q or g.
+// Points with more than 256 observations (none in the benchmark workloads)
+// go through k_schur_tiles with FP64 atomics into a separate accumulator.
+#include "ba_internal.h"
+
+namespace ba {
+
+template <typename T>
+__device__ __forceinline__ void fetch_tile_obs(int32_t ti, int32_t r1, const int32_t* __restrict__ tile,
+                                               const int32_t* __restrict__ short_idx,
+                                               const int32_t* __restrict__ cam, const int32_t* __restrict__ pt,
+                                               const T* __restrict__ hcp, int64_t N, int lt, int32_t& s,
+                                               int32_t& len, int32_t& j, int32_t& i, T h[27])
+{
+    s = 0;
+    len = 0;
+    if (ti < r1) {
+        const int32_t t = short_idx[ti];
+        s = tile[t];
+        len = tile[t + 1] - s;
+    }
+    j = 0;
+    i = -1;
+    if (lt < len) {
+        const int64_t k = (int64_t)s + lt;
+        j = cam[k];
+        i = pt[k];
+#pragma unroll
+        for (int q = 0; q < 27; ++q) h[q] = hcp[(int64_t)q * N + k];
+    } else {
+#pragma unroll
+        for (int q = 0; q < 27; ++q) h[q] = (T)0;
+    }
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(HotGroups<T>::value* kTile) void k_schur_hot(
+    const int32_t* __restrict__ tile, const int32_t* __restrict__ short_idx, const int32_t* __restrict__ wg_range,
+    const int32_t* __restrict__ cam, const int32_t* __restrict__ pt, int64_t N, const T* __restrict__ hcp,
+    const T* __restrict__ cinv, const double* __restrict__ wpt, const T* __restrict__ xcam, int32_t K,
+    T* __restrict__ hot_part, T* __restrict__ bcold, const uint8_t* __restrict__ has_cold)
+{
+    constexpr int G = HotGroups<T>::value;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* cl = reinterpret_cast<T*>(smem);
+    T* scr = cl + (size_t)K * 9;
+    int32_t* spt = reinterpret_cast<int32_t*>(scr + G * 3 * kTile);
+    const int g = threadIdx.x / kTile, lt = threadIdx.x % kTile;
+    T* sg = scr + g * 3 * kTile;
+    int32_t* pg = spt + g * kTile;
+    for (int q = threadIdx.x; q < K * 9; q += G * kTile) cl[q] = (T)0;
+    const int32_t r0 = wg_range[blockIdx.x], r1 = wg_range[blockIdx.x + 1];
+    const int32_t rounds = (r1 - r0 + G - 1) / G;
+
+    int32_t cs, clen, cj, ci;
+    T ch[27];
+    fetch_tile_obs<T>(r0 + g, r1, tile, short_idx, cam, pt, hcp, N, lt, cs, clen, cj, ci, ch);
+    __syncthreads();
+    for (int32_t r = 0; r < rounds; ++r) {
+        int32_t ns, nlen, nj, ni;
+        T nh[27];
+        fetch_tile_obs<T>(r0 + (r + 1) * G + g, r1, tile, short_idx, cam, pt, hcp, N, lt, ns, nlen, nj, ni, nh);
+        const bool valid = lt < clen;
+        if (MODE == 0 && valid) {
+            T x[9];
+#pragma unroll
+            for (int a = 0; a < 9; ++a) x[a] = xcam[9 * (int64_t)cj + a];
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                T acc = (T)0;
+#pragma unroll
+                for (int a = 0; a < 9; ++a) acc += ch[a * 3 + b] * x[a];
+                sg[b * kTile + lt] = acc;
+            }
+        }
+        pg[lt] = ci;
+        __syncthreads();
+        if (valid && (lt == 0 || pg[lt - 1] != ci)) {
+            const T* c6 = cinv + 6 * (int64_t)ci;
+            T a0, a1, a2;
+            if (MODE == 0) {
+                a0 = a1 = a2 = (T)0;
+                for (int u = lt; u < clen && pg[u] == ci; ++u) {
+                    a0 += sg[u];
+                    a1 += sg[kTile + u];
+                    a2 += sg[2 * kTile + u];
+                }
+            } else {
+                a0 = (T)wpt[3 * (int64_t)ci];
+                a1 = (T)wpt[3 * (int64_t)ci + 1];
+                a2 = (T)wpt[3 * (int64_t)ci + 2];
+            }
+            const T b0 = c6[0] * a0 + c6[1] * a1 + c6[2] * a2;
+            const T b1 = c6[1] * a0 + c6[3] * a1 + c6[4] * a2;
+            const T b2 = c6[2] * a0 + c6[4] * a1 + c6[5] * a2;
+            sg[lt] = b0;
+            sg[kTile + lt] = b1;
+            sg[2 * kTile + lt] = b2;
+            if (has_cold[ci]) {
+                bcold[3 * (int64_t)ci] = b0;
+                bcold[3 * (int64_t)ci + 1] = b1;
+                bcold[3 * (int64_t)ci + 2] = b2;
+            }
+        }
+        __syncthreads();
+        if (valid && cj < K) {
+            int hd = lt;
+            while (hd > 0 && pg[hd - 1] == ci) --hd;
+            const T b0 = sg[hd], b1 = sg[kTile + hd], b2 = sg[2 * kTile + hd];
+            T* dst = cl + 9 * cj;
+#pragma unroll
+            for (int a = 0; a < 9; ++a) atomicAdd(dst + a, ch[a * 3] * b0 + ch[a * 3 + 1] * b1 + ch[a * 3 + 2] * b2);
+        }
+        __syncthreads();
+        cs = ns;
+        clen = nlen;
+        cj = nj;
+        ci = ni;
+#pragma unroll
+        for (int q = 0; q < 27; ++q) ch[q] = nh[q];
+    }
+    T* out = hot_part + (int64_t)blockIdx.x * K * 9;
+    for (int q = threadIdx.x; q < K * 9; q += G * kTile) out[q] = cl[q];
+}
+
+__device__ __forceinline__ double wave_sum_d(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Cold observations, camera-major: c_k = E_k b_i, reduced per camera by wave
+// chunks of kCmChunk observations into slots (one per chunk and camera run).
+template <typename T>
+__global__ __launch_bounds__(256) void k_schur_cold(int64_t Nc, int32_t num_chunks, const int32_t* __restrict__ ccam,
+                                                    const int32_t* __restrict__ cpt, const T* __restrict__ chcp,
+                                                    const T* __restrict__ bcold, const int32_t* __restrict__ chunk_slot,
+                                                    double* __restrict__ slots)
+{
+    const int lane = threadIdx.x & 63;
+    const int32_t chunk = (int32_t)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
+    if (chunk >= num_chunks) return;
+    const int64_t start = (int64_t)chunk * kCmChunk;
+    const int64_t end = start + kCmChunk < Nc ? start + kCmChunk : Nc;
+    int32_t slot = chunk_slot[chunk];
+    int32_t cur = ccam[start];
+    double acc[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) acc[a] = 0.0;
+    for (int row = 0; row < kCmRows; ++row) {
+        if (start + (int64_t)row * 64 >= end) break;
+        const int64_t k = start + (int64_t)row * 64 + lane;
+        const bool valid = k < end;
+        int32_t j = 0x7fffffff;
+        T c[9];
+        if (valid) {
+            j = ccam[k];
+            const int32_t i = cpt[k];
+            const T b0 = bcold[3 * (int64_t)i], b1 = bcold[3 * (int64_t)i + 1], b2 = bcold[3 * (int64_t)i + 2];
+#pragma unroll
+            for (int a = 0; a < 9; ++a)
+                c[a] = chcp[(int64_t)(a * 3) * Nc + k] * b0 + chcp[(int64_t)(a * 3 + 1) * Nc + k] * b1 +
+                       chcp[(int64_t)(a * 3 + 2) * Nc + k] * b2;
+        }
+        while (true) {
+            if (valid && j == cur)
+#pragma unroll
+                for (int a = 0; a < 9; ++a) acc[a] += (double)c[a];
+            const uint64_t more = __ballot(valid && j > cur);
+            if (more == 0) break;
+#pragma unroll
+            for (int a = 0; a < 9; ++a) {
+                const double v = wave_sum_d(acc[a]);
+                if (lane == 0) slots[(int64_t)slot * 9 + a] = v;
+                acc[a] = 0.0;
+            }
+            ++slot;
+            cur = __shfl(j, __ffsll((unsigned long long)more) - 1, 64);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        const double v = wave_sum_d(acc[a]);
+        if (lane == 0) slots[(int64_t)slot * 9 + a] = v;
+    }
+}
+
+// q = B~ x - c (mode 0, partial p^T q) or g = v - c, r = g, x = 0 (mode 1,
+// partial ||g||^2); c from the hot partials, the cold slots and c_long.
+template <typename T, int MODE>
+__global__ __launch_bounds__(kRedBlock) void k_schur_epilogue(
+    int32_t m, int32_t K, int32_t G, const T* __restrict__ hot_part, const int32_t* __restrict__ cold_cam_slot,
+    const double* __restrict__ cold_slots, const double* __restrict__ c_long, const double* __restrict__ bd,
+    const double* __restrict__ pvec, const double* __restrict__ vcam, double* __restrict__ out,
+    double* __restrict__ xvec, double* __restrict__ rvec, double* __restrict__ partials,
+    const PcgScalars* __restrict__ sc)
+{
+    __shared__ double sh[kRedBlock / 64];
+    double acc = 0.0;
+    const bool skip = MODE == 0 && sc->breakdown;
+    const int64_t len = 9 * (int64_t)m;
+    if (!skip) {
+        for (int64_t t = blockIdx.x * (int64_t)kRedBlock + threadIdx.x; t < len; t += (int64_t)gridDim.x * kRedBlock) {
+            const int64_t j = t / 9;
+            const int a = (int)(t - 9 * j);
+            double c = 0.0;
+            if (j < K) {
+                const int64_t stride = (int64_t)K * 9;
+                double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+                int32_t w = 0;
+                for (; w + 4 <= G; w += 4) {
+                    c0 += (double)hot_part[(int64_t)w * stride + t];
+                    c1 += (double)hot_part[(int64_t)(w + 1) * stride + t];
+                    c2 += (double)hot_part[(int64_t)(w + 2) * stride + t];
+                    c3 += (double)hot_part[(int64_t)(w + 3) * stride + t];
+                }
+                for (; w < G; ++w) c0 += (double)hot_part[(int64_t)w * stride + t];
+                c = (c0 + c1) + (c2 + c3);
+            } else {
+                for (int32_t s = cold_cam_slot[j]; s < cold_cam_slot[j + 1]; ++s) c += cold_slots[(int64_t)s * 9 + a];
+            }
+            if (c_long) c += c_long[t];
+            if (MODE == 0) {
+                const double* B = bd + 81 * j + 9 * a;
+                const double* pj = pvec + 9 * j;
+                double v = 0.0;
+#pragma unroll
+                for (int u = 0; u < 9; ++u) v += B[u] * pj[u];
+                v -= c;
+                out[t] = v;
+                acc += pvec[t] * v;
+            } else {
+                const double v = vcam[t] - c;
+                out[t] = v;
+                rvec[t] = v;
+                xvec[t] = 0.0;
+                acc += v * v;
+            }
+        }
+    }
+    acc = wave_sum_d(acc);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < kRedBlock / 64; ++w) s += sh[w];
+        partials[blockIdx.x] = s;
+    }
+}
+
+template <typename T>
+size_t hot_lds_bytes(int32_t K)
+{
+    return (size_t)K * 9 * sizeof(T) + (size_t)HotGroups<T>::value * (3 * kTile * sizeof(T) + kTile * sizeof(int32_t));
+}
+
+template <typename T>
+int32_t hot_max_cameras(size_t lds_limit)
+{
+    const size_t fixed = hot_lds_bytes<T>(0);
+    if (lds_limit <= fixed + 1024) return 0;
+    return (int32_t)((lds_limit - fixed - 1024) / (9 * sizeof(T)));
+}
+
+template <typename T>
+hipError_t prepare_schur_kernels(int32_t K)
+{
+    const int bytes = (int)hot_lds_bytes<T>(K);
+    hipError_t e = hipFuncSetAttribute((const void*)k_schur_hot<T, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)k_schur_hot<T, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+template <typename T>
+hipError_t launch_schur_product(int mode, const SchurPlan& sp, const PointMajor& pm, int64_t N, const T* hcp,
+                                const T* cinv, const double* wpt, const T* xcam, int32_t m, const double* bd,
+                                const double* pvec, const double* vcam, double* out, double* xvec, double* rvec,
+                                double* partials, int32_t* nblocks, const PcgScalars* sc, hipEvent_t hot_begin,
+                                hipEvent_t hot_end, hipStream_t s)
+{
+    hipError_t e;
+    const size_t lds = hot_lds_bytes<T>(sp.K);
+    if (hot_begin && (e = hipEventRecord(hot_begin, s)) != hipSuccess) return e;
+    if (sp.num_wg > 0) {
+        if (mode == 0)
+            hipLaunchKernelGGL((k_schur_hot<T, 0>), dim3(sp.num_wg), dim3(HotGroups<T>::value * kTile), lds, s, pm.tile,
+                               sp.short_idx, sp.wg_range, pm.cam, pm.pt, N, hcp, cinv, wpt, xcam, sp.K,
+                               (T*)sp.hot_part, (T*)sp.bcold, sp.has_cold);
+        else
+            hipLaunchKernelGGL((k_schur_hot<T, 1>), dim3(sp.num_wg), dim3(HotGroups<T>::value * kTile), lds, s, pm.tile,
+                               sp.short_idx, sp.wg_range, pm.cam, pm.pt, N, hcp, cinv, wpt, xcam, sp.K,
+                               (T*)sp.hot_part, (T*)sp.bcold, sp.has_cold);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (hot_end && (e = hipEventRecord(hot_end, s)) != hipSuccess) return e;
+    if (sp.cold.num_chunks > 0) {
+        hipLaunchKernelGGL((k_schur_cold<T>), dim3((sp.cold.num_chunks + 3) / 4), dim3(256), 0, s, sp.cold.N,
+                           sp.cold.num_chunks, sp.cold.cam, sp.cold.pt, (const T*)sp.cold.hcp, (const T*)sp.bcold,
+                           sp.cold.chunk_slot, sp.cold.slots);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (sp.num_long > 0) {
+        if ((e = launch_zero(sp.c_long, 9 * (int64_t)m, s)) != hipSuccess) return e;
+        if ((e = launch_schur_tiles<T>(mode, pm, sp.long_idx, sp.num_long, N, hcp, cinv, wpt, xcam, sp.c_long, nullptr,
+                                       s)) != hipSuccess)
+            return e;
+    }
+    const int32_t b = reduce_blocks(9 * (int64_t)m);
+    *nblocks = b;
+    const double* cl = sp.num_long > 0 ? sp.c_long : nullptr;
+    if (mode == 0)
+        hipLaunchKernelGGL((k_schur_epilogue<T, 0>), dim3(b), dim3(kRedBlock), 0, s, m, sp.K, sp.num_wg,
+                           (const T*)sp.hot_part, sp.cold.cam_slot, sp.cold.slots, cl, bd, pvec, vcam, out, xvec,
+                           rvec, partials, sc);
+    else
+        hipLaunchKernelGGL((k_schur_epilogue<T, 1>), dim3(b), dim3(kRedBlock), 0, s, m, sp.K, sp.num_wg,
+                           (const T*)sp.hot_part, sp.cold.cam_slot, sp.cold.slots, cl, bd, pvec, vcam, out, xvec,
+                           rvec, partials, sc);
+    return hipGetLastError();
+}
+
+template size_t hot_lds_bytes<float>(int32_t);
+template size_t hot_lds_bytes<double>(int32_t);
+template int32_t hot_max_cameras<float>(size_t);
+template int32_t hot_max_cameras<double>(size_t);
+template hipError_t prepare_schur_kernels<float>(int32_t);
+template hipError_t prepare_schur_kernels<double>(int32_t);
+template hipError_t launch_schur_product<float>(int, const SchurPlan&, const PointMajor&, int64_t, const float*,
+                                                const float*, const double*, const float*, int32_t, const double*,
+                                                const double*, const double*, double*, double*, double*, double*,
+                                                int32_t*, const PcgScalars*, hipEvent_t, hipEvent_t, hipStream_t);
+template hipError_t launch_schur_product<double>(int, const SchurPlan&, const PointMajor&, int64_t, const double*,
+                                                 const double*, const double*, const double*, int32_t, const double*,
+                                                 const double*, const double*, double*, double*, double*, double*,
+                                                 int32_t*, const PcgScalars*, hipEvent_t, hipEvent_t, hipStream_t);
+
+}  // namespace ba

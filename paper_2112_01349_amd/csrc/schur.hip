@@ -144,6 +144,7 @@ __device__ __forceinline__ void atomic_add_f64(double* p, double v) { unsafeAtom
 
 template <typename T, int MODE>
 __global__ __launch_bounds__(kTile) void k_schur_tiles(const int32_t* __restrict__ tile,
+                                                       const int32_t* __restrict__ tile_list,
                                                        const int32_t* __restrict__ cam,
                                                        const int32_t* __restrict__ pt, int64_t N,
                                                        const T* __restrict__ hcp, const T* __restrict__ cinv,
@@ -154,7 +155,8 @@ __global__ __launch_bounds__(kTile) void k_schur_tiles(const int32_t* __restrict
     __shared__ T shb[3][kTile];
     __shared__ int32_t shpt[kTile];
     const int tid = threadIdx.x;
-    const int32_t s = tile[blockIdx.x], e = tile[blockIdx.x + 1];
+    const int32_t tix = tile_list ? tile_list[blockIdx.x] : (int32_t)blockIdx.x;
+    const int32_t s = tile[tix], e = tile[tix + 1];
     const int32_t len = e - s;
     if (len <= kTile) {
         const bool valid = tid < len;
@@ -288,25 +290,32 @@ __global__ __launch_bounds__(kTile) void k_schur_tiles(const int32_t* __restrict
 }
 
 template <typename T>
-hipError_t launch_schur_tiles(int mode, const PointMajor& pm, int64_t N, const T* hcp, const T* cinv,
-                              const double* wpt, const T* xcam, double* cacc, double* dp, hipStream_t s)
+hipError_t launch_schur_tiles(int mode, const PointMajor& pm, const int32_t* tile_list, int32_t count, int64_t N,
+                              const T* hcp, const T* cinv, const double* wpt, const T* xcam, double* cacc,
+                              double* dp, hipStream_t s)
 {
-    if (pm.num_tiles <= 0) return hipGetLastError();
-    const dim3 g(pm.num_tiles), b(kTile);
+    if (!tile_list) count = pm.num_tiles;
+    if (count <= 0) return hipGetLastError();
+    const dim3 g(count), b(kTile);
     if (mode == 0)
-        hipLaunchKernelGGL((k_schur_tiles<T, 0>), g, b, 0, s, pm.tile, pm.cam, pm.pt, N, hcp, cinv, wpt, xcam, cacc, dp);
+        hipLaunchKernelGGL((k_schur_tiles<T, 0>), g, b, 0, s, pm.tile, tile_list, pm.cam, pm.pt, N, hcp, cinv, wpt,
+                           xcam, cacc, dp);
     else if (mode == 1)
-        hipLaunchKernelGGL((k_schur_tiles<T, 1>), g, b, 0, s, pm.tile, pm.cam, pm.pt, N, hcp, cinv, wpt, xcam, cacc, dp);
+        hipLaunchKernelGGL((k_schur_tiles<T, 1>), g, b, 0, s, pm.tile, tile_list, pm.cam, pm.pt, N, hcp, cinv, wpt,
+                           xcam, cacc, dp);
     else
-        hipLaunchKernelGGL((k_schur_tiles<T, 2>), g, b, 0, s, pm.tile, pm.cam, pm.pt, N, hcp, cinv, wpt, xcam, cacc, dp);
+        hipLaunchKernelGGL((k_schur_tiles<T, 2>), g, b, 0, s, pm.tile, tile_list, pm.cam, pm.pt, N, hcp, cinv, wpt,
+                           xcam, cacc, dp);
     return hipGetLastError();
 }
 
 template hipError_t launch_damp_points<double>(int32_t, const double*, double, int32_t, double*, int32_t*, hipStream_t);
 template hipError_t launch_damp_points<float>(int32_t, const float*, double, int32_t, float*, int32_t*, hipStream_t);
-template hipError_t launch_schur_tiles<double>(int, const PointMajor&, int64_t, const double*, const double*,
-                                               const double*, const double*, double*, double*, hipStream_t);
-template hipError_t launch_schur_tiles<float>(int, const PointMajor&, int64_t, const float*, const float*,
-                                              const double*, const float*, double*, double*, hipStream_t);
+template hipError_t launch_schur_tiles<double>(int, const PointMajor&, const int32_t*, int32_t, int64_t,
+                                               const double*, const double*, const double*, const double*, double*,
+                                               double*, hipStream_t);
+template hipError_t launch_schur_tiles<float>(int, const PointMajor&, const int32_t*, int32_t, int64_t, const float*,
+                                              const float*, const double*, const float*, double*, double*,
+                                              hipStream_t);
 
 }  // namespace ba

@@ -44,7 +44,7 @@ class Report(C.Structure):
                 ("lambda_", C.c_void_p), ("pred", C.c_void_p), ("ms", C.c_void_p),
                 ("pcg_iters", C.c_void_p), ("accepted", C.c_void_p), ("total_ms", C.c_double),
                 ("pcg_ms", C.c_double), ("pcg_iters_total", C.c_int64), ("matvec_ms", C.c_double),
-                ("matvec_launches", C.c_int64)]
+                ("matvec_launches", C.c_int64), ("schur_hot_ms", C.c_double)]
 
 
 _lib = None
@@ -206,7 +206,8 @@ class Problem:
         out = {k.rstrip("_"): arrs[k][:n_it].copy() for k in arrs}
         out.update(iters_run=n_it, initial_cost=rep.initial_cost, final_cost=rep.final_cost,
                    total_ms=rep.total_ms, pcg_ms=rep.pcg_ms, pcg_iters_total=rep.pcg_iters_total,
-                   matvec_ms=rep.matvec_ms, matvec_launches=rep.matvec_launches, status=st)
+                   matvec_ms=rep.matvec_ms, matvec_launches=rep.matvec_launches,
+                   schur_hot_ms=rep.schur_hot_ms, status=st)
         if st not in (BA_OK, BA_ENUMERIC):
             self._check(st)
         return out

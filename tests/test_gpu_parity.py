@@ -161,3 +161,26 @@ def test_lm_monotone_and_state_consistent(tiny):
     c, p = prob.get_params()
     assert abs(orc.cost(c, p, tiny.obs_camera, tiny.obs_point, tiny.obs_uv) - gpu["final_cost"]) \
         <= 1e-12 * gpu["final_cost"]
+
+
+@pytest.mark.parametrize("hot", [0, 3, 7])
+def test_hot_cold_split_matches_oracle(hot, monkeypatch):
+    """The Schur product splits cameras into an LDS-held hot set and a
+    camera-major cold stream; every split gives the oracle's product and LM
+    trace (with a point longer than one tile in the problem)."""
+    monkeypatch.setenv("BA_HOT_CAMERAS", str(hot))
+    arrays = with_edge_cases(small_zipf(seed=13, m=14, n=300, N=1500))
+    cams, pts, oc, op, uv, _ = arrays
+    for precision in (FP64, FP32_MIXED):
+        prob, _ = make(arrays, precision=precision, huber_delta=1.0)
+        lam = 1e-3
+        A = orc.assemble(cams, pts, oc, op, uv, 1.0)
+        Bd, Cd, Dc, Dp = orc.damp(A["B"], A["C"], lam, 0)
+        Ci = orc.invert_points(Cd)
+        x = np.random.default_rng(hot).normal(size=(len(cams), 9))
+        ref = orc.schur_matvec(oc, op, Bd, A["E"], Ci, x)
+        tol = 1e-10 if precision == FP64 else 1e-4
+        assert rel_err(prob.schur_matvec(x, lam), ref) <= tol, precision
+        prob.close()
+    tr, gpu, prob, _ = lm_pair(arrays, delta=1.0, iters=5, max_pcg=40, rtol=1e-8)
+    assert_traces_match(tr, gpu)
