@@ -375,50 +375,66 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
         if (const char* env = std::getenv("BA_HOT_CAMERAS")) kmax = std::min(kmax, std::max(0, std::atoi(env)));
         sp.K = std::max(0, std::min(m, kmax));
     }
-    std::vector<int32_t> short_idx, long_idx;
-    std::vector<uint8_t> tile_is_long(tiles.size() > 1 ? tiles.size() - 1 : 0, 0);
-    int64_t short_obs = 0;
-    for (size_t t = 0; t + 1 < tiles.size(); ++t) {
-        const int32_t len = tiles[t + 1] - tiles[t];
-        if (len > kTile) {
-            long_idx.push_back((int32_t)t);
-            tile_is_long[t] = 1;
-        } else {
-            short_idx.push_back((int32_t)t);
-            short_obs += len;
-        }
-    }
-    sp.num_short = (int32_t)short_idx.size();
-    sp.num_long = (int32_t)long_idx.size();
-    sp.num_wg = std::min<int32_t>(std::max(1, cus), std::max<int32_t>(1, sp.num_short));
-    if (sp.num_short == 0) sp.num_wg = 0;
-    std::vector<int32_t> wg_range((size_t)sp.num_wg + 1, 0);
+    // wave tiles: whole points packed into <= 64 observations; a point with
+    // more observations is a tile of its own
+    std::vector<int32_t> wtiles;
+    wtiles.push_back(0);
     {
-        int64_t acc = 0;
-        int32_t w = 1;
-        for (int32_t u = 0; u < sp.num_short && w < sp.num_wg; ++u) {
-            const int32_t t = short_idx[(size_t)u];
-            acc += tiles[(size_t)t + 1] - tiles[t];
-            if (acc * sp.num_wg >= short_obs * w) wg_range[(size_t)w++] = u + 1;
+        int64_t cur = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            const int64_t a = poff[i], b = poff[(size_t)i + 1];
+            if (b == a) continue;
+            if (b - cur > 64 && a > cur) {
+                wtiles.push_back((int32_t)a);
+                cur = a;
+            }
+            if (b - a > 64) {
+                wtiles.push_back((int32_t)b);
+                cur = b;
+            }
         }
-        for (; w <= sp.num_wg; ++w) wg_range[(size_t)w] = sp.num_short;
+        if (cur < N) wtiles.push_back((int32_t)N);
     }
-    // cold stream: observations of short tiles on cameras >= K, camera-major
-    std::vector<uint8_t> obs_long((size_t)N, 0);
-    for (int32_t t : long_idx)
-        for (int32_t k = tiles[t]; k < tiles[(size_t)t + 1]; ++k) obs_long[(size_t)k] = 1;
+    sp.num_wtiles = (int32_t)wtiles.size() - 1;
+    const int32_t waves_per_wg = P->is_f32() ? HotThreads<float>::value / 64 : HotThreads<double>::value / 64;
+    sp.num_wg = 0;
+    if (sp.num_wtiles > 0)
+        sp.num_wg = std::max(1, std::min(std::max(1, cus), (sp.num_wtiles + waves_per_wg - 1) / waves_per_wg));
+    const int32_t num_waves = sp.num_wg * waves_per_wg;
+    std::vector<int32_t> wrange((size_t)num_waves + 1, sp.num_wtiles);
+    {
+        // contiguous tile ranges of about equal work (a long tile is read twice)
+        std::vector<int64_t> work((size_t)sp.num_wtiles + 1, 0);
+        for (int32_t t = 0; t < sp.num_wtiles; ++t) {
+            const int64_t len = wtiles[(size_t)t + 1] - wtiles[t];
+            work[(size_t)t + 1] = work[t] + (len > 64 ? 2 * len : len) + 8;
+        }
+        const int64_t total = work[(size_t)sp.num_wtiles];
+        int32_t t = 0;
+        wrange[0] = 0;
+        for (int32_t w = 1; w < num_waves; ++w) {
+            const int64_t target = total * w / num_waves;
+            while (t < sp.num_wtiles && work[(size_t)t] < target) ++t;
+            wrange[(size_t)w] = t;
+        }
+    }
+    // cold stream: observations on cameras >= K, camera-major
     std::vector<int32_t> cold_pos((size_t)N, -1), h_cold_cam, h_cold_pt;
     std::vector<uint8_t> has_cold((size_t)(n > 0 ? n : 1), 0);
     for (int64_t d = 0; d < N; ++d) {
-        const int32_t t = h_cm_src[(size_t)d];
-        if (h_cm_cam[(size_t)d] >= sp.K && !obs_long[(size_t)t]) {
-            cold_pos[(size_t)t] = (int32_t)h_cold_cam.size();
+        if (h_cm_cam[(size_t)d] >= sp.K) {
+            cold_pos[(size_t)h_cm_src[(size_t)d]] = (int32_t)h_cold_cam.size();
             h_cold_cam.push_back(h_cm_cam[(size_t)d]);
             h_cold_pt.push_back(h_cm_pt[(size_t)d]);
             has_cold[(size_t)h_cm_pt[(size_t)d]] = 1;
         }
     }
     sp.cold.N = (int64_t)h_cold_cam.size();
+    if (std::getenv("BA_VERBOSE"))
+        std::fprintf(stderr,
+                     "[ba] m=%d n=%d N=%lld cus=%d lds/block=%d hot K=%d wg=%d wave tiles=%d cold obs=%lld (%.2f%%)\n",
+                     m, n, (long long)N, cus, lds_limit, sp.K, sp.num_wg, sp.num_wtiles, (long long)sp.cold.N,
+                     N > 0 ? 100.0 * (double)sp.cold.N / (double)N : 0.0);
     std::vector<int32_t> cold_chunk_slot, cold_cam_slot;
     sp.cold.num_slots = plan_slots(h_cold_cam, m, cold_chunk_slot, cold_cam_slot);
     sp.cold.num_chunks = (int32_t)cold_chunk_slot.size() - 1;
@@ -457,14 +473,12 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     P->dcam = A.get<double>(9 * (int64_t)m);
     for (double** v : {&P->g, &P->x, &P->r, &P->z, &P->p, &P->q, &P->cacc}) *v = A.get<double>(9 * (int64_t)m);
     P->pT = A.get<char>(9 * (int64_t)m * (int64_t)tsz);
-    sp.short_idx = A.get<int32_t>(sp.num_short);
-    sp.long_idx = A.get<int32_t>(sp.num_long);
-    sp.wg_range = A.get<int32_t>((int64_t)sp.num_wg + 1);
+    sp.wtile = A.get<int32_t>((int64_t)wtiles.size());
+    sp.wrange = A.get<int32_t>((int64_t)wrange.size());
     sp.has_cold = A.get<uint8_t>(n);
     sp.cold_pos = A.get<int32_t>(N);
     sp.hot_part = A.get<char>((int64_t)sp.num_wg * sp.K * 9 * (int64_t)tsz);
     sp.bcold = A.get<char>(3 * (int64_t)n * (int64_t)tsz);
-    sp.c_long = A.get<double>(9 * (int64_t)m);
     sp.cold.cam = A.get<int32_t>(sp.cold.N);
     sp.cold.pt = A.get<int32_t>(sp.cold.N);
     sp.cold.hcp = A.get<char>(27 * sp.cold.N * (int64_t)tsz);
@@ -506,9 +520,8 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     if (e == hipSuccess) e = up(P->cm.uvy, h_cm_uvy.data(), sizeof(double) * N);
     if (e == hipSuccess) e = up(P->cm.chunk_slot, chunk_slot.data(), sizeof(int32_t) * chunk_slot.size());
     if (e == hipSuccess) e = up(P->cm.cam_slot, cam_slot.data(), sizeof(int32_t) * cam_slot.size());
-    if (e == hipSuccess) e = up(sp.short_idx, short_idx.data(), sizeof(int32_t) * short_idx.size());
-    if (e == hipSuccess) e = up(sp.long_idx, long_idx.data(), sizeof(int32_t) * long_idx.size());
-    if (e == hipSuccess) e = up(sp.wg_range, wg_range.data(), sizeof(int32_t) * wg_range.size());
+    if (e == hipSuccess) e = up(sp.wtile, wtiles.data(), sizeof(int32_t) * wtiles.size());
+    if (e == hipSuccess) e = up(sp.wrange, wrange.data(), sizeof(int32_t) * wrange.size());
     if (e == hipSuccess) e = up(sp.has_cold, has_cold.data(), (size_t)n);
     if (e == hipSuccess) e = up(sp.cold_pos, cold_pos.data(), sizeof(int32_t) * N);
     if (e == hipSuccess) e = up(sp.cold.cam, h_cold_cam.data(), sizeof(int32_t) * h_cold_cam.size());

@@ -50,16 +50,16 @@ struct CameraMajor {
     double* slots;        // [num_slots][54]
 };
 
-// Workgroup shape of the hot-camera Schur pass: tiles in flight per workgroup.
+// Threads per workgroup of the hot-camera Schur pass (one workgroup per CU).
 template <typename T>
-struct HotGroups;
+struct HotThreads;
 template <>
-struct HotGroups<float> {
-    static constexpr int value = 4;
+struct HotThreads<float> {
+    static constexpr int value = 1024;
 };
 template <>
-struct HotGroups<double> {
-    static constexpr int value = 2;
+struct HotThreads<double> {
+    static constexpr int value = 512;
 };
 
 // Observations on cameras outside the hot set, in camera-major order.
@@ -79,15 +79,14 @@ struct ColdStream {
 struct SchurPlan {
     int32_t K = 0;                  // hot cameras: internal ids [0, K)
     int32_t num_wg = 0;             // persistent workgroups of the hot pass
-    int32_t num_short = 0, num_long = 0;
-    int32_t* short_idx = nullptr;   // [num_short] tiles of <= kTile observations
-    int32_t* long_idx = nullptr;    // [num_long] single-point tiles longer than kTile
-    int32_t* wg_range = nullptr;    // [num_wg + 1] ranges of short_idx per workgroup
+    int32_t num_wtiles = 0;         // point-aligned wave tiles
+    int32_t* wtile = nullptr;       // [num_wtiles + 1] observation offsets; a tile is
+                                    // whole points (<= 64 obs) or one longer point
+    int32_t* wrange = nullptr;      // [num_wg * waves per workgroup + 1] tile ranges per wave
     uint8_t* has_cold = nullptr;    // [n] point has an observation in the cold stream
     int32_t* cold_pos = nullptr;    // [N] point-major observation -> cold index or -1
     void* hot_part = nullptr;       // [num_wg][K][9] of T
     void* bcold = nullptr;          // [n][3] of T
-    double* c_long = nullptr;       // [m][9]
     ColdStream cold;
 };
 

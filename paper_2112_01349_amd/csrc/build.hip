@@ -144,7 +144,13 @@ __global__ __launch_bounds__(kTile) void k_build_points(
                 T e0, e1, wt, Jc[18], Jp[6];
                 int32_t ii;
                 observation<T>(k, cam, pt, uvx, uvy, pts, ck, delta, e0, e1, wt, Jc, Jp, ii);
-                if (!GRAD_ONLY) store_coupling<T>(k, N, Jc, Jp, wt, hcp);
+                if (!GRAD_ONLY) {
+                    store_coupling<T>(k, N, Jc, Jp, wt, hcp);
+                    if (cold_pos) {
+                        const int32_t c = cold_pos[k];
+                        if (c >= 0) store_coupling<T>(c, Nc, Jc, Jp, wt, chcp);
+                    }
+                }
                 double t[9];
                 point_terms<T>(Jp, e0, e1, wt, t);
 #pragma unroll

@@ -10,42 +10,35 @@
 // seen camera is in ~60% of the points), so the scatter is organised by
 // camera popularity (cameras are relabelled most-observed first):
 //
-//   pass 1 (k_schur_hot): persistent workgroups, one per CU, stream
-//     point-aligned tiles of <= 256 observations (several tiles in flight
-//     per workgroup, the next round's blocks prefetched into registers).
-//     a_i and b_i are reduced in LDS; contributions to the K hottest
-//     cameras accumulate in a per-workgroup LDS copy of their 9-vectors
-//     (K sized to fill the 160 KB LDS), written out once at the end.
-//     b_i of points that also have observations on colder cameras is stored.
+//   pass 1 (k_schur_hot): persistent workgroups, one per CU; every
+//     wavefront streams its own range of point-aligned wave tiles (<= 64
+//     observations, one per lane) with the next tile prefetched into
+//     registers.  a_i is summed by a segmented scan over shuffles and b_i is
+//     formed in registers; contributions to the K hottest cameras accumulate
+//     in a per-workgroup LDS copy of their 9-vectors (K sized to fill the
+//     160 KB LDS), written out once at the end.  b_i of points that also have
+//     observations on colder cameras is stored.
 //   pass 2 (k_schur_cold): the observations on cameras >= K, from their own
 //     camera-major copy of E, gather b_i and are reduced per camera by
 //     wavefront chunks into fixed partial-sum slots (no atomics).
 //   epilogue (k_schur_epilogue): per camera entry, sums the workgroup
 //     partials (hot) or the slots (cold) in a fixed order and forms q or g.
-// Points with more than 256 observations (none in the benchmark workloads)
-// go through k_schur_tiles with FP64 atomics into a separate accumulator.
+// A point with more than 64 observations takes a wave tile of its own and is
+// read in rows of 64.
 #include "ba_internal.h"
 
 namespace ba {
 
+// Observation `lane` of a packed wave tile (<= 64 observations).
 template <typename T>
-__device__ __forceinline__ void fetch_tile_obs(int32_t ti, int32_t r1, const int32_t* __restrict__ tile,
-                                               const int32_t* __restrict__ short_idx,
-                                               const int32_t* __restrict__ cam, const int32_t* __restrict__ pt,
-                                               const T* __restrict__ hcp, int64_t N, int lt, int32_t& s,
-                                               int32_t& len, int32_t& j, int32_t& i, T h[27])
+__device__ __forceinline__ void fetch_wave_obs(int32_t s, int32_t len, int lane, const int32_t* __restrict__ cam,
+                                               const int32_t* __restrict__ pt, const T* __restrict__ hcp, int64_t N,
+                                               int32_t& j, int32_t& i, T h[27])
 {
-    s = 0;
-    len = 0;
-    if (ti < r1) {
-        const int32_t t = short_idx[ti];
-        s = tile[t];
-        len = tile[t + 1] - s;
-    }
     j = 0;
     i = -1;
-    if (lt < len) {
-        const int64_t k = (int64_t)s + lt;
+    if (lane < len && len <= 64) {
+        const int64_t k = (int64_t)s + lane;
         j = cam[k];
         i = pt[k];
 #pragma unroll
@@ -56,85 +49,163 @@ __device__ __forceinline__ void fetch_tile_obs(int32_t ti, int32_t r1, const int
     }
 }
 
-template <typename T, int MODE>
-__global__ __launch_bounds__(HotGroups<T>::value* kTile) void k_schur_hot(
-    const int32_t* __restrict__ tile, const int32_t* __restrict__ short_idx, const int32_t* __restrict__ wg_range,
-    const int32_t* __restrict__ cam, const int32_t* __restrict__ pt, int64_t N, const T* __restrict__ hcp,
-    const T* __restrict__ cinv, const double* __restrict__ wpt, const T* __restrict__ xcam, int32_t K,
-    T* __restrict__ hot_part, T* __restrict__ bcold, const uint8_t* __restrict__ has_cold)
+template <typename T>
+__device__ __forceinline__ T wave_allsum(T v)
 {
-    constexpr int G = HotGroups<T>::value;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ void add_hot(T* __restrict__ cl, int32_t j, const T h[27], T b0, T b1, T b2)
+{
+    T* dst = cl + 9 * j;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) atomicAdd(dst + a, h[a * 3] * b0 + h[a * 3 + 1] * b1 + h[a * 3 + 2] * b2);
+}
+
+// Pass 1.  Each wavefront walks its own range of wave tiles: a packed tile
+// holds whole points (<= 64 observations, one per lane); a tile of one point
+// with more observations is looped over in rows of 64 (its blocks are read
+// twice).  Per-point sums use a segmented inclusive scan over DPP shuffles,
+// so the wavefronts never wait for each other; the next packed tile's blocks
+// are loaded while the current one is processed.
+template <typename T, int MODE>
+__global__ __launch_bounds__(HotThreads<T>::value) void k_schur_hot(
+    const int32_t* __restrict__ wtile, const int32_t* __restrict__ wrange, const int32_t* __restrict__ cam,
+    const int32_t* __restrict__ pt, int64_t N, const T* __restrict__ hcp, const T* __restrict__ cinv,
+    const double* __restrict__ wpt, const T* __restrict__ xcam, int32_t K, T* __restrict__ hot_part,
+    T* __restrict__ bcold, const uint8_t* __restrict__ has_cold)
+{
+    constexpr int NT = HotThreads<T>::value;
     extern __shared__ __align__(16) unsigned char smem[];
     T* cl = reinterpret_cast<T*>(smem);
-    T* scr = cl + (size_t)K * 9;
-    int32_t* spt = reinterpret_cast<int32_t*>(scr + G * 3 * kTile);
-    const int g = threadIdx.x / kTile, lt = threadIdx.x % kTile;
-    T* sg = scr + g * 3 * kTile;
-    int32_t* pg = spt + g * kTile;
-    for (int q = threadIdx.x; q < K * 9; q += G * kTile) cl[q] = (T)0;
-    const int32_t r0 = wg_range[blockIdx.x], r1 = wg_range[blockIdx.x + 1];
-    const int32_t rounds = (r1 - r0 + G - 1) / G;
-
-    int32_t cs, clen, cj, ci;
-    T ch[27];
-    fetch_tile_obs<T>(r0 + g, r1, tile, short_idx, cam, pt, hcp, N, lt, cs, clen, cj, ci, ch);
+    for (int q = threadIdx.x; q < K * 9; q += NT) cl[q] = (T)0;
     __syncthreads();
-    for (int32_t r = 0; r < rounds; ++r) {
-        int32_t ns, nlen, nj, ni;
+    const int lane = threadIdx.x & 63;
+    const int32_t gw = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+    const int32_t t0 = wrange[gw], t1 = wrange[gw + 1];
+    int32_t cs = 0, clen = 0, cj, ci;
+    T ch[27];
+    if (t0 < t1) {
+        cs = wtile[t0];
+        clen = wtile[t0 + 1] - cs;
+    }
+    fetch_wave_obs<T>(cs, clen, lane, cam, pt, hcp, N, cj, ci, ch);
+    for (int32_t t = t0; t < t1; ++t) {
+        int32_t ns = 0, nlen = 0, nj, ni;
         T nh[27];
-        fetch_tile_obs<T>(r0 + (r + 1) * G + g, r1, tile, short_idx, cam, pt, hcp, N, lt, ns, nlen, nj, ni, nh);
-        const bool valid = lt < clen;
-        if (MODE == 0 && valid) {
-            T x[9];
-#pragma unroll
-            for (int a = 0; a < 9; ++a) x[a] = xcam[9 * (int64_t)cj + a];
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                T acc = (T)0;
-#pragma unroll
-                for (int a = 0; a < 9; ++a) acc += ch[a * 3 + b] * x[a];
-                sg[b * kTile + lt] = acc;
-            }
+        if (t + 1 < t1) {
+            ns = wtile[t + 1];
+            nlen = wtile[t + 2] - ns;
         }
-        pg[lt] = ci;
-        __syncthreads();
-        if (valid && (lt == 0 || pg[lt - 1] != ci)) {
-            const T* c6 = cinv + 6 * (int64_t)ci;
+        fetch_wave_obs<T>(ns, nlen, lane, cam, pt, hcp, N, nj, ni, nh);
+        if (clen <= 64) {
+            const bool valid = lane < clen;
+            const int32_t prev = __shfl_up(ci, 1, 64);
+            const bool head = valid && (lane == 0 || prev != ci);
+            const uint64_t hm = __ballot(head);
+            const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+            const int seg_s = 63 - __clzll((hm & upto) | 1ull);
+            const uint64_t above = hm & ~upto;
+            const int seg_e = above ? __ffsll((unsigned long long)above) - 2 : clen - 1;
             T a0, a1, a2;
             if (MODE == 0) {
                 a0 = a1 = a2 = (T)0;
-                for (int u = lt; u < clen && pg[u] == ci; ++u) {
-                    a0 += sg[u];
-                    a1 += sg[kTile + u];
-                    a2 += sg[2 * kTile + u];
+                if (valid) {
+                    T x[9];
+#pragma unroll
+                    for (int a = 0; a < 9; ++a) x[a] = xcam[9 * (int64_t)cj + a];
+#pragma unroll
+                    for (int a = 0; a < 9; ++a) {
+                        a0 += ch[a * 3] * x[a];
+                        a1 += ch[a * 3 + 1] * x[a];
+                        a2 += ch[a * 3 + 2] * x[a];
+                    }
                 }
+#pragma unroll
+                for (int off = 1; off < 64; off <<= 1) {
+                    const T u0 = __shfl_up(a0, off, 64), u1 = __shfl_up(a1, off, 64), u2 = __shfl_up(a2, off, 64);
+                    if (lane - off >= seg_s) {
+                        a0 += u0;
+                        a1 += u1;
+                        a2 += u2;
+                    }
+                }
+                a0 = __shfl(a0, seg_e, 64);
+                a1 = __shfl(a1, seg_e, 64);
+                a2 = __shfl(a2, seg_e, 64);
             } else {
-                a0 = (T)wpt[3 * (int64_t)ci];
-                a1 = (T)wpt[3 * (int64_t)ci + 1];
-                a2 = (T)wpt[3 * (int64_t)ci + 2];
+                a0 = a1 = a2 = (T)0;
+                if (valid) {
+                    a0 = (T)wpt[3 * (int64_t)ci];
+                    a1 = (T)wpt[3 * (int64_t)ci + 1];
+                    a2 = (T)wpt[3 * (int64_t)ci + 2];
+                }
             }
+            if (valid) {
+                const T* c6 = cinv + 6 * (int64_t)ci;
+                const T b0 = c6[0] * a0 + c6[1] * a1 + c6[2] * a2;
+                const T b1 = c6[1] * a0 + c6[3] * a1 + c6[4] * a2;
+                const T b2 = c6[2] * a0 + c6[4] * a1 + c6[5] * a2;
+                if (lane == seg_e && has_cold[ci]) {
+                    bcold[3 * (int64_t)ci] = b0;
+                    bcold[3 * (int64_t)ci + 1] = b1;
+                    bcold[3 * (int64_t)ci + 2] = b2;
+                }
+                if (cj < K) add_hot<T>(cl, cj, ch, b0, b1, b2);
+            }
+        } else {
+            // one point with more than 64 observations
+            const int32_t i = pt[cs];
+            T a0 = (T)0, a1 = (T)0, a2 = (T)0;
+            if (MODE == 0) {
+                for (int32_t base = 0; base < clen; base += 64) {
+                    const int32_t u = base + lane;
+                    if (u < clen) {
+                        const int64_t k = (int64_t)cs + u;
+                        const int32_t j = cam[k];
+#pragma unroll
+                        for (int a = 0; a < 9; ++a) {
+                            const T xa = xcam[9 * (int64_t)j + a];
+                            a0 += hcp[(int64_t)(a * 3) * N + k] * xa;
+                            a1 += hcp[(int64_t)(a * 3 + 1) * N + k] * xa;
+                            a2 += hcp[(int64_t)(a * 3 + 2) * N + k] * xa;
+                        }
+                    }
+                }
+                a0 = wave_allsum<T>(a0);
+                a1 = wave_allsum<T>(a1);
+                a2 = wave_allsum<T>(a2);
+            } else {
+                a0 = (T)wpt[3 * (int64_t)i];
+                a1 = (T)wpt[3 * (int64_t)i + 1];
+                a2 = (T)wpt[3 * (int64_t)i + 2];
+            }
+            const T* c6 = cinv + 6 * (int64_t)i;
             const T b0 = c6[0] * a0 + c6[1] * a1 + c6[2] * a2;
             const T b1 = c6[1] * a0 + c6[3] * a1 + c6[4] * a2;
             const T b2 = c6[2] * a0 + c6[4] * a1 + c6[5] * a2;
-            sg[lt] = b0;
-            sg[kTile + lt] = b1;
-            sg[2 * kTile + lt] = b2;
-            if (has_cold[ci]) {
-                bcold[3 * (int64_t)ci] = b0;
-                bcold[3 * (int64_t)ci + 1] = b1;
-                bcold[3 * (int64_t)ci + 2] = b2;
+            if (lane == 0 && has_cold[i]) {
+                bcold[3 * (int64_t)i] = b0;
+                bcold[3 * (int64_t)i + 1] = b1;
+                bcold[3 * (int64_t)i + 2] = b2;
+            }
+            for (int32_t base = 0; base < clen; base += 64) {
+                const int32_t u = base + lane;
+                if (u < clen) {
+                    const int64_t k = (int64_t)cs + u;
+                    const int32_t j = cam[k];
+                    if (j < K) {
+                        T h[27];
+#pragma unroll
+                        for (int q = 0; q < 27; ++q) h[q] = hcp[(int64_t)q * N + k];
+                        add_hot<T>(cl, j, h, b0, b1, b2);
+                    }
+                }
             }
         }
-        __syncthreads();
-        if (valid && cj < K) {
-            int hd = lt;
-            while (hd > 0 && pg[hd - 1] == ci) --hd;
-            const T b0 = sg[hd], b1 = sg[kTile + hd], b2 = sg[2 * kTile + hd];
-            T* dst = cl + 9 * cj;
-#pragma unroll
-            for (int a = 0; a < 9; ++a) atomicAdd(dst + a, ch[a * 3] * b0 + ch[a * 3 + 1] * b1 + ch[a * 3 + 2] * b2);
-        }
-        __syncthreads();
         cs = ns;
         clen = nlen;
         cj = nj;
@@ -142,8 +213,9 @@ __global__ __launch_bounds__(HotGroups<T>::value* kTile) void k_schur_hot(
 #pragma unroll
         for (int q = 0; q < 27; ++q) ch[q] = nh[q];
     }
+    __syncthreads();
     T* out = hot_part + (int64_t)blockIdx.x * K * 9;
-    for (int q = threadIdx.x; q < K * 9; q += G * kTile) out[q] = cl[q];
+    for (int q = threadIdx.x; q < K * 9; q += NT) out[q] = cl[q];
 }
 
 __device__ __forceinline__ double wave_sum_d(double v)
@@ -210,11 +282,11 @@ __global__ __launch_bounds__(256) void k_schur_cold(int64_t Nc, int32_t num_chun
 }
 
 // q = B~ x - c (mode 0, partial p^T q) or g = v - c, r = g, x = 0 (mode 1,
-// partial ||g||^2); c from the hot partials, the cold slots and c_long.
+// partial ||g||^2); c from the hot partials and the cold slots.
 template <typename T, int MODE>
 __global__ __launch_bounds__(kRedBlock) void k_schur_epilogue(
     int32_t m, int32_t K, int32_t G, const T* __restrict__ hot_part, const int32_t* __restrict__ cold_cam_slot,
-    const double* __restrict__ cold_slots, const double* __restrict__ c_long, const double* __restrict__ bd,
+    const double* __restrict__ cold_slots, const double* __restrict__ bd,
     const double* __restrict__ pvec, const double* __restrict__ vcam, double* __restrict__ out,
     double* __restrict__ xvec, double* __restrict__ rvec, double* __restrict__ partials,
     const PcgScalars* __restrict__ sc)
@@ -243,7 +315,6 @@ __global__ __launch_bounds__(kRedBlock) void k_schur_epilogue(
             } else {
                 for (int32_t s = cold_cam_slot[j]; s < cold_cam_slot[j + 1]; ++s) c += cold_slots[(int64_t)s * 9 + a];
             }
-            if (c_long) c += c_long[t];
             if (MODE == 0) {
                 const double* B = bd + 81 * j + 9 * a;
                 const double* pj = pvec + 9 * j;
@@ -275,15 +346,14 @@ __global__ __launch_bounds__(kRedBlock) void k_schur_epilogue(
 template <typename T>
 size_t hot_lds_bytes(int32_t K)
 {
-    return (size_t)K * 9 * sizeof(T) + (size_t)HotGroups<T>::value * (3 * kTile * sizeof(T) + kTile * sizeof(int32_t));
+    return (size_t)K * 9 * sizeof(T);
 }
 
 template <typename T>
 int32_t hot_max_cameras(size_t lds_limit)
 {
-    const size_t fixed = hot_lds_bytes<T>(0);
-    if (lds_limit <= fixed + 1024) return 0;
-    return (int32_t)((lds_limit - fixed - 1024) / (9 * sizeof(T)));
+    if (lds_limit <= 1024) return 0;
+    return (int32_t)((lds_limit - 1024) / (9 * sizeof(T)));
 }
 
 template <typename T>
@@ -306,14 +376,13 @@ hipError_t launch_schur_product(int mode, const SchurPlan& sp, const PointMajor&
     const size_t lds = hot_lds_bytes<T>(sp.K);
     if (hot_begin && (e = hipEventRecord(hot_begin, s)) != hipSuccess) return e;
     if (sp.num_wg > 0) {
+        const dim3 g(sp.num_wg), b(HotThreads<T>::value);
         if (mode == 0)
-            hipLaunchKernelGGL((k_schur_hot<T, 0>), dim3(sp.num_wg), dim3(HotGroups<T>::value * kTile), lds, s, pm.tile,
-                               sp.short_idx, sp.wg_range, pm.cam, pm.pt, N, hcp, cinv, wpt, xcam, sp.K,
-                               (T*)sp.hot_part, (T*)sp.bcold, sp.has_cold);
+            hipLaunchKernelGGL((k_schur_hot<T, 0>), g, b, lds, s, sp.wtile, sp.wrange, pm.cam, pm.pt, N, hcp, cinv,
+                               wpt, xcam, sp.K, (T*)sp.hot_part, (T*)sp.bcold, sp.has_cold);
         else
-            hipLaunchKernelGGL((k_schur_hot<T, 1>), dim3(sp.num_wg), dim3(HotGroups<T>::value * kTile), lds, s, pm.tile,
-                               sp.short_idx, sp.wg_range, pm.cam, pm.pt, N, hcp, cinv, wpt, xcam, sp.K,
-                               (T*)sp.hot_part, (T*)sp.bcold, sp.has_cold);
+            hipLaunchKernelGGL((k_schur_hot<T, 1>), g, b, lds, s, sp.wtile, sp.wrange, pm.cam, pm.pt, N, hcp, cinv,
+                               wpt, xcam, sp.K, (T*)sp.hot_part, (T*)sp.bcold, sp.has_cold);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (hot_end && (e = hipEventRecord(hot_end, s)) != hipSuccess) return e;
@@ -323,22 +392,15 @@ hipError_t launch_schur_product(int mode, const SchurPlan& sp, const PointMajor&
                            sp.cold.chunk_slot, sp.cold.slots);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if (sp.num_long > 0) {
-        if ((e = launch_zero(sp.c_long, 9 * (int64_t)m, s)) != hipSuccess) return e;
-        if ((e = launch_schur_tiles<T>(mode, pm, sp.long_idx, sp.num_long, N, hcp, cinv, wpt, xcam, sp.c_long, nullptr,
-                                       s)) != hipSuccess)
-            return e;
-    }
     const int32_t b = reduce_blocks(9 * (int64_t)m);
     *nblocks = b;
-    const double* cl = sp.num_long > 0 ? sp.c_long : nullptr;
     if (mode == 0)
         hipLaunchKernelGGL((k_schur_epilogue<T, 0>), dim3(b), dim3(kRedBlock), 0, s, m, sp.K, sp.num_wg,
-                           (const T*)sp.hot_part, sp.cold.cam_slot, sp.cold.slots, cl, bd, pvec, vcam, out, xvec,
+                           (const T*)sp.hot_part, sp.cold.cam_slot, sp.cold.slots, bd, pvec, vcam, out, xvec,
                            rvec, partials, sc);
     else
         hipLaunchKernelGGL((k_schur_epilogue<T, 1>), dim3(b), dim3(kRedBlock), 0, s, m, sp.K, sp.num_wg,
-                           (const T*)sp.hot_part, sp.cold.cam_slot, sp.cold.slots, cl, bd, pvec, vcam, out, xvec,
+                           (const T*)sp.hot_part, sp.cold.cam_slot, sp.cold.slots, bd, pvec, vcam, out, xvec,
                            rvec, partials, sc);
     return hipGetLastError();
 }
