@@ -477,7 +477,7 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     sp.wrange = A.get<int32_t>((int64_t)wrange.size());
     sp.has_cold = A.get<uint8_t>(n);
     sp.cold_pos = A.get<int32_t>(N);
-    sp.hot_part = A.get<char>((int64_t)sp.num_wg * sp.K * 9 * (int64_t)tsz);
+    sp.hot_part = A.get<double>((int64_t)sp.num_wg * sp.K * 9);
     sp.bcold = A.get<char>(3 * (int64_t)n * (int64_t)tsz);
     sp.cold.cam = A.get<int32_t>(sp.cold.N);
     sp.cold.pt = A.get<int32_t>(sp.cold.N);

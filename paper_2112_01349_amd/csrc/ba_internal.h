@@ -85,7 +85,7 @@ struct SchurPlan {
     int32_t* wrange = nullptr;      // [num_wg * waves per workgroup + 1] tile ranges per wave
     uint8_t* has_cold = nullptr;    // [n] point has an observation in the cold stream
     int32_t* cold_pos = nullptr;    // [N] point-major observation -> cold index or -1
-    void* hot_part = nullptr;       // [num_wg][K][9] of T
+    void* hot_part = nullptr;       // [num_wg][K][9] FP64
     void* bcold = nullptr;          // [n][3] of T
     ColdStream cold;
 };

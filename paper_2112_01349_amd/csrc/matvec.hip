@@ -57,12 +57,16 @@ __device__ __forceinline__ T wave_allsum(T v)
     return v;
 }
 
+// The hot-camera table is FP64 in both precisions: LDS FP64 adds issue
+// without the back-pressure FP32 LDS adds show here, and the per-workgroup
+// sums of the most observed cameras keep FP64 accuracy.
 template <typename T>
-__device__ __forceinline__ void add_hot(T* __restrict__ cl, int32_t j, const T h[27], T b0, T b1, T b2)
+__device__ __forceinline__ void add_hot(double* __restrict__ cl, int32_t j, const T h[27], T b0, T b1, T b2)
 {
-    T* dst = cl + 9 * j;
+    double* dst = cl + 9 * j;
 #pragma unroll
-    for (int a = 0; a < 9; ++a) atomicAdd(dst + a, h[a * 3] * b0 + h[a * 3 + 1] * b1 + h[a * 3 + 2] * b2);
+    for (int a = 0; a < 9; ++a)
+        atomicAdd(dst + a, (double)(h[a * 3] * b0 + h[a * 3 + 1] * b1 + h[a * 3 + 2] * b2));
 }
 
 // Pass 1.  Each wavefront walks its own range of wave tiles: a packed tile
@@ -75,13 +79,13 @@ template <typename T, int MODE>
 __global__ __launch_bounds__(HotThreads<T>::value) void k_schur_hot(
     const int32_t* __restrict__ wtile, const int32_t* __restrict__ wrange, const int32_t* __restrict__ cam,
     const int32_t* __restrict__ pt, int64_t N, const T* __restrict__ hcp, const T* __restrict__ cinv,
-    const double* __restrict__ wpt, const T* __restrict__ xcam, int32_t K, T* __restrict__ hot_part,
+    const double* __restrict__ wpt, const T* __restrict__ xcam, int32_t K, double* __restrict__ hot_part,
     T* __restrict__ bcold, const uint8_t* __restrict__ has_cold)
 {
     constexpr int NT = HotThreads<T>::value;
     extern __shared__ __align__(16) unsigned char smem[];
-    T* cl = reinterpret_cast<T*>(smem);
-    for (int q = threadIdx.x; q < K * 9; q += NT) cl[q] = (T)0;
+    double* cl = reinterpret_cast<double*>(smem);
+    for (int q = threadIdx.x; q < K * 9; q += NT) cl[q] = 0.0;
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int32_t gw = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
@@ -214,7 +218,7 @@ __global__ __launch_bounds__(HotThreads<T>::value) void k_schur_hot(
         for (int q = 0; q < 27; ++q) ch[q] = nh[q];
     }
     __syncthreads();
-    T* out = hot_part + (int64_t)blockIdx.x * K * 9;
+    double* out = hot_part + (int64_t)blockIdx.x * K * 9;
     for (int q = threadIdx.x; q < K * 9; q += NT) out[q] = cl[q];
 }
 
@@ -285,7 +289,7 @@ __global__ __launch_bounds__(256) void k_schur_cold(int64_t Nc, int32_t num_chun
 // partial ||g||^2); c from the hot partials and the cold slots.
 template <typename T, int MODE>
 __global__ __launch_bounds__(kRedBlock) void k_schur_epilogue(
-    int32_t m, int32_t K, int32_t G, const T* __restrict__ hot_part, const int32_t* __restrict__ cold_cam_slot,
+    int32_t m, int32_t K, int32_t G, const double* __restrict__ hot_part, const int32_t* __restrict__ cold_cam_slot,
     const double* __restrict__ cold_slots, const double* __restrict__ bd,
     const double* __restrict__ pvec, const double* __restrict__ vcam, double* __restrict__ out,
     double* __restrict__ xvec, double* __restrict__ rvec, double* __restrict__ partials,
@@ -305,12 +309,12 @@ __global__ __launch_bounds__(kRedBlock) void k_schur_epilogue(
                 double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
                 int32_t w = 0;
                 for (; w + 4 <= G; w += 4) {
-                    c0 += (double)hot_part[(int64_t)w * stride + t];
-                    c1 += (double)hot_part[(int64_t)(w + 1) * stride + t];
-                    c2 += (double)hot_part[(int64_t)(w + 2) * stride + t];
-                    c3 += (double)hot_part[(int64_t)(w + 3) * stride + t];
+                    c0 += hot_part[(int64_t)w * stride + t];
+                    c1 += hot_part[(int64_t)(w + 1) * stride + t];
+                    c2 += hot_part[(int64_t)(w + 2) * stride + t];
+                    c3 += hot_part[(int64_t)(w + 3) * stride + t];
                 }
-                for (; w < G; ++w) c0 += (double)hot_part[(int64_t)w * stride + t];
+                for (; w < G; ++w) c0 += hot_part[(int64_t)w * stride + t];
                 c = (c0 + c1) + (c2 + c3);
             } else {
                 for (int32_t s = cold_cam_slot[j]; s < cold_cam_slot[j + 1]; ++s) c += cold_slots[(int64_t)s * 9 + a];
@@ -346,14 +350,14 @@ __global__ __launch_bounds__(kRedBlock) void k_schur_epilogue(
 template <typename T>
 size_t hot_lds_bytes(int32_t K)
 {
-    return (size_t)K * 9 * sizeof(T);
+    return (size_t)K * 9 * sizeof(double);
 }
 
 template <typename T>
 int32_t hot_max_cameras(size_t lds_limit)
 {
     if (lds_limit <= 1024) return 0;
-    return (int32_t)((lds_limit - 1024) / (9 * sizeof(T)));
+    return (int32_t)((lds_limit - 1024) / (9 * sizeof(double)));
 }
 
 template <typename T>
@@ -379,10 +383,10 @@ hipError_t launch_schur_product(int mode, const SchurPlan& sp, const PointMajor&
         const dim3 g(sp.num_wg), b(HotThreads<T>::value);
         if (mode == 0)
             hipLaunchKernelGGL((k_schur_hot<T, 0>), g, b, lds, s, sp.wtile, sp.wrange, pm.cam, pm.pt, N, hcp, cinv,
-                               wpt, xcam, sp.K, (T*)sp.hot_part, (T*)sp.bcold, sp.has_cold);
+                               wpt, xcam, sp.K, (double*)sp.hot_part, (T*)sp.bcold, sp.has_cold);
         else
             hipLaunchKernelGGL((k_schur_hot<T, 1>), g, b, lds, s, sp.wtile, sp.wrange, pm.cam, pm.pt, N, hcp, cinv,
-                               wpt, xcam, sp.K, (T*)sp.hot_part, (T*)sp.bcold, sp.has_cold);
+                               wpt, xcam, sp.K, (double*)sp.hot_part, (T*)sp.bcold, sp.has_cold);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (hot_end && (e = hipEventRecord(hot_end, s)) != hipSuccess) return e;
@@ -396,11 +400,11 @@ hipError_t launch_schur_product(int mode, const SchurPlan& sp, const PointMajor&
     *nblocks = b;
     if (mode == 0)
         hipLaunchKernelGGL((k_schur_epilogue<T, 0>), dim3(b), dim3(kRedBlock), 0, s, m, sp.K, sp.num_wg,
-                           (const T*)sp.hot_part, sp.cold.cam_slot, sp.cold.slots, bd, pvec, vcam, out, xvec,
+                           (const double*)sp.hot_part, sp.cold.cam_slot, sp.cold.slots, bd, pvec, vcam, out, xvec,
                            rvec, partials, sc);
     else
         hipLaunchKernelGGL((k_schur_epilogue<T, 1>), dim3(b), dim3(kRedBlock), 0, s, m, sp.K, sp.num_wg,
-                           (const T*)sp.hot_part, sp.cold.cam_slot, sp.cold.slots, bd, pvec, vcam, out, xvec,
+                           (const double*)sp.hot_part, sp.cold.cam_slot, sp.cold.slots, bd, pvec, vcam, out, xvec,
                            rvec, partials, sc);
     return hipGetLastError();
 }
