@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -188,19 +189,19 @@ ba_status ba_memory_bytes(const ba_problem* prob, int64_t* bytes)
 
 // ------------------------------------------------------------------ set-up
 // Partial-sum slots of a camera-sorted stream cut into wave chunks of
-// kCmChunk: one slot per (chunk, camera run); a camera's slots are
-// contiguous.  Returns the slot count.
-static int32_t plan_slots(const std::vector<int32_t>& cam_sorted, int32_t m, std::vector<int32_t>& chunk_slot,
-                          std::vector<int32_t>& cam_slot)
+// `chunk` observations: one slot per (chunk, camera run); a camera's slots
+// are contiguous.  Returns the slot count.
+static int32_t plan_slots(const std::vector<int32_t>& cam_sorted, int32_t m, int32_t chunk,
+                          std::vector<int32_t>& chunk_slot, std::vector<int32_t>& cam_slot)
 {
     const int64_t len = (int64_t)cam_sorted.size();
-    const int32_t num_chunks = (int32_t)((len + kCmChunk - 1) / kCmChunk);
+    const int32_t num_chunks = (int32_t)((len + chunk - 1) / chunk);
     chunk_slot.assign((size_t)num_chunks + 1, 0);
     std::vector<int32_t> per_cam((size_t)m, 0);
     int32_t slot = 0;
     for (int32_t c = 0; c < num_chunks; ++c) {
         chunk_slot[c] = slot;
-        const int64_t s = (int64_t)c * kCmChunk, e = std::min<int64_t>(len, s + kCmChunk);
+        const int64_t s = (int64_t)c * chunk, e = std::min<int64_t>(len, s + chunk);
         for (int64_t t = s; t < e; ++t)
             if (t == s || cam_sorted[(size_t)t] != cam_sorted[(size_t)t - 1]) {
                 per_cam[cam_sorted[(size_t)t]]++;
@@ -354,7 +355,7 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
         }
     }
     std::vector<int32_t> chunk_slot, cam_slot;
-    P->cm.num_slots = plan_slots(h_cm_cam, m, chunk_slot, cam_slot);
+    P->cm.num_slots = plan_slots(h_cm_cam, m, kCmChunk, chunk_slot, cam_slot);
     const int32_t num_chunks = (int32_t)chunk_slot.size() - 1;
     P->cm.num_chunks = num_chunks;
 
@@ -436,7 +437,7 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
                      m, n, (long long)N, cus, lds_limit, sp.K, sp.num_wg, sp.num_wtiles, (long long)sp.cold.N,
                      N > 0 ? 100.0 * (double)sp.cold.N / (double)N : 0.0);
     std::vector<int32_t> cold_chunk_slot, cold_cam_slot;
-    sp.cold.num_slots = plan_slots(h_cold_cam, m, cold_chunk_slot, cold_cam_slot);
+    sp.cold.num_slots = plan_slots(h_cold_cam, m, kColdChunk, cold_chunk_slot, cold_cam_slot);
     sp.cold.num_chunks = (int32_t)cold_chunk_slot.size() - 1;
 
     // Workspace: everything the solve needs, sized once.
@@ -637,74 +638,66 @@ struct PcgTimer {
     }
 };
 
-// PCG on the reduced camera system (Alg. 2, one partition); dc = x.
+// PCG on the reduced camera system (Alg. 2, one partition); dc = x.  The
+// stopping test runs on the device before every matvec (as in the oracle);
+// the host enqueues iterations in batches and reads the `done` flag between
+// batches.  With a fixed count everything is enqueued at once.
 template <typename T>
 static ba_status run_pcg(ba_problem* P, const ba_options& o, int32_t fixed, int32_t* iters, PcgTimer* tm,
                          double* matvec_ms, double* hot_ms, int64_t* launches)
 {
     hipStream_t s = P->stream;
     const int32_t m = P->m;
-    int32_t nb = 0;
-    // b = v - E C^-1 w; x = 0; r = b
+    const int32_t cap = fixed > 0 ? fixed : o.max_pcg_iters;
+    BA_TRY(P, launch_pcg_reset(P->sc, o.pcg_rtol, o.max_pcg_iters, fixed, s));
+    // b = v - E C^-1 w; x = 0; r = b; ||b||^2; then z = M^-1 r and the first test
     BA_TRY(P, launch_schur_product<T>(1, P->sp, P->pm, P->N, (const T*)P->hcp, (const T*)P->cinv, P->wpt, nullptr, m,
-                                      P->bd, nullptr, P->vcam, P->g, P->x, P->r, P->partials, &nb, P->sc, nullptr,
-                                      nullptr, s));
-    BA_TRY(P, launch_sum_partials(P->partials, nb, 1, 1, P->sums, s));
-    BA_TRY(P, launch_pcg_finish_scalars(P->sc, P->sums, 0, s));
-    int32_t it = 0;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> marks, hot_marks;
-    while (true) {
-        if (fixed > 0) {
-            if (it >= fixed) break;
-        } else {
-            ba_status st = read_scalars(P, P->sc, sizeof(PcgScalars));
-            if (st != BA_OK) return st;
-            const PcgScalars* h = (const PcgScalars*)P->h_scalars;
-            if (h->breakdown) break;
-            if (std::sqrt(h->rr) <= o.pcg_rtol * std::sqrt(h->bb) || it >= o.max_pcg_iters) break;
+                                      P->bd, nullptr, P->vcam, P->g, P->x, P->r, P->partials, P->sc, nullptr, nullptr,
+                                      s));
+    BA_TRY(P, launch_pcg_step(m, true, P->lfac, P->p, P->q, P->x, P->r, P->z, P->partials, P->sc, s));
+    std::vector<std::array<hipEvent_t, 4>> marks;
+    const int32_t batch = fixed > 0 ? std::max(1, cap) : 8;
+    int32_t enqueued = 0;
+    while (enqueued < cap) {
+        const int32_t nb = std::min(batch, cap - enqueued);
+        for (int32_t b = 0; b < nb; ++b) {
+            BA_TRY(P, launch_pcg_direction<T>(m, false, P->z, P->p, (T*)P->pT, P->sc, s));
+            std::array<hipEvent_t, 4> ev{nullptr, nullptr, nullptr, nullptr};
+            if (tm) {
+                BA_TRY(P, tm->next(&ev[0], &ev[1]));
+                BA_TRY(P, tm->next(&ev[2], &ev[3]));
+                BA_TRY(P, hipEventRecord(ev[0], s));
+            }
+            BA_TRY(P, launch_schur_product<T>(0, P->sp, P->pm, P->N, (const T*)P->hcp, (const T*)P->cinv, P->wpt,
+                                              (const T*)P->pT, m, P->bd, P->p, nullptr, P->q, nullptr, nullptr,
+                                              P->partials, P->sc, ev[2], ev[3], s));
+            if (tm) {
+                BA_TRY(P, hipEventRecord(ev[1], s));
+                marks.push_back(ev);
+            }
+            BA_TRY(P, launch_pcg_step(m, false, P->lfac, P->p, P->q, P->x, P->r, P->z, P->partials, P->sc, s));
+            ++enqueued;
         }
-        BA_TRY(P, launch_pcg_precond(m, P->lfac, P->r, P->z, P->partials, &nb, P->sc, s));
-        BA_TRY(P, launch_sum_partials(P->partials, nb, 2, 2, P->sums, s));
-        BA_TRY(P, launch_pcg_finish_scalars(P->sc, P->sums, 1, s));
-        BA_TRY(P, launch_pcg_direction<T>(m, it == 0, P->z, P->p, (T*)P->pT, P->sc, s));
-        hipEvent_t ea = nullptr, eb = nullptr, ha = nullptr, hb = nullptr;
-        if (tm) {
-            BA_TRY(P, tm->next(&ea, &eb));
-            BA_TRY(P, tm->next(&ha, &hb));
-            BA_TRY(P, hipEventRecord(ea, s));
-        }
-        BA_TRY(P, launch_schur_product<T>(0, P->sp, P->pm, P->N, (const T*)P->hcp, (const T*)P->cinv, P->wpt,
-                                          (const T*)P->pT, m, P->bd, P->p, nullptr, P->q, nullptr, nullptr,
-                                          P->partials, &nb, P->sc, ha, hb, s));
-        if (tm) {
-            BA_TRY(P, hipEventRecord(eb, s));
-            marks.emplace_back(ea, eb);
-            hot_marks.emplace_back(ha, hb);
-        }
-        BA_TRY(P, launch_sum_partials(P->partials, nb, 1, 1, P->sums, s));
-        BA_TRY(P, launch_pcg_finish_scalars(P->sc, P->sums, 2, s));
-        BA_TRY(P, launch_pcg_update(m, P->p, P->q, P->x, P->r, P->partials, &nb, P->sc, s));
-        BA_TRY(P, launch_sum_partials(P->partials, nb, 1, 1, P->sums, s));
-        BA_TRY(P, launch_pcg_finish_scalars(P->sc, P->sums, 3, s));
-        ++it;
+        ba_status st = read_scalars(P, P->sc, sizeof(PcgScalars));
+        if (st != BA_OK) return st;
+        if (((const PcgScalars*)P->h_scalars)->done) break;
     }
-    *iters = it;
     ba_status st = read_scalars(P, P->sc, sizeof(PcgScalars));
     if (st != BA_OK) return st;
-    if (((const PcgScalars*)P->h_scalars)->breakdown) {
+    const PcgScalars* h = (const PcgScalars*)P->h_scalars;
+    *iters = h->iters;
+    if (h->breakdown) {
         P->last_error = "PCG breakdown: p^T q <= 0 or non-finite";
         return BA_ENUMERIC;
     }
-    for (auto& pr : marks) {
-        float ms = 0.0f;
-        BA_TRY(P, hipEventElapsedTime(&ms, pr.first, pr.second));
+    // matvecs run in order: the first `iters` marks timed real work
+    for (size_t u = 0; u < marks.size() && (int32_t)u < h->iters; ++u) {
+        float ms = 0.0f, hms = 0.0f;
+        BA_TRY(P, hipEventElapsedTime(&ms, marks[u][0], marks[u][1]));
+        BA_TRY(P, hipEventElapsedTime(&hms, marks[u][2], marks[u][3]));
         *matvec_ms += ms;
+        *hot_ms += hms;
         *launches += 1;
-    }
-    for (auto& pr : hot_marks) {
-        float ms = 0.0f;
-        BA_TRY(P, hipEventElapsedTime(&ms, pr.first, pr.second));
-        *hot_ms += ms;
     }
     if (tm) tm->used = 0;
     return BA_OK;
@@ -761,7 +754,7 @@ static ba_status lm_solve_t(ba_problem* P, const ba_options& o, ba_report* rep)
             break;
         }
         // dp = C~^-1 (w - E^T dc); trial state; F(x + dx); predicted decrease
-        BA_TRY(P, launch_pcg_direction<T>(m, true, P->x, P->p, (T*)P->pT, P->sc, s));
+        BA_TRY(P, launch_pcg_direction<T>(m, true, P->x, P->p, (T*)P->pT, P->sc, s));  // pT = (T) dc
         BA_TRY(P, launch_schur_tiles<T>(2, P->pm, nullptr, 0, P->N, (const T*)P->hcp, (const T*)P->cinv, P->wpt,
                                         (const T*)P->pT, nullptr, P->dp, s));
         BA_TRY(P, launch_trial_state(m, n, P->cams, P->x, P->pts, P->dp, P->cams_t, P->pts_t, s));
@@ -944,13 +937,11 @@ static ba_status schur_matvec_t(ba_problem* P, double lambda, int32_t damping, c
     for (int32_t j = 0; j < m; ++j)
         std::memcpy(&xi[(size_t)9 * j], x + (size_t)9 * P->old_of_new[j], 9 * sizeof(double));
     BA_TRY(P, hipMemcpyAsync(P->x, xi.data(), xi.size() * sizeof(double), hipMemcpyHostToDevice, s));
-    BA_TRY(P, launch_zero(P->sums, 1, s));
-    BA_TRY(P, launch_pcg_finish_scalars(P->sc, P->sums, 0, s));
+    BA_TRY(P, launch_pcg_reset(P->sc, 0.0, 1, 0, s));
     BA_TRY(P, launch_pcg_direction<T>(m, true, P->x, P->p, (T*)P->pT, P->sc, s));
-    int32_t nb = 0;
     BA_TRY(P, launch_schur_product<T>(0, P->sp, P->pm, P->N, (const T*)P->hcp, (const T*)P->cinv, P->wpt,
                                       (const T*)P->pT, m, P->bd, P->p, nullptr, P->q, nullptr, nullptr, P->partials,
-                                      &nb, P->sc, nullptr, nullptr, s));
+                                      P->sc, nullptr, nullptr, s));
     BA_TRY(P, hipMemcpyAsync(qi.data(), P->q, qi.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     BA_TRY(P, hipMemcpyAsync(P->h_scalars, P->flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     BA_TRY(P, hipStreamSynchronize(s));

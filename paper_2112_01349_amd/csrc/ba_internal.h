@@ -12,20 +12,45 @@ namespace ba {
 constexpr int kTile = 256;      // observations per point-aligned tile (one workgroup)
 constexpr int kCmRows = 32;     // rows of 64 observations per camera-major wave chunk
 constexpr int kCmChunk = 64 * kCmRows;
+constexpr int kColdRows = 8;    // rows of 64 observations per cold-stream wave chunk
+constexpr int kColdChunk = 64 * kColdRows;
 constexpr int kRedBlock = 256;  // threads of reduction blocks
 constexpr int kCamSlotWords = 54;  // 45 upper-triangle B terms + 9 v terms
 
-// Scalars of one PCG run, kept on the device.
+// Scalars of one PCG run, kept on the device.  Kernels of the PCG loop read
+// `done` first and do nothing once it is set, so the host can enqueue
+// iterations ahead and read the flag only now and then.
 struct PcgScalars {
-    double rho;       // r^T z of the current iteration
-    double rho_prev;  // r^T z of the previous iteration
-    double pq;        // p^T q
-    double rr;        // ||r||^2 after the last update
-    double bb;        // ||b||^2
+    double rho;         // r^T z of the current iteration
+    double rho_prev;    // r^T z of the previous iteration
+    double pq;          // p^T q
+    double rr;          // ||r||^2 of the current residual
+    double bb;          // ||b||^2
     double alpha, beta;
-    int32_t breakdown;  // set when p^T q <= 0 or non-finite; later updates are skipped
-    int32_t pad;
+    double rtol;        // stop when ||r|| <= rtol ||b|| ...
+    int32_t max_iters;  // ... or when this many matvecs ran
+    int32_t fixed;      // > 0: run exactly this many matvecs instead
+    int32_t iters;      // matvecs executed
+    int32_t done;       // loop finished (converged, count reached or breakdown)
+    int32_t breakdown;  // p^T q <= 0 or non-finite
+    uint32_t arrive[3]; // arrival counters of last-block reductions
 };
+
+// Last-block reduction: every block stores its partial sums, then the last
+// block to arrive (device-scope counter) adds all partials in block order.
+__device__ __forceinline__ bool last_block_arrives(uint32_t* counter)
+{
+    __shared__ bool last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t prev = atomicAdd(counter, 1u);
+        last = prev == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last) __threadfence();
+    return last;
+}
 
 // Point-major observation stream (sorted by point, then camera).
 struct PointMajor {
@@ -121,15 +146,17 @@ hipError_t launch_schur_tiles(int mode, const PointMajor& pm, const int32_t* til
                               const T* hcp, const T* cinv, const double* wpt, const T* xcam, double* cacc,
                               double* dp, hipStream_t s);
 
-// Full implicit Schur product (mode 0: out = q = B~ x - E C~^-1 E^T x with
-// partial p^T q; mode 1: out = g = v - E C~^-1 w, r = g, x = 0, partial
-// ||g||^2).  xcam: x in T (mode 0); pvec: x in FP64 (mode 0).
+// Full implicit Schur product.  mode 0: out = q = B~ x - E C~^-1 E^T x, then
+// p^T q, alpha and the matvec count into sc (skipped once sc->done);
+// mode 1: out = g = v - E C~^-1 w, r = g, x = 0 and ||g||^2 into sc.
+// xcam: x in T and pvec: x in FP64 (mode 0).  hot_begin/hot_end (nullable)
+// bracket the point-major pass.
 template <typename T>
 hipError_t launch_schur_product(int mode, const SchurPlan& sp, const PointMajor& pm, int64_t N, const T* hcp,
                                 const T* cinv, const double* wpt, const T* xcam, int32_t m, const double* bd,
                                 const double* pvec, const double* vcam, double* out, double* xvec, double* rvec,
-                                double* partials, int32_t* nblocks, const PcgScalars* sc, hipEvent_t hot_begin,
-                                hipEvent_t hot_end, hipStream_t s);
+                                double* partials, PcgScalars* sc, hipEvent_t hot_begin, hipEvent_t hot_end,
+                                hipStream_t s);
 template <typename T>
 size_t hot_lds_bytes(int32_t K);
 template <typename T>
@@ -138,21 +165,19 @@ template <typename T>
 hipError_t prepare_schur_kernels(int32_t K);
 
 hipError_t launch_zero(double* p, int64_t count, hipStream_t s);
-hipError_t launch_rhs_combine(int32_t m, const double* vcam, const double* cacc, double* g, double* x,
-                              double* r, double* partials, int32_t* nblocks, hipStream_t s);
 hipError_t launch_sum_partials(const double* partials, int32_t count, int32_t stride, int32_t ncols,
                                double* out, hipStream_t s);
-hipError_t launch_pcg_precond(int32_t m, const double* lfac, const double* r, double* z, double* partials,
-                              int32_t* nblocks, const PcgScalars* sc, hipStream_t s);
+// Resets the PCG scalars with the stopping rule of this run.
+hipError_t launch_pcg_reset(PcgScalars* sc, double rtol, int32_t max_iters, int32_t fixed, hipStream_t s);
+// One PCG step on the camera vectors: (unless first) x += alpha p, r -= alpha q;
+// z = M^-1 r; then rho, ||r||^2, the stopping test and beta (last block).
+hipError_t launch_pcg_step(int32_t m, bool first, const double* lfac, const double* p, const double* q,
+                           double* x, double* r, double* z, double* partials, PcgScalars* sc, hipStream_t s);
+// p = z (first iteration) or z + beta p; pT = (T) p.  With force, runs even
+// after the loop stopped (used to hand x to the back-substitution).
 template <typename T>
-hipError_t launch_pcg_direction(int32_t m, bool first, const double* z, double* p, T* pT, PcgScalars* sc,
+hipError_t launch_pcg_direction(int32_t m, bool force, const double* z, double* p, T* pT, PcgScalars* sc,
                                 hipStream_t s);
-hipError_t launch_matvec_combine(int32_t m, const double* bd, const double* p, const double* cacc, double* q,
-                                 double* partials, int32_t* nblocks, const PcgScalars* sc, hipStream_t s);
-hipError_t launch_pcg_update(int32_t m, const double* p, const double* q, double* x, double* r,
-                             double* partials, int32_t* nblocks, PcgScalars* sc, hipStream_t s);
-hipError_t launch_pcg_finish_scalars(PcgScalars* sc, const double* sums, int which, hipStream_t s);
-
 hipError_t launch_trial_state(int32_t m, int32_t n, const double* cams, const double* dc, const double* pts,
                               const double* dp, double* cams_t, double* pts_t, hipStream_t s);
 hipError_t launch_cost(const PointMajor& pm, int64_t N, const double* pts, const CamK<double>* ck,

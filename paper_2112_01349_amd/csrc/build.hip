@@ -204,6 +204,7 @@ template <bool GRAD_ONLY>
 __device__ __forceinline__ void flush_slot(double* acc, double* __restrict__ slots, int32_t slot, int lane)
 {
     constexpr int W = GRAD_ONLY ? 9 : kCamSlotWords;
+#pragma unroll
     for (int q = 0; q < W; ++q) {
         const double v = wave_sum(acc[q]);
         if (lane == 0) slots[(int64_t)slot * kCamSlotWords + q] = v;

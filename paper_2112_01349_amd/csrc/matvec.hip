@@ -80,9 +80,10 @@ __global__ __launch_bounds__(HotThreads<T>::value) void k_schur_hot(
     const int32_t* __restrict__ wtile, const int32_t* __restrict__ wrange, const int32_t* __restrict__ cam,
     const int32_t* __restrict__ pt, int64_t N, const T* __restrict__ hcp, const T* __restrict__ cinv,
     const double* __restrict__ wpt, const T* __restrict__ xcam, int32_t K, double* __restrict__ hot_part,
-    T* __restrict__ bcold, const uint8_t* __restrict__ has_cold)
+    T* __restrict__ bcold, const uint8_t* __restrict__ has_cold, const PcgScalars* __restrict__ sc)
 {
     constexpr int NT = HotThreads<T>::value;
+    if (MODE == 0 && sc->done) return;  // uniform over the grid
     extern __shared__ __align__(16) unsigned char smem[];
     double* cl = reinterpret_cast<double*>(smem);
     for (int q = threadIdx.x; q < K * 9; q += NT) cl[q] = 0.0;
@@ -230,24 +231,26 @@ __device__ __forceinline__ double wave_sum_d(double v)
 }
 
 // Cold observations, camera-major: c_k = E_k b_i, reduced per camera by wave
-// chunks of kCmChunk observations into slots (one per chunk and camera run).
+// chunks of kColdChunk observations into slots (one per chunk and camera run).
 template <typename T>
 __global__ __launch_bounds__(256) void k_schur_cold(int64_t Nc, int32_t num_chunks, const int32_t* __restrict__ ccam,
                                                     const int32_t* __restrict__ cpt, const T* __restrict__ chcp,
                                                     const T* __restrict__ bcold, const int32_t* __restrict__ chunk_slot,
-                                                    double* __restrict__ slots)
+                                                    double* __restrict__ slots, const PcgScalars* __restrict__ sc,
+                                                    int skip_if_done)
 {
+    if (skip_if_done && sc->done) return;
     const int lane = threadIdx.x & 63;
     const int32_t chunk = (int32_t)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
     if (chunk >= num_chunks) return;
-    const int64_t start = (int64_t)chunk * kCmChunk;
-    const int64_t end = start + kCmChunk < Nc ? start + kCmChunk : Nc;
+    const int64_t start = (int64_t)chunk * kColdChunk;
+    const int64_t end = start + kColdChunk < Nc ? start + kColdChunk : Nc;
     int32_t slot = chunk_slot[chunk];
     int32_t cur = ccam[start];
     double acc[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) acc[a] = 0.0;
-    for (int row = 0; row < kCmRows; ++row) {
+    for (int row = 0; row < kColdRows; ++row) {
         if (start + (int64_t)row * 64 >= end) break;
         const int64_t k = start + (int64_t)row * 64 + lane;
         const bool valid = k < end;
@@ -285,56 +288,56 @@ __global__ __launch_bounds__(256) void k_schur_cold(int64_t Nc, int32_t num_chun
     }
 }
 
-// q = B~ x - c (mode 0, partial p^T q) or g = v - c, r = g, x = 0 (mode 1,
-// partial ||g||^2); c from the hot partials and the cold slots.
-template <typename T, int MODE>
+// q = B~ x - c (mode 0) or g = v - c, r = g, x = 0 (mode 1); c from the hot
+// partials and the cold slots.  The last block adds the per-block partial sums:
+// mode 0: p^T q, then alpha = rho / p^T q and the matvec count (or a breakdown
+// when p^T q <= 0); mode 1: ||b||^2.
+template <int MODE>
 __global__ __launch_bounds__(kRedBlock) void k_schur_epilogue(
     int32_t m, int32_t K, int32_t G, const double* __restrict__ hot_part, const int32_t* __restrict__ cold_cam_slot,
     const double* __restrict__ cold_slots, const double* __restrict__ bd,
     const double* __restrict__ pvec, const double* __restrict__ vcam, double* __restrict__ out,
     double* __restrict__ xvec, double* __restrict__ rvec, double* __restrict__ partials,
-    const PcgScalars* __restrict__ sc)
+    PcgScalars* __restrict__ sc)
 {
     __shared__ double sh[kRedBlock / 64];
+    if (MODE == 0 && sc->done) return;  // uniform over the grid
     double acc = 0.0;
-    const bool skip = MODE == 0 && sc->breakdown;
     const int64_t len = 9 * (int64_t)m;
-    if (!skip) {
-        for (int64_t t = blockIdx.x * (int64_t)kRedBlock + threadIdx.x; t < len; t += (int64_t)gridDim.x * kRedBlock) {
-            const int64_t j = t / 9;
-            const int a = (int)(t - 9 * j);
-            double c = 0.0;
-            if (j < K) {
-                const int64_t stride = (int64_t)K * 9;
-                double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
-                int32_t w = 0;
-                for (; w + 4 <= G; w += 4) {
-                    c0 += hot_part[(int64_t)w * stride + t];
-                    c1 += hot_part[(int64_t)(w + 1) * stride + t];
-                    c2 += hot_part[(int64_t)(w + 2) * stride + t];
-                    c3 += hot_part[(int64_t)(w + 3) * stride + t];
-                }
-                for (; w < G; ++w) c0 += hot_part[(int64_t)w * stride + t];
-                c = (c0 + c1) + (c2 + c3);
-            } else {
-                for (int32_t s = cold_cam_slot[j]; s < cold_cam_slot[j + 1]; ++s) c += cold_slots[(int64_t)s * 9 + a];
+    for (int64_t t = blockIdx.x * (int64_t)kRedBlock + threadIdx.x; t < len; t += (int64_t)gridDim.x * kRedBlock) {
+        const int64_t j = t / 9;
+        const int a = (int)(t - 9 * j);
+        double c = 0.0;
+        if (j < K) {
+            const int64_t stride = (int64_t)K * 9;
+            double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+            int32_t w = 0;
+            for (; w + 4 <= G; w += 4) {
+                c0 += hot_part[(int64_t)w * stride + t];
+                c1 += hot_part[(int64_t)(w + 1) * stride + t];
+                c2 += hot_part[(int64_t)(w + 2) * stride + t];
+                c3 += hot_part[(int64_t)(w + 3) * stride + t];
             }
-            if (MODE == 0) {
-                const double* B = bd + 81 * j + 9 * a;
-                const double* pj = pvec + 9 * j;
-                double v = 0.0;
+            for (; w < G; ++w) c0 += hot_part[(int64_t)w * stride + t];
+            c = (c0 + c1) + (c2 + c3);
+        } else {
+            for (int32_t s = cold_cam_slot[j]; s < cold_cam_slot[j + 1]; ++s) c += cold_slots[(int64_t)s * 9 + a];
+        }
+        if (MODE == 0) {
+            const double* B = bd + 81 * j + 9 * a;
+            const double* pj = pvec + 9 * j;
+            double v = 0.0;
 #pragma unroll
-                for (int u = 0; u < 9; ++u) v += B[u] * pj[u];
-                v -= c;
-                out[t] = v;
-                acc += pvec[t] * v;
-            } else {
-                const double v = vcam[t] - c;
-                out[t] = v;
-                rvec[t] = v;
-                xvec[t] = 0.0;
-                acc += v * v;
-            }
+            for (int u = 0; u < 9; ++u) v += B[u] * pj[u];
+            v -= c;
+            out[t] = v;
+            acc += pvec[t] * v;
+        } else {
+            const double v = vcam[t] - c;
+            out[t] = v;
+            rvec[t] = v;
+            xvec[t] = 0.0;
+            acc += v * v;
         }
     }
     acc = wave_sum_d(acc);
@@ -344,6 +347,32 @@ __global__ __launch_bounds__(kRedBlock) void k_schur_epilogue(
         double s = 0.0;
         for (int w = 0; w < kRedBlock / 64; ++w) s += sh[w];
         partials[blockIdx.x] = s;
+    }
+    if (!last_block_arrives(&sc->arrive[MODE == 0 ? 1 : 2])) return;
+    double tot = 0.0;
+    for (int32_t b = threadIdx.x; b < (int32_t)gridDim.x; b += kRedBlock) tot += partials[b];
+    tot = wave_sum_d(tot);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < kRedBlock / 64; ++w) s += sh[w];
+        if (MODE == 0) {
+            sc->pq = s;
+            if (!(s > 0.0) || !isfinite(s)) {
+                sc->breakdown = 1;
+                sc->done = 1;
+            } else {
+                sc->alpha = sc->rho / s;
+            }
+            sc->iters = sc->iters + 1;
+            sc->arrive[1] = 0u;
+        } else {
+            sc->bb = s;
+            sc->rr = s;
+            sc->arrive[2] = 0u;
+        }
     }
 }
 
@@ -373,8 +402,8 @@ template <typename T>
 hipError_t launch_schur_product(int mode, const SchurPlan& sp, const PointMajor& pm, int64_t N, const T* hcp,
                                 const T* cinv, const double* wpt, const T* xcam, int32_t m, const double* bd,
                                 const double* pvec, const double* vcam, double* out, double* xvec, double* rvec,
-                                double* partials, int32_t* nblocks, const PcgScalars* sc, hipEvent_t hot_begin,
-                                hipEvent_t hot_end, hipStream_t s)
+                                double* partials, PcgScalars* sc, hipEvent_t hot_begin, hipEvent_t hot_end,
+                                hipStream_t s)
 {
     hipError_t e;
     const size_t lds = hot_lds_bytes<T>(sp.K);
@@ -383,27 +412,26 @@ hipError_t launch_schur_product(int mode, const SchurPlan& sp, const PointMajor&
         const dim3 g(sp.num_wg), b(HotThreads<T>::value);
         if (mode == 0)
             hipLaunchKernelGGL((k_schur_hot<T, 0>), g, b, lds, s, sp.wtile, sp.wrange, pm.cam, pm.pt, N, hcp, cinv,
-                               wpt, xcam, sp.K, (double*)sp.hot_part, (T*)sp.bcold, sp.has_cold);
+                               wpt, xcam, sp.K, (double*)sp.hot_part, (T*)sp.bcold, sp.has_cold, sc);
         else
             hipLaunchKernelGGL((k_schur_hot<T, 1>), g, b, lds, s, sp.wtile, sp.wrange, pm.cam, pm.pt, N, hcp, cinv,
-                               wpt, xcam, sp.K, (double*)sp.hot_part, (T*)sp.bcold, sp.has_cold);
+                               wpt, xcam, sp.K, (double*)sp.hot_part, (T*)sp.bcold, sp.has_cold, sc);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (hot_end && (e = hipEventRecord(hot_end, s)) != hipSuccess) return e;
     if (sp.cold.num_chunks > 0) {
         hipLaunchKernelGGL((k_schur_cold<T>), dim3((sp.cold.num_chunks + 3) / 4), dim3(256), 0, s, sp.cold.N,
                            sp.cold.num_chunks, sp.cold.cam, sp.cold.pt, (const T*)sp.cold.hcp, (const T*)sp.bcold,
-                           sp.cold.chunk_slot, sp.cold.slots);
+                           sp.cold.chunk_slot, sp.cold.slots, (const PcgScalars*)sc, mode == 0 ? 1 : 0);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    const int32_t b = reduce_blocks(9 * (int64_t)m);
-    *nblocks = b;
+    const int32_t nb = reduce_blocks(9 * (int64_t)m);
     if (mode == 0)
-        hipLaunchKernelGGL((k_schur_epilogue<T, 0>), dim3(b), dim3(kRedBlock), 0, s, m, sp.K, sp.num_wg,
+        hipLaunchKernelGGL((k_schur_epilogue<0>), dim3(nb), dim3(kRedBlock), 0, s, m, sp.K, sp.num_wg,
                            (const double*)sp.hot_part, sp.cold.cam_slot, sp.cold.slots, bd, pvec, vcam, out, xvec,
                            rvec, partials, sc);
     else
-        hipLaunchKernelGGL((k_schur_epilogue<T, 1>), dim3(b), dim3(kRedBlock), 0, s, m, sp.K, sp.num_wg,
+        hipLaunchKernelGGL((k_schur_epilogue<1>), dim3(nb), dim3(kRedBlock), 0, s, m, sp.K, sp.num_wg,
                            (const double*)sp.hot_part, sp.cold.cam_slot, sp.cold.slots, bd, pvec, vcam, out, xvec,
                            rvec, partials, sc);
     return hipGetLastError();
@@ -418,10 +446,10 @@ template hipError_t prepare_schur_kernels<double>(int32_t);
 template hipError_t launch_schur_product<float>(int, const SchurPlan&, const PointMajor&, int64_t, const float*,
                                                 const float*, const double*, const float*, int32_t, const double*,
                                                 const double*, const double*, double*, double*, double*, double*,
-                                                int32_t*, const PcgScalars*, hipEvent_t, hipEvent_t, hipStream_t);
+                                                PcgScalars*, hipEvent_t, hipEvent_t, hipStream_t);
 template hipError_t launch_schur_product<double>(int, const SchurPlan&, const PointMajor&, int64_t, const double*,
                                                  const double*, const double*, const double*, int32_t, const double*,
                                                  const double*, const double*, double*, double*, double*, double*,
-                                                 int32_t*, const PcgScalars*, hipEvent_t, hipEvent_t, hipStream_t);
+                                                 PcgScalars*, hipEvent_t, hipEvent_t, hipStream_t);
 
 }  // namespace ba

@@ -87,196 +87,143 @@ hipError_t launch_sum_partials(const double* partials, int32_t count, int32_t st
     return hipGetLastError();
 }
 
-// g = v - c; x = 0; r = g; partial ||g||^2
-__global__ __launch_bounds__(kRedBlock) void k_rhs_combine(int64_t len, const double* __restrict__ vcam,
-                                                           const double* __restrict__ cacc, double* __restrict__ g,
-                                                           double* __restrict__ x, double* __restrict__ r,
-                                                           double* __restrict__ partials)
+__global__ void k_pcg_reset(PcgScalars* __restrict__ sc, double rtol, int32_t max_iters, int32_t fixed)
 {
-    double acc = 0.0;
-    for (int64_t t = blockIdx.x * (int64_t)kRedBlock + threadIdx.x; t < len; t += (int64_t)gridDim.x * kRedBlock) {
-        const double v = vcam[t] - cacc[t];
-        g[t] = v;
-        r[t] = v;
-        x[t] = 0.0;
-        acc += v * v;
-    }
-    block_partials<1>(acc, 0.0, partials);
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    sc->rho = sc->rho_prev = sc->pq = sc->rr = sc->bb = sc->alpha = sc->beta = 0.0;
+    sc->rtol = rtol;
+    sc->max_iters = max_iters;
+    sc->fixed = fixed;
+    sc->iters = 0;
+    sc->done = 0;
+    sc->breakdown = 0;
+    sc->arrive[0] = sc->arrive[1] = sc->arrive[2] = 0u;
 }
 
-hipError_t launch_rhs_combine(int32_t m, const double* vcam, const double* cacc, double* g, double* x, double* r,
-                              double* partials, int32_t* nblocks, hipStream_t s)
+hipError_t launch_pcg_reset(PcgScalars* sc, double rtol, int32_t max_iters, int32_t fixed, hipStream_t s)
 {
-    const int64_t len = 9 * (int64_t)m;
-    const int32_t b = reduce_blocks(len);
-    *nblocks = b;
-    hipLaunchKernelGGL(k_rhs_combine, dim3(b), dim3(kRedBlock), 0, s, len, vcam, cacc, g, x, r, partials);
+    hipLaunchKernelGGL(k_pcg_reset, dim3(1), dim3(64), 0, s, sc, rtol, max_iters, fixed);
     return hipGetLastError();
 }
 
 __host__ __device__ constexpr int tri2(int r, int c) { return r * (r + 1) / 2 + c; }
 
-// z_j = (L L^T)^-1 r_j per camera; partials: r^T z and ||r||^2
-__global__ __launch_bounds__(kRedBlock) void k_pcg_precond(int32_t m, const double* __restrict__ lfac,
-                                                           const double* __restrict__ r, double* __restrict__ z,
-                                                           double* __restrict__ partials,
-                                                           const PcgScalars* __restrict__ sc)
+// One thread per camera: (unless first) x += alpha p, r -= alpha q on its 9
+// entries, then z = (L L^T)^-1 r with the camera block's Cholesky factor.
+// The last block adds rho = r^T z and ||r||^2 over all blocks and takes the
+// decision the next matvec depends on: stop (converged or count reached) or
+// continue with beta = rho / rho_prev.
+__global__ __launch_bounds__(kRedBlock) void k_pcg_step(int32_t m, int first, const double* __restrict__ lfac,
+                                                        const double* __restrict__ p, const double* __restrict__ q,
+                                                        double* __restrict__ x, double* __restrict__ r,
+                                                        double* __restrict__ z, double* __restrict__ partials,
+                                                        PcgScalars* __restrict__ sc)
 {
+    if (sc->done) return;  // uniform: nobody writes `done` while this kernel runs
+    const double alpha = first ? 0.0 : sc->alpha;
     double rz = 0.0, rr = 0.0;
-    if (!sc->breakdown) {
-        for (int32_t j = blockIdx.x * kRedBlock + threadIdx.x; j < m; j += gridDim.x * kRedBlock) {
-            const double* L = lfac + 45 * (int64_t)j;
-            double rj[9], y[9];
-            for (int a = 0; a < 9; ++a) rj[a] = r[9 * (int64_t)j + a];
-            for (int a = 0; a < 9; ++a) {
-                double v = rj[a];
-                for (int t = 0; t < a; ++t) v -= L[tri2(a, t)] * y[t];
-                y[a] = v / L[tri2(a, a)];
+    for (int32_t j = blockIdx.x * kRedBlock + threadIdx.x; j < m; j += gridDim.x * kRedBlock) {
+        const double* L = lfac + 45 * (int64_t)j;
+        double rj[9], y[9];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            const int64_t t = 9 * (int64_t)j + a;
+            double v = r[t];
+            if (!first) {
+                x[t] += alpha * p[t];
+                v -= alpha * q[t];
+                r[t] = v;
             }
-            for (int a = 8; a >= 0; --a) {
-                double v = y[a];
-                for (int t = a + 1; t < 9; ++t) v -= L[tri2(t, a)] * y[t];
-                y[a] = v / L[tri2(a, a)];
-            }
-            for (int a = 0; a < 9; ++a) {
-                z[9 * (int64_t)j + a] = y[a];
-                rz += rj[a] * y[a];
-                rr += rj[a] * rj[a];
-            }
+            rj[a] = v;
+        }
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            double v = rj[a];
+#pragma unroll
+            for (int t = 0; t < a; ++t) v -= L[tri2(a, t)] * y[t];
+            y[a] = v / L[tri2(a, a)];
+        }
+#pragma unroll
+        for (int a = 8; a >= 0; --a) {
+            double v = y[a];
+#pragma unroll
+            for (int t = a + 1; t < 9; ++t) v -= L[tri2(t, a)] * y[t];
+            y[a] = v / L[tri2(a, a)];
+        }
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            z[9 * (int64_t)j + a] = y[a];
+            rz += rj[a] * y[a];
+            rr += rj[a] * rj[a];
         }
     }
     block_partials<2>(rz, rr, partials);
+    if (!last_block_arrives(&sc->arrive[0])) return;
+    __shared__ double sh2[2][kRedBlock / 64];
+    double a = 0.0, b = 0.0;
+    for (int32_t t = threadIdx.x; t < (int32_t)gridDim.x; t += kRedBlock) {
+        a += partials[2 * (int64_t)t];
+        b += partials[2 * (int64_t)t + 1];
+    }
+    a = wave_sum64(a);
+    b = wave_sum64(b);
+    if ((threadIdx.x & 63) == 0) {
+        sh2[0][threadIdx.x >> 6] = a;
+        sh2[1][threadIdx.x >> 6] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double rho = 0.0, rrs = 0.0;
+        for (int w = 0; w < kRedBlock / 64; ++w) {
+            rho += sh2[0][w];
+            rrs += sh2[1][w];
+        }
+        const int32_t it = sc->iters;
+        sc->rr = rrs;
+        const bool stop = sc->fixed > 0 ? it >= sc->fixed
+                                        : (sqrt(rrs) <= sc->rtol * sqrt(sc->bb) || it >= sc->max_iters);
+        if (stop) {
+            sc->done = 1;
+        } else {
+            sc->beta = it == 0 ? 0.0 : rho / sc->rho;
+            sc->rho_prev = sc->rho;
+            sc->rho = rho;
+        }
+        sc->arrive[0] = 0u;
+    }
 }
 
-hipError_t launch_pcg_precond(int32_t m, const double* lfac, const double* r, double* z, double* partials,
-                              int32_t* nblocks, const PcgScalars* sc, hipStream_t s)
+hipError_t launch_pcg_step(int32_t m, bool first, const double* lfac, const double* p, const double* q, double* x,
+                           double* r, double* z, double* partials, PcgScalars* sc, hipStream_t s)
 {
     const int32_t b = reduce_blocks(m);
-    *nblocks = b;
-    hipLaunchKernelGGL(k_pcg_precond, dim3(b), dim3(kRedBlock), 0, s, m, lfac, r, z, partials, sc);
+    hipLaunchKernelGGL(k_pcg_step, dim3(b), dim3(kRedBlock), 0, s, m, first ? 1 : 0, lfac, p, q, x, r, z, partials, sc);
     return hipGetLastError();
 }
 
-// p = z (first) or z + beta p, beta = rho / rho_prev; pT = (T) p
+// p = z (first iteration) or z + beta p; pT = (T) p
 template <typename T>
-__global__ void k_pcg_direction(int64_t len, int first, const double* __restrict__ z, double* __restrict__ p,
-                                T* __restrict__ pT, PcgScalars* __restrict__ sc)
+__global__ void k_pcg_direction(int64_t len, int force, const double* __restrict__ z, double* __restrict__ p,
+                                T* __restrict__ pT, const PcgScalars* __restrict__ sc)
 {
-    if (sc->breakdown) return;
-    const double beta = first ? 0.0 : sc->rho / sc->rho_prev;
+    if (!force && sc->done) return;
+    const bool first = force || sc->iters == 0;
+    const double beta = first ? 0.0 : sc->beta;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < len; t += (int64_t)gridDim.x * blockDim.x) {
         const double v = first ? z[t] : z[t] + beta * p[t];
         p[t] = v;
         pT[t] = (T)v;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) sc->beta = beta;
 }
 
 template <typename T>
-hipError_t launch_pcg_direction(int32_t m, bool first, const double* z, double* p, T* pT, PcgScalars* sc,
+hipError_t launch_pcg_direction(int32_t m, bool force, const double* z, double* p, T* pT, PcgScalars* sc,
                                 hipStream_t s)
 {
     const int64_t len = 9 * (int64_t)m;
     int64_t b = (len + 255) / 256;
     if (b > 1024) b = 1024;
-    hipLaunchKernelGGL((k_pcg_direction<T>), dim3((unsigned)b), dim3(256), 0, s, len, first ? 1 : 0, z, p, pT, sc);
-    return hipGetLastError();
-}
-
-// q = B~ p - c; partial p^T q
-__global__ __launch_bounds__(kRedBlock) void k_matvec_combine(int32_t m, const double* __restrict__ bd,
-                                                              const double* __restrict__ p,
-                                                              const double* __restrict__ cacc, double* __restrict__ q,
-                                                              double* __restrict__ partials,
-                                                              const PcgScalars* __restrict__ sc)
-{
-    double acc = 0.0;
-    if (!sc->breakdown) {
-        const int64_t len = 9 * (int64_t)m;
-        for (int64_t t = blockIdx.x * (int64_t)kRedBlock + threadIdx.x; t < len; t += (int64_t)gridDim.x * kRedBlock) {
-            const int64_t j = t / 9;
-            const int a = (int)(t - 9 * j);
-            const double* B = bd + 81 * j + 9 * a;
-            const double* pj = p + 9 * j;
-            double v = 0.0;
-            for (int c = 0; c < 9; ++c) v += B[c] * pj[c];
-            v -= cacc[t];
-            q[t] = v;
-            acc += p[t] * v;
-        }
-    }
-    block_partials<1>(acc, 0.0, partials);
-}
-
-hipError_t launch_matvec_combine(int32_t m, const double* bd, const double* p, const double* cacc, double* q,
-                                 double* partials, int32_t* nblocks, const PcgScalars* sc, hipStream_t s)
-{
-    const int32_t b = reduce_blocks(9 * (int64_t)m);
-    *nblocks = b;
-    hipLaunchKernelGGL(k_matvec_combine, dim3(b), dim3(kRedBlock), 0, s, m, bd, p, cacc, q, partials, sc);
-    return hipGetLastError();
-}
-
-// alpha = rho / pq; x += alpha p; r -= alpha q; partial ||r||^2
-__global__ __launch_bounds__(kRedBlock) void k_pcg_update(int64_t len, const double* __restrict__ p,
-                                                          const double* __restrict__ q, double* __restrict__ x,
-                                                          double* __restrict__ r, double* __restrict__ partials,
-                                                          const PcgScalars* __restrict__ sc)
-{
-    double acc = 0.0;
-    if (!sc->breakdown) {
-        const double alpha = sc->rho / sc->pq;
-        for (int64_t t = blockIdx.x * (int64_t)kRedBlock + threadIdx.x; t < len; t += (int64_t)gridDim.x * kRedBlock) {
-            x[t] += alpha * p[t];
-            const double rn = r[t] - alpha * q[t];
-            r[t] = rn;
-            acc += rn * rn;
-        }
-    }
-    block_partials<1>(acc, 0.0, partials);
-}
-
-hipError_t launch_pcg_update(int32_t m, const double* p, const double* q, double* x, double* r, double* partials,
-                             int32_t* nblocks, PcgScalars* sc, hipStream_t s)
-{
-    const int64_t len = 9 * (int64_t)m;
-    const int32_t b = reduce_blocks(len);
-    *nblocks = b;
-    hipLaunchKernelGGL(k_pcg_update, dim3(b), dim3(kRedBlock), 0, s, len, p, q, x, r, partials, sc);
-    return hipGetLastError();
-}
-
-// Moves reduced sums into the scalar block.
-//   which 0: sums[0] = ||b||^2              -> bb, rr
-//   which 1: sums[0] = r^T z, sums[1] = ||r||^2 -> rho (rr unchanged)
-//   which 2: sums[0] = p^T q                -> pq; breakdown if <= 0 or non-finite
-//   which 3: sums[0] = ||r||^2 after update -> rr; rho_prev = rho
-__global__ void k_finish_scalars(PcgScalars* __restrict__ sc, const double* __restrict__ sums, int which)
-{
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    if (which == 0) {
-        sc->bb = sums[0];
-        sc->rr = sums[0];
-        sc->breakdown = 0;
-        sc->rho = sc->rho_prev = sc->pq = 0.0;
-    } else if (sc->breakdown) {
-        return;
-    } else if (which == 1) {
-        sc->rho = sums[0];
-    } else if (which == 2) {
-        const double pq = sums[0];
-        sc->pq = pq;
-        if (!(pq > 0.0) || !isfinite(pq)) sc->breakdown = 1;
-        else sc->alpha = sc->rho / pq;
-    } else {
-        sc->rr = sums[0];
-        sc->rho_prev = sc->rho;
-    }
-}
-
-hipError_t launch_pcg_finish_scalars(PcgScalars* sc, const double* sums, int which, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_finish_scalars, dim3(1), dim3(64), 0, s, sc, sums, which);
+    hipLaunchKernelGGL((k_pcg_direction<T>), dim3((unsigned)b), dim3(256), 0, s, len, force ? 1 : 0, z, p, pT, sc);
     return hipGetLastError();
 }
 
