@@ -77,6 +77,56 @@ def run_precision(prob_data, precision, wl, steps, warmup):
     return rep, wall
 
 
+def time_to_cost(rep, target):
+    """Wall time (ms) of the LM iterations until the accepted cost first
+    reaches `target`, or None."""
+    t = 0.0
+    for c, ms in zip(rep["cost"], rep["ms"]):
+        t += ms
+        if c <= target:
+            return t
+    return None
+
+
+def equal_cost_speedup(rep32, rep64):
+    """FP64 time / FP32-mixed time to reach the FP64 run's final cost
+    x (1 + 1e-4)."""
+    target = rep64["final_cost"] * (1 + 1e-4)
+    t64, t32 = time_to_cost(rep64, target), time_to_cost(rep32, target)
+    if t64 is None or t32 is None:
+        return None
+    return dict(target_cost=target, fp64_ms=t64, fp32_mixed_ms=t32, speedup=t64 / t32)
+
+
+def autograd_throughput(reps=5):
+    """Forward + backward of HuberReprojCost on the differentiation workload
+    (1,000 cameras, 200k points, 1M observations), observations per second."""
+    import torch
+
+    from paper_2112_01349_amd import Problem, synth
+    from paper_2112_01349_amd.autograd import HuberReprojCost
+
+    prob = synth.generate("diff", seed=0)
+    gpu = Problem(prob.cameras0, prob.points0, prob.obs_camera, prob.obs_point, prob.obs_uv, huber_delta=1.0)
+    out = {"workload": "diff: 1000 cameras, 200000 points, 1000000 observations, Huber delta=1"}
+    for name, dt in (("fp64", torch.float64), ("fp32", torch.float32)):
+        cams = torch.tensor(prob.cameras0, dtype=dt, device="cuda", requires_grad=True)
+        pts = torch.tensor(prob.points0, dtype=dt, device="cuda", requires_grad=True)
+        HuberReprojCost.apply(cams, pts, gpu).backward()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            cams.grad = None
+            pts.grad = None
+            HuberReprojCost.apply(cams, pts, gpu).backward()
+        torch.cuda.synchronize()
+        dt_s = (time.perf_counter() - t0) / reps
+        out[f"{name}_fwd_bwd_ms"] = 1e3 * dt_s
+        out[f"{name}_obs_per_s"] = prob.num_obs / dt_s
+    gpu.close()
+    return out
+
+
 def cpu_baseline(prob, wl, n_pcg):
     """The FP64 oracle on a bounded sample: the observations of the first
     points (about a quarter of the problem) with every camera, one LM iteration
@@ -106,6 +156,7 @@ def main():
     ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp64", type=int, default=1, help="also time the FP64 form")
+    ap.add_argument("--autograd", type=int, default=1, help="also time the autograd Function (1M observations)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (scale reference for HBM byte counters)")
     args = ap.parse_args()
@@ -184,6 +235,9 @@ def main():
         s64 = summary(*res["fp64"])
         out["fp64"] = s64
         out["mixed_speedup_lm"] = s32["lm_iter_per_s"] / s64["lm_iter_per_s"]
+        out["mixed_speedup_equal_cost"] = equal_cost_speedup(res["fp32_mixed"][0], res["fp64"][0])
+    if args.autograd:
+        out["autograd"] = autograd_throughput()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, wl, s32["pcg_iters"] / max(1, args.steps))
     print(json.dumps(out), flush=True)

@@ -358,6 +358,15 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     P->cm.num_slots = plan_slots(h_cm_cam, m, kCmChunk, chunk_slot, cam_slot);
     const int32_t num_chunks = (int32_t)chunk_slot.size() - 1;
     P->cm.num_chunks = num_chunks;
+    std::vector<int32_t> seg_cam, seg_slot, cam_seg((size_t)m + 1, 0);
+    for (int32_t j = 0; j < m; ++j) {
+        for (int32_t sl = cam_slot[j]; sl < cam_slot[(size_t)j + 1]; sl += kSlotSeg) {
+            seg_cam.push_back(j);
+            seg_slot.push_back(sl);
+        }
+        cam_seg[(size_t)j + 1] = (int32_t)seg_cam.size();
+    }
+    P->cm.num_segs = (int32_t)seg_cam.size();
 
     // Schur-product schedule: hot cameras held in LDS, persistent workgroups
     // over short tiles, long tiles apart, cold observations camera-major.
@@ -376,49 +385,22 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
         if (const char* env = std::getenv("BA_HOT_CAMERAS")) kmax = std::min(kmax, std::max(0, std::atoi(env)));
         sp.K = std::max(0, std::min(m, kmax));
     }
-    // wave tiles: whole points packed into <= 64 observations; a point with
-    // more observations is a tile of its own
-    std::vector<int32_t> wtiles;
-    wtiles.push_back(0);
-    {
-        int64_t cur = 0;
-        for (int32_t i = 0; i < n; ++i) {
-            const int64_t a = poff[i], b = poff[(size_t)i + 1];
-            if (b == a) continue;
-            if (b - cur > 64 && a > cur) {
-                wtiles.push_back((int32_t)a);
-                cur = a;
-            }
-            if (b - a > 64) {
-                wtiles.push_back((int32_t)b);
-                cur = b;
-            }
-        }
-        if (cur < N) wtiles.push_back((int32_t)N);
-    }
-    sp.num_wtiles = (int32_t)wtiles.size() - 1;
+    // line-aligned 64-observation tiles split evenly over the hot pass's wavefronts
+    P->pm.ld = (N + 63) / 64 * 64;
+    const int64_t ntiles64 = (N + 63) / 64;
     const int32_t waves_per_wg = P->is_f32() ? HotThreads<float>::value / 64 : HotThreads<double>::value / 64;
     sp.num_wg = 0;
-    if (sp.num_wtiles > 0)
-        sp.num_wg = std::max(1, std::min(std::max(1, cus), (sp.num_wtiles + waves_per_wg - 1) / waves_per_wg));
+    if (ntiles64 > 0)
+        sp.num_wg = (int32_t)std::max<int64_t>(1, std::min<int64_t>(std::max(1, cus),
+                                                                   (ntiles64 + waves_per_wg - 1) / waves_per_wg));
     const int32_t num_waves = sp.num_wg * waves_per_wg;
-    std::vector<int32_t> wrange((size_t)num_waves + 1, sp.num_wtiles);
-    {
-        // contiguous tile ranges of about equal work (a long tile is read twice)
-        std::vector<int64_t> work((size_t)sp.num_wtiles + 1, 0);
-        for (int32_t t = 0; t < sp.num_wtiles; ++t) {
-            const int64_t len = wtiles[(size_t)t + 1] - wtiles[t];
-            work[(size_t)t + 1] = work[t] + (len > 64 ? 2 * len : len) + 8;
-        }
-        const int64_t total = work[(size_t)sp.num_wtiles];
-        int32_t t = 0;
-        wrange[0] = 0;
-        for (int32_t w = 1; w < num_waves; ++w) {
-            const int64_t target = total * w / num_waves;
-            while (t < sp.num_wtiles && work[(size_t)t] < target) ++t;
-            wrange[(size_t)w] = t;
-        }
-    }
+    std::vector<int32_t> wrange((size_t)num_waves + 1, 0);
+    for (int32_t w = 0; w <= num_waves; ++w) wrange[(size_t)w] = (int32_t)((int64_t)w * ntiles64 / num_waves);
+    // the build: 32 wavefronts per CU over the same tiles
+    P->pm.build_waves = (int32_t)std::min<int64_t>(ntiles64, (int64_t)std::max(1, cus) * 32);
+    std::vector<int32_t> build_wrange((size_t)P->pm.build_waves + 1, 0);
+    for (int32_t w = 0; w <= P->pm.build_waves; ++w)
+        build_wrange[(size_t)w] = (int32_t)((int64_t)w * ntiles64 / std::max(1, P->pm.build_waves));
     // cold stream: observations on cameras >= K, camera-major
     std::vector<int32_t> cold_pos((size_t)N, -1), h_cold_cam, h_cold_pt;
     std::vector<uint8_t> has_cold((size_t)(n > 0 ? n : 1), 0);
@@ -433,8 +415,8 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     sp.cold.N = (int64_t)h_cold_cam.size();
     if (std::getenv("BA_VERBOSE"))
         std::fprintf(stderr,
-                     "[ba] m=%d n=%d N=%lld cus=%d lds/block=%d hot K=%d wg=%d wave tiles=%d cold obs=%lld (%.2f%%)\n",
-                     m, n, (long long)N, cus, lds_limit, sp.K, sp.num_wg, sp.num_wtiles, (long long)sp.cold.N,
+                     "[ba] m=%d n=%d N=%lld cus=%d lds/block=%d hot K=%d wg=%d tiles=%lld cold obs=%lld (%.2f%%)\n",
+                     m, n, (long long)N, cus, lds_limit, sp.K, sp.num_wg, (long long)ntiles64, (long long)sp.cold.N,
                      N > 0 ? 100.0 * (double)sp.cold.N / (double)N : 0.0);
     std::vector<int32_t> cold_chunk_slot, cold_cam_slot;
     sp.cold.num_slots = plan_slots(h_cold_cam, m, kColdChunk, cold_chunk_slot, cold_cam_slot);
@@ -456,6 +438,7 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     P->pm.uvx = A.get<double>(N);
     P->pm.uvy = A.get<double>(N);
     P->pm.tile = A.get<int32_t>((int64_t)tiles.size());
+    P->pm.build_wrange = A.get<int32_t>((int64_t)build_wrange.size());
     P->cm.cam = A.get<int32_t>(N);
     P->cm.pt = A.get<int32_t>(N);
     P->cm.uvx = A.get<double>(N);
@@ -463,7 +446,12 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     P->cm.chunk_slot = A.get<int32_t>((int64_t)num_chunks + 1);
     P->cm.cam_slot = A.get<int32_t>((int64_t)m + 1);
     P->cm.slots = A.get<double>((int64_t)P->cm.num_slots * kCamSlotWords);
-    P->hcp = A.get<char>(27 * N * (int64_t)tsz);
+    P->cm.seg_cam = A.get<int32_t>(P->cm.num_segs);
+    P->cm.seg_slot = A.get<int32_t>(P->cm.num_segs);
+    P->cm.cam_seg = A.get<int32_t>((int64_t)m + 1);
+    P->cm.seg_part = A.get<double>((int64_t)P->cm.num_segs * kCamSlotWords);
+    P->cm.arrive = A.get<uint32_t>(m);
+    P->hcp = A.get<char>(27 * P->pm.ld * (int64_t)tsz);
     P->hpp = A.get<char>(6 * (int64_t)n * (int64_t)tsz);
     P->cinv = A.get<char>(6 * (int64_t)n * (int64_t)tsz);
     P->wpt = A.get<double>(3 * (int64_t)n);
@@ -474,11 +462,11 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     P->dcam = A.get<double>(9 * (int64_t)m);
     for (double** v : {&P->g, &P->x, &P->r, &P->z, &P->p, &P->q, &P->cacc}) *v = A.get<double>(9 * (int64_t)m);
     P->pT = A.get<char>(9 * (int64_t)m * (int64_t)tsz);
-    sp.wtile = A.get<int32_t>((int64_t)wtiles.size());
     sp.wrange = A.get<int32_t>((int64_t)wrange.size());
     sp.has_cold = A.get<uint8_t>(n);
     sp.cold_pos = A.get<int32_t>(N);
     sp.hot_part = A.get<double>((int64_t)sp.num_wg * sp.K * 9);
+    sp.hot_fold = A.get<double>((int64_t)kHotFold * sp.K * 9);
     sp.bcold = A.get<char>(3 * (int64_t)n * (int64_t)tsz);
     sp.cold.cam = A.get<int32_t>(sp.cold.N);
     sp.cold.pt = A.get<int32_t>(sp.cold.N);
@@ -515,13 +503,19 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     if (e == hipSuccess) e = up(P->pm.uvx, h_uvx.data(), sizeof(double) * N);
     if (e == hipSuccess) e = up(P->pm.uvy, h_uvy.data(), sizeof(double) * N);
     if (e == hipSuccess) e = up(P->pm.tile, tiles.data(), sizeof(int32_t) * tiles.size());
+    if (e == hipSuccess) e = up(P->pm.build_wrange, build_wrange.data(), sizeof(int32_t) * build_wrange.size());
     if (e == hipSuccess) e = up(P->cm.cam, h_cm_cam.data(), sizeof(int32_t) * N);
     if (e == hipSuccess) e = up(P->cm.pt, h_cm_pt.data(), sizeof(int32_t) * N);
     if (e == hipSuccess) e = up(P->cm.uvx, h_cm_uvx.data(), sizeof(double) * N);
     if (e == hipSuccess) e = up(P->cm.uvy, h_cm_uvy.data(), sizeof(double) * N);
     if (e == hipSuccess) e = up(P->cm.chunk_slot, chunk_slot.data(), sizeof(int32_t) * chunk_slot.size());
     if (e == hipSuccess) e = up(P->cm.cam_slot, cam_slot.data(), sizeof(int32_t) * cam_slot.size());
-    if (e == hipSuccess) e = up(sp.wtile, wtiles.data(), sizeof(int32_t) * wtiles.size());
+    if (e == hipSuccess) e = up(P->cm.seg_cam, seg_cam.data(), sizeof(int32_t) * seg_cam.size());
+    if (e == hipSuccess) e = up(P->cm.seg_slot, seg_slot.data(), sizeof(int32_t) * seg_slot.size());
+    if (e == hipSuccess) e = up(P->cm.cam_seg, cam_seg.data(), sizeof(int32_t) * cam_seg.size());
+    if (e == hipSuccess) e = hipMemset(P->cm.arrive, 0, sizeof(uint32_t) * (size_t)m);
+    if (e == hipSuccess) e = hipMemset(P->hcc, 0, sizeof(double) * 81 * (size_t)m);
+    if (e == hipSuccess) e = hipMemset(P->vcam, 0, sizeof(double) * 9 * (size_t)m);
     if (e == hipSuccess) e = up(sp.wrange, wrange.data(), sizeof(int32_t) * wrange.size());
     if (e == hipSuccess) e = up(sp.has_cold, has_cold.data(), (size_t)n);
     if (e == hipSuccess) e = up(sp.cold_pos, cold_pos.data(), sizeof(int32_t) * N);
@@ -639,7 +633,7 @@ struct PcgTimer {
 };
 
 // PCG on the reduced camera system (Alg. 2, one partition); dc = x.  The
-// stopping test runs on the device before every matvec (as in the oracle);
+// stopping test runs on the device before every matvec (the loop test of Alg. 2);
 // the host enqueues iterations in batches and reads the `done` flag between
 // batches.  With a fixed count everything is enqueued at once.
 template <typename T>
@@ -755,7 +749,7 @@ static ba_status lm_solve_t(ba_problem* P, const ba_options& o, ba_report* rep)
         }
         // dp = C~^-1 (w - E^T dc); trial state; F(x + dx); predicted decrease
         BA_TRY(P, launch_pcg_direction<T>(m, true, P->x, P->p, (T*)P->pT, P->sc, s));  // pT = (T) dc
-        BA_TRY(P, launch_schur_tiles<T>(2, P->pm, nullptr, 0, P->N, (const T*)P->hcp, (const T*)P->cinv, P->wpt,
+        BA_TRY(P, launch_schur_tiles<T>(2, P->pm, nullptr, 0, P->pm.ld, (const T*)P->hcp, (const T*)P->cinv, P->wpt,
                                         (const T*)P->pT, nullptr, P->dp, s));
         BA_TRY(P, launch_trial_state(m, n, P->cams, P->x, P->pts, P->dp, P->cams_t, P->pts_t, s));
         BA_TRY(P, launch_camera_constants_f64(m, P->cams_t, P->ck64_t, s));

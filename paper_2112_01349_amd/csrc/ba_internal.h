@@ -16,6 +16,8 @@ constexpr int kColdRows = 8;    // rows of 64 observations per cold-stream wave 
 constexpr int kColdChunk = 64 * kColdRows;
 constexpr int kRedBlock = 256;  // threads of reduction blocks
 constexpr int kCamSlotWords = 54;  // 45 upper-triangle B terms + 9 v terms
+constexpr int kSlotSeg = 32;       // slots summed by one wavefront before the per-camera combine
+constexpr int kHotFold = 8;        // slices the per-workgroup hot partials are folded into
 
 // Scalars of one PCG run, kept on the device.  Kernels of the PCG loop read
 // `done` first and do nothing once it is set, so the host can enqueue
@@ -60,6 +62,10 @@ struct PointMajor {
     double* uvy;       // [N]
     int32_t* tile;     // [num_tiles + 1] observation offsets of point-aligned tiles
     int32_t num_tiles;
+    int64_t ld;        // leading dimension of the [27][ld] coupling-block streams
+                       // (N rounded up to 64, so 64-observation tiles are line-aligned)
+    int32_t build_waves;      // wavefronts of the point-major build
+    int32_t* build_wrange;    // [build_waves + 1] ranges of 64-observation tiles
 };
 
 // Camera-major observation stream (sorted by camera, then point).
@@ -73,6 +79,13 @@ struct CameraMajor {
     int32_t num_chunks;
     int32_t num_slots;
     double* slots;        // [num_slots][54]
+    // per-camera reduction of the slots in segments of <= kSlotSeg
+    int32_t num_segs;
+    int32_t* seg_cam;     // [num_segs] camera of each segment
+    int32_t* seg_slot;    // [num_segs] first slot of each segment
+    int32_t* cam_seg;     // [m + 1] segments of each camera (contiguous)
+    double* seg_part;     // [num_segs][54]
+    uint32_t* arrive;     // [m] arrival counters (zero between calls)
 };
 
 // Threads per workgroup of the hot-camera Schur pass (one workgroup per CU).
@@ -104,13 +117,12 @@ struct ColdStream {
 struct SchurPlan {
     int32_t K = 0;                  // hot cameras: internal ids [0, K)
     int32_t num_wg = 0;             // persistent workgroups of the hot pass
-    int32_t num_wtiles = 0;         // point-aligned wave tiles
-    int32_t* wtile = nullptr;       // [num_wtiles + 1] observation offsets; a tile is
-                                    // whole points (<= 64 obs) or one longer point
-    int32_t* wrange = nullptr;      // [num_wg * waves per workgroup + 1] tile ranges per wave
+    int32_t* wrange = nullptr;      // [num_wg * waves per workgroup + 1] ranges of 64-observation
+                                    // tiles per wavefront
     uint8_t* has_cold = nullptr;    // [n] point has an observation in the cold stream
     int32_t* cold_pos = nullptr;    // [N] point-major observation -> cold index or -1
     void* hot_part = nullptr;       // [num_wg][K][9] FP64
+    double* hot_fold = nullptr;     // [kHotFold][K][9] FP64
     void* bcold = nullptr;          // [n][3] of T
     ColdStream cold;
 };

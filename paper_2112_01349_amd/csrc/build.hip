@@ -4,11 +4,12 @@
 //
 // Two passes over the observations, each with its own sorted copy of the
 // index and pixel streams:
-//   * point-major (k_build_points): one workgroup per point-aligned tile of
-//     <= 256 observations, one lane per observation.  Writes the coupling
-//     block E_k = w J_c^T J_p of every observation as 27 coalesced streams
-//     [27][N], and reduces the point blocks C_i = sum w J_p^T J_p and
-//     w_i = -sum w J_p^T e over the point's contiguous segment in LDS.
+//   * point-major (k_build_points): wavefronts over line-aligned tiles of 64
+//     observations, one lane per observation.  Writes the coupling block
+//     E_k = w J_c^T J_p of every observation as 27 coalesced streams [27][ld]
+//     (ld = N rounded up to 64), and forms the point blocks
+//     C_i = sum w J_p^T J_p and w_i = -sum w J_p^T e by a segmented scan over
+//     the point's contiguous segment.
 //   * camera-major (k_build_cameras): one wavefront per contiguous chunk of
 //     2048 observations sorted by camera.  Lanes accumulate the camera terms
 //     B_j = sum w J_c^T J_c and v_j = -sum w J_c^T e in registers while the
@@ -86,92 +87,100 @@ __device__ __forceinline__ void store_coupling(int64_t k, int64_t N, const T Jc[
             hcp[(int64_t)(a * 3 + b) * N + k] = wt * (Jc[a] * Jp[b] + Jc[9 + a] * Jp[3 + b]);
 }
 
+__device__ __forceinline__ double shfl_up_d(double v, int off) { return __shfl_up(v, off, 64); }
+
+// Point-major build over line-aligned 64-observation tiles, one wavefront
+// per contiguous range of tiles (the ownership and carry scheme of the Schur
+// pass): every lane computes its observation's residual and Jacobian, stores
+// E_k (and its cold copy), and the point sums C_i, w_i are formed by a
+// segmented scan over shuffles, carried across tiles, and written by the
+// point's last lane.
 template <typename T, bool GRAD_ONLY>
-__global__ __launch_bounds__(kTile) void k_build_points(
-    const int32_t* __restrict__ tile, const int32_t* __restrict__ cam, const int32_t* __restrict__ pt,
+__global__ __launch_bounds__(256) void k_build_points(
+    int32_t num_waves, const int32_t* __restrict__ wrange, int64_t N, const int32_t* __restrict__ cam,
+    const int32_t* __restrict__ pt,
     const double* __restrict__ uvx, const double* __restrict__ uvy, const double* __restrict__ pts,
-    const CamK<T>* __restrict__ ck, T delta, int64_t N, T* __restrict__ hcp, T* __restrict__ hpp,
+    const CamK<T>* __restrict__ ck, T delta, int64_t ld, T* __restrict__ hcp, T* __restrict__ hpp,
     double* __restrict__ wpt, const int32_t* __restrict__ cold_pos, int64_t Nc, T* __restrict__ chcp)
 {
-    __shared__ double sh[9][kTile];
-    __shared__ int32_t shpt[kTile];
-    const int tid = threadIdx.x;
-    const int32_t s = tile[blockIdx.x], e = tile[blockIdx.x + 1];
-    const int32_t len = e - s;
-    if (len <= kTile) {
-        const bool valid = tid < len;
-        int32_t i = -1;
-        if (valid) {
-            const int64_t k = s + tid;
+    const int lane = threadIdx.x & 63;
+    const int32_t gw = (int32_t)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
+    if (gw >= num_waves) return;  // the grid rounds the wavefront count up to whole blocks
+    const int64_t T0 = wrange[gw], T1 = wrange[gw + 1];
+    if (T0 >= T1) return;  // no barriers in this kernel
+    const int64_t ntiles = (N + 63) >> 6;
+    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+    const int32_t skip_pt = T0 > 0 ? pt[64 * T0 - 1] : -1;  // owned by the previous wavefront
+    int32_t carry_pt = -1;
+    double cr[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) cr[q] = 0.0;
+    for (int64_t t = T0; t < ntiles && (t < T1 || carry_pt >= 0); ++t) {
+        const int64_t k = 64 * t + lane;
+        const bool valid = k < N;
+        const int32_t i = valid ? pt[k] : -1;
+        const bool owned = valid && (t < T1 ? i != skip_pt : i == carry_pt);
+        const uint64_t om = __ballot(owned);
+        if (om == 0) {
+            if (t >= T1) break;  // past the range: the carried point has ended
+            continue;            // a tile inside the previous wavefront's last point
+        }
+        double v[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) v[q] = 0.0;
+        if (owned) {
             T e0, e1, wt, Jc[18], Jp[6];
-            observation<T>(k, cam, pt, uvx, uvy, pts, ck, delta, e0, e1, wt, Jc, Jp, i);
+            int32_t ii;
+            observation<T>(k, cam, pt, uvx, uvy, pts, ck, delta, e0, e1, wt, Jc, Jp, ii);
             if (!GRAD_ONLY) {
-                store_coupling<T>(k, N, Jc, Jp, wt, hcp);
+                store_coupling<T>(k, ld, Jc, Jp, wt, hcp);
                 if (cold_pos) {
                     const int32_t c = cold_pos[k];
                     if (c >= 0) store_coupling<T>(c, Nc, Jc, Jp, wt, chcp);
                 }
             }
-            double t[9];
-            point_terms<T>(Jp, e0, e1, wt, t);
-#pragma unroll
-            for (int q = 0; q < 9; ++q) sh[q][tid] = t[q];
+            point_terms<T>(Jp, e0, e1, wt, v);
         }
-        shpt[tid] = i;
-        __syncthreads();
-        if (valid && (tid == 0 || shpt[tid - 1] != i)) {
-            double acc[9];
+        const int32_t prev_i = __shfl_up(i, 1, 64);
+        const int prev_own = __shfl_up(owned ? 1 : 0, 1, 64);
+        const bool head = owned && (lane == 0 || !prev_own || prev_i != i);
+        const uint64_t hm = __ballot(head);
+        const int seg_s = 63 - __clzll((hm & upto) | 1ull);
+        const int last_owned = 63 - __clzll(om);
+        const uint64_t above = hm & ~upto;
+        const int seg_e = above ? __ffsll((unsigned long long)above) - 2 : last_owned;
+        const int first_head = __ffsll((unsigned long long)hm) - 1;
+        const int last_head = 63 - __clzll(hm);
+        const int32_t i_first = __shfl(i, first_head, 64);
+        const int32_t i_last = __shfl(i, last_owned, 64);
+        const bool cont = carry_pt >= 0 && i_first == carry_pt;
+        const bool last_inc = last_owned == 63 && t + 1 < ntiles && pt[64 * (t + 1)] == i_last;
 #pragma unroll
-            for (int q = 0; q < 9; ++q) acc[q] = 0.0;
-            for (int u = tid; u < len && shpt[u] == i; ++u)
+        for (int off = 1; off < 64; off <<= 1) {
+            const bool take = lane - off >= seg_s;
 #pragma unroll
-                for (int q = 0; q < 9; ++q) acc[q] += sh[q][u];
-            if (!GRAD_ONLY)
-#pragma unroll
-                for (int q = 0; q < 6; ++q) hpp[6 * (int64_t)i + q] = (T)acc[q];
-#pragma unroll
-            for (int q = 0; q < 3; ++q) wpt[3 * (int64_t)i + q] = acc[6 + q];
-        }
-    } else {
-        // one point with more than kTile observations: chunked, fixed-order reduction
-        double acc[9];
-#pragma unroll
-        for (int q = 0; q < 9; ++q) acc[q] = 0.0;
-        int32_t i = pt[s];
-        for (int32_t base = s; base < e; base += kTile) {
-            const int64_t k = base + tid;
-            if (k < e) {
-                T e0, e1, wt, Jc[18], Jp[6];
-                int32_t ii;
-                observation<T>(k, cam, pt, uvx, uvy, pts, ck, delta, e0, e1, wt, Jc, Jp, ii);
-                if (!GRAD_ONLY) {
-                    store_coupling<T>(k, N, Jc, Jp, wt, hcp);
-                    if (cold_pos) {
-                        const int32_t c = cold_pos[k];
-                        if (c >= 0) store_coupling<T>(c, Nc, Jc, Jp, wt, chcp);
-                    }
-                }
-                double t[9];
-                point_terms<T>(Jp, e0, e1, wt, t);
-#pragma unroll
-                for (int q = 0; q < 9; ++q) acc[q] += t[q];
+            for (int q = 0; q < 9; ++q) {
+                const double u = shfl_up_d(v[q], off);
+                if (take) v[q] += u;
             }
         }
+        if (cont && seg_s == first_head)
 #pragma unroll
-        for (int q = 0; q < 9; ++q) sh[q][tid] = acc[q];
-        __syncthreads();
-        for (int stride = kTile / 2; stride > 0; stride >>= 1) {
-            if (tid < stride)
-#pragma unroll
-                for (int q = 0; q < 9; ++q) sh[q][tid] += sh[q][tid + stride];
-            __syncthreads();
-        }
-        if (tid == 0) {
+            for (int q = 0; q < 9; ++q) v[q] += cr[q];
+        // lane seg_e now holds its point's running total
+        if (owned && lane == seg_e && !(last_inc && seg_s == last_head)) {
             if (!GRAD_ONLY)
 #pragma unroll
-                for (int q = 0; q < 6; ++q) hpp[6 * (int64_t)i + q] = (T)sh[q][0];
+                for (int q = 0; q < 6; ++q) hpp[6 * (int64_t)i + q] = (T)v[q];
 #pragma unroll
-            for (int q = 0; q < 3; ++q) wpt[3 * (int64_t)i + q] = sh[6 + q][0];
+            for (int q = 0; q < 3; ++q) wpt[3 * (int64_t)i + q] = v[6 + q];
+        }
+        if (last_inc) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) cr[q] = __shfl(v[q], 63, 64);
+            carry_pt = i_last;
+        } else {
+            carry_pt = -1;
         }
     }
 }
@@ -181,14 +190,14 @@ hipError_t launch_build_points(const PointMajor& pm, int64_t N, const double* pt
                                double delta, bool grad_only, T* hcp, T* hpp, double* wpt,
                                const int32_t* cold_pos, int64_t Nc, T* chcp, hipStream_t s)
 {
-    if (pm.num_tiles <= 0) return hipGetLastError();
+    if (pm.build_waves <= 0 || N <= 0) return hipGetLastError();
+    const dim3 g((pm.build_waves + 3) / 4), b(256);
     if (grad_only)
-        hipLaunchKernelGGL((k_build_points<T, true>), dim3(pm.num_tiles), dim3(kTile), 0, s, pm.tile, pm.cam,
-                           pm.pt, pm.uvx, pm.uvy, pts, ck, (T)delta, N, hcp, hpp, wpt, nullptr, (int64_t)0,
-                           (T*)nullptr);
+        hipLaunchKernelGGL((k_build_points<T, true>), g, b, 0, s, pm.build_waves, pm.build_wrange, N, pm.cam, pm.pt,
+                           pm.uvx, pm.uvy, pts, ck, (T)delta, pm.ld, hcp, hpp, wpt, nullptr, (int64_t)0, (T*)nullptr);
     else
-        hipLaunchKernelGGL((k_build_points<T, false>), dim3(pm.num_tiles), dim3(kTile), 0, s, pm.tile, pm.cam,
-                           pm.pt, pm.uvx, pm.uvy, pts, ck, (T)delta, N, hcp, hpp, wpt, cold_pos, Nc, chcp);
+        hipLaunchKernelGGL((k_build_points<T, false>), g, b, 0, s, pm.build_waves, pm.build_wrange, N, pm.cam, pm.pt,
+                           pm.uvx, pm.uvy, pts, ck, (T)delta, pm.ld, hcp, hpp, wpt, cold_pos, Nc, chcp);
     return hipGetLastError();
 }
 
@@ -265,21 +274,45 @@ __global__ __launch_bounds__(256) void k_build_cameras(
     flush_slot<GRAD_ONLY>(acc, slots, slot, lane);
 }
 
-// One wavefront per camera sums its slots in order (deterministic).
+// One wavefront per segment of <= kSlotSeg consecutive slots of one camera
+// (lanes = the 54 terms).  A camera with one segment is written directly;
+// otherwise the last of its segments to finish (device-scope counter) adds
+// the segment sums in segment order, so the result is deterministic.
 template <bool GRAD_ONLY>
-__global__ __launch_bounds__(256) void k_reduce_slots(int32_t m, const int32_t* __restrict__ cam_slot,
-                                                      const double* __restrict__ slots, double* __restrict__ hcc,
-                                                      double* __restrict__ vcam)
+__global__ __launch_bounds__(256) void k_reduce_slots(int32_t num_segs, const int32_t* __restrict__ seg_cam,
+                                                      const int32_t* __restrict__ seg_slot,
+                                                      const int32_t* __restrict__ cam_slot,
+                                                      const int32_t* __restrict__ cam_seg,
+                                                      const double* __restrict__ slots,
+                                                      double* __restrict__ seg_part, uint32_t* __restrict__ arrive,
+                                                      double* __restrict__ hcc, double* __restrict__ vcam)
 {
     const int lane = threadIdx.x & 63;
-    const int32_t j = (int32_t)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
-    if (j >= m) return;
-    const int32_t s0 = cam_slot[j], s1 = cam_slot[j + 1];
-    const int q = GRAD_ONLY ? 45 + lane : lane;
-    if (q >= kCamSlotWords) return;
+    const int32_t sg = (int32_t)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
+    if (sg >= num_segs) return;
+    const int32_t j = seg_cam[sg];
+    const int32_t s0 = seg_slot[sg];
+    const int32_t s1 = min(s0 + kSlotSeg, cam_slot[j + 1]);
+    const int W = GRAD_ONLY ? 9 : kCamSlotWords;
     double acc = 0.0;
-    const int col = GRAD_ONLY ? lane : q;
-    for (int32_t sl = s0; sl < s1; ++sl) acc += slots[(int64_t)sl * kCamSlotWords + col];
+    if (lane < W)
+        for (int32_t sl = s0; sl < s1; ++sl) acc += slots[(int64_t)sl * kCamSlotWords + lane];
+    const int32_t g0 = cam_seg[j], g1 = cam_seg[j + 1];
+    if (g1 - g0 > 1) {
+        if (lane < W) seg_part[(int64_t)sg * kCamSlotWords + lane] = acc;
+        __threadfence();
+        uint32_t prev = 0;
+        if (lane == 0) prev = atomicAdd(arrive + j, 1u);
+        prev = __shfl(prev, 0, 64);
+        if (prev != (uint32_t)(g1 - g0 - 1)) return;
+        __threadfence();
+        acc = 0.0;
+        if (lane < W)
+            for (int32_t g = g0; g < g1; ++g) acc += seg_part[(int64_t)g * kCamSlotWords + lane];
+        if (lane == 0) arrive[j] = 0u;
+    }
+    if (lane >= W) return;
+    const int q = GRAD_ONLY ? 45 + lane : lane;
     if (q < 45) {
         // upper-triangle index q -> (a, b), a <= b
         int a = 0, rem = q;
@@ -308,14 +341,14 @@ hipError_t launch_build_cameras(const CameraMajor& cm, int32_t m, int64_t N, con
             hipLaunchKernelGGL((k_build_cameras<T, false>), dim3(blocks), dim3(256), 0, s, N, cm.num_chunks,
                                cm.cam, cm.pt, cm.uvx, cm.uvy, pts, ck, (T)delta, cm.chunk_slot, cm.slots);
     }
-    const int blocks = (m + 3) / 4;
-    if (m > 0) {
+    if (cm.num_segs > 0) {
+        const int blocks = (cm.num_segs + 3) / 4;
         if (grad_only)
-            hipLaunchKernelGGL((k_reduce_slots<true>), dim3(blocks), dim3(256), 0, s, m, cm.cam_slot, cm.slots, hcc,
-                               vcam);
+            hipLaunchKernelGGL((k_reduce_slots<true>), dim3(blocks), dim3(256), 0, s, cm.num_segs, cm.seg_cam,
+                               cm.seg_slot, cm.cam_slot, cm.cam_seg, cm.slots, cm.seg_part, cm.arrive, hcc, vcam);
         else
-            hipLaunchKernelGGL((k_reduce_slots<false>), dim3(blocks), dim3(256), 0, s, m, cm.cam_slot, cm.slots, hcc,
-                               vcam);
+            hipLaunchKernelGGL((k_reduce_slots<false>), dim3(blocks), dim3(256), 0, s, cm.num_segs, cm.seg_cam,
+                               cm.seg_slot, cm.cam_slot, cm.cam_seg, cm.slots, cm.seg_part, cm.arrive, hcc, vcam);
     }
     return hipGetLastError();
 }

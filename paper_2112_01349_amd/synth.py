@@ -132,12 +132,21 @@ def _apply_rows(R, X):
     return out
 
 
-def _power_law_exponent(mean: float, vmax: int) -> float:
-    k = np.arange(2, vmax + 1, dtype=np.float64)
+def _powers(base_from: int, base_to: int, expo: float) -> np.ndarray:
+    """base**expo for integer bases, by scalar libm pow (identical on any CPU,
+    unlike vectorised ufunc dispatch)."""
+    return np.array([math.pow(float(b), expo) for b in range(base_from, base_to + 1)], dtype=np.float64)
 
+
+def _power_law_exponent(mean: float, vmax: int) -> float:
     def mean_of(a):
-        w = k ** (-a)
-        return float((k * w).sum() / w.sum())
+        w = _powers(2, vmax, -a)
+        num = 0.0
+        den = 0.0
+        for t, wt in enumerate(w):
+            num += (t + 2) * wt
+            den += wt
+        return num / den
 
     lo, hi = 0.0, 10.0          # mean_of is decreasing in a
     for _ in range(200):
@@ -153,8 +162,8 @@ def _views_per_point(rng, n, N, vmax, m):
     vmax = min(vmax, m)
     a = _power_law_exponent(N / n, vmax)
     k = np.arange(2, vmax + 1)
-    w = k.astype(np.float64) ** (-a)
-    cdf = np.cumsum(w / w.sum())
+    w = _powers(2, vmax, -a)
+    cdf = np.cumsum(w / math.fsum(w))
     cdf[-1] = 1.0
     views = k[np.searchsorted(cdf, rng.random(n), side="right")].astype(np.int64)
     # seeded fix-up: move the total onto N one view at a time, within bounds
@@ -178,7 +187,7 @@ def _distinct_weighted(rng, views, weights):
     are distinct."""
     n = views.shape[0]
     m = weights.shape[0]
-    cdf = np.cumsum(weights / weights.sum())
+    cdf = np.cumsum(weights / math.fsum(weights))
     cdf[-1] = 1.0
     N = int(views.sum())
     owner = np.repeat(np.arange(n, dtype=np.int64), views)
@@ -230,7 +239,7 @@ def generate(name: str, seed: int = 0, outliers: float | None = None) -> Problem
         expo = None
     else:
         views, expo = _views_per_point(rng, n, cfg["N"], vmax, m)
-        weights = np.arange(1, m + 1, dtype=np.float64) ** -1.2
+        weights = _powers(1, m, -1.2)
         perm = rng.permutation(m)
     owner, rank = _distinct_weighted(rng, views, weights)
     obs_point = owner.astype(np.int32)
