@@ -1,0 +1,122 @@
+"""Full-size parity: the 29M-observation workload (13,700 cameras, 4.5M points,
+Huber delta = 1 px, 5% outliers) in the launch configuration bench.py times.
+
+At this size the oracle computes sampled outputs one by one: the FP64 cost
+over all observations, the gradient of sampled cameras (including the most
+observed one) and points from their own observation lists, and rows of the
+reduced camera system S x for sampled cameras from scratch.  The LM traces
+are compared with the oracle's stored traces (tests/golden/lm_trace_*.json,
+written by tests/golden/make_golden.py), replaying the oracle's PCG counts.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2112_01349_amd import FP32_MIXED, FP64, Problem, synth
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+DELTA = 1.0
+
+
+@pytest.fixture(scope="module")
+def large():
+    prob = synth.generate("large", seed=0)
+    args = (prob.cameras0, prob.points0, prob.obs_camera, prob.obs_point, prob.obs_uv)
+    cam_csr = orc.csr(prob.obs_camera, prob.num_cameras)
+    pt_csr = orc.csr(prob.obs_point, prob.num_points)
+    return dict(prob=prob, args=args, cam_csr=cam_csr, pt_csr=pt_csr)
+
+
+def sampled_cameras(d):
+    counts = np.diff(d["cam_csr"][0])
+    order = np.argsort(-counts, kind="stable")
+    rng = np.random.default_rng(5)
+    return [int(order[0]), int(order[1]), int(order[3000])] + [int(x) for x in
+                                                               rng.choice(order[2261:], 3, replace=False)]
+
+
+def test_large_cost_gradient_fp64(large):
+    prob = large["prob"]
+    gpu = Problem(*large["args"], huber_delta=DELTA)
+    F, gc, gp = gpu.eval_cost_grad()
+    gpu.close()
+    Fo = orc.cost(*large["args"], DELTA)
+    assert abs(F - Fo) <= 1e-12 * Fo
+    off, order = large["cam_csr"]
+    for j in sampled_cameras(large):
+        s = orc.subset_sums(order[off[j]:off[j + 1]], *large["args"], DELTA)
+        ref = -s["v"]
+        assert np.max(np.abs(gc[j] - ref)) <= 1e-10 * np.max(np.abs(ref)), j
+    poff, porder = large["pt_csr"]
+    rng = np.random.default_rng(6)
+    for i in rng.choice(prob.num_points, 200, replace=False):
+        s = orc.subset_sums(porder[poff[i]:poff[i + 1]], *large["args"], DELTA)
+        ref = -s["w"]
+        assert np.max(np.abs(gp[i] - ref)) <= 1e-10 * np.max(np.abs(ref)) + 1e-300, i
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32_MIXED])
+def test_large_schur_rows(large, precision):
+    prob = large["prob"]
+    gpu = Problem(*large["args"], precision=precision, huber_delta=DELTA)
+    lam = 1e-3
+    x = np.random.default_rng(7).normal(size=(prob.num_cameras, 9))
+    q = gpu.schur_matvec(x, lam)
+    gpu.close()
+    rows = sampled_cameras(large)[2:]   # the oracle's per-row cost grows with the camera's points
+    ref = orc.schur_rows(rows, *large["args"][:2], *large["args"][2:], x, lam, DELTA,
+                         cam_csr=large["cam_csr"], pt_csr=large["pt_csr"])
+    tol = 1e-9 if precision == FP64 else 2e-3
+    for t, j in enumerate(rows):
+        assert np.max(np.abs(q[j] - ref[t])) <= tol * np.max(np.abs(ref[t])), (j, q[j], ref[t])
+
+
+def load_golden(name):
+    path = os.path.join(GOLDEN, f"lm_trace_{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not written yet")
+    return json.load(open(path))
+
+
+def replay(name, precision=FP64, schedule=True):
+    g = load_golden(name)
+    prob = synth.generate(name, seed=0)
+    assert prob.digest() == g["digest"], "generator output differs from the one the trace was taken on"
+    o = g["options"]
+    gpu = Problem(prob.cameras0, prob.points0, prob.obs_camera, prob.obs_point, prob.obs_uv,
+                  precision=precision, huber_delta=o["huber_delta"])
+    kw = dict(max_lm_iters=o["max_lm_iters"], max_pcg_iters=o["max_pcg_iters"], pcg_rtol=o["pcg_rtol"])
+    if schedule:
+        kw["pcg_schedule"] = g["pcg_iters"]
+    rep = gpu.lm_solve(**kw)
+    gpu.close()
+    return g, rep
+
+
+@pytest.mark.parametrize("name", ["medium", "large"])
+def test_lm_trace_fp64_matches_oracle(name):
+    g, rep = replay(name)
+    assert rep["status"] == 0 and rep["iters_run"] == g["iters_run"]
+    assert abs(rep["initial_cost"] - g["initial_cost"]) <= 1e-12 * g["initial_cost"]
+    prev = g["initial_cost"]
+    same_path = True
+    for k in range(g["iters_run"]):
+        assert abs(rep["trial_cost"][k] - g["trial_cost"][k]) <= 1e-9 * g["trial_cost"][k], k
+        assert abs(rep["cost"][k] - g["cost"][k]) <= 1e-9 * g["cost"][k], k
+        if same_path and abs(prev - g["trial_cost"][k]) > 1e-10 * prev:
+            assert rep["accepted"][k] == g["accepted"][k], k
+        else:
+            same_path = False
+        prev = g["cost"][k]
+
+
+def test_lm_mixed_reaches_oracle_final_cost():
+    g, rep = replay("large", precision=FP32_MIXED, schedule=False)
+    assert rep["status"] == 0
+    costs = np.concatenate([[rep["initial_cost"]], rep["cost"]])
+    assert np.all(np.diff(costs) <= 0)
+    assert rep["final_cost"] <= g["final_cost"] * (1 + 1e-4), (rep["final_cost"], g["final_cost"])
