@@ -511,7 +511,10 @@ static double dot(const double *a, const double *b, int64_t len)
  * passes 0), so r^0 = b.  Preconditioner: the damped camera blocks B~_j.
  * Stopping (Reading): before each matvec, stop when ||r|| <= rtol ||b|| or
  * when the matvec count reaches max_iters; fixed_iters > 0 runs exactly that
- * many matvecs.  p^T q <= 0 (or non-finite) is a breakdown. */
+ * many matvecs.  p^T q <= 0 (or non-finite) is a breakdown (Reading, the
+ * paper is silent): the loop stops with x at the last iterate, as truncated
+ * CG does on a direction of non-positive curvature, and returns
+ * ORC_BREAKDOWN; the failed matvec counts. */
 int orc_pcg(int32_t m, int32_t n, int64_t N, const int32_t *oc, const int32_t *op,
             const double *Bd, const double *E, const double *Cinv, const double *b,
             double rtol, int32_t max_iters, int32_t fixed_iters, double *x, int32_t *iters)
@@ -550,7 +553,7 @@ int orc_pcg(int32_t m, int32_t n, int64_t N, const int32_t *oc, const int32_t *o
         ++it;
         double pq = dot(p, q, len);
         if (!(pq > 0.0) || !isfinite(pq)) {
-            status = ORC_ENUMERIC;
+            status = ORC_BREAKDOWN;
             break;
         }
         double alpha = rho / pq;
@@ -644,8 +647,9 @@ int orc_lm_solve(int32_t m, int32_t n, int64_t N, double *cams, double *pts,
         orc_reduced_rhs(m, n, N, oc, op, v, w, E, Ci, g, wb);
         int32_t fixed = opt->pcg_schedule ? opt->pcg_schedule[it] : 0;
         int32_t npcg = 0;
-        if (orc_pcg(m, n, N, oc, op, Bd, E, Ci, g, opt->pcg_rtol, opt->max_pcg_iters, fixed,
-                    dc, &npcg)) {
+        /* a breakdown leaves dc at the last iterate, which is still a step */
+        int pst = orc_pcg(m, n, N, oc, op, Bd, E, Ci, g, opt->pcg_rtol, opt->max_pcg_iters, fixed, dc, &npcg);
+        if (pst != ORC_OK && pst != ORC_BREAKDOWN) {
             trace->pcg_iters[it] = npcg;
             status = ORC_ENUMERIC;
             break;

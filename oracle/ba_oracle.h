@@ -23,6 +23,7 @@
 
 #define ORC_OK 0
 #define ORC_ENUMERIC 4
+#define ORC_BREAKDOWN 5   /* orc_pcg: p^T q <= 0 or non-finite; x holds the last iterate */
 
 typedef struct {
     double huber_delta;        /* <= 0: squared loss */

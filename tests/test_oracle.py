@@ -331,6 +331,38 @@ def test_pcg_matches_scipy_cg(tiny, k):
     np.testing.assert_allclose(x.ravel(), xs, rtol=1e-10, atol=1e-10 * np.abs(xs).max())
 
 
+def test_pcg_breakdown_keeps_last_iterate(tiny):
+    """On an indefinite operator (C~^-1 scaled up so that E C~^-1 E^T outweighs
+    B~ along some directions) some step has p^T q <= 0: the PCG stops there with x at the previous
+    iterate (truncated CG), counts the failed matvec and reports the
+    breakdown.  Checked against a dense preconditioned CG written out here."""
+    A, Bd, Cd, Dc, Dp, Ci = damped_problem(tiny)
+    Ci = Ci * 1.05  # indefinite along a few directions: breaks down after a few steps
+    S, _ = explicit_schur(tiny, A, Bd, Ci)
+    b = orc.reduced_rhs(tiny.obs_camera, tiny.obs_point, A["v"], A["w"], A["E"], Ci)
+    x, it, rc = orc.pcg(tiny.obs_camera, tiny.obs_point, Bd, A["E"], Ci, b, rtol=0.0, max_iters=300)
+    assert rc == 5
+    Minv = [np.linalg.inv(B) for B in Bd]
+    r = b.ravel().copy()
+    xr = np.zeros_like(r)
+    p = None
+    k = 0
+    while True:
+        z = np.concatenate([Minv[j] @ r[9 * j:9 * j + 9] for j in range(len(Bd))])
+        rho = r @ z
+        p = z if k == 0 else z + rho / rho_prev * p
+        q = S @ p
+        k += 1
+        if p @ q <= 0:
+            break
+        alpha = rho / (p @ q)
+        xr += alpha * p
+        r -= alpha * q
+        rho_prev = rho
+    assert it == k and k > 1
+    np.testing.assert_allclose(x.ravel(), xr, rtol=1e-9, atol=1e-9 * np.abs(xr).max())
+
+
 def test_schur_pcg_solves_full_damped_system(tiny):
     """Tight PCG on the reduced camera system plus back-substitution equals a
     dense Cholesky solve of the full damped [[B, E], [E^T, C]] system, and the
