@@ -44,7 +44,7 @@ typedef enum {
     BA_EINVAL = 1,   /* bad count, index out of range, non-finite input, bad option */
     BA_ENOMEM = 2,   /* device workspace does not fit */
     BA_EDEVICE = 3,  /* HIP runtime error (message in ba_last_error) */
-    BA_ENUMERIC = 4  /* PCG breakdown (p^T q <= 0 or NaN) or a non-SPD damped block */
+    BA_ENUMERIC = 4  /* a damped block that is not positive definite */
 } ba_status;
 
 typedef enum {
@@ -137,8 +137,11 @@ ba_status ba_eval_cost_grad(ba_problem *prob, double *cost, double *grad_cameras
 /* Runs the LM loop from the current state (Alg. 1 with one partition inside
  * the trust-region wrapper) and leaves the last accepted state in the handle.
  * opt: NULL = the create-time options; opt->precision must equal the
- * create-time precision.  rep: nullable.  BA_ENUMERIC stops the loop and
- * keeps the last accepted state; the report holds the iterations run. */
+ * create-time precision.  rep: nullable.  A PCG breakdown (p^T q <= 0 or
+ * non-finite, possible in the FP32 products near a gauge direction once
+ * lambda is small) ends that PCG run with its last iterate as the step
+ * (truncated CG) and the loop goes on.  BA_ENUMERIC stops the loop and keeps
+ * the last accepted state; the report holds the iterations run. */
 ba_status ba_lm_solve(ba_problem *prob, const ba_options *opt, ba_report *rep);
 
 /* Applies the damped reduced camera system of the current state,

@@ -340,7 +340,7 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     std::vector<int64_t> coff((size_t)m + 1, 0);
     for (int64_t t = 0; t < N; ++t) coff[(size_t)h_pm_cam[(size_t)t] + 1]++;
     for (int32_t j = 0; j < m; ++j) coff[(size_t)j + 1] += coff[j];
-    std::vector<int32_t> h_cm_cam((size_t)N), h_cm_pt((size_t)N), h_cm_src((size_t)N);
+    std::vector<int32_t> h_cm_cam((size_t)N), h_cm_pt((size_t)N);
     std::vector<double> h_cm_uvx((size_t)N), h_cm_uvy((size_t)N);
     {
         std::vector<int64_t> fill(coff.begin(), coff.end() - 1);
@@ -349,7 +349,6 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
             const int64_t d = fill[j]++;
             h_cm_cam[(size_t)d] = j;
             h_cm_pt[(size_t)d] = h_pm_pt[(size_t)t];
-            h_cm_src[(size_t)d] = (int32_t)t;
             h_cm_uvx[(size_t)d] = h_uvx[(size_t)t];
             h_cm_uvy[(size_t)d] = h_uvy[(size_t)t];
         }
@@ -385,8 +384,9 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
         if (const char* env = std::getenv("BA_HOT_CAMERAS")) kmax = std::min(kmax, std::max(0, std::atoi(env)));
         sp.K = std::max(0, std::min(m, kmax));
     }
-    // line-aligned 64-observation tiles split evenly over the hot pass's wavefronts
-    P->pm.ld = (N + 63) / 64 * 64;
+    // line-aligned 64-observation tiles split evenly over the hot pass's
+    // wavefronts; the point-major arrays end with one padding tile (point -1)
+    P->pm.ld = ((N + 63) / 64 + 1) * 64;
     const int64_t ntiles64 = (N + 63) / 64;
     const int32_t waves_per_wg = P->is_f32() ? HotThreads<float>::value / 64 : HotThreads<double>::value / 64;
     sp.num_wg = 0;
@@ -397,16 +397,11 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     std::vector<int32_t> wrange((size_t)num_waves + 1, 0);
     for (int32_t w = 0; w <= num_waves; ++w) wrange[(size_t)w] = (int32_t)((int64_t)w * ntiles64 / num_waves);
     // the build: 32 wavefronts per CU over the same tiles
-    P->pm.build_waves = (int32_t)std::min<int64_t>(ntiles64, (int64_t)std::max(1, cus) * 32);
-    std::vector<int32_t> build_wrange((size_t)P->pm.build_waves + 1, 0);
-    for (int32_t w = 0; w <= P->pm.build_waves; ++w)
-        build_wrange[(size_t)w] = (int32_t)((int64_t)w * ntiles64 / std::max(1, P->pm.build_waves));
     // cold stream: observations on cameras >= K, camera-major
-    std::vector<int32_t> cold_pos((size_t)N, -1), h_cold_cam, h_cold_pt;
+    std::vector<int32_t> h_cold_cam, h_cold_pt;
     std::vector<uint8_t> has_cold((size_t)(n > 0 ? n : 1), 0);
     for (int64_t d = 0; d < N; ++d) {
         if (h_cm_cam[(size_t)d] >= sp.K) {
-            cold_pos[(size_t)h_cm_src[(size_t)d]] = (int32_t)h_cold_cam.size();
             h_cold_cam.push_back(h_cm_cam[(size_t)d]);
             h_cold_pt.push_back(h_cm_pt[(size_t)d]);
             has_cold[(size_t)h_cm_pt[(size_t)d]] = 1;
@@ -433,12 +428,11 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     P->ck64_t = A.get<CamK<double>>(m);
     P->ck32 = A.get<CamK<float>>(m);
     P->d_old_of_new = A.get<int32_t>(m);
-    P->pm.cam = A.get<int32_t>(N);
-    P->pm.pt = A.get<int32_t>(N);
+    P->pm.cam = A.get<int32_t>(P->pm.ld);
+    P->pm.pt = A.get<int32_t>(P->pm.ld);
     P->pm.uvx = A.get<double>(N);
     P->pm.uvy = A.get<double>(N);
     P->pm.tile = A.get<int32_t>((int64_t)tiles.size());
-    P->pm.build_wrange = A.get<int32_t>((int64_t)build_wrange.size());
     P->cm.cam = A.get<int32_t>(N);
     P->cm.pt = A.get<int32_t>(N);
     P->cm.uvx = A.get<double>(N);
@@ -464,7 +458,6 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     P->pT = A.get<char>(9 * (int64_t)m * (int64_t)tsz);
     sp.wrange = A.get<int32_t>((int64_t)wrange.size());
     sp.has_cold = A.get<uint8_t>(n);
-    sp.cold_pos = A.get<int32_t>(N);
     sp.hot_part = A.get<double>((int64_t)sp.num_wg * sp.K * 9);
     sp.hot_fold = A.get<double>((int64_t)kHotFold * sp.K * 9);
     sp.bcold = A.get<char>(3 * (int64_t)n * (int64_t)tsz);
@@ -498,12 +491,14 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     };
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = up(P->d_old_of_new, P->old_of_new.data(), sizeof(int32_t) * m);
-    if (e == hipSuccess) e = up(P->pm.cam, h_pm_cam.data(), sizeof(int32_t) * N);
-    if (e == hipSuccess) e = up(P->pm.pt, h_pm_pt.data(), sizeof(int32_t) * N);
+    h_pm_cam.resize((size_t)P->pm.ld, 0);
+    h_pm_pt.resize((size_t)P->pm.ld, -1);
+    if (e == hipSuccess) e = up(P->pm.cam, h_pm_cam.data(), sizeof(int32_t) * (size_t)P->pm.ld);
+    if (e == hipSuccess) e = up(P->pm.pt, h_pm_pt.data(), sizeof(int32_t) * (size_t)P->pm.ld);
+    if (e == hipSuccess) e = hipMemset(P->hcp, 0, 27 * (size_t)P->pm.ld * tsz);
     if (e == hipSuccess) e = up(P->pm.uvx, h_uvx.data(), sizeof(double) * N);
     if (e == hipSuccess) e = up(P->pm.uvy, h_uvy.data(), sizeof(double) * N);
     if (e == hipSuccess) e = up(P->pm.tile, tiles.data(), sizeof(int32_t) * tiles.size());
-    if (e == hipSuccess) e = up(P->pm.build_wrange, build_wrange.data(), sizeof(int32_t) * build_wrange.size());
     if (e == hipSuccess) e = up(P->cm.cam, h_cm_cam.data(), sizeof(int32_t) * N);
     if (e == hipSuccess) e = up(P->cm.pt, h_cm_pt.data(), sizeof(int32_t) * N);
     if (e == hipSuccess) e = up(P->cm.uvx, h_cm_uvx.data(), sizeof(double) * N);
@@ -518,7 +513,6 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     if (e == hipSuccess) e = hipMemset(P->vcam, 0, sizeof(double) * 9 * (size_t)m);
     if (e == hipSuccess) e = up(sp.wrange, wrange.data(), sizeof(int32_t) * wrange.size());
     if (e == hipSuccess) e = up(sp.has_cold, has_cold.data(), (size_t)n);
-    if (e == hipSuccess) e = up(sp.cold_pos, cold_pos.data(), sizeof(int32_t) * N);
     if (e == hipSuccess) e = up(sp.cold.cam, h_cold_cam.data(), sizeof(int32_t) * h_cold_cam.size());
     if (e == hipSuccess) e = up(sp.cold.pt, h_cold_pt.data(), sizeof(int32_t) * h_cold_pt.size());
     if (e == hipSuccess) e = up(sp.cold.chunk_slot, cold_chunk_slot.data(), sizeof(int32_t) * cold_chunk_slot.size());
@@ -604,9 +598,9 @@ static ba_status build_system(ba_problem* P)
     } else {
         ck = (const CamK<T>*)P->ck64;
     }
-    BA_TRY(P, launch_build_points<T>(P->pm, P->N, P->pts, ck, P->opt.huber_delta, false, (T*)P->hcp, (T*)P->hpp,
-                                     P->wpt, P->sp.cold_pos, P->sp.cold.N, (T*)P->sp.cold.hcp, s));
-    BA_TRY(P, launch_build_cameras<T>(P->cm, P->m, P->N, P->pts, ck, P->opt.huber_delta, false, P->hcc, P->vcam, s));
+    BA_TRY(P, launch_build_points<T>(P->pm, P->opt.huber_delta, false, P->pts, ck, (T*)P->hcp, (T*)P->hpp, P->wpt, s));
+    BA_TRY(P, launch_build_cameras<T>(P->cm, P->m, P->N, P->pts, ck, P->opt.huber_delta, false, P->hcc, P->vcam,
+                                      P->sp.cold.N, (T*)P->sp.cold.hcp, s));
     return BA_OK;
 }
 
@@ -680,10 +674,8 @@ static ba_status run_pcg(ba_problem* P, const ba_options& o, int32_t fixed, int3
     if (st != BA_OK) return st;
     const PcgScalars* h = (const PcgScalars*)P->h_scalars;
     *iters = h->iters;
-    if (h->breakdown) {
-        P->last_error = "PCG breakdown: p^T q <= 0 or non-finite";
-        return BA_ENUMERIC;
-    }
+    // A breakdown (p^T q <= 0 or non-finite) stops the loop before that
+    // update, so x holds the last iterate: it is used as the step (truncated CG).
     // matvecs run in order: the first `iters` marks timed real work
     for (size_t u = 0; u < marks.size() && (int32_t)u < h->iters; ++u) {
         float ms = 0.0f, hms = 0.0f;
@@ -836,9 +828,9 @@ extern "C" ba_status ba_lm_solve(ba_problem* P, const ba_options* opt, ba_report
 template <typename T>
 static ba_status grad_into(ba_problem* P, const double* pts, const CamK<T>* ck, hipStream_t s)
 {
-    BA_TRY(P, launch_build_points<T>(P->pm, P->N, pts, ck, P->opt.huber_delta, true, nullptr, nullptr, P->wpt,
-                                     nullptr, 0, nullptr, s));
-    BA_TRY(P, launch_build_cameras<T>(P->cm, P->m, P->N, pts, ck, P->opt.huber_delta, true, nullptr, P->vcam, s));
+    BA_TRY(P, launch_build_points<T>(P->pm, P->opt.huber_delta, true, pts, ck, nullptr, nullptr, P->wpt, s));
+    BA_TRY(P, launch_build_cameras<T>(P->cm, P->m, P->N, pts, ck, P->opt.huber_delta, true, nullptr, P->vcam, 0,
+                                      nullptr, s));
     return BA_OK;
 }
 

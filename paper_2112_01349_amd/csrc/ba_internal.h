@@ -56,16 +56,15 @@ __device__ __forceinline__ bool last_block_arrives(uint32_t* counter)
 
 // Point-major observation stream (sorted by point, then camera).
 struct PointMajor {
-    int32_t* cam;      // [N] internal camera id
-    int32_t* pt;       // [N]
+    int32_t* cam;      // [ld] internal camera id
+    int32_t* pt;       // [ld]
     double* uvx;       // [N]
     double* uvy;       // [N]
     int32_t* tile;     // [num_tiles + 1] observation offsets of point-aligned tiles
     int32_t num_tiles;
-    int64_t ld;        // leading dimension of the [27][ld] coupling-block streams
-                       // (N rounded up to 64, so 64-observation tiles are line-aligned)
-    int32_t build_waves;      // wavefronts of the point-major build
-    int32_t* build_wrange;    // [build_waves + 1] ranges of 64-observation tiles
+    int64_t ld;        // leading dimension of the [27][ld] coupling-block streams: N
+                       // rounded up to 64 plus one padding tile (cam 0, pt -1), so
+                       // 64-observation tiles are line-aligned and tile t + 1 exists
 };
 
 // Camera-major observation stream (sorted by camera, then point).
@@ -120,7 +119,6 @@ struct SchurPlan {
     int32_t* wrange = nullptr;      // [num_wg * waves per workgroup + 1] ranges of 64-observation
                                     // tiles per wavefront
     uint8_t* has_cold = nullptr;    // [n] point has an observation in the cold stream
-    int32_t* cold_pos = nullptr;    // [N] point-major observation -> cold index or -1
     void* hot_part = nullptr;       // [num_wg][K][9] FP64
     double* hot_fold = nullptr;     // [kHotFold][K][9] FP64
     void* bcold = nullptr;          // [n][3] of T
@@ -132,16 +130,18 @@ struct SchurPlan {
 hipError_t launch_camera_constants_f64(int32_t m, const double* cams, CamK<double>* out, hipStream_t s);
 hipError_t launch_camera_constants_f32(int32_t m, const double* cams, CamK<float>* out, hipStream_t s);
 
-// cold_pos / chcp (nullable): observations with cold_pos[k] >= 0 also write
-// their coupling block to chcp[q * Nc + cold_pos[k]].
+// Point-major build: E_k into hcp (unless grad_only), C_i into hpp (unless
+// grad_only) and w_i into wpt.
 template <typename T>
-hipError_t launch_build_points(const PointMajor& pm, int64_t N, const double* pts, const CamK<T>* ck,
-                               double delta, bool grad_only, T* hcp, T* hpp, double* wpt,
-                               const int32_t* cold_pos, int64_t Nc, T* chcp, hipStream_t s);
+hipError_t launch_build_points(const PointMajor& pm, double delta, bool grad_only, const double* pts,
+                               const CamK<T>* ck, T* hcp, T* hpp, double* wpt, hipStream_t s);
+// Camera-major build: B_j (unless grad_only) and v_j; the last Nc
+// observations of the camera-major stream (the cold cameras) also store E_k
+// into chcp[q * Nc + k - (N - Nc)].
 template <typename T>
 hipError_t launch_build_cameras(const CameraMajor& cm, int32_t m, int64_t N, const double* pts,
                                 const CamK<T>* ck, double delta, bool grad_only, double* hcc,
-                                double* vcam, hipStream_t s);
+                                double* vcam, int64_t Nc, T* chcp, hipStream_t s);
 
 hipError_t launch_damp_cameras(int32_t m, const double* hcc, double lambda, int32_t damping,
                                double* bd, double* lfac, double* dcam, int32_t* flag, hipStream_t s);

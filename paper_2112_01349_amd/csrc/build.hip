@@ -4,12 +4,11 @@
 //
 // Two passes over the observations, each with its own sorted copy of the
 // index and pixel streams:
-//   * point-major (k_build_points): wavefronts over line-aligned tiles of 64
-//     observations, one lane per observation.  Writes the coupling block
-//     E_k = w J_c^T J_p of every observation as 27 coalesced streams [27][ld]
-//     (ld = N rounded up to 64), and forms the point blocks
-//     C_i = sum w J_p^T J_p and w_i = -sum w J_p^T e by a segmented scan over
-//     the point's contiguous segment.
+//   * point-major (k_build_points): one workgroup per point-aligned tile of
+//     <= 256 observations, one thread per observation.  Writes the coupling
+//     block E_k = w J_c^T J_p as 27 coalesced streams [27][ld], and sums the
+//     point blocks C_i = sum w J_p^T J_p and w_i = -sum w J_p^T e over each
+//     point's run through LDS.
 //   * camera-major (k_build_cameras): one wavefront per contiguous chunk of
 //     2048 observations sorted by camera.  Lanes accumulate the camera terms
 //     B_j = sum w J_c^T J_c and v_j = -sum w J_c^T e in registers while the
@@ -49,17 +48,17 @@ hipError_t launch_camera_constants_f32(int32_t m, const double* cams, CamK<float
 // ------------------------------------------------------ point-major build
 // Terms of one observation for its point: C (upper 6) and w (3).
 template <typename T>
-__device__ __forceinline__ void point_terms(const T Jp[6], T e0, T e1, T wt, double out[9])
+__device__ __forceinline__ void point_terms(const T Jp[6], T e0, T e1, T wt, T out[9])
 {
-    out[0] = (double)(wt * (Jp[0] * Jp[0] + Jp[3] * Jp[3]));
-    out[1] = (double)(wt * (Jp[0] * Jp[1] + Jp[3] * Jp[4]));
-    out[2] = (double)(wt * (Jp[0] * Jp[2] + Jp[3] * Jp[5]));
-    out[3] = (double)(wt * (Jp[1] * Jp[1] + Jp[4] * Jp[4]));
-    out[4] = (double)(wt * (Jp[1] * Jp[2] + Jp[4] * Jp[5]));
-    out[5] = (double)(wt * (Jp[2] * Jp[2] + Jp[5] * Jp[5]));
-    out[6] = (double)(-wt * (Jp[0] * e0 + Jp[3] * e1));
-    out[7] = (double)(-wt * (Jp[1] * e0 + Jp[4] * e1));
-    out[8] = (double)(-wt * (Jp[2] * e0 + Jp[5] * e1));
+    out[0] = wt * (Jp[0] * Jp[0] + Jp[3] * Jp[3]);
+    out[1] = wt * (Jp[0] * Jp[1] + Jp[3] * Jp[4]);
+    out[2] = wt * (Jp[0] * Jp[2] + Jp[3] * Jp[5]);
+    out[3] = wt * (Jp[1] * Jp[1] + Jp[4] * Jp[4]);
+    out[4] = wt * (Jp[1] * Jp[2] + Jp[4] * Jp[5]);
+    out[5] = wt * (Jp[2] * Jp[2] + Jp[5] * Jp[5]);
+    out[6] = -wt * (Jp[0] * e0 + Jp[3] * e1);
+    out[7] = -wt * (Jp[1] * e0 + Jp[4] * e1);
+    out[8] = -wt * (Jp[2] * e0 + Jp[5] * e1);
 }
 
 template <typename T>
@@ -87,127 +86,116 @@ __device__ __forceinline__ void store_coupling(int64_t k, int64_t N, const T Jc[
             hcp[(int64_t)(a * 3 + b) * N + k] = wt * (Jc[a] * Jp[b] + Jc[9 + a] * Jp[3 + b]);
 }
 
-__device__ __forceinline__ double shfl_up_d(double v, int off) { return __shfl_up(v, off, 64); }
-
-// Point-major build over line-aligned 64-observation tiles, one wavefront
-// per contiguous range of tiles (the ownership and carry scheme of the Schur
-// pass): every lane computes its observation's residual and Jacobian, stores
-// E_k (and its cold copy), and the point sums C_i, w_i are formed by a
-// segmented scan over shuffles, carried across tiles, and written by the
-// point's last lane.
-template <typename T, bool GRAD_ONLY>
-__global__ __launch_bounds__(256) void k_build_points(
-    int32_t num_waves, const int32_t* __restrict__ wrange, int64_t N, const int32_t* __restrict__ cam,
-    const int32_t* __restrict__ pt,
-    const double* __restrict__ uvx, const double* __restrict__ uvy, const double* __restrict__ pts,
-    const CamK<T>* __restrict__ ck, T delta, int64_t ld, T* __restrict__ hcp, T* __restrict__ hpp,
-    double* __restrict__ wpt, const int32_t* __restrict__ cold_pos, int64_t Nc, T* __restrict__ chcp)
-{
-    const int lane = threadIdx.x & 63;
-    const int32_t gw = (int32_t)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
-    if (gw >= num_waves) return;  // the grid rounds the wavefront count up to whole blocks
-    const int64_t T0 = wrange[gw], T1 = wrange[gw + 1];
-    if (T0 >= T1) return;  // no barriers in this kernel
-    const int64_t ntiles = (N + 63) >> 6;
-    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
-    const int32_t skip_pt = T0 > 0 ? pt[64 * T0 - 1] : -1;  // owned by the previous wavefront
-    int32_t carry_pt = -1;
-    double cr[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) cr[q] = 0.0;
-    for (int64_t t = T0; t < ntiles && (t < T1 || carry_pt >= 0); ++t) {
-        const int64_t k = 64 * t + lane;
-        const bool valid = k < N;
-        const int32_t i = valid ? pt[k] : -1;
-        const bool owned = valid && (t < T1 ? i != skip_pt : i == carry_pt);
-        const uint64_t om = __ballot(owned);
-        if (om == 0) {
-            if (t >= T1) break;  // past the range: the carried point has ended
-            continue;            // a tile inside the previous wavefront's last point
-        }
-        double v[9];
-#pragma unroll
-        for (int q = 0; q < 9; ++q) v[q] = 0.0;
-        if (owned) {
-            T e0, e1, wt, Jc[18], Jp[6];
-            int32_t ii;
-            observation<T>(k, cam, pt, uvx, uvy, pts, ck, delta, e0, e1, wt, Jc, Jp, ii);
-            if (!GRAD_ONLY) {
-                store_coupling<T>(k, ld, Jc, Jp, wt, hcp);
-                if (cold_pos) {
-                    const int32_t c = cold_pos[k];
-                    if (c >= 0) store_coupling<T>(c, Nc, Jc, Jp, wt, chcp);
-                }
-            }
-            point_terms<T>(Jp, e0, e1, wt, v);
-        }
-        const int32_t prev_i = __shfl_up(i, 1, 64);
-        const int prev_own = __shfl_up(owned ? 1 : 0, 1, 64);
-        const bool head = owned && (lane == 0 || !prev_own || prev_i != i);
-        const uint64_t hm = __ballot(head);
-        const int seg_s = 63 - __clzll((hm & upto) | 1ull);
-        const int last_owned = 63 - __clzll(om);
-        const uint64_t above = hm & ~upto;
-        const int seg_e = above ? __ffsll((unsigned long long)above) - 2 : last_owned;
-        const int first_head = __ffsll((unsigned long long)hm) - 1;
-        const int last_head = 63 - __clzll(hm);
-        const int32_t i_first = __shfl(i, first_head, 64);
-        const int32_t i_last = __shfl(i, last_owned, 64);
-        const bool cont = carry_pt >= 0 && i_first == carry_pt;
-        const bool last_inc = last_owned == 63 && t + 1 < ntiles && pt[64 * (t + 1)] == i_last;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const bool take = lane - off >= seg_s;
-#pragma unroll
-            for (int q = 0; q < 9; ++q) {
-                const double u = shfl_up_d(v[q], off);
-                if (take) v[q] += u;
-            }
-        }
-        if (cont && seg_s == first_head)
-#pragma unroll
-            for (int q = 0; q < 9; ++q) v[q] += cr[q];
-        // lane seg_e now holds its point's running total
-        if (owned && lane == seg_e && !(last_inc && seg_s == last_head)) {
-            if (!GRAD_ONLY)
-#pragma unroll
-                for (int q = 0; q < 6; ++q) hpp[6 * (int64_t)i + q] = (T)v[q];
-#pragma unroll
-            for (int q = 0; q < 3; ++q) wpt[3 * (int64_t)i + q] = v[6 + q];
-        }
-        if (last_inc) {
-#pragma unroll
-            for (int q = 0; q < 9; ++q) cr[q] = __shfl(v[q], 63, 64);
-            carry_pt = i_last;
-        } else {
-            carry_pt = -1;
-        }
-    }
-}
-
-template <typename T>
-hipError_t launch_build_points(const PointMajor& pm, int64_t N, const double* pts, const CamK<T>* ck,
-                               double delta, bool grad_only, T* hcp, T* hpp, double* wpt,
-                               const int32_t* cold_pos, int64_t Nc, T* chcp, hipStream_t s)
-{
-    if (pm.build_waves <= 0 || N <= 0) return hipGetLastError();
-    const dim3 g((pm.build_waves + 3) / 4), b(256);
-    if (grad_only)
-        hipLaunchKernelGGL((k_build_points<T, true>), g, b, 0, s, pm.build_waves, pm.build_wrange, N, pm.cam, pm.pt,
-                           pm.uvx, pm.uvy, pts, ck, (T)delta, pm.ld, hcp, hpp, wpt, nullptr, (int64_t)0, (T*)nullptr);
-    else
-        hipLaunchKernelGGL((k_build_points<T, false>), g, b, 0, s, pm.build_waves, pm.build_wrange, N, pm.cam, pm.pt,
-                           pm.uvx, pm.uvy, pts, ck, (T)delta, pm.ld, hcp, hpp, wpt, cold_pos, Nc, chcp);
-    return hipGetLastError();
-}
-
-// ----------------------------------------------------- camera-major build
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
 }
+
+// Point-major build over point-aligned tiles of <= kTile observations (a
+// longer point is a tile alone).  One thread per observation computes its
+// residual and Jacobian and stores E_k = w J_c^T J_p (27 coalesced streams);
+// its terms of C_i and w_i go to LDS, and the first thread of each point sums
+// the point's terms in stream order (FP64) and stores C_i (upper 6, as T)
+// and w_i (FP64).  GRAD_ONLY forms w_i only.
+template <typename T, bool GRAD_ONLY>
+__global__ __launch_bounds__(kTile) void k_build_points(
+    const int32_t* __restrict__ tile, const int32_t* __restrict__ cam, const int32_t* __restrict__ pt,
+    const double* __restrict__ uvx, const double* __restrict__ uvy, const double* __restrict__ pts,
+    const CamK<T>* __restrict__ ck, T delta, int64_t ld, T* __restrict__ hcp, T* __restrict__ hpp,
+    double* __restrict__ wpt)
+{
+    constexpr int R = GRAD_ONLY ? 3 : 9;  // terms kept: [C upper 6 |] w 3
+    __shared__ T sh[R][kTile];
+    __shared__ int32_t shpt[kTile];
+    __shared__ double red[R][kTile / 64];
+    const int tid = threadIdx.x;
+    const int32_t s = tile[blockIdx.x], e = tile[blockIdx.x + 1];
+    const int32_t len = e - s;
+    if (len <= kTile) {
+        const bool valid = tid < len;
+        int32_t i = -1;
+        if (valid) {
+            const int64_t k = s + tid;
+            T e0, e1, wt, Jc[18], Jp[6];
+            observation<T>(k, cam, pt, uvx, uvy, pts, ck, delta, e0, e1, wt, Jc, Jp, i);
+            if (!GRAD_ONLY) store_coupling<T>(k, ld, Jc, Jp, wt, hcp);
+            T v[9];
+            point_terms<T>(Jp, e0, e1, wt, v);
+#pragma unroll
+            for (int q = 0; q < R; ++q) sh[q][tid] = v[9 - R + q];
+        }
+        shpt[tid] = i;
+        __syncthreads();
+        if (valid && (tid == 0 || shpt[tid - 1] != i)) {
+            double acc[R];
+#pragma unroll
+            for (int q = 0; q < R; ++q) acc[q] = 0.0;
+            for (int u = tid; u < len && shpt[u] == i; ++u)
+#pragma unroll
+                for (int q = 0; q < R; ++q) acc[q] += (double)sh[q][u];
+            if (!GRAD_ONLY)
+#pragma unroll
+                for (int q = 0; q < 6; ++q) hpp[6 * (int64_t)i + q] = (T)acc[q];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) wpt[3 * (int64_t)i + q] = acc[R - 3 + q];
+        }
+    } else {
+        // one point with more than kTile observations: strided partial sums,
+        // then a fixed-order reduction over the block
+        const int32_t i = pt[s];
+        double acc[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) acc[q] = 0.0;
+        for (int64_t k = s + tid; k < e; k += kTile) {
+            T e0, e1, wt, Jc[18], Jp[6];
+            int32_t ii;
+            observation<T>(k, cam, pt, uvx, uvy, pts, ck, delta, e0, e1, wt, Jc, Jp, ii);
+            if (!GRAD_ONLY) store_coupling<T>(k, ld, Jc, Jp, wt, hcp);
+            T v[9];
+            point_terms<T>(Jp, e0, e1, wt, v);
+#pragma unroll
+            for (int q = 0; q < R; ++q) acc[q] += (double)v[9 - R + q];
+        }
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const double w = wave_sum(acc[q]);
+            if ((tid & 63) == 0) red[q][tid >> 6] = w;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double tot[R];
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                tot[q] = 0.0;
+                for (int w = 0; w < kTile / 64; ++w) tot[q] += red[q][w];
+            }
+            if (!GRAD_ONLY)
+#pragma unroll
+                for (int q = 0; q < 6; ++q) hpp[6 * (int64_t)i + q] = (T)tot[q];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) wpt[3 * (int64_t)i + q] = tot[R - 3 + q];
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_build_points(const PointMajor& pm, double delta, bool grad_only, const double* pts,
+                               const CamK<T>* ck, T* hcp, T* hpp, double* wpt, hipStream_t s)
+{
+    if (pm.num_tiles <= 0) return hipGetLastError();
+    const dim3 g((unsigned)pm.num_tiles), b(kTile);
+    if (grad_only)
+        hipLaunchKernelGGL((k_build_points<T, true>), g, b, 0, s, pm.tile, pm.cam, pm.pt, pm.uvx, pm.uvy, pts, ck,
+                           (T)delta, pm.ld, (T*)nullptr, (T*)nullptr, wpt);
+    else
+        hipLaunchKernelGGL((k_build_points<T, false>), g, b, 0, s, pm.tile, pm.cam, pm.pt, pm.uvx, pm.uvy, pts, ck,
+                           (T)delta, pm.ld, hcp, hpp, wpt);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------- camera-major build
 
 template <bool GRAD_ONLY>
 __device__ __forceinline__ void flush_slot(double* acc, double* __restrict__ slots, int32_t slot, int lane)
@@ -225,9 +213,11 @@ template <typename T, bool GRAD_ONLY>
 __global__ __launch_bounds__(256) void k_build_cameras(
     int64_t N, int32_t num_chunks, const int32_t* __restrict__ cam, const int32_t* __restrict__ pt,
     const double* __restrict__ uvx, const double* __restrict__ uvy, const double* __restrict__ pts,
-    const CamK<T>* __restrict__ ck, T delta, const int32_t* __restrict__ chunk_slot, double* __restrict__ slots)
+    const CamK<T>* __restrict__ ck, T delta, const int32_t* __restrict__ chunk_slot, double* __restrict__ slots,
+    int64_t Nc, T* __restrict__ chcp)
 {
     constexpr int W = GRAD_ONLY ? 9 : kCamSlotWords;
+    const int64_t cold0 = N - Nc;  // the cold cameras' observations are the stream's tail
     const int lane = threadIdx.x & 63;
     const int32_t chunk = (int32_t)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
     if (chunk >= num_chunks) return;  // whole wavefront leaves together
@@ -248,6 +238,7 @@ __global__ __launch_bounds__(256) void k_build_cameras(
             int32_t i;
             j = cam[k];
             observation<T>(k, cam, pt, uvx, uvy, pts, ck, delta, e0, e1, wt, Jc, Jp, i);
+            if (!GRAD_ONLY && k >= cold0) store_coupling<T>(k - cold0, Nc, Jc, Jp, wt, chcp);
         }
         while (true) {
             if (valid && j == cur) {
@@ -330,16 +321,18 @@ __global__ __launch_bounds__(256) void k_reduce_slots(int32_t num_segs, const in
 
 template <typename T>
 hipError_t launch_build_cameras(const CameraMajor& cm, int32_t m, int64_t N, const double* pts, const CamK<T>* ck,
-                                double delta, bool grad_only, double* hcc, double* vcam, hipStream_t s)
+                                double delta, bool grad_only, double* hcc, double* vcam, int64_t Nc, T* chcp,
+                                hipStream_t s)
 {
     if (cm.num_chunks > 0) {
         const int blocks = (cm.num_chunks + 3) / 4;
         if (grad_only)
             hipLaunchKernelGGL((k_build_cameras<T, true>), dim3(blocks), dim3(256), 0, s, N, cm.num_chunks, cm.cam,
-                               cm.pt, cm.uvx, cm.uvy, pts, ck, (T)delta, cm.chunk_slot, cm.slots);
+                               cm.pt, cm.uvx, cm.uvy, pts, ck, (T)delta, cm.chunk_slot, cm.slots, (int64_t)0,
+                               (T*)nullptr);
         else
             hipLaunchKernelGGL((k_build_cameras<T, false>), dim3(blocks), dim3(256), 0, s, N, cm.num_chunks,
-                               cm.cam, cm.pt, cm.uvx, cm.uvy, pts, ck, (T)delta, cm.chunk_slot, cm.slots);
+                               cm.cam, cm.pt, cm.uvx, cm.uvy, pts, ck, (T)delta, cm.chunk_slot, cm.slots, Nc, chcp);
     }
     if (cm.num_segs > 0) {
         const int blocks = (cm.num_segs + 3) / 4;
@@ -406,16 +399,16 @@ hipError_t launch_cost(const PointMajor& pm, int64_t N, const double* pts, const
     return launch_cost_t<double>(pm, N, pts, ck, delta, partials, nblocks, s);
 }
 
-template hipError_t launch_build_points<double>(const PointMajor&, int64_t, const double*, const CamK<double>*,
-                                                double, bool, double*, double*, double*, const int32_t*, int64_t,
-                                                double*, hipStream_t);
-template hipError_t launch_build_points<float>(const PointMajor&, int64_t, const double*, const CamK<float>*,
-                                               double, bool, float*, float*, double*, const int32_t*, int64_t,
-                                               float*, hipStream_t);
+template hipError_t launch_build_points<double>(const PointMajor&, double, bool, const double*, const CamK<double>*,
+                                                double*, double*, double*, hipStream_t);
+template hipError_t launch_build_points<float>(const PointMajor&, double, bool, const double*, const CamK<float>*,
+                                               float*, float*, double*, hipStream_t);
 template hipError_t launch_build_cameras<double>(const CameraMajor&, int32_t, int64_t, const double*,
-                                                 const CamK<double>*, double, bool, double*, double*, hipStream_t);
+                                                 const CamK<double>*, double, bool, double*, double*, int64_t,
+                                                 double*, hipStream_t);
 template hipError_t launch_build_cameras<float>(const CameraMajor&, int32_t, int64_t, const double*,
-                                                const CamK<float>*, double, bool, double*, double*, hipStream_t);
+                                                const CamK<float>*, double, bool, double*, double*, int64_t, float*,
+                                                hipStream_t);
 template hipError_t launch_cost_t<float>(const PointMajor&, int64_t, const double*, const CamK<float>*, double,
                                          double*, int32_t*, hipStream_t);
 

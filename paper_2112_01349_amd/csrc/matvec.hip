@@ -10,43 +10,40 @@
 // seen camera is in ~60% of the points), so the scatter is organised by
 // camera popularity (cameras are relabelled most-observed first):
 //
-//   pass 1 (k_schur_hot): persistent workgroups, one per CU; every
-//     wavefront streams its own range of line-aligned 64-observation tiles
-//     (one observation per lane) with the next tile prefetched into
-//     registers.  a_i is summed by a segmented scan over shuffles (points
-//     that straddle tiles are carried) and b_i is formed in registers;
-//     contributions to the K hottest cameras accumulate in a per-workgroup
-//     LDS copy of their 9-vectors (K sized to fill the 160 KB LDS), written
-//     out once at the end.  b_i of points that also have observations on
-//     colder cameras is stored.
+//   pass 1 (k_schur_hot, or k_schur_rhs for mode 1): persistent
+//     workgroups, one per CU; every wavefront streams its own range of
+//     line-aligned 64-observation tiles (one observation per lane) with the
+//     next tile prefetched into registers.  a_i is summed by a segmented scan
+//     over shuffles (a point that runs on into the next tile is finished from
+//     the prefetched registers) and b_i is formed in registers; contributions
+//     to the K hottest cameras accumulate in a per-workgroup LDS copy of their
+//     9-vectors (K sized to fill the 160 KB LDS), written out once at the
+//     end.  b_i of points that also have observations on colder cameras is
+//     stored.
 //   pass 2 (k_schur_cold): the observations on cameras >= K, from their own
 //     camera-major copy of E, gather b_i and are reduced per camera by
 //     wavefront chunks into fixed partial-sum slots (no atomics).
-//   epilogue (k_schur_epilogue): per camera entry, sums the workgroup
-//     partials (hot) or the slots (cold) in a fixed order and forms q or g.
-// A point spanning more than two tiles re-reads its older blocks once (L2).
+//   fold + epilogue (k_hot_fold, k_schur_epilogue): per camera entry, sums
+//     the workgroup partials (hot) or the slots (cold) in a fixed order and
+//     forms q or g.
 #include "ba_internal.h"
 
 namespace ba {
 
-// Observation 64 t + lane of line-aligned tile t.
+// Observation 64 t + lane of line-aligned tile t, for t uniform over the
+// wavefront and at most the tile count: the point-major arrays end with a
+// padding tile (point index -1), so no lane needs a bounds test and every row
+// is read as a scalar base plus the lane offset.
 template <typename T>
-__device__ __forceinline__ void load_tile(int64_t t, int64_t N, int64_t ld, int lane, const int32_t* __restrict__ cam,
+__device__ __forceinline__ void load_tile(int64_t t, int64_t ld, int lane, const int32_t* __restrict__ cam,
                                           const int32_t* __restrict__ pt, const T* __restrict__ hcp, int32_t& j,
                                           int32_t& i, T h[27])
 {
-    const int64_t k = 64 * t + lane;
-    if (k < N) {
-        j = cam[k];
-        i = pt[k];
+    const int64_t k0 = 64 * t;
+    j = (cam + k0)[lane];
+    i = (pt + k0)[lane];
 #pragma unroll
-        for (int q = 0; q < 27; ++q) h[q] = hcp[(int64_t)q * ld + k];
-    } else {
-        j = 0;
-        i = -1;
-#pragma unroll
-        for (int q = 0; q < 27; ++q) h[q] = (T)0;
-    }
+    for (int q = 0; q < 27; ++q) h[q] = (hcp + ((int64_t)q * ld + k0))[lane];
 }
 
 template <typename T>
@@ -58,166 +55,181 @@ __device__ __forceinline__ void add_hot(double* __restrict__ cl, int32_t j, cons
         atomicAdd(dst + a, (double)(h[a * 3] * b0 + h[a * 3 + 1] * b1 + h[a * 3 + 2] * b2));
 }
 
-// Pass 1.  Tile t holds observations [64 t, 64 t + 64), one per lane, so
-// every load is whole 128-byte lines.  Each wavefront owns the points that
-// start in its range of tiles.  Per-point sums use a segmented scan over
-// shuffles; a point that runs on into the next tile is carried (its partial
-// sum) and finished when its
-// last observation arrives (its earlier blocks are read again, from L2); the
-// last point of a range is followed past the range end.  The next tile is
-// loaded while the current one is processed.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// a = E_k^T x_j for one observation's 9x3 block.
+template <typename T>
+__device__ __forceinline__ void block_t_times_x(const T h[27], const T* __restrict__ xcam, int32_t j, T& a0, T& a1,
+                                                T& a2)
+{
+    T x[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) x[a] = xcam[9 * (int64_t)j + a];
+    a0 = (T)0;
+    a1 = (T)0;
+    a2 = (T)0;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        a0 += h[a * 3] * x[a];
+        a1 += h[a * 3 + 1] * x[a];
+        a2 += h[a * 3 + 2] * x[a];
+    }
+}
+
+// Pass 1 of the matvec.  Tile t holds observations [64 t, 64 t + 64), one
+// per lane, so every load is whole 128-byte lines.  A point belongs to the
+// tile that holds its first observation, and each wavefront takes the points
+// that start in its range of tiles.  The next tile is always prefetched into
+// registers, so the tile's last point, when it runs on into the next tile, is
+// finished at once from those registers and no block is read twice.  A point
+// that fills the whole next tile and goes on (longer than the point lengths
+// of the usual workloads) is finished by a second walk over its further tiles.
 // The hot-camera table is FP64 in both precisions: LDS FP64 adds issue
 // without the back-pressure FP32 LDS adds show here, and the per-workgroup
 // sums of the most observed cameras keep FP64 accuracy.
-template <typename T, int MODE>
+template <typename T>
 __global__ __launch_bounds__(HotThreads<T>::value) void k_schur_hot(
     const int32_t* __restrict__ wrange, int64_t N, int64_t ld, const int32_t* __restrict__ cam,
     const int32_t* __restrict__ pt, const T* __restrict__ hcp, const T* __restrict__ cinv,
-    const double* __restrict__ wpt, const T* __restrict__ xcam, int32_t K, double* __restrict__ hot_part,
-    T* __restrict__ bcold, const uint8_t* __restrict__ has_cold, const PcgScalars* __restrict__ sc)
+    const T* __restrict__ xcam, int32_t K, double* __restrict__ hot_part, T* __restrict__ bcold,
+    const uint8_t* __restrict__ has_cold, const PcgScalars* __restrict__ sc)
 {
     constexpr int NT = HotThreads<T>::value;
-    if (MODE == 0 && sc->done) return;  // uniform over the grid
+    if (sc->done) return;  // uniform over the grid
     extern __shared__ __align__(16) unsigned char smem[];
     double* cl = reinterpret_cast<double*>(smem);
     for (int q = threadIdx.x; q < K * 9; q += NT) cl[q] = 0.0;
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    const int32_t gw = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+    const int32_t gw = __builtin_amdgcn_readfirstlane(blockIdx.x * (NT / 64) + (threadIdx.x >> 6));
     const int64_t T0 = wrange[gw], T1 = wrange[gw + 1];
     const int64_t ntiles = (N + 63) >> 6;
     const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
     if (T0 < T1) {
-        const int32_t skip_pt = T0 > 0 ? pt[64 * T0 - 1] : -1;  // owned by the previous wavefront
-        int32_t carry_pt = -1;
-        T cr0 = (T)0, cr1 = (T)0, cr2 = (T)0;
-        int64_t carry_start = 0;
+        int32_t before = T0 > 0 ? pt[64 * T0 - 1] : -1;  // point of the observation just before tile t
         int32_t cj, ci;
         T ch[27];
-        load_tile<T>(T0, N, ld, lane, cam, pt, hcp, cj, ci, ch);
-        for (int64_t t = T0; t < ntiles && (t < T1 || carry_pt >= 0); ++t) {
-            int32_t nj = 0, ni = -1;
+        load_tile<T>(T0, ld, lane, cam, pt, hcp, cj, ci, ch);
+        int64_t t = T0;
+        while (t < T1) {
+            int32_t nj, ni;
             T nh[27];
-            const bool prefetch = t + 1 < T1;
-            if (prefetch) load_tile<T>(t + 1, N, ld, lane, cam, pt, hcp, nj, ni, nh);
-            const bool valid = 64 * t + lane < N;
-            const bool owned = valid && (t < T1 ? ci != skip_pt : ci == carry_pt);
-            const uint64_t om = __ballot(owned);
-            if (om != 0) {
-                const int32_t prev_i = __shfl_up(ci, 1, 64);
-                const int prev_own = __shfl_up(owned ? 1 : 0, 1, 64);
-                const bool head = owned && (lane == 0 || !prev_own || prev_i != ci);
-                const uint64_t hm = __ballot(head);
+            load_tile<T>(t + 1, ld, lane, cam, pt, hcp, nj, ni, nh);  // the padding tile when t + 1 = ntiles
+            int32_t s_pt = -2;  // the tile's last point when it runs on into the next tile
+            const int32_t prev = __shfl_up(ci, 1, 64);
+            const int32_t last_i = __builtin_amdgcn_readlane(ci, 63);
+            const bool valid = ci >= 0;
+            const bool head = valid && ci != (lane == 0 ? before : prev);
+            const uint64_t hm = __ballot(head);
+            if (hm != 0) {
+                const int first_head = __ffsll((unsigned long long)hm) - 1;
+                const bool owned = valid && lane >= first_head;
+                const int last_owned = 63 - __clzll(__ballot(owned));
+                const int last_head = 63 - __clzll(hm);
                 const int seg_s = 63 - __clzll((hm & upto) | 1ull);
-                const int last_owned = 63 - __clzll(om);
                 const uint64_t above = hm & ~upto;
                 const int seg_e = above ? __ffsll((unsigned long long)above) - 2 : last_owned;
-                const int first_head = __ffsll((unsigned long long)hm) - 1;
-                const int last_head = 63 - __clzll(hm);
-                const int32_t i_first = __shfl(ci, first_head, 64);
-                const int32_t i_last = __shfl(ci, last_owned, 64);
-                const bool cont = carry_pt >= 0 && i_first == carry_pt;
-                int32_t inext0 = -2;
-                if (last_owned == 63 && t + 1 < ntiles) inext0 = prefetch ? __shfl(ni, 0, 64) : pt[64 * (t + 1)];
-                const bool last_inc = last_owned == 63 && inext0 == i_last;
-                if (MODE == 0) {
-                    T a0 = (T)0, a1 = (T)0, a2 = (T)0;
-                    if (owned) {
-                        T x[9];
+                if (last_owned == 63) s_pt = last_i;
+                const bool cn = ni == s_pt;  // a prefix of the next tile
+                const uint64_t cm = __ballot(cn);
+                T a0 = (T)0, a1 = (T)0, a2 = (T)0;
+                if (owned) block_t_times_x<T>(ch, xcam, cj, a0, a1, a2);
 #pragma unroll
-                        for (int a = 0; a < 9; ++a) x[a] = xcam[9 * (int64_t)cj + a];
-#pragma unroll
-                        for (int a = 0; a < 9; ++a) {
-                            a0 += ch[a * 3] * x[a];
-                            a1 += ch[a * 3 + 1] * x[a];
-                            a2 += ch[a * 3 + 2] * x[a];
-                        }
+                for (int off = 1; off < 64; off <<= 1) {
+                    const T u0 = __shfl_up(a0, off, 64), u1 = __shfl_up(a1, off, 64), u2 = __shfl_up(a2, off, 64);
+                    if (lane - off >= seg_s) {
+                        a0 += u0;
+                        a1 += u1;
+                        a2 += u2;
                     }
-#pragma unroll
-                    for (int off = 1; off < 64; off <<= 1) {
-                        const T u0 = __shfl_up(a0, off, 64), u1 = __shfl_up(a1, off, 64), u2 = __shfl_up(a2, off, 64);
-                        if (lane - off >= seg_s) {
-                            a0 += u0;
-                            a1 += u1;
-                            a2 += u2;
-                        }
+                }
+                a0 = __shfl(a0, seg_e, 64);
+                a1 = __shfl(a1, seg_e, 64);
+                a2 = __shfl(a2, seg_e, 64);
+                T c0 = (T)0, c1 = (T)0, c2 = (T)0;
+                if (cm != 0) {
+                    if (cn) block_t_times_x<T>(nh, xcam, nj, c0, c1, c2);
+                    c0 = wave_sum(c0);
+                    c1 = wave_sum(c1);
+                    c2 = wave_sum(c2);
+                }
+                const bool longpt = cm == ~0ull && t + 2 < ntiles && pt[64 * (t + 2)] == s_pt;
+                const bool strad = owned && s_pt >= 0 && seg_s == last_head;  // the last point's lanes here
+                if (strad) {
+                    a0 += c0;
+                    a1 += c1;
+                    a2 += c2;
+                }
+                T b0 = (T)0, b1 = (T)0, b2 = (T)0;
+                if (owned && !(longpt && strad)) {
+                    const T* c6 = cinv + 6 * (int64_t)ci;
+                    b0 = c6[0] * a0 + c6[1] * a1 + c6[2] * a2;
+                    b1 = c6[1] * a0 + c6[3] * a1 + c6[4] * a2;
+                    b2 = c6[2] * a0 + c6[4] * a1 + c6[5] * a2;
+                    if (lane == seg_e && has_cold[ci]) {
+                        bcold[3 * (int64_t)ci] = b0;
+                        bcold[3 * (int64_t)ci + 1] = b1;
+                        bcold[3 * (int64_t)ci + 2] = b2;
                     }
-                    a0 = __shfl(a0, seg_e, 64);
-                    a1 = __shfl(a1, seg_e, 64);
-                    a2 = __shfl(a2, seg_e, 64);
-                    if (cont && seg_s == first_head) {
-                        a0 += cr0;
-                        a1 += cr1;
-                        a2 += cr2;
+                    if (cj < K) add_hot<T>(cl, cj, ch, b0, b1, b2);
+                }
+                if (longpt) {
+                    // The last point fills the next tile and goes on.  Its sum so
+                    // far (tiles t and t + 1) is on lane 63; add its further tiles,
+                    // then walk all of its tiles again for the camera side.
+                    T p0 = __shfl(a0, 63, 64), p1 = __shfl(a1, 63, 64), p2 = __shfl(a2, 63, 64);
+                    int64_t u = t + 2;
+                    while (true) {
+                        int32_t j, i;
+                        T h[27];
+                        load_tile<T>(u, ld, lane, cam, pt, hcp, j, i, h);
+                        const bool in = i == s_pt;
+                        T d0 = (T)0, d1 = (T)0, d2 = (T)0;
+                        if (in) block_t_times_x<T>(h, xcam, j, d0, d1, d2);
+                        p0 += wave_sum(d0);
+                        p1 += wave_sum(d1);
+                        p2 += wave_sum(d2);
+                        if (__ballot(in) != ~0ull || u + 1 >= ntiles || pt[64 * (u + 1)] != s_pt) break;
+                        ++u;
                     }
-                    const bool deferred = last_inc && seg_s == last_head;
-                    T b0 = (T)0, b1 = (T)0, b2 = (T)0;
-                    if (owned && !deferred) {
-                        const T* c6 = cinv + 6 * (int64_t)ci;
-                        b0 = c6[0] * a0 + c6[1] * a1 + c6[2] * a2;
-                        b1 = c6[1] * a0 + c6[3] * a1 + c6[4] * a2;
-                        b2 = c6[2] * a0 + c6[4] * a1 + c6[5] * a2;
-                        if (lane == seg_e && has_cold[ci]) {
-                            bcold[3 * (int64_t)ci] = b0;
-                            bcold[3 * (int64_t)ci + 1] = b1;
-                            bcold[3 * (int64_t)ci + 2] = b2;
-                        }
-                        if (cj < K) add_hot<T>(cl, cj, ch, b0, b1, b2);
+                    const T* c6 = cinv + 6 * (int64_t)s_pt;
+                    const T s0 = c6[0] * p0 + c6[1] * p1 + c6[2] * p2;
+                    const T s1 = c6[1] * p0 + c6[3] * p1 + c6[4] * p2;
+                    const T s2 = c6[2] * p0 + c6[4] * p1 + c6[5] * p2;
+                    if (lane == 0 && has_cold[s_pt]) {
+                        bcold[3 * (int64_t)s_pt] = s0;
+                        bcold[3 * (int64_t)s_pt + 1] = s1;
+                        bcold[3 * (int64_t)s_pt + 2] = s2;
                     }
-                    if (cont && !(last_inc && first_head == last_head)) {
-                        // the carried point ends here: its observations in earlier tiles,
-                        // streamed moments ago, are read again (from L2)
-                        const T cb0 = __shfl(b0, first_head, 64), cb1 = __shfl(b1, first_head, 64),
-                                cb2 = __shfl(b2, first_head, 64);
-                        const int64_t older_end = 64 * t;
-                        for (int64_t base = carry_start; base < older_end; base += 64) {
-                            const int64_t kk = base + lane;
-                            if (kk < older_end) {
-                                const int32_t j = cam[kk];
-                                if (j < K) {
-                                    T h[27];
-#pragma unroll
-                                    for (int q = 0; q < 27; ++q) h[q] = hcp[(int64_t)q * ld + kk];
-                                    add_hot<T>(cl, j, h, cb0, cb1, cb2);
-                                }
-                            }
-                        }
+                    for (int64_t v = t; v <= u; ++v) {
+                        int32_t j, i;
+                        T h[27];
+                        load_tile<T>(v, ld, lane, cam, pt, hcp, j, i, h);
+                        if (i == s_pt && j < K) add_hot<T>(cl, j, h, s0, s1, s2);
                     }
-                    if (last_inc) {
-                        cr0 = __shfl(a0, last_head, 64);
-                        cr1 = __shfl(a1, last_head, 64);
-                        cr2 = __shfl(a2, last_head, 64);
-                        if (!(cont && first_head == last_head)) carry_start = 64 * t + last_head;
-                        carry_pt = i_last;
-                    } else {
-                        carry_pt = -1;
-                    }
-                } else {
-                    if (owned) {
-                        const T* c6 = cinv + 6 * (int64_t)ci;
-                        const T w0 = (T)wpt[3 * (int64_t)ci], w1 = (T)wpt[3 * (int64_t)ci + 1],
-                                w2 = (T)wpt[3 * (int64_t)ci + 2];
-                        const T b0 = c6[0] * w0 + c6[1] * w1 + c6[2] * w2;
-                        const T b1 = c6[1] * w0 + c6[3] * w1 + c6[4] * w2;
-                        const T b2 = c6[2] * w0 + c6[4] * w1 + c6[5] * w2;
-                        if (lane == seg_s && has_cold[ci]) {
-                            bcold[3 * (int64_t)ci] = b0;
-                            bcold[3 * (int64_t)ci + 1] = b1;
-                            bcold[3 * (int64_t)ci + 2] = b2;
-                        }
-                        if (cj < K) add_hot<T>(cl, cj, ch, b0, b1, b2);
-                    }
-                    carry_pt = last_inc ? i_last : -1;
+                    // tiles t + 1 .. u - 1 hold only this point; go on at tile u
+                    before = s_pt;
+                    t = u;
+                    if (t < T1) load_tile<T>(t, ld, lane, cam, pt, hcp, cj, ci, ch);
+                    continue;
+                }
+                if (cm != 0) {
+                    const T s0 = __shfl(b0, 63, 64), s1 = __shfl(b1, 63, 64), s2 = __shfl(b2, 63, 64);
+                    if (cn && nj < K) add_hot<T>(cl, nj, nh, s0, s1, s2);
                 }
             }
-            if (prefetch) {
-                cj = nj;
-                ci = ni;
+            before = last_i;
+            cj = nj;
+            ci = ni;
 #pragma unroll
-                for (int q = 0; q < 27; ++q) ch[q] = nh[q];
-            } else if (carry_pt >= 0 && t + 1 < ntiles) {
-                load_tile<T>(t + 1, N, ld, lane, cam, pt, hcp, cj, ci, ch);
-            }
+            for (int q = 0; q < 27; ++q) ch[q] = nh[q];
+            ++t;
         }
     }
     __syncthreads();
@@ -225,11 +237,48 @@ __global__ __launch_bounds__(HotThreads<T>::value) void k_schur_hot(
     for (int q = threadIdx.x; q < K * 9; q += NT) out[q] = cl[q];
 }
 
-__device__ __forceinline__ double wave_sum_d(double v)
+// Point-major pass of the reduced right-hand side: every observation adds
+// E_k C~_i^-1 w_i into its camera (hot cameras into the LDS table), and the
+// first lane of each point run in a tile stores b_i for the cold pass (runs
+// of one point in several tiles store the same value).  Observations are
+// independent here, so the tiles need no ownership rule.
+template <typename T>
+__global__ __launch_bounds__(HotThreads<T>::value) void k_schur_rhs(
+    const int32_t* __restrict__ wrange, int64_t N, int64_t ld, const int32_t* __restrict__ cam,
+    const int32_t* __restrict__ pt, const T* __restrict__ hcp, const T* __restrict__ cinv,
+    const double* __restrict__ wpt, int32_t K, double* __restrict__ hot_part, T* __restrict__ bcold,
+    const uint8_t* __restrict__ has_cold)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    constexpr int NT = HotThreads<T>::value;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* cl = reinterpret_cast<double*>(smem);
+    for (int q = threadIdx.x; q < K * 9; q += NT) cl[q] = 0.0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int32_t gw = __builtin_amdgcn_readfirstlane(blockIdx.x * (NT / 64) + (threadIdx.x >> 6));
+    const int64_t T0 = wrange[gw], T1 = wrange[gw + 1];
+    for (int64_t t = T0; t < T1; ++t) {
+        int32_t j, i;
+        T h[27];
+        load_tile<T>(t, ld, lane, cam, pt, hcp, j, i, h);
+        const int32_t prev = __shfl_up(i, 1, 64);
+        if (i >= 0) {
+            const T* c6 = cinv + 6 * (int64_t)i;
+            const T w0 = (T)wpt[3 * (int64_t)i], w1 = (T)wpt[3 * (int64_t)i + 1], w2 = (T)wpt[3 * (int64_t)i + 2];
+            const T b0 = c6[0] * w0 + c6[1] * w1 + c6[2] * w2;
+            const T b1 = c6[1] * w0 + c6[3] * w1 + c6[4] * w2;
+            const T b2 = c6[2] * w0 + c6[4] * w1 + c6[5] * w2;
+            if ((lane == 0 || prev != i) && has_cold[i]) {
+                bcold[3 * (int64_t)i] = b0;
+                bcold[3 * (int64_t)i + 1] = b1;
+                bcold[3 * (int64_t)i + 2] = b2;
+            }
+            if (j < K) add_hot<T>(cl, j, h, b0, b1, b2);
+        }
+    }
+    __syncthreads();
+    double* out = hot_part + (int64_t)blockIdx.x * K * 9;
+    for (int q = threadIdx.x; q < K * 9; q += NT) out[q] = cl[q];
 }
 
 // Cold observations, camera-major: c_k = E_k b_i, reduced per camera by wave
@@ -275,7 +324,7 @@ __global__ __launch_bounds__(256) void k_schur_cold(int64_t Nc, int32_t num_chun
             if (more == 0) break;
 #pragma unroll
             for (int a = 0; a < 9; ++a) {
-                const double v = wave_sum_d(acc[a]);
+                const double v = wave_sum(acc[a]);
                 if (lane == 0) slots[(int64_t)slot * 9 + a] = v;
                 acc[a] = 0.0;
             }
@@ -285,7 +334,7 @@ __global__ __launch_bounds__(256) void k_schur_cold(int64_t Nc, int32_t num_chun
     }
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-        const double v = wave_sum_d(acc[a]);
+        const double v = wave_sum(acc[a]);
         if (lane == 0) slots[(int64_t)slot * 9 + a] = v;
     }
 }
@@ -355,7 +404,7 @@ __global__ __launch_bounds__(kRedBlock) void k_schur_epilogue(
             acc += v * v;
         }
     }
-    acc = wave_sum_d(acc);
+    acc = wave_sum(acc);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -366,7 +415,7 @@ __global__ __launch_bounds__(kRedBlock) void k_schur_epilogue(
     if (!last_block_arrives(&sc->arrive[MODE == 0 ? 1 : 2])) return;
     double tot = 0.0;
     for (int32_t b = threadIdx.x; b < (int32_t)gridDim.x; b += kRedBlock) tot += partials[b];
-    tot = wave_sum_d(tot);
+    tot = wave_sum(tot);
     __syncthreads();
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = tot;
     __syncthreads();
@@ -408,9 +457,9 @@ template <typename T>
 hipError_t prepare_schur_kernels(int32_t K)
 {
     const int bytes = (int)hot_lds_bytes<T>(K);
-    hipError_t e = hipFuncSetAttribute((const void*)k_schur_hot<T, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    hipError_t e = hipFuncSetAttribute((const void*)k_schur_hot<T>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)k_schur_hot<T, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    return hipFuncSetAttribute((const void*)k_schur_rhs<T>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 template <typename T>
@@ -426,11 +475,11 @@ hipError_t launch_schur_product(int mode, const SchurPlan& sp, const PointMajor&
     if (sp.num_wg > 0) {
         const dim3 g(sp.num_wg), b(HotThreads<T>::value);
         if (mode == 0)
-            hipLaunchKernelGGL((k_schur_hot<T, 0>), g, b, lds, s, sp.wrange, N, pm.ld, pm.cam, pm.pt, hcp, cinv,
-                               wpt, xcam, sp.K, (double*)sp.hot_part, (T*)sp.bcold, sp.has_cold, sc);
+            hipLaunchKernelGGL((k_schur_hot<T>), g, b, lds, s, sp.wrange, N, pm.ld, pm.cam, pm.pt, hcp, cinv, xcam,
+                               sp.K, (double*)sp.hot_part, (T*)sp.bcold, sp.has_cold, sc);
         else
-            hipLaunchKernelGGL((k_schur_hot<T, 1>), g, b, lds, s, sp.wrange, N, pm.ld, pm.cam, pm.pt, hcp, cinv,
-                               wpt, xcam, sp.K, (double*)sp.hot_part, (T*)sp.bcold, sp.has_cold, sc);
+            hipLaunchKernelGGL((k_schur_rhs<T>), g, b, lds, s, sp.wrange, N, pm.ld, pm.cam, pm.pt, hcp, cinv, wpt,
+                               sp.K, (double*)sp.hot_part, (T*)sp.bcold, sp.has_cold);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (hot_end && (e = hipEventRecord(hot_end, s)) != hipSuccess) return e;

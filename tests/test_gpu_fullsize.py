@@ -99,15 +99,36 @@ def replay(name, precision=FP64, schedule=True):
 
 @pytest.mark.parametrize("name", ["medium", "large"])
 def test_lm_trace_fp64_matches_oracle(name):
+    """Per-iteration parity on the trial and accepted costs: relative 1e-9,
+    widened where the step itself is known only loosely.
+      * PCG stopped at its iteration cap without reaching rtol: two FP64 CG
+        runs that differ only in summation order drift apart over many
+        unconverged iterations, so the trial cost may also differ by 1e-7 of
+        the cost change |F_trial - F|.
+      * A trial point far outside the region where the step's linear model
+        holds (its cost rises more than tenfold) puts observations close to a
+        camera's principal plane, where the cost is very sensitive to the
+        values; there the costs are compared to 1e-5 and both sides must
+        reject."""
     g, rep = replay(name)
     assert rep["status"] == 0 and rep["iters_run"] == g["iters_run"]
     assert abs(rep["initial_cost"] - g["initial_cost"]) <= 1e-12 * g["initial_cost"]
+    cap = g["options"]["max_pcg_iters"]
     prev = g["initial_cost"]
     same_path = True
     for k in range(g["iters_run"]):
-        assert abs(rep["trial_cost"][k] - g["trial_cost"][k]) <= 1e-9 * g["trial_cost"][k], k
-        assert abs(rep["cost"][k] - g["cost"][k]) <= 1e-9 * g["cost"][k], k
-        if same_path and abs(prev - g["trial_cost"][k]) > 1e-10 * prev:
+        ft = g["trial_cost"][k]
+        wild = ft > 10 * prev
+        tol = 1e-5 * ft if wild else 1e-9 * ft
+        if not wild and g["pcg_iters"][k] >= cap:
+            tol += 1e-7 * abs(ft - prev)
+        err = abs(rep["trial_cost"][k] - ft)
+        print(f"iter {k}: trial rel diff {err / ft:.2e} (tol {tol / ft:.1e}), pcg {g['pcg_iters'][k]}")
+        assert err <= tol, k
+        assert abs(rep["cost"][k] - g["cost"][k]) <= max(tol, 1e-9 * g["cost"][k]), k
+        if wild:
+            assert not rep["accepted"][k] and not g["accepted"][k], k
+        if same_path and abs(prev - ft) > 1e-10 * prev:
             assert rep["accepted"][k] == g["accepted"][k], k
         else:
             same_path = False
