@@ -52,6 +52,28 @@ def hot_pass_algorithmic_bytes(n, N, w):
     return N * (27 * w + 4) + n * (6 * w + 4)
 
 
+def counted_traffic(kernel="k_schur_hot<float>"):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's reading),
+    or None when the kernel source has changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "schur_hot_29M_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        key, sep, val = line.strip().partition(": ")
+        if sep:
+            fields[key] = val
+    h = hashlib.sha256()
+    for f in ("matvec.hip", "ba_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2112_01349_amd", "csrc", f), "rb").read())
+    if fields.get("kernel") != kernel or fields.get("source_sha256") != h.hexdigest()[:16]:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def run_precision(prob_data, precision, wl, steps, warmup):
     import torch
 
@@ -226,8 +248,9 @@ def main():
                    "cameras": m, "points": n, "observations": N},
         "pcg_iter_per_s": s32["pcg_iter_per_s"],
         "roofline": {"bound": "hbm", "achieved": s32["hot_kernel_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": s32["hot_kernel_frac"], "traffic": None,
-                     "kernel": "k_schur_hot<float,0> (point-major pass of the implicit Schur matvec)",
+                     "frac": s32["hot_kernel_frac"],
+                     "traffic": counted_traffic() if args.workload == "large" else None,
+                     "kernel": "k_schur_hot<float> (point-major pass of the implicit Schur matvec)",
                      "bytes_per_launch": s32["hot_kernel_bytes"], "avg_ms": s32["hot_kernel_ms"]},
         "fp32_mixed": s32,
     }
