@@ -30,6 +30,8 @@ WORKLOADS = {  # name -> synth config and solver settings
     "large": dict(config="large", huber_delta=1.0, max_pcg_iters=100, pcg_rtol=1e-6),
     "medium": dict(config="medium", huber_delta=0.0, max_pcg_iters=100, pcg_rtol=1e-6),
     "stress": dict(config="stress", huber_delta=1.0, max_pcg_iters=200, pcg_rtol=1e-6),
+    # one GPU's share of the 29M workload split over 8 GPUs (point-aligned edge partition)
+    "large_chunk8": dict(config="large", chunk=(0, 8), huber_delta=1.0, max_pcg_iters=100, pcg_rtol=1e-6),
     "tiny": dict(config="tiny", huber_delta=0.0, max_pcg_iters=50, pcg_rtol=1e-8),
 }
 
@@ -83,8 +85,9 @@ def run_precision(prob_data, precision, wl, steps, warmup):
     t0 = time.perf_counter()
     prob = Problem(cams, pts, oc, op, uv, precision=precision, huber_delta=wl["huber_delta"],
                    max_pcg_iters=wl["max_pcg_iters"], pcg_rtol=wl["pcg_rtol"])
+    device_bytes = prob.memory_bytes()
     log(f"[bench] precision={precision} create {time.perf_counter() - t0:.1f}s "
-        f"device bytes {prob.memory_bytes() / 1e9:.2f} GB")
+        f"device bytes {device_bytes / 1e9:.2f} GB")
     if warmup > 0:
         prob.lm_solve(max_lm_iters=warmup)
         prob.set_params(cams, pts)
@@ -96,6 +99,7 @@ def run_precision(prob_data, precision, wl, steps, warmup):
     log(f"[bench] precision={precision} {steps} LM iters in {wall:.3f}s; pcg {rep['pcg_iters'].tolist()} "
         f"accepted {rep['accepted'].tolist()} cost {rep['initial_cost']:.6g} -> {rep['final_cost']:.6g}")
     prob.close()
+    rep["device_bytes"] = device_bytes
     return rep, wall
 
 
@@ -205,6 +209,8 @@ def main():
         del src, dst
     t0 = time.perf_counter()
     prob = synth.generate(wl["config"], seed=0)
+    if "chunk" in wl:
+        prob = synth.point_chunk(prob, *wl["chunk"])
     log(f"[bench] generated {args.workload}: m={prob.num_cameras} n={prob.num_points} N={prob.num_obs} "
         f"in {time.perf_counter() - t0:.1f}s")
     data = (prob.cameras0, prob.points0, prob.obs_camera, prob.obs_point, prob.obs_uv)
@@ -231,6 +237,7 @@ def main():
                     matvec_frac=gbs / HBM_PEAK_GBS, hot_kernel_ms=hot_ms, hot_kernel_bytes=hot_bytes,
                     hot_kernel_gbs=hot_gbs, hot_kernel_frac=hot_gbs / HBM_PEAK_GBS,
                     initial_cost=rep["initial_cost"], final_cost=rep["final_cost"],
+                    device_bytes=int(rep["device_bytes"]),
                     pcg_per_lm=rep["pcg_iters"].tolist(), accepted=rep["accepted"].tolist())
 
     s32 = summary(*res["fp32_mixed"])
@@ -243,7 +250,9 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64 (mixed)", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {m} cameras, {n} points, {N} observations, "
-                               f"Zipf visibility, Huber delta={wl['huber_delta']}, PCG max "
+                               + (f"point-aligned chunk {wl['chunk'][0]} of {wl['chunk'][1]} of '{wl['config']}', "
+                                  if "chunk" in wl else "")
+                               + f"Zipf visibility, Huber delta={wl['huber_delta']}, PCG max "
                                f"{wl['max_pcg_iters']} rtol {wl['pcg_rtol']}",
                    "cameras": m, "points": n, "observations": N},
         "pcg_iter_per_s": s32["pcg_iter_per_s"],

@@ -54,6 +54,12 @@ __device__ __forceinline__ bool last_block_arrives(uint32_t* counter)
     return last;
 }
 
+// The point-major coupling blocks E are stored tile-blocked: the 27 rows of
+// each 64-observation tile are contiguous ([tile][27][64] of T), so one tile
+// is a single run of memory (6.9 KB in FP32) and every row is a 256-byte
+// (FP32) or 512-byte (FP64) aligned piece of it.
+__host__ __device__ __forceinline__ int64_t eidx(int64_t k, int q) { return ((k >> 6) * 27 + q) * 64 + (k & 63); }
+
 // Point-major observation stream (sorted by point, then camera).
 struct PointMajor {
     int32_t* cam;      // [ld] internal camera id
@@ -62,9 +68,8 @@ struct PointMajor {
     double* uvy;       // [N]
     int32_t* tile;     // [num_tiles + 1] observation offsets of point-aligned tiles
     int32_t num_tiles;
-    int64_t ld;        // leading dimension of the [27][ld] coupling-block streams: N
-                       // rounded up to 64 plus one padding tile (cam 0, pt -1), so
-                       // 64-observation tiles are line-aligned and tile t + 1 exists
+    int64_t ld;        // stream length: N rounded up to 64 plus one padding tile
+                       // (cam 0, pt -1), so tile t + 1 always exists; E holds 27 ld
 };
 
 // Camera-major observation stream (sorted by camera, then point).

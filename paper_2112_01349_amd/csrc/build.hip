@@ -6,7 +6,7 @@
 // index and pixel streams:
 //   * point-major (k_build_points): one workgroup per point-aligned tile of
 //     <= 256 observations, one thread per observation.  Writes the coupling
-//     block E_k = w J_c^T J_p as 27 coalesced streams [27][ld], and sums the
+//     block E_k = w J_c^T J_p (tile-blocked, see eidx), and sums the
 //     point blocks C_i = sum w J_p^T J_p and w_i = -sum w J_p^T e over each
 //     point's run through LDS.
 //   * camera-major (k_build_cameras): one wavefront per contiguous chunk of
@@ -75,6 +75,19 @@ __device__ __forceinline__ void observation(int64_t k, const int32_t* __restrict
     wt = huber_weight<T>(e0 * e0 + e1 * e1, delta);
 }
 
+// E_k into the tile-blocked point-major array.
+template <typename T>
+__device__ __forceinline__ void store_coupling_blocked(int64_t k, const T Jc[18], const T Jp[6], T wt,
+                                                       T* __restrict__ hcp)
+{
+    T* base = hcp + eidx(k, 0);
+#pragma unroll
+    for (int a = 0; a < 9; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) base[(a * 3 + b) * 64] = wt * (Jc[a] * Jp[b] + Jc[9 + a] * Jp[3 + b]);
+}
+
+// E_k into row-major streams [27][N] (the cold copy).
 template <typename T>
 __device__ __forceinline__ void store_coupling(int64_t k, int64_t N, const T Jc[18], const T Jp[6], T wt,
                                                T* __restrict__ hcp)
@@ -120,7 +133,7 @@ __global__ __launch_bounds__(kTile) void k_build_points(
             const int64_t k = s + tid;
             T e0, e1, wt, Jc[18], Jp[6];
             observation<T>(k, cam, pt, uvx, uvy, pts, ck, delta, e0, e1, wt, Jc, Jp, i);
-            if (!GRAD_ONLY) store_coupling<T>(k, ld, Jc, Jp, wt, hcp);
+            if (!GRAD_ONLY) store_coupling_blocked<T>(k, Jc, Jp, wt, hcp);
             T v[9];
             point_terms<T>(Jp, e0, e1, wt, v);
 #pragma unroll
@@ -152,7 +165,7 @@ __global__ __launch_bounds__(kTile) void k_build_points(
             T e0, e1, wt, Jc[18], Jp[6];
             int32_t ii;
             observation<T>(k, cam, pt, uvx, uvy, pts, ck, delta, e0, e1, wt, Jc, Jp, ii);
-            if (!GRAD_ONLY) store_coupling<T>(k, ld, Jc, Jp, wt, hcp);
+            if (!GRAD_ONLY) store_coupling_blocked<T>(k, Jc, Jp, wt, hcp);
             T v[9];
             point_terms<T>(Jp, e0, e1, wt, v);
 #pragma unroll

@@ -167,7 +167,7 @@ __global__ __launch_bounds__(kTile) void k_schur_tiles(const int32_t* __restrict
             j = cam[k];
             i = pt[k];
 #pragma unroll
-            for (int q = 0; q < 27; ++q) h[q] = hcp[(int64_t)q * N + k];
+            for (int q = 0; q < 27; ++q) h[q] = hcp[eidx(k, q)];
             if (MODE != 1) {
                 T x[9];
 #pragma unroll
@@ -236,7 +236,7 @@ __global__ __launch_bounds__(kTile) void k_schur_tiles(const int32_t* __restrict
                     for (int b = 0; b < 3; ++b) {
                         T acc = 0;
 #pragma unroll
-                        for (int a = 0; a < 9; ++a) acc += hcp[(int64_t)(a * 3 + b) * N + k] * xcam[9 * (int64_t)j + a];
+                        for (int a = 0; a < 9; ++a) acc += hcp[eidx(k, a * 3 + b)] * xcam[9 * (int64_t)j + a];
                         if (b == 0) a0 += acc;
                         if (b == 1) a1 += acc;
                         if (b == 2) a2 += acc;
@@ -282,8 +282,8 @@ __global__ __launch_bounds__(kTile) void k_schur_tiles(const int32_t* __restrict
 #pragma unroll
                 for (int a = 0; a < 9; ++a)
                     atomic_add_f64(cacc + 9 * (int64_t)j + a,
-                                   (double)(hcp[(int64_t)(a * 3) * N + k] * b0 + hcp[(int64_t)(a * 3 + 1) * N + k] * b1 +
-                                            hcp[(int64_t)(a * 3 + 2) * N + k] * b2));
+                                   (double)(hcp[eidx(k, a * 3)] * b0 + hcp[eidx(k, a * 3 + 1)] * b1 +
+                                            hcp[eidx(k, a * 3 + 2)] * b2));
             }
         }
     }

@@ -36,7 +36,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-__all__ = ["Problem", "CONFIGS", "generate", "ring_rotation", "rotvec_from_matrix"]
+__all__ = ["Problem", "CONFIGS", "generate", "point_chunk", "ring_rotation", "rotvec_from_matrix"]
 
 
 @dataclass
@@ -274,6 +274,24 @@ def generate(name: str, seed: int = 0, outliers: float | None = None) -> Problem
 
     meta = dict(config=name, seed=seed, power_law_exponent=expo, outlier_fraction=out_frac)
     return Problem(name, cams, pts, cams0, pts0, obs_camera, obs_point, uv_obs, flag, meta)
+
+
+def point_chunk(prob: Problem, k: int, K: int) -> Problem:
+    """Chunk k of K of the edge partition made point-aligned: the points are
+    cut, in index order, into K runs of about N/K observations each (a point
+    is never split); the chunk keeps every camera and its own points,
+    renumbered from 0, with their observations in the original order.  This
+    is the share one of K GPUs would hold."""
+    counts = np.bincount(prob.obs_point, minlength=prob.num_points)
+    cum = np.concatenate([[0], np.cumsum(counts)])
+    bounds = np.searchsorted(cum, np.arange(K + 1) * (prob.num_obs / K), side="left")
+    bounds[0], bounds[-1] = 0, prob.num_points
+    p0, p1 = int(bounds[k]), int(bounds[k + 1])
+    sel = (prob.obs_point >= p0) & (prob.obs_point < p1)
+    meta = dict(prob.meta, chunk=(k, K), points=(p0, p1))
+    return Problem(f"{prob.name}_chunk{k}of{K}", prob.cameras_true, prob.points_true[p0:p1], prob.cameras0,
+                   prob.points0[p0:p1], prob.obs_camera[sel], (prob.obs_point[sel] - p0).astype(np.int32),
+                   prob.obs_uv[sel], prob.outlier[sel], meta)
 
 
 def render_exact(prob: Problem) -> np.ndarray:

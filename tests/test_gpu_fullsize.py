@@ -141,3 +141,58 @@ def test_lm_mixed_reaches_oracle_final_cost():
     costs = np.concatenate([[rep["initial_cost"]], rep["cost"]])
     assert np.all(np.diff(costs) <= 0)
     assert rep["final_cost"] <= g["final_cost"] * (1 + 1e-4), (rep["final_cost"], g["final_cost"])
+
+
+def test_stress_cost_gradient_and_schur_rows():
+    """The 60M-observation stress workload (20,000 cameras, 10M points, Huber,
+    5% outliers) in the FP32-mixed form: FP64 cost and sampled gradients
+    against the oracle, sampled reduced-system rows against the oracle's rows
+    computed from scratch, and two LM iterations with non-increasing cost."""
+    prob = synth.generate("stress", seed=0)
+    args = (prob.cameras0, prob.points0, prob.obs_camera, prob.obs_point, prob.obs_uv)
+    gpu = Problem(*args, precision=FP32_MIXED, huber_delta=DELTA)
+    F, gc, gp = gpu.eval_cost_grad()
+    Fo = orc.cost(*args, DELTA)
+    assert abs(F - Fo) <= 1e-12 * Fo
+    cam_csr = orc.csr(prob.obs_camera, prob.num_cameras)
+    pt_csr = orc.csr(prob.obs_point, prob.num_points)
+    counts = np.diff(cam_csr[0])
+    order = np.argsort(-counts, kind="stable")
+    rows = [int(order[5000]), int(order[-1]), int(order[12000])]
+    off, obs = cam_csr
+    for j in rows:
+        ref = -orc.subset_sums(obs[off[j]:off[j + 1]], *args, DELTA)["v"]
+        assert np.max(np.abs(gc[j] - ref)) <= 1e-10 * np.max(np.abs(ref)), j
+    x = np.random.default_rng(8).normal(size=(prob.num_cameras, 9))
+    q = gpu.schur_matvec(x, 1e-3)
+    ref = orc.schur_rows(rows, *args[:2], *args[2:], x, 1e-3, DELTA, cam_csr=cam_csr, pt_csr=pt_csr)
+    for t, j in enumerate(rows):
+        assert np.max(np.abs(q[j] - ref[t])) <= 2e-3 * np.max(np.abs(ref[t])), j
+    rep = gpu.lm_solve(max_lm_iters=2, max_pcg_iters=200, pcg_rtol=1e-6)
+    gpu.close()
+    assert rep["status"] == 0
+    costs = np.concatenate([[rep["initial_cost"]], rep["cost"]])
+    assert np.all(np.diff(costs) <= 0)
+
+
+def test_chunk_of_eight_lm_matches_oracle():
+    """One GPU's share of the 29M workload split over eight GPUs (all 13,700
+    cameras, the first 1/8 of the observations at point boundaries): three
+    FP64 LM iterations (lambda_0 = 1e-2, so the steps are accepted, and a
+    fixed PCG count of 12) match the oracle's costs to 1e-9."""
+    full = synth.generate("large", seed=0)
+    prob = synth.point_chunk(full, 0, 8)
+    del full
+    assert abs(prob.num_obs - 29_000_000 / 8) < 100
+    args = (prob.cameras0, prob.points0, prob.obs_camera, prob.obs_point, prob.obs_uv)
+    kw = dict(huber_delta=DELTA, max_lm_iters=3, pcg_schedule=[12, 12, 12], lambda_init=1e-2)
+    _, _, tr, rc = orc.lm_solve(*args, **kw)
+    assert rc == 0 and list(tr["accepted"]) == [1, 1, 1]
+    gpu = Problem(*args, huber_delta=DELTA)
+    rep = gpu.lm_solve(max_lm_iters=3, pcg_schedule=[12, 12, 12], lambda_init=1e-2)
+    gpu.close()
+    assert rep["status"] == 0
+    assert abs(rep["initial_cost"] - tr["initial_cost"]) <= 1e-12 * tr["initial_cost"]
+    for k in range(3):
+        assert abs(rep["trial_cost"][k] - tr["trial_cost"][k]) <= 1e-9 * tr["trial_cost"][k], k
+        assert rep["accepted"][k] == 1, k
