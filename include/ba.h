@@ -49,9 +49,10 @@ typedef enum {
 
 typedef enum {
     BA_FP64 = 0,       /* every step in FP64 */
-    BA_FP32_MIXED = 1  /* Jacobians, Schur blocks and matvecs in FP32; cost sums,
-                          PCG vectors/dots/scalars and the 9x9 camera-block
-                          factorisations in FP64 (paper Sec. 6, Table float) */
+    BA_FP32_MIXED = 1  /* Jacobians, coupling blocks E, C~^-1 and matvecs in FP32;
+                          cost sums, PCG vectors/dots/scalars, the 9x9 camera-block
+                          factorisations and the 3x3 point-block sums and
+                          inversions in FP64 (paper Sec. 6, Table float) */
 } ba_precision;
 
 typedef enum {

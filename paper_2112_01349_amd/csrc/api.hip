@@ -68,7 +68,7 @@ struct ba_problem {
     SchurPlan sp{};
     // blocks
     void* hcp = nullptr;   // [27][N] of T
-    void* hpp = nullptr;   // [n][6] of T
+    void* hpp = nullptr;   // [n][6] FP64 (summed and inverted in FP64 in both forms)
     void* cinv = nullptr;  // [n][6] of T
     double* wpt = nullptr; // [n][3]
     double *hcc = nullptr, *vcam = nullptr, *bd = nullptr, *lfac = nullptr, *dcam = nullptr;
@@ -446,7 +446,7 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     P->cm.seg_part = A.get<double>((int64_t)P->cm.num_segs * kCamSlotWords);
     P->cm.arrive = A.get<uint32_t>(m);
     P->hcp = A.get<char>(27 * P->pm.ld * (int64_t)tsz);
-    P->hpp = A.get<char>(6 * (int64_t)n * (int64_t)tsz);
+    P->hpp = A.get<char>(6 * (int64_t)n * (int64_t)sizeof(double));
     P->cinv = A.get<char>(6 * (int64_t)n * (int64_t)tsz);
     P->wpt = A.get<double>(3 * (int64_t)n);
     P->hcc = A.get<double>(81 * (int64_t)m);
@@ -519,7 +519,7 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     if (e == hipSuccess) e = up(sp.cold.cam_slot, cold_cam_slot.data(), sizeof(int32_t) * cold_cam_slot.size());
     if (e == hipSuccess)
         e = P->is_f32() ? prepare_schur_kernels<float>(sp.K) : prepare_schur_kernels<double>(sp.K);
-    if (e == hipSuccess) e = hipMemset(P->hpp, 0, 6 * (size_t)(n > 0 ? n : 1) * tsz);
+    if (e == hipSuccess) e = hipMemset(P->hpp, 0, 6 * (size_t)(n > 0 ? n : 1) * sizeof(double));
     if (e == hipSuccess) e = hipMemset(P->wpt, 0, 3 * (size_t)(n > 0 ? n : 1) * sizeof(double));
     if (e == hipSuccess) e = hipMemset(P->sc, 0, sizeof(PcgScalars));
     if (e == hipSuccess) e = hipMemset(P->flag, 0, sizeof(int32_t));
@@ -598,7 +598,7 @@ static ba_status build_system(ba_problem* P)
     } else {
         ck = (const CamK<T>*)P->ck64;
     }
-    BA_TRY(P, launch_build_points<T>(P->pm, P->opt.huber_delta, false, P->pts, ck, (T*)P->hcp, (T*)P->hpp, P->wpt, s));
+    BA_TRY(P, launch_build_points<T>(P->pm, P->opt.huber_delta, false, P->pts, ck, (T*)P->hcp, (double*)P->hpp, P->wpt, s));
     BA_TRY(P, launch_build_cameras<T>(P->cm, P->m, P->N, P->pts, ck, P->opt.huber_delta, false, P->hcc, P->vcam,
                                       P->sp.cold.N, (T*)P->sp.cold.hcp, s));
     return BA_OK;
@@ -719,7 +719,7 @@ static ba_status lm_solve_t(ba_problem* P, const ba_options& o, ba_report* rep)
             need_build = false;
         }
         BA_TRY(P, launch_damp_cameras(m, P->hcc, lambda, o.damping, P->bd, P->lfac, P->dcam, P->flag, s));
-        BA_TRY(P, launch_damp_points<T>(n, (const T*)P->hpp, lambda, o.damping, (T*)P->cinv, P->flag, s));
+        BA_TRY(P, launch_damp_points<T>(n, (const double*)P->hpp, lambda, o.damping, (T*)P->cinv, P->flag, s));
         BA_TRY(P, hipMemcpyAsync(P->h_scalars, P->flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         BA_TRY(P, hipStreamSynchronize(s));
         if (*(int32_t*)P->h_scalars != 0) {
@@ -747,7 +747,7 @@ static ba_status lm_solve_t(ba_problem* P, const ba_options& o, ba_report* rep)
         BA_TRY(P, launch_camera_constants_f64(m, P->cams_t, P->ck64_t, s));
         if ((st = cost_into_sums<double>(P, P->pts_t, P->ck64_t, s)) != BA_OK) return st;
         int32_t nb = 0;
-        BA_TRY(P, launch_pred<T>(m, n, P->x, P->dcam, P->vcam, P->dp, (const T*)P->hpp, P->wpt, lambda, o.damping,
+        BA_TRY(P, launch_pred<T>(m, n, P->x, P->dcam, P->vcam, P->dp, (const double*)P->hpp, P->wpt, lambda, o.damping,
                                  P->partials, &nb, s));
         BA_TRY(P, launch_sum_partials(P->partials, nb, 2, 2, P->sums + 1, s));
         if ((st = read_scalars(P, P->sums, 3 * sizeof(double))) != BA_OK) return st;
@@ -918,7 +918,7 @@ static ba_status schur_matvec_t(ba_problem* P, double lambda, int32_t damping, c
     ba_status st;
     if ((st = build_system<T>(P)) != BA_OK) return st;
     BA_TRY(P, launch_damp_cameras(m, P->hcc, lambda, damping, P->bd, P->lfac, P->dcam, P->flag, s));
-    BA_TRY(P, launch_damp_points<T>(n, (const T*)P->hpp, lambda, damping, (T*)P->cinv, P->flag, s));
+    BA_TRY(P, launch_damp_points<T>(n, (const double*)P->hpp, lambda, damping, (T*)P->cinv, P->flag, s));
     std::vector<double> xi((size_t)9 * m), qi((size_t)9 * m);
     for (int32_t j = 0; j < m; ++j)
         std::memcpy(&xi[(size_t)9 * j], x + (size_t)9 * P->old_of_new[j], 9 * sizeof(double));

@@ -139,7 +139,7 @@ hipError_t launch_camera_constants_f32(int32_t m, const double* cams, CamK<float
 // grad_only) and w_i into wpt.
 template <typename T>
 hipError_t launch_build_points(const PointMajor& pm, double delta, bool grad_only, const double* pts,
-                               const CamK<T>* ck, T* hcp, T* hpp, double* wpt, hipStream_t s);
+                               const CamK<T>* ck, T* hcp, double* hpp, double* wpt, hipStream_t s);
 // Camera-major build: B_j (unless grad_only) and v_j; the last Nc
 // observations of the camera-major stream (the cold cameras) also store E_k
 // into chcp[q * Nc + k - (N - Nc)].
@@ -151,7 +151,7 @@ hipError_t launch_build_cameras(const CameraMajor& cm, int32_t m, int64_t N, con
 hipError_t launch_damp_cameras(int32_t m, const double* hcc, double lambda, int32_t damping,
                                double* bd, double* lfac, double* dcam, int32_t* flag, hipStream_t s);
 template <typename T>
-hipError_t launch_damp_points(int32_t n, const T* hpp, double lambda, int32_t damping, T* cinv,
+hipError_t launch_damp_points(int32_t n, const double* hpp, double lambda, int32_t damping, T* cinv,
                               int32_t* flag, hipStream_t s);
 
 // mode 0: c = E C^-1 E^T x    (implicit Schur product without the B term)
@@ -204,7 +204,7 @@ hipError_t launch_cost_t(const PointMajor& pm, int64_t N, const double* pts, con
                          double delta, double* partials, int32_t* nblocks, hipStream_t s);
 template <typename T>
 hipError_t launch_pred(int32_t m, int32_t n, const double* dc, const double* dcam, const double* vcam,
-                       const double* dp, const T* hpp, const double* wpt, double lambda, int32_t damping,
+                       const double* dp, const double* hpp, const double* wpt, double lambda, int32_t damping,
                        double* partials, int32_t* nblocks, hipStream_t s);
 
 // caller order <-> internal order, with dtype conversion

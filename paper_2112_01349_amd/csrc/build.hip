@@ -116,7 +116,7 @@ template <typename T, bool GRAD_ONLY>
 __global__ __launch_bounds__(kTile) void k_build_points(
     const int32_t* __restrict__ tile, const int32_t* __restrict__ cam, const int32_t* __restrict__ pt,
     const double* __restrict__ uvx, const double* __restrict__ uvy, const double* __restrict__ pts,
-    const CamK<T>* __restrict__ ck, T delta, int64_t ld, T* __restrict__ hcp, T* __restrict__ hpp,
+    const CamK<T>* __restrict__ ck, T delta, int64_t ld, T* __restrict__ hcp, double* __restrict__ hpp,
     double* __restrict__ wpt)
 {
     constexpr int R = GRAD_ONLY ? 3 : 9;  // terms kept: [C upper 6 |] w 3
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(kTile) void k_build_points(
                 for (int q = 0; q < R; ++q) acc[q] += (double)sh[q][u];
             if (!GRAD_ONLY)
 #pragma unroll
-                for (int q = 0; q < 6; ++q) hpp[6 * (int64_t)i + q] = (T)acc[q];
+                for (int q = 0; q < 6; ++q) hpp[6 * (int64_t)i + q] = acc[q];
 #pragma unroll
             for (int q = 0; q < 3; ++q) wpt[3 * (int64_t)i + q] = acc[R - 3 + q];
         }
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(kTile) void k_build_points(
             }
             if (!GRAD_ONLY)
 #pragma unroll
-                for (int q = 0; q < 6; ++q) hpp[6 * (int64_t)i + q] = (T)tot[q];
+                for (int q = 0; q < 6; ++q) hpp[6 * (int64_t)i + q] = tot[q];
 #pragma unroll
             for (int q = 0; q < 3; ++q) wpt[3 * (int64_t)i + q] = tot[R - 3 + q];
         }
@@ -195,13 +195,13 @@ __global__ __launch_bounds__(kTile) void k_build_points(
 
 template <typename T>
 hipError_t launch_build_points(const PointMajor& pm, double delta, bool grad_only, const double* pts,
-                               const CamK<T>* ck, T* hcp, T* hpp, double* wpt, hipStream_t s)
+                               const CamK<T>* ck, T* hcp, double* hpp, double* wpt, hipStream_t s)
 {
     if (pm.num_tiles <= 0) return hipGetLastError();
     const dim3 g((unsigned)pm.num_tiles), b(kTile);
     if (grad_only)
         hipLaunchKernelGGL((k_build_points<T, true>), g, b, 0, s, pm.tile, pm.cam, pm.pt, pm.uvx, pm.uvy, pts, ck,
-                           (T)delta, pm.ld, (T*)nullptr, (T*)nullptr, wpt);
+                           (T)delta, pm.ld, (T*)nullptr, (double*)nullptr, wpt);
     else
         hipLaunchKernelGGL((k_build_points<T, false>), g, b, 0, s, pm.tile, pm.cam, pm.pt, pm.uvx, pm.uvy, pts, ck,
                            (T)delta, pm.ld, hcp, hpp, wpt);
@@ -415,7 +415,7 @@ hipError_t launch_cost(const PointMajor& pm, int64_t N, const double* pts, const
 template hipError_t launch_build_points<double>(const PointMajor&, double, bool, const double*, const CamK<double>*,
                                                 double*, double*, double*, hipStream_t);
 template hipError_t launch_build_points<float>(const PointMajor&, double, bool, const double*, const CamK<float>*,
-                                               float*, float*, double*, hipStream_t);
+                                               float*, double*, double*, hipStream_t);
 template hipError_t launch_build_cameras<double>(const CameraMajor&, int32_t, int64_t, const double*,
                                                  const CamK<double>*, double, bool, double*, double*, int64_t,
                                                  double*, hipStream_t);

@@ -87,13 +87,16 @@ __device__ __forceinline__ void block_t_times_x(const T h[27], const T* __restri
 }
 
 // Pass 1 of the matvec.  Tile t holds observations [64 t, 64 t + 64), one
-// per lane, so every load is whole 128-byte lines.  A point belongs to the
-// tile that holds its first observation, and each wavefront takes the points
-// that start in its range of tiles.  The next tile is always prefetched into
-// registers, so the tile's last point, when it runs on into the next tile, is
-// finished at once from those registers and no block is read twice.  A point
-// that fills the whole next tile and goes on (longer than the point lengths
-// of the usual workloads) is finished by a second walk over its further tiles.
+// per lane.  A point belongs to the tile that holds its first observation,
+// and each wavefront takes the points that start in its range of tiles.
+// Per iteration the wave gathers what this tile needs per lane (camera
+// vectors, C~^-1, the cold flag), then prefetches the next tile, then
+// finishes every point that ends inside this tile.  A wave's loads complete
+// in issue order, so only the tile's last point, which may run on into the
+// next tile, waits for the prefetch: it is finished from the prefetched
+// registers and no block is read twice.  A point that fills the whole next
+// tile and goes on (longer than the point lengths of the usual workloads) is
+// finished by a second walk over its further tiles.
 // The hot-camera table is FP64 in both precisions: LDS FP64 adds issue
 // without the back-pressure FP32 LDS adds show here, and the per-workgroup
 // sums of the most observed cameras keep FP64 accuracy.
@@ -122,28 +125,43 @@ __global__ __launch_bounds__(HotThreads<T>::value) void k_schur_hot(
         load_tile<T>(T0, lane, cam, pt, hcp, cj, ci, ch);
         int64_t t = T0;
         while (t < T1) {
-            int32_t nj, ni;
-            T nh[27];
-            load_tile<T>(t + 1, lane, cam, pt, hcp, nj, ni, nh);  // the padding tile when t + 1 = ntiles
-            int32_t s_pt = -2;  // the tile's last point when it runs on into the next tile
             const int32_t prev = __shfl_up(ci, 1, 64);
             const int32_t last_i = __builtin_amdgcn_readlane(ci, 63);
             const bool valid = ci >= 0;
             const bool head = valid && ci != (lane == 0 ? before : prev);
             const uint64_t hm = __ballot(head);
+            const int first_head = hm ? __ffsll((unsigned long long)hm) - 1 : 64;
+            const bool owned = valid && lane >= first_head;
+            // this tile's gathers first, then the next tile's prefetch: loads complete
+            // in issue order, so waiting for these never waits for the prefetch
+            T x[9], c6[6];
+            const int64_t ii = ci >= 0 ? ci : 0;
+#pragma unroll
+            for (int a = 0; a < 9; ++a) x[a] = xcam[9 * (int64_t)cj + a];
+#pragma unroll
+            for (int a = 0; a < 6; ++a) c6[a] = cinv[6 * ii + a];
+            const bool hc = has_cold[ii] != 0;
+            __builtin_amdgcn_sched_barrier(0);
+            int32_t nj, ni;
+            T nh[27];
+            load_tile<T>(t + 1, lane, cam, pt, hcp, nj, ni, nh);  // the padding tile when t + 1 = ntiles
+            __builtin_amdgcn_sched_barrier(0);
             if (hm != 0) {
-                const int first_head = __ffsll((unsigned long long)hm) - 1;
-                const bool owned = valid && lane >= first_head;
                 const int last_owned = 63 - __clzll(__ballot(owned));
                 const int last_head = 63 - __clzll(hm);
                 const int seg_s = 63 - __clzll((hm & upto) | 1ull);
                 const uint64_t above = hm & ~upto;
                 const int seg_e = above ? __ffsll((unsigned long long)above) - 2 : last_owned;
-                if (last_owned == 63) s_pt = last_i;
-                const bool cn = ni == s_pt;  // a prefix of the next tile
-                const uint64_t cm = __ballot(cn);
+                const int32_t s_pt = last_owned == 63 ? last_i : -2;  // the last point reaches lane 63
                 T a0 = (T)0, a1 = (T)0, a2 = (T)0;
-                if (owned) block_t_times_x<T>(ch, xcam, cj, a0, a1, a2);
+                if (owned) {
+#pragma unroll
+                    for (int a = 0; a < 9; ++a) {
+                        a0 += ch[a * 3] * x[a];
+                        a1 += ch[a * 3 + 1] * x[a];
+                        a2 += ch[a * 3 + 2] * x[a];
+                    }
+                }
 #pragma unroll
                 for (int off = 1; off < 64; off <<= 1) {
                     const T u0 = __shfl_up(a0, off, 64), u1 = __shfl_up(a1, off, 64), u2 = __shfl_up(a2, off, 64);
@@ -156,76 +174,89 @@ __global__ __launch_bounds__(HotThreads<T>::value) void k_schur_hot(
                 a0 = __shfl(a0, seg_e, 64);
                 a1 = __shfl(a1, seg_e, 64);
                 a2 = __shfl(a2, seg_e, 64);
-                T c0 = (T)0, c1 = (T)0, c2 = (T)0;
-                if (cm != 0) {
-                    if (cn) block_t_times_x<T>(nh, xcam, nj, c0, c1, c2);
-                    c0 = wave_sum(c0);
-                    c1 = wave_sum(c1);
-                    c2 = wave_sum(c2);
-                }
-                const bool longpt = cm == ~0ull && t + 2 < ntiles && pt[64 * (t + 2)] == s_pt;
-                const bool strad = owned && s_pt >= 0 && seg_s == last_head;  // the last point's lanes here
-                if (strad) {
-                    a0 += c0;
-                    a1 += c1;
-                    a2 += c2;
-                }
-                T b0 = (T)0, b1 = (T)0, b2 = (T)0;
-                if (owned && !(longpt && strad)) {
-                    const T* c6 = cinv + 6 * (int64_t)ci;
-                    b0 = c6[0] * a0 + c6[1] * a1 + c6[2] * a2;
-                    b1 = c6[1] * a0 + c6[3] * a1 + c6[4] * a2;
-                    b2 = c6[2] * a0 + c6[4] * a1 + c6[5] * a2;
-                    if (lane == seg_e && has_cold[ci]) {
-                        bcold[3 * (int64_t)ci] = b0;
-                        bcold[3 * (int64_t)ci + 1] = b1;
-                        bcold[3 * (int64_t)ci + 2] = b2;
+                const bool strad = owned && s_pt >= 0 && seg_s == last_head;  // the last point's lanes
+                // the points that end inside this tile
+                if (owned && !strad) {
+                    const T b0 = c6[0] * a0 + c6[1] * a1 + c6[2] * a2;
+                    const T b1 = c6[1] * a0 + c6[3] * a1 + c6[4] * a2;
+                    const T b2 = c6[2] * a0 + c6[4] * a1 + c6[5] * a2;
+                    if (lane == seg_e && hc) {
+                        bcold[3 * ii] = b0;
+                        bcold[3 * ii + 1] = b1;
+                        bcold[3 * ii + 2] = b2;
                     }
                     if (cj < K) add_hot<T>(cl, cj, ch, b0, b1, b2);
                 }
-                if (longpt) {
-                    // The last point fills the next tile and goes on.  Its sum so
-                    // far (tiles t and t + 1) is on lane 63; add its further tiles,
-                    // then walk all of its tiles again for the camera side.
-                    T p0 = __shfl(a0, 63, 64), p1 = __shfl(a1, 63, 64), p2 = __shfl(a2, 63, 64);
-                    int64_t u = t + 2;
-                    while (true) {
-                        int32_t j, i;
-                        T h[27];
-                        load_tile<T>(u, lane, cam, pt, hcp, j, i, h);
-                        const bool in = i == s_pt;
-                        T d0 = (T)0, d1 = (T)0, d2 = (T)0;
-                        if (in) block_t_times_x<T>(h, xcam, j, d0, d1, d2);
-                        p0 += wave_sum(d0);
-                        p1 += wave_sum(d1);
-                        p2 += wave_sum(d2);
-                        if (__ballot(in) != ~0ull || u + 1 >= ntiles || pt[64 * (u + 1)] != s_pt) break;
-                        ++u;
+                if (s_pt >= 0) {
+                    // the last point, which may run on into the next tile: this is
+                    // where the wave waits for the prefetched tile
+                    const bool cn = ni == s_pt;  // a prefix of the next tile
+                    const uint64_t cm = __ballot(cn);
+                    T c0 = (T)0, c1 = (T)0, c2 = (T)0;
+                    if (cm != 0) {
+                        if (cn) block_t_times_x<T>(nh, xcam, nj, c0, c1, c2);
+                        c0 = wave_sum(c0);
+                        c1 = wave_sum(c1);
+                        c2 = wave_sum(c2);
                     }
-                    const T* c6 = cinv + 6 * (int64_t)s_pt;
-                    const T s0 = c6[0] * p0 + c6[1] * p1 + c6[2] * p2;
-                    const T s1 = c6[1] * p0 + c6[3] * p1 + c6[4] * p2;
-                    const T s2 = c6[2] * p0 + c6[4] * p1 + c6[5] * p2;
-                    if (lane == 0 && has_cold[s_pt]) {
-                        bcold[3 * (int64_t)s_pt] = s0;
-                        bcold[3 * (int64_t)s_pt + 1] = s1;
-                        bcold[3 * (int64_t)s_pt + 2] = s2;
+                    a0 += c0;
+                    a1 += c1;
+                    a2 += c2;
+                    if (cm == ~0ull && t + 2 < ntiles && pt[64 * (t + 2)] == s_pt) {
+                        // it fills the next tile and goes on: add its further tiles,
+                        // then walk all of its tiles again for the camera side
+                        T p0 = __shfl(a0, 63, 64), p1 = __shfl(a1, 63, 64), p2 = __shfl(a2, 63, 64);
+                        int64_t u = t + 2;
+                        while (true) {
+                            int32_t j, i;
+                            T h[27];
+                            load_tile<T>(u, lane, cam, pt, hcp, j, i, h);
+                            const bool in = i == s_pt;
+                            T d0 = (T)0, d1 = (T)0, d2 = (T)0;
+                            if (in) block_t_times_x<T>(h, xcam, j, d0, d1, d2);
+                            p0 += wave_sum(d0);
+                            p1 += wave_sum(d1);
+                            p2 += wave_sum(d2);
+                            if (__ballot(in) != ~0ull || u + 1 >= ntiles || pt[64 * (u + 1)] != s_pt) break;
+                            ++u;
+                        }
+                        const T* q6 = cinv + 6 * (int64_t)s_pt;
+                        const T s0 = q6[0] * p0 + q6[1] * p1 + q6[2] * p2;
+                        const T s1 = q6[1] * p0 + q6[3] * p1 + q6[4] * p2;
+                        const T s2 = q6[2] * p0 + q6[4] * p1 + q6[5] * p2;
+                        if (lane == 0 && has_cold[s_pt]) {
+                            bcold[3 * (int64_t)s_pt] = s0;
+                            bcold[3 * (int64_t)s_pt + 1] = s1;
+                            bcold[3 * (int64_t)s_pt + 2] = s2;
+                        }
+                        for (int64_t v = t; v <= u; ++v) {
+                            int32_t j, i;
+                            T h[27];
+                            load_tile<T>(v, lane, cam, pt, hcp, j, i, h);
+                            if (i == s_pt && j < K) add_hot<T>(cl, j, h, s0, s1, s2);
+                        }
+                        // tiles t + 1 .. u - 1 hold only this point; go on at tile u
+                        before = s_pt;
+                        t = u;
+                        if (t < T1) load_tile<T>(t, lane, cam, pt, hcp, cj, ci, ch);
+                        continue;
                     }
-                    for (int64_t v = t; v <= u; ++v) {
-                        int32_t j, i;
-                        T h[27];
-                        load_tile<T>(v, lane, cam, pt, hcp, j, i, h);
-                        if (i == s_pt && j < K) add_hot<T>(cl, j, h, s0, s1, s2);
+                    T b0 = (T)0, b1 = (T)0, b2 = (T)0;
+                    if (strad) {
+                        b0 = c6[0] * a0 + c6[1] * a1 + c6[2] * a2;
+                        b1 = c6[1] * a0 + c6[3] * a1 + c6[4] * a2;
+                        b2 = c6[2] * a0 + c6[4] * a1 + c6[5] * a2;
+                        if (lane == 63 && hc) {
+                            bcold[3 * ii] = b0;
+                            bcold[3 * ii + 1] = b1;
+                            bcold[3 * ii + 2] = b2;
+                        }
+                        if (cj < K) add_hot<T>(cl, cj, ch, b0, b1, b2);
                     }
-                    // tiles t + 1 .. u - 1 hold only this point; go on at tile u
-                    before = s_pt;
-                    t = u;
-                    if (t < T1) load_tile<T>(t, lane, cam, pt, hcp, cj, ci, ch);
-                    continue;
-                }
-                if (cm != 0) {
-                    const T s0 = __shfl(b0, 63, 64), s1 = __shfl(b1, 63, 64), s2 = __shfl(b2, 63, 64);
-                    if (cn && nj < K) add_hot<T>(cl, nj, nh, s0, s1, s2);
+                    if (cm != 0) {
+                        const T s0 = __shfl(b0, 63, 64), s1 = __shfl(b1, 63, 64), s2 = __shfl(b2, 63, 64);
+                        if (cn && nj < K) add_hot<T>(cl, nj, nh, s0, s1, s2);
+                    }
                 }
             }
             before = last_i;

@@ -255,7 +255,7 @@ __device__ __forceinline__ double clamp_d(double h) { return h < 1e-6 ? 1e-6 : (
 template <typename T>
 __global__ __launch_bounds__(kRedBlock) void k_pred(int64_t lc, int64_t lp, const double* __restrict__ dc,
                                                     const double* __restrict__ dcam, const double* __restrict__ vcam,
-                                                    const double* __restrict__ dp, const T* __restrict__ hpp,
+                                                    const double* __restrict__ dp, const double* __restrict__ hpp,
                                                     const double* __restrict__ wpt, double lambda, int32_t damping,
                                                     double* __restrict__ partials)
 {
@@ -277,7 +277,7 @@ __global__ __launch_bounds__(kRedBlock) void k_pred(int64_t lc, int64_t lp, cons
 
 template <typename T>
 hipError_t launch_pred(int32_t m, int32_t n, const double* dc, const double* dcam, const double* vcam,
-                       const double* dp, const T* hpp, const double* wpt, double lambda, int32_t damping,
+                       const double* dp, const double* hpp, const double* wpt, double lambda, int32_t damping,
                        double* partials, int32_t* nblocks, hipStream_t s)
 {
     const int64_t lc = 9 * (int64_t)m, lp = 3 * (int64_t)n;
@@ -379,6 +379,6 @@ template hipError_t launch_pcg_direction<float>(int32_t, bool, const double*, do
 template hipError_t launch_pred<double>(int32_t, int32_t, const double*, const double*, const double*, const double*,
                                         const double*, const double*, double, int32_t, double*, int32_t*, hipStream_t);
 template hipError_t launch_pred<float>(int32_t, int32_t, const double*, const double*, const double*, const double*,
-                                       const float*, const double*, double, int32_t, double*, int32_t*, hipStream_t);
+                                       const double*, const double*, double, int32_t, double*, int32_t*, hipStream_t);
 
 }  // namespace ba

@@ -79,49 +79,49 @@ hipError_t launch_damp_cameras(int32_t m, const double* hcc, double lambda, int3
 // C~ = C + lambda D, inverse through its Cholesky factor; packed symmetric
 // order (00, 01, 02, 11, 12, 22).
 template <typename T>
-__global__ void k_damp_points(int32_t n, const T* __restrict__ hpp, double lambda, int32_t damping,
+__global__ void k_damp_points(int32_t n, const double* __restrict__ hpp, double lambda, int32_t damping,
                               T* __restrict__ cinv, int32_t* __restrict__ flag)
 {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const T* h = hpp + 6 * (int64_t)i;
-    T a00 = h[0], a01 = h[1], a02 = h[2], a11 = h[3], a12 = h[4], a22 = h[5];
-    const T lam = (T)lambda;
+    const double* h = hpp + 6 * (int64_t)i;
+    double a00 = h[0], a01 = h[1], a02 = h[2], a11 = h[3], a12 = h[4], a22 = h[5];
+    const double lam = lambda;
     if (damping == 0) {
-        a00 += lam * (T)clamp_diag((double)a00);
-        a11 += lam * (T)clamp_diag((double)a11);
-        a22 += lam * (T)clamp_diag((double)a22);
+        a00 += lam * clamp_diag(a00);
+        a11 += lam * clamp_diag(a11);
+        a22 += lam * clamp_diag(a22);
     } else {
         a00 += lam;
         a11 += lam;
         a22 += lam;
     }
-    bool ok = a00 > (T)0;
-    const T l00 = sqrt(ok ? a00 : (T)1);
-    const T l10 = a01 / l00, l20 = a02 / l00;
-    T s11 = a11 - l10 * l10;
-    ok = ok && s11 > (T)0;
-    const T l11 = sqrt(s11 > (T)0 ? s11 : (T)1);
-    const T l21 = (a12 - l20 * l10) / l11;
-    T s22 = a22 - l20 * l20 - l21 * l21;
-    ok = ok && s22 > (T)0;
-    const T l22 = sqrt(s22 > (T)0 ? s22 : (T)1);
-    const T m00 = (T)1 / l00, m11 = (T)1 / l11, m22 = (T)1 / l22;
-    const T m10 = -l10 * m00 * m11;
-    const T m21 = -l21 * m11 * m22;
-    const T m20 = -(l20 * m00 + l21 * m10) * m22;
+    bool ok = a00 > 0.0;
+    const double l00 = sqrt(ok ? a00 : 1.0);
+    const double l10 = a01 / l00, l20 = a02 / l00;
+    double s11 = a11 - l10 * l10;
+    ok = ok && s11 > 0.0;
+    const double l11 = sqrt(s11 > 0.0 ? s11 : 1.0);
+    const double l21 = (a12 - l20 * l10) / l11;
+    double s22 = a22 - l20 * l20 - l21 * l21;
+    ok = ok && s22 > 0.0;
+    const double l22 = sqrt(s22 > 0.0 ? s22 : 1.0);
+    const double m00 = 1.0 / l00, m11 = 1.0 / l11, m22 = 1.0 / l22;
+    const double m10 = -l10 * m00 * m11;
+    const double m21 = -l21 * m11 * m22;
+    const double m20 = -(l20 * m00 + l21 * m10) * m22;
     T* o = cinv + 6 * (int64_t)i;
-    o[0] = m00 * m00 + m10 * m10 + m20 * m20;
-    o[1] = m10 * m11 + m20 * m21;
-    o[2] = m20 * m22;
-    o[3] = m11 * m11 + m21 * m21;
-    o[4] = m21 * m22;
-    o[5] = m22 * m22;
+    o[0] = (T)(m00 * m00 + m10 * m10 + m20 * m20);
+    o[1] = (T)(m10 * m11 + m20 * m21);
+    o[2] = (T)(m20 * m22);
+    o[3] = (T)(m11 * m11 + m21 * m21);
+    o[4] = (T)(m21 * m22);
+    o[5] = (T)(m22 * m22);
     if (!ok) atomicOr(flag, 2);
 }
 
 template <typename T>
-hipError_t launch_damp_points(int32_t n, const T* hpp, double lambda, int32_t damping, T* cinv, int32_t* flag,
+hipError_t launch_damp_points(int32_t n, const double* hpp, double lambda, int32_t damping, T* cinv, int32_t* flag,
                               hipStream_t s)
 {
     if (n > 0)
@@ -310,7 +310,7 @@ hipError_t launch_schur_tiles(int mode, const PointMajor& pm, const int32_t* til
 }
 
 template hipError_t launch_damp_points<double>(int32_t, const double*, double, int32_t, double*, int32_t*, hipStream_t);
-template hipError_t launch_damp_points<float>(int32_t, const float*, double, int32_t, float*, int32_t*, hipStream_t);
+template hipError_t launch_damp_points<float>(int32_t, const double*, double, int32_t, float*, int32_t*, hipStream_t);
 template hipError_t launch_schur_tiles<double>(int, const PointMajor&, const int32_t*, int32_t, int64_t,
                                                const double*, const double*, const double*, const double*, double*,
                                                double*, hipStream_t);
