@@ -76,7 +76,7 @@ def counted_traffic(kernel="k_schur_hot<float>"):
     return float(fields["traffic_bytes_per_launch"])
 
 
-def run_precision(prob_data, precision, wl, steps, warmup):
+def run_precision(prob_data, precision, wl, steps, warmup, jacobian=0):
     import torch
 
     from paper_2112_01349_amd import Problem
@@ -84,7 +84,7 @@ def run_precision(prob_data, precision, wl, steps, warmup):
     cams, pts, oc, op, uv = prob_data
     t0 = time.perf_counter()
     prob = Problem(cams, pts, oc, op, uv, precision=precision, huber_delta=wl["huber_delta"],
-                   max_pcg_iters=wl["max_pcg_iters"], pcg_rtol=wl["pcg_rtol"])
+                   max_pcg_iters=wl["max_pcg_iters"], pcg_rtol=wl["pcg_rtol"], jacobian=jacobian)
     device_bytes = prob.memory_bytes()
     log(f"[bench] precision={precision} create {time.perf_counter() - t0:.1f}s "
         f"device bytes {device_bytes / 1e9:.2f} GB")
@@ -183,6 +183,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp64", type=int, default=1, help="also time the FP64 form")
     ap.add_argument("--autograd", type=int, default=1, help="also time the autograd Function (1M observations)")
+    ap.add_argument("--jacobian", default="analytic", choices=["analytic", "autodiff"],
+                    help="analytic Jacobians (the paper's -m) or forward-mode autodiff (-a)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (scale reference for HBM byte counters)")
     args = ap.parse_args()
@@ -216,12 +218,13 @@ def main():
     data = (prob.cameras0, prob.points0, prob.obs_camera, prob.obs_point, prob.obs_uv)
     m, n, N = prob.num_cameras, prob.num_points, prob.num_obs
 
-    rep32, wall32 = run_precision(data, FP32_MIXED, wl, args.steps, args.warmup)
+    jac = 1 if args.jacobian == "autodiff" else 0
+    rep32, wall32 = run_precision(data, FP32_MIXED, wl, args.steps, args.warmup, jac)
     res = {}
     for name, rep, wall, w in [("fp32_mixed", rep32, wall32, 4)]:
         res[name] = rep, wall, w
     if args.fp64:
-        rep64, wall64 = run_precision(data, FP64, wl, args.steps, args.warmup)
+        rep64, wall64 = run_precision(data, FP64, wl, args.steps, args.warmup, jac)
         res["fp64"] = rep64, wall64, 8
 
     def summary(rep, wall, w):
@@ -252,7 +255,7 @@ def main():
         "config": {"workload": f"{args.workload}: {m} cameras, {n} points, {N} observations, "
                                + (f"point-aligned chunk {wl['chunk'][0]} of {wl['chunk'][1]} of '{wl['config']}', "
                                   if "chunk" in wl else "")
-                               + f"Zipf visibility, Huber delta={wl['huber_delta']}, PCG max "
+                               + f"Zipf visibility, Huber delta={wl['huber_delta']}, {args.jacobian} Jacobians, PCG max "
                                f"{wl['max_pcg_iters']} rtol {wl['pcg_rtol']}",
                    "cameras": m, "points": n, "observations": N},
         "pcg_iter_per_s": s32["pcg_iter_per_s"],

@@ -60,6 +60,12 @@ typedef enum {
     BA_DAMP_IDENTITY = 1   /* lambda * I, as printed in Sec. 3 */
 } ba_damping;
 
+typedef enum {
+    BA_JACOBIAN_ANALYTIC = 0, /* closed-form Jacobian (the paper's "-m" variant, Sec. 6) */
+    BA_JACOBIAN_AUTODIFF = 1  /* forward-mode automatic differentiation of the residual
+                                 (the paper's "-a" variant, Sec. 5 JetVector) */
+} ba_jacobian;
+
 typedef struct {
     uint32_t struct_size;          /* sizeof(ba_options) */
     int32_t precision;             /* ba_precision; fixed at ba_create */
@@ -69,7 +75,7 @@ typedef struct {
     int32_t max_pcg_iters;         /* cap on Schur matvecs per LM iteration */
     double pcg_rtol;               /* stop PCG when ||r||_2 <= pcg_rtol * ||b||_2 */
     int32_t pcg_fixed_iters;       /* > 0: run exactly this many matvecs per LM iteration */
-    int32_t reserved0;
+    int32_t jacobian;              /* ba_jacobian: how J_c and J_p are formed */
     const int32_t *pcg_schedule;   /* nullable [max_lm_iters]: exact matvec count per LM
                                       iteration; overrides pcg_fixed_iters and pcg_rtol */
     double lambda_init;            /* initial LM damping, default 1e-4 */

@@ -519,6 +519,46 @@ int orc_pcg(int32_t m, int32_t n, int64_t N, const int32_t *oc, const int32_t *o
             const double *Bd, const double *E, const double *Cinv, const double *b,
             double rtol, int32_t max_iters, int32_t fixed_iters, double *x, int32_t *iters)
 {
+    return orc_pcg_m(m, n, N, oc, op, Bd, E, Cinv, Bd, b, rtol, max_iters, fixed_iters, x, iters);
+}
+
+/* Schur-Jacobi preconditioner blocks, an option beside Alg. 2's damped camera
+ * blocks (the paper's Sec. 3 names iterative solvers on the reduced system and
+ * leaves the preconditioner to Alg. 2; this is the block diagonal of S itself):
+ *   M_j = B~_j - sum_{k in obs(j)} E_k C~_{i(k)}^{-1} E_k^T,
+ * summed per observation, which is the diagonal block S_jj exactly when no
+ * camera sees a point twice (with a repeated pair the cross terms are left out;
+ * every term stays positive semi-definite, so M_j >= lambda D_j). */
+void orc_schur_jacobi(int32_t m, int64_t N, const int32_t *oc, const int32_t *op,
+                      const double *Bd, const double *E, const double *Cinv, double *M)
+{
+    memcpy(M, Bd, sizeof(double) * 81 * (size_t)m);
+    for (int64_t k = 0; k < N; ++k) {
+        const double *Ek = E + 27 * k;
+        const double *Ci = Cinv + 9 * (int64_t)op[k];
+        double T[27];   /* E_k C~^{-1}, 9x3 */
+        for (int a = 0; a < 9; ++a)
+            for (int c = 0; c < 3; ++c) {
+                double s = 0.0;
+                for (int d = 0; d < 3; ++d) s += Ek[a * 3 + d] * Ci[d * 3 + c];
+                T[a * 3 + c] = s;
+            }
+        double *Mj = M + 81 * (int64_t)oc[k];
+        for (int a = 0; a < 9; ++a)
+            for (int b2 = 0; b2 < 9; ++b2) {
+                double s = 0.0;
+                for (int c = 0; c < 3; ++c) s += T[a * 3 + c] * Ek[b2 * 3 + c];
+                Mj[a * 9 + b2] -= s;
+            }
+    }
+}
+
+/* PCG of Alg. 2 with the preconditioner blocks Mblk (Bd for Alg. 2 itself). */
+int orc_pcg_m(int32_t m, int32_t n, int64_t N, const int32_t *oc, const int32_t *op,
+              const double *Bd, const double *E, const double *Cinv, const double *Mblk,
+              const double *b, double rtol, int32_t max_iters, int32_t fixed_iters, double *x,
+              int32_t *iters)
+{
     int64_t len = 9 * (int64_t)m;
     double *r = malloc(sizeof(double) * (size_t)len);
     double *z = malloc(sizeof(double) * (size_t)len);
@@ -529,7 +569,7 @@ int orc_pcg(int32_t m, int32_t n, int64_t N, const int32_t *oc, const int32_t *o
     double *L = malloc(sizeof(double) * 81 * (size_t)(m > 0 ? m : 1));
     int status = ORC_OK;
     for (int64_t j = 0; j < m; ++j)
-        if (cholesky(Bd + 81 * j, 9, L + 81 * j)) status = ORC_ENUMERIC;
+        if (cholesky(Mblk + 81 * j, 9, L + 81 * j)) status = ORC_ENUMERIC;
     memset(x, 0, sizeof(double) * (size_t)len);
     memcpy(r, b, sizeof(double) * (size_t)len);
     double bnorm = sqrt(dot(b, b, len));
@@ -626,6 +666,7 @@ int orc_lm_solve(int32_t m, int32_t n, int64_t N, double *cams, double *pts,
     double *g = malloc(sizeof(double) * 9 * M), *dc = malloc(sizeof(double) * 9 * M);
     double *dp = malloc(sizeof(double) * 3 * P), *wb = malloc(sizeof(double) * 3 * P);
     double *cams_t = malloc(sizeof(double) * 9 * M), *pts_t = malloc(sizeof(double) * 3 * P);
+    double *Mj = malloc(sizeof(double) * 81 * M);
     int status = ORC_OK;
     double delta = opt->huber_delta;
     double F = orc_cost(N, cams, pts, oc, op, uv, delta);
@@ -647,8 +688,10 @@ int orc_lm_solve(int32_t m, int32_t n, int64_t N, double *cams, double *pts,
         orc_reduced_rhs(m, n, N, oc, op, v, w, E, Ci, g, wb);
         int32_t fixed = opt->pcg_schedule ? opt->pcg_schedule[it] : 0;
         int32_t npcg = 0;
+        if (opt->preconditioner == 1) orc_schur_jacobi(m, N, oc, op, Bd, E, Ci, Mj);
         /* a breakdown leaves dc at the last iterate, which is still a step */
-        int pst = orc_pcg(m, n, N, oc, op, Bd, E, Ci, g, opt->pcg_rtol, opt->max_pcg_iters, fixed, dc, &npcg);
+        int pst = orc_pcg_m(m, n, N, oc, op, Bd, E, Ci, opt->preconditioner == 1 ? Mj : Bd, g, opt->pcg_rtol,
+                            opt->max_pcg_iters, fixed, dc, &npcg);
         if (pst != ORC_OK && pst != ORC_BREAKDOWN) {
             trace->pcg_iters[it] = npcg;
             status = ORC_ENUMERIC;
@@ -691,7 +734,7 @@ int orc_lm_solve(int32_t m, int32_t n, int64_t N, double *cams, double *pts,
     trace->iters_run = it;
     trace->final_cost = F;
     free(B); free(Bd); free(C); free(Cd); free(Ci); free(E); free(v); free(w);
-    free(Dc); free(Dp); free(g); free(dc); free(dp); free(wb); free(cams_t); free(pts_t);
+    free(Dc); free(Dp); free(g); free(dc); free(dp); free(wb); free(cams_t); free(pts_t); free(Mj);
     return status;
 }
 

@@ -34,6 +34,7 @@ typedef struct {
     const int32_t *pcg_schedule; /* nullable [max_lm_iters]: exact PCG counts */
     double lambda_init;
     double min_relative_decrease;
+    int32_t preconditioner;    /* 0: damped camera blocks B~_j (Alg. 2); 1: Schur-Jacobi */
 } orc_options;
 
 typedef struct {               /* caller-owned arrays of length max_lm_iters */
@@ -77,6 +78,12 @@ void orc_schur_matvec(int32_t m, int32_t n, int64_t N, const int32_t *oc, const 
 void orc_reduced_rhs(int32_t m, int32_t n, int64_t N, const int32_t *oc, const int32_t *op,
                      const double *v, const double *w, const double *E, const double *Cinv,
                      double *g, double *work_b);
+void orc_schur_jacobi(int32_t m, int64_t N, const int32_t *oc, const int32_t *op,
+                      const double *Bd, const double *E, const double *Cinv, double *M);
+int orc_pcg_m(int32_t m, int32_t n, int64_t N, const int32_t *oc, const int32_t *op,
+              const double *Bd, const double *E, const double *Cinv, const double *Mblk,
+              const double *b, double rtol, int32_t max_iters, int32_t fixed_iters, double *x,
+              int32_t *iters);
 int orc_pcg(int32_t m, int32_t n, int64_t N, const int32_t *oc, const int32_t *op,
             const double *Bd, const double *E, const double *Cinv, const double *b,
             double rtol, int32_t max_iters, int32_t fixed_iters, double *x, int32_t *iters);

@@ -32,7 +32,8 @@ class Options(C.Structure):
     _fields_ = [("huber_delta", C.c_double), ("damping", C.c_int32),
                 ("max_lm_iters", C.c_int32), ("max_pcg_iters", C.c_int32),
                 ("pcg_rtol", C.c_double), ("pcg_schedule", C.c_void_p),
-                ("lambda_init", C.c_double), ("min_relative_decrease", C.c_double)]
+                ("lambda_init", C.c_double), ("min_relative_decrease", C.c_double),
+                ("preconditioner", C.c_int32)]
 
 
 class Trace(C.Structure):
@@ -82,6 +83,11 @@ def lib():
         L.orc_pcg.argtypes = [C.c_int32, C.c_int32, C.c_int64, _i32p, _i32p, _f64p, _f64p,
                               _f64p, _f64p, C.c_double, C.c_int32, C.c_int32, _f64p,
                               C.POINTER(C.c_int32)]
+        L.orc_pcg_m.argtypes = [C.c_int32, C.c_int32, C.c_int64, _i32p, _i32p, _f64p, _f64p,
+                                _f64p, _f64p, _f64p, C.c_double, C.c_int32, C.c_int32, _f64p,
+                                C.POINTER(C.c_int32)]
+        L.orc_schur_jacobi.argtypes = [C.c_int32, C.c_int64, _i32p, _i32p, _f64p, _f64p, _f64p,
+                                       _f64p]
         L.orc_back_substitute.argtypes = [C.c_int32, C.c_int64, _i32p, _i32p, _f64p, _f64p,
                                           _f64p, _f64p, _f64p]
         L.orc_lm_solve.argtypes = [C.c_int32, C.c_int32, C.c_int64, _f64p, _f64p, _i32p, _i32p,
@@ -190,13 +196,22 @@ def reduced_rhs(oc, op, v, w, E, Ci):
     return g
 
 
-def pcg(oc, op, Bd, E, Ci, b, rtol=1e-8, max_iters=50, fixed_iters=0):
+def pcg(oc, op, Bd, E, Ci, b, rtol=1e-8, max_iters=50, fixed_iters=0, M=None):
+    """Alg. 2; M: preconditioner blocks [m][9][9] (default: the damped camera blocks Bd)."""
     m, n, N = len(Bd), len(Ci), len(oc)
     x = np.zeros((m, 9))
     it = C.c_int32(0)
-    rc = lib().orc_pcg(m, n, N, _i(oc), _i(op), _f(Bd), _f(E), _f(Ci), _f(b), float(rtol),
-                       int(max_iters), int(fixed_iters), x, C.byref(it))
+    rc = lib().orc_pcg_m(m, n, N, _i(oc), _i(op), _f(Bd), _f(E), _f(Ci), _f(Bd if M is None else M), _f(b),
+                         float(rtol), int(max_iters), int(fixed_iters), x, C.byref(it))
     return x, it.value, rc
+
+
+def schur_jacobi(oc, op, Bd, E, Ci):
+    """Schur-Jacobi preconditioner blocks M_j = B~_j - sum_k E_k C~^-1 E_k^T."""
+    m = len(Bd)
+    M = np.zeros((m, 9, 9))
+    lib().orc_schur_jacobi(m, len(oc), _i(oc), _i(op), _f(Bd), _f(E), _f(Ci), M)
+    return M
 
 
 def back_substitute(oc, op, E, Ci, w, dc):
@@ -208,8 +223,9 @@ def back_substitute(oc, op, E, Ci, w, dc):
 
 def lm_solve(cams, pts, oc, op, uv, huber_delta=0.0, damping=0, max_lm_iters=10,
              max_pcg_iters=50, pcg_rtol=1e-8, pcg_schedule=None, lambda_init=1e-4,
-             min_relative_decrease=1e-3):
-    """Runs the LM loop; returns (cams, pts, trace dict, status)."""
+             min_relative_decrease=1e-3, preconditioner=0):
+    """Runs the LM loop; returns (cams, pts, trace dict, status).  preconditioner:
+    0 = the damped camera blocks (Alg. 2), 1 = Schur-Jacobi blocks."""
     cams = np.array(cams, dtype=np.float64, order="C", copy=True)
     pts = np.array(pts, dtype=np.float64, order="C", copy=True)
     K = int(max_lm_iters)
@@ -219,7 +235,7 @@ def lm_solve(cams, pts, oc, op, uv, huber_delta=0.0, damping=0, max_lm_iters=10,
         assert len(sched) >= K
     opt = Options(float(huber_delta), int(damping), K, int(max_pcg_iters), float(pcg_rtol),
                   sched.ctypes.data if sched is not None else None, float(lambda_init),
-                  float(min_relative_decrease))
+                  float(min_relative_decrease), int(preconditioner))
     arrs = dict(cost=np.zeros(K), trial_cost=np.zeros(K), lambda_=np.zeros(K), pred=np.zeros(K),
                 pcg_iters=np.zeros(K, np.int32), accepted=np.zeros(K, np.int32))
     tr = Trace(0, 0.0, 0.0, *(arrs[k].ctypes.data for k in

@@ -114,6 +114,10 @@ static ba_status check_options(const ba_options* o, std::string& msg)
         msg = "unknown damping";
         return BA_EINVAL;
     }
+    if (o->jacobian != BA_JACOBIAN_ANALYTIC && o->jacobian != BA_JACOBIAN_AUTODIFF) {
+        msg = "unknown jacobian";
+        return BA_EINVAL;
+    }
     if (o->max_lm_iters < 0 || o->max_pcg_iters < 0 || o->pcg_fixed_iters < 0 || !std::isfinite(o->pcg_rtol) ||
         !(o->lambda_init > 0.0) || !std::isfinite(o->lambda_init) || !std::isfinite(o->min_relative_decrease) ||
         !std::isfinite(o->huber_delta)) {
@@ -147,6 +151,7 @@ ba_status ba_options_default(ba_options* opt)
     opt->lambda_init = 1e-4;
     opt->min_relative_decrease = 1e-3;
     opt->time_kernels = 0;
+    opt->jacobian = BA_JACOBIAN_ANALYTIC;
     return BA_OK;
 }
 
@@ -598,8 +603,10 @@ static ba_status build_system(ba_problem* P)
     } else {
         ck = (const CamK<T>*)P->ck64;
     }
-    BA_TRY(P, launch_build_points<T>(P->pm, P->opt.huber_delta, false, P->pts, ck, (T*)P->hcp, (double*)P->hpp, P->wpt, s));
-    BA_TRY(P, launch_build_cameras<T>(P->cm, P->m, P->N, P->pts, ck, P->opt.huber_delta, false, P->hcc, P->vcam,
+    const JacSource<T> js{ck, P->opt.jacobian == BA_JACOBIAN_AUTODIFF ? P->cams : nullptr};
+    BA_TRY(P, launch_build_points<T>(P->pm, P->opt.huber_delta, false, P->pts, js, (T*)P->hcp, (double*)P->hpp,
+                                     P->wpt, s));
+    BA_TRY(P, launch_build_cameras<T>(P->cm, P->m, P->N, P->pts, js, P->opt.huber_delta, false, P->hcc, P->vcam,
                                       P->sp.cold.N, (T*)P->sp.cold.hcp, s));
     return BA_OK;
 }
@@ -818,18 +825,22 @@ extern "C" ba_status ba_lm_solve(ba_problem* P, const ba_options* opt, ba_report
         return BA_EINVAL;
     }
     const double delta_saved = P->opt.huber_delta;
+    const int32_t jacobian_saved = P->opt.jacobian;
     P->opt.huber_delta = o.huber_delta;
+    P->opt.jacobian = o.jacobian;
     ba_status st = P->is_f32() ? lm_solve_t<float>(P, o, rep) : lm_solve_t<double>(P, o, rep);
     P->opt.huber_delta = delta_saved;
+    P->opt.jacobian = jacobian_saved;
     return st;
 }
 
 // --------------------------------------------------- cost and gradients
 template <typename T>
-static ba_status grad_into(ba_problem* P, const double* pts, const CamK<T>* ck, hipStream_t s)
+static ba_status grad_into(ba_problem* P, const double* cams, const double* pts, const CamK<T>* ck, hipStream_t s)
 {
-    BA_TRY(P, launch_build_points<T>(P->pm, P->opt.huber_delta, true, pts, ck, nullptr, nullptr, P->wpt, s));
-    BA_TRY(P, launch_build_cameras<T>(P->cm, P->m, P->N, pts, ck, P->opt.huber_delta, true, nullptr, P->vcam, 0,
+    const JacSource<T> js{ck, P->opt.jacobian == BA_JACOBIAN_AUTODIFF ? cams : nullptr};
+    BA_TRY(P, launch_build_points<T>(P->pm, P->opt.huber_delta, true, pts, js, nullptr, nullptr, P->wpt, s));
+    BA_TRY(P, launch_build_cameras<T>(P->cm, P->m, P->N, pts, js, P->opt.huber_delta, true, nullptr, P->vcam, 0,
                                       nullptr, s));
     return BA_OK;
 }
@@ -845,7 +856,7 @@ extern "C" ba_status ba_eval_cost_grad(ba_problem* P, double* cost, double* grad
         *cost = P->h_scalars[0];
     }
     if (grad_cameras || grad_points) {
-        if ((st = grad_into<double>(P, P->pts, P->ck64, s)) != BA_OK) return st;
+        if ((st = grad_into<double>(P, P->cams, P->pts, P->ck64, s)) != BA_OK) return st;
         // gradients land in cams_t / pts_t (caller order), then to the host
         BA_TRY(P, launch_scatter_grad(P->m, P->n, 0, 1.0, P->vcam, P->wpt, P->d_old_of_new,
                                       grad_cameras ? (void*)P->cams_t : nullptr,
@@ -879,7 +890,7 @@ static ba_status device_form(ba_problem* P, int32_t dtype, const void* d_cams, c
         BA_TRY(P, launch_store_cost(P->sums, (double*)d_cost, s));
         return BA_OK;
     }
-    if ((st = grad_into<T>(P, P->pts_t, ck, s)) != BA_OK) return st;
+    if ((st = grad_into<T>(P, P->cams_t, P->pts_t, ck, s)) != BA_OK) return st;
     BA_TRY(P, launch_scatter_grad(P->m, P->n, dtype, gout, P->vcam, P->wpt, P->d_old_of_new, d_gc, d_gp, s));
     return BA_OK;
 }

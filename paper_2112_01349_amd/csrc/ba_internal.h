@@ -135,17 +135,26 @@ struct SchurPlan {
 hipError_t launch_camera_constants_f64(int32_t m, const double* cams, CamK<double>* out, hipStream_t s);
 hipError_t launch_camera_constants_f32(int32_t m, const double* cams, CamK<float>* out, hipStream_t s);
 
+// Where the build's Jacobians come from: the per-camera constants of the
+// analytic form (ck), or, when cams is set, forward-mode differentiation of
+// the residual at the FP64 camera parameters cams [m][9] (internal order).
+template <typename T>
+struct JacSource {
+    const CamK<T>* ck;
+    const double* cams;
+};
+
 // Point-major build: E_k into hcp (unless grad_only), C_i into hpp (unless
 // grad_only) and w_i into wpt.
 template <typename T>
 hipError_t launch_build_points(const PointMajor& pm, double delta, bool grad_only, const double* pts,
-                               const CamK<T>* ck, T* hcp, double* hpp, double* wpt, hipStream_t s);
+                               JacSource<T> js, T* hcp, double* hpp, double* wpt, hipStream_t s);
 // Camera-major build: B_j (unless grad_only) and v_j; the last Nc
 // observations of the camera-major stream (the cold cameras) also store E_k
 // into chcp[q * Nc + k - (N - Nc)].
 template <typename T>
 hipError_t launch_build_cameras(const CameraMajor& cm, int32_t m, int64_t N, const double* pts,
-                                const CamK<T>* ck, double delta, bool grad_only, double* hcc,
+                                JacSource<T> js, double delta, bool grad_only, double* hcc,
                                 double* vcam, int64_t Nc, T* chcp, hipStream_t s);
 
 hipError_t launch_damp_cameras(int32_t m, const double* hcc, double lambda, int32_t damping,

@@ -19,6 +19,7 @@
 //     about 60% of all points) over the whole chip, as the paper's equal-edge
 //     partition (Sec. 4.1) does over GPUs.
 #include "ba_internal.h"
+#include "autodiff.h"
 
 namespace ba {
 
@@ -61,17 +62,21 @@ __device__ __forceinline__ void point_terms(const T Jp[6], T e0, T e1, T wt, T o
     out[8] = -wt * (Jp[2] * e0 + Jp[5] * e1);
 }
 
-template <typename T>
+template <typename T, bool AD>
 __device__ __forceinline__ void observation(int64_t k, const int32_t* __restrict__ cam, const int32_t* __restrict__ pt,
                                             const double* __restrict__ uvx, const double* __restrict__ uvy,
-                                            const double* __restrict__ pts, const CamK<T>* __restrict__ ck,
-                                            T delta, T& e0, T& e1, T& wt, T Jc[18], T Jp[6], int32_t& i)
+                                            const double* __restrict__ pts, JacSource<T> js, T delta, T& e0, T& e1,
+                                            T& wt, T Jc[18], T Jp[6], int32_t& i)
 {
     const int32_t j = cam[k];
     i = pt[k];
-    const CamK<T> kk = ck[j];
     const T X0 = (T)pts[3 * (int64_t)i], X1 = (T)pts[3 * (int64_t)i + 1], X2 = (T)pts[3 * (int64_t)i + 2];
-    residual_jacobian<T>(kk, X0, X1, X2, (T)uvx[k], (T)uvy[k], e0, e1, Jc, Jp);
+    if (AD) {
+        residual_jacobian_ad<T>(js.cams + 9 * (int64_t)j, X0, X1, X2, (T)uvx[k], (T)uvy[k], e0, e1, Jc, Jp);
+    } else {
+        const CamK<T> kk = js.ck[j];
+        residual_jacobian<T>(kk, X0, X1, X2, (T)uvx[k], (T)uvy[k], e0, e1, Jc, Jp);
+    }
     wt = huber_weight<T>(e0 * e0 + e1 * e1, delta);
 }
 
@@ -112,11 +117,11 @@ __device__ __forceinline__ double wave_sum(double v)
 // its terms of C_i and w_i go to LDS, and the first thread of each point sums
 // the point's terms in stream order (FP64) and stores C_i (upper 6, as T)
 // and w_i (FP64).  GRAD_ONLY forms w_i only.
-template <typename T, bool GRAD_ONLY>
+template <typename T, bool GRAD_ONLY, bool AD>
 __global__ __launch_bounds__(kTile) void k_build_points(
     const int32_t* __restrict__ tile, const int32_t* __restrict__ cam, const int32_t* __restrict__ pt,
     const double* __restrict__ uvx, const double* __restrict__ uvy, const double* __restrict__ pts,
-    const CamK<T>* __restrict__ ck, T delta, int64_t ld, T* __restrict__ hcp, double* __restrict__ hpp,
+    JacSource<T> js, T delta, int64_t ld, T* __restrict__ hcp, double* __restrict__ hpp,
     double* __restrict__ wpt)
 {
     constexpr int R = GRAD_ONLY ? 3 : 9;  // terms kept: [C upper 6 |] w 3
@@ -132,7 +137,7 @@ __global__ __launch_bounds__(kTile) void k_build_points(
         if (valid) {
             const int64_t k = s + tid;
             T e0, e1, wt, Jc[18], Jp[6];
-            observation<T>(k, cam, pt, uvx, uvy, pts, ck, delta, e0, e1, wt, Jc, Jp, i);
+            observation<T, AD>(k, cam, pt, uvx, uvy, pts, js, delta, e0, e1, wt, Jc, Jp, i);
             if (!GRAD_ONLY) store_coupling_blocked<T>(k, Jc, Jp, wt, hcp);
             T v[9];
             point_terms<T>(Jp, e0, e1, wt, v);
@@ -164,7 +169,7 @@ __global__ __launch_bounds__(kTile) void k_build_points(
         for (int64_t k = s + tid; k < e; k += kTile) {
             T e0, e1, wt, Jc[18], Jp[6];
             int32_t ii;
-            observation<T>(k, cam, pt, uvx, uvy, pts, ck, delta, e0, e1, wt, Jc, Jp, ii);
+            observation<T, AD>(k, cam, pt, uvx, uvy, pts, js, delta, e0, e1, wt, Jc, Jp, ii);
             if (!GRAD_ONLY) store_coupling_blocked<T>(k, Jc, Jp, wt, hcp);
             T v[9];
             point_terms<T>(Jp, e0, e1, wt, v);
@@ -193,18 +198,28 @@ __global__ __launch_bounds__(kTile) void k_build_points(
     }
 }
 
+template <typename T, bool G, bool A>
+static void build_points_variant(const PointMajor& pm, const double* pts, JacSource<T> js, T delta, T* hcp,
+                                 double* hpp, double* wpt, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_build_points<T, G, A>), dim3((unsigned)pm.num_tiles), dim3(kTile), 0, s, pm.tile, pm.cam,
+                       pm.pt, pm.uvx, pm.uvy, pts, js, delta, pm.ld, hcp, hpp, wpt);
+}
+
 template <typename T>
 hipError_t launch_build_points(const PointMajor& pm, double delta, bool grad_only, const double* pts,
-                               const CamK<T>* ck, T* hcp, double* hpp, double* wpt, hipStream_t s)
+                               JacSource<T> js, T* hcp, double* hpp, double* wpt, hipStream_t s)
 {
     if (pm.num_tiles <= 0) return hipGetLastError();
-    const dim3 g((unsigned)pm.num_tiles), b(kTile);
-    if (grad_only)
-        hipLaunchKernelGGL((k_build_points<T, true>), g, b, 0, s, pm.tile, pm.cam, pm.pt, pm.uvx, pm.uvy, pts, ck,
-                           (T)delta, pm.ld, (T*)nullptr, (double*)nullptr, wpt);
-    else
-        hipLaunchKernelGGL((k_build_points<T, false>), g, b, 0, s, pm.tile, pm.cam, pm.pt, pm.uvx, pm.uvy, pts, ck,
-                           (T)delta, pm.ld, hcp, hpp, wpt);
+    const bool ad = js.cams != nullptr;
+    const T d = (T)delta;
+    if (grad_only) {
+        if (ad) build_points_variant<T, true, true>(pm, pts, js, d, nullptr, nullptr, wpt, s);
+        else build_points_variant<T, true, false>(pm, pts, js, d, nullptr, nullptr, wpt, s);
+    } else {
+        if (ad) build_points_variant<T, false, true>(pm, pts, js, d, hcp, hpp, wpt, s);
+        else build_points_variant<T, false, false>(pm, pts, js, d, hcp, hpp, wpt, s);
+    }
     return hipGetLastError();
 }
 
@@ -222,11 +237,11 @@ __device__ __forceinline__ void flush_slot(double* acc, double* __restrict__ slo
     }
 }
 
-template <typename T, bool GRAD_ONLY>
+template <typename T, bool GRAD_ONLY, bool AD>
 __global__ __launch_bounds__(256) void k_build_cameras(
     int64_t N, int32_t num_chunks, const int32_t* __restrict__ cam, const int32_t* __restrict__ pt,
     const double* __restrict__ uvx, const double* __restrict__ uvy, const double* __restrict__ pts,
-    const CamK<T>* __restrict__ ck, T delta, const int32_t* __restrict__ chunk_slot, double* __restrict__ slots,
+    JacSource<T> js, T delta, const int32_t* __restrict__ chunk_slot, double* __restrict__ slots,
     int64_t Nc, T* __restrict__ chcp)
 {
     constexpr int W = GRAD_ONLY ? 9 : kCamSlotWords;
@@ -250,7 +265,7 @@ __global__ __launch_bounds__(256) void k_build_cameras(
         if (valid) {
             int32_t i;
             j = cam[k];
-            observation<T>(k, cam, pt, uvx, uvy, pts, ck, delta, e0, e1, wt, Jc, Jp, i);
+            observation<T, AD>(k, cam, pt, uvx, uvy, pts, js, delta, e0, e1, wt, Jc, Jp, i);
             if (!GRAD_ONLY && k >= cold0) store_coupling<T>(k - cold0, Nc, Jc, Jp, wt, chcp);
         }
         while (true) {
@@ -332,20 +347,29 @@ __global__ __launch_bounds__(256) void k_reduce_slots(int32_t num_segs, const in
     }
 }
 
+template <typename T, bool G, bool A>
+static void build_cameras_variant(const CameraMajor& cm, int64_t N, const double* pts, JacSource<T> js, T delta,
+                                  int64_t Nc, T* chcp, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_build_cameras<T, G, A>), dim3((cm.num_chunks + 3) / 4), dim3(256), 0, s, N, cm.num_chunks,
+                       cm.cam, cm.pt, cm.uvx, cm.uvy, pts, js, delta, cm.chunk_slot, cm.slots, Nc, chcp);
+}
+
 template <typename T>
-hipError_t launch_build_cameras(const CameraMajor& cm, int32_t m, int64_t N, const double* pts, const CamK<T>* ck,
+hipError_t launch_build_cameras(const CameraMajor& cm, int32_t m, int64_t N, const double* pts, JacSource<T> js,
                                 double delta, bool grad_only, double* hcc, double* vcam, int64_t Nc, T* chcp,
                                 hipStream_t s)
 {
     if (cm.num_chunks > 0) {
-        const int blocks = (cm.num_chunks + 3) / 4;
-        if (grad_only)
-            hipLaunchKernelGGL((k_build_cameras<T, true>), dim3(blocks), dim3(256), 0, s, N, cm.num_chunks, cm.cam,
-                               cm.pt, cm.uvx, cm.uvy, pts, ck, (T)delta, cm.chunk_slot, cm.slots, (int64_t)0,
-                               (T*)nullptr);
-        else
-            hipLaunchKernelGGL((k_build_cameras<T, false>), dim3(blocks), dim3(256), 0, s, N, cm.num_chunks,
-                               cm.cam, cm.pt, cm.uvx, cm.uvy, pts, ck, (T)delta, cm.chunk_slot, cm.slots, Nc, chcp);
+        const bool ad = js.cams != nullptr;
+        const T d = (T)delta;
+        if (grad_only) {
+            if (ad) build_cameras_variant<T, true, true>(cm, N, pts, js, d, 0, nullptr, s);
+            else build_cameras_variant<T, true, false>(cm, N, pts, js, d, 0, nullptr, s);
+        } else {
+            if (ad) build_cameras_variant<T, false, true>(cm, N, pts, js, d, Nc, chcp, s);
+            else build_cameras_variant<T, false, false>(cm, N, pts, js, d, Nc, chcp, s);
+        }
     }
     if (cm.num_segs > 0) {
         const int blocks = (cm.num_segs + 3) / 4;
@@ -412,15 +436,15 @@ hipError_t launch_cost(const PointMajor& pm, int64_t N, const double* pts, const
     return launch_cost_t<double>(pm, N, pts, ck, delta, partials, nblocks, s);
 }
 
-template hipError_t launch_build_points<double>(const PointMajor&, double, bool, const double*, const CamK<double>*,
+template hipError_t launch_build_points<double>(const PointMajor&, double, bool, const double*, JacSource<double>,
                                                 double*, double*, double*, hipStream_t);
-template hipError_t launch_build_points<float>(const PointMajor&, double, bool, const double*, const CamK<float>*,
+template hipError_t launch_build_points<float>(const PointMajor&, double, bool, const double*, JacSource<float>,
                                                float*, double*, double*, hipStream_t);
 template hipError_t launch_build_cameras<double>(const CameraMajor&, int32_t, int64_t, const double*,
-                                                 const CamK<double>*, double, bool, double*, double*, int64_t,
+                                                 JacSource<double>, double, bool, double*, double*, int64_t,
                                                  double*, hipStream_t);
 template hipError_t launch_build_cameras<float>(const CameraMajor&, int32_t, int64_t, const double*,
-                                                const CamK<float>*, double, bool, double*, double*, int64_t, float*,
+                                                JacSource<float>, double, bool, double*, double*, int64_t, float*,
                                                 hipStream_t);
 template hipError_t launch_cost_t<float>(const PointMajor&, int64_t, const double*, const CamK<float>*, double,
                                          double*, int32_t*, hipStream_t);

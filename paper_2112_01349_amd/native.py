@@ -32,7 +32,7 @@ class BAError(RuntimeError):
 class Options(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("precision", C.c_int32), ("damping", C.c_int32),
                 ("huber_delta", C.c_double), ("max_lm_iters", C.c_int32), ("max_pcg_iters", C.c_int32),
-                ("pcg_rtol", C.c_double), ("pcg_fixed_iters", C.c_int32), ("reserved0", C.c_int32),
+                ("pcg_rtol", C.c_double), ("pcg_fixed_iters", C.c_int32), ("jacobian", C.c_int32),
                 ("pcg_schedule", C.c_void_p), ("lambda_init", C.c_double),
                 ("min_relative_decrease", C.c_double), ("time_kernels", C.c_int32),
                 ("reserved1", C.c_int32)]
@@ -95,7 +95,7 @@ def _ptr(a):
 
 def make_options(precision=FP64, damping=DAMP_MARQUARDT, huber_delta=0.0, max_lm_iters=10,
                  max_pcg_iters=50, pcg_rtol=1e-8, pcg_fixed_iters=0, pcg_schedule=None,
-                 lambda_init=1e-4, min_relative_decrease=1e-3, time_kernels=False):
+                 lambda_init=1e-4, min_relative_decrease=1e-3, time_kernels=False, jacobian=0):
     o = Options()
     lib().ba_options_default(C.byref(o))
     o.precision = int(precision)
@@ -114,6 +114,7 @@ def make_options(precision=FP64, damping=DAMP_MARQUARDT, huber_delta=0.0, max_lm
     o.lambda_init = float(lambda_init)
     o.min_relative_decrease = float(min_relative_decrease)
     o.time_kernels = 1 if time_kernels else 0
+    o.jacobian = int(jacobian)
     return o, keep
 
 

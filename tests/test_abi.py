@@ -81,6 +81,11 @@ def test_invalid_inputs_are_rejected_on_the_host(native):
     o.precision = 7
     st, h = _create(native, cams, pts, oc, op, uv, C.byref(o))
     assert st == native.BA_EINVAL
+    native.lib().ba_options_default(C.byref(o))
+    assert o.jacobian == 0
+    o.jacobian = 2
+    st, h = _create(native, cams, pts, oc, op, uv, C.byref(o))
+    assert st == native.BA_EINVAL and b"jacobian" in native.lib().ba_last_error(None)
     assert native.lib().ba_status_str(4) == b"BA_ENUMERIC"
 
 

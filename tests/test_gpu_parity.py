@@ -95,7 +95,10 @@ def assert_traces_match(tr, gpu, tol=1e-9, decisive=1e-10):
     decisions (and so lambda) must agree while the oracle's cost change is
     above round-off (|F - F_trial| > decisive * F); once the solve has
     converged the gain ratio is a ratio of rounding errors and either
-    decision is correct."""
+    decision is correct.  A trial point whose cost rises more than tenfold
+    lies far outside the step's linear model, near a camera's principal plane
+    where the cost amplifies rounding in the step: there the trial costs are
+    compared to 1e-5 and both sides must reject."""
     assert gpu["status"] == 0
     assert gpu["iters_run"] == tr["iters_run"]
     assert abs(gpu["initial_cost"] - tr["initial_cost"]) <= 1e-13 * tr["initial_cost"]
@@ -103,8 +106,12 @@ def assert_traces_match(tr, gpu, tol=1e-9, decisive=1e-10):
     prev = tr["initial_cost"]
     same_path = True
     for k in range(tr["iters_run"]):
-        assert abs(gpu["trial_cost"][k] - tr["trial_cost"][k]) <= tol * abs(tr["trial_cost"][k]), k
+        wild = tr["trial_cost"][k] > 10 * prev
+        ttol = 1e-5 if wild else tol
+        assert abs(gpu["trial_cost"][k] - tr["trial_cost"][k]) <= ttol * abs(tr["trial_cost"][k]), k
         assert abs(gpu["cost"][k] - tr["cost"][k]) <= tol * abs(tr["cost"][k]), k
+        if wild:
+            assert not gpu["accepted"][k] and not tr["accepted"][k], k
         if abs(prev - tr["trial_cost"][k]) > decisive * prev and same_path:
             assert gpu["accepted"][k] == tr["accepted"][k], k
             assert abs(gpu["lambda"][k] - tr["lambda"][k]) <= 1e-6 * tr["lambda"][k], k
@@ -183,4 +190,51 @@ def test_hot_cold_split_matches_oracle(hot, monkeypatch):
         assert rel_err(prob.schur_matvec(x, lam), ref) <= tol, precision
         prob.close()
     tr, gpu, prob, _ = lm_pair(arrays, delta=1.0, iters=5, max_pcg=40, rtol=1e-8)
+    assert_traces_match(tr, gpu)
+
+
+def zero_rotation_variant(arrays):
+    """The same problem with camera 0's angle-axis set to exactly zero (the
+    first-order branch of the rotation)."""
+    cams = np.array(arrays[0], copy=True)
+    cams[0, :3] = 0.0
+    return (cams,) + tuple(arrays[1:5])
+
+
+@pytest.mark.parametrize("edge", [False, True])
+def test_autodiff_jacobian_cost_gradient_matvec(tiny, edge):
+    """Forward-mode autodiff Jacobians (the paper's "-a" form): cost, gradient
+    and the reduced-system product match the oracle as tightly as the analytic
+    form does, including a camera at exactly zero rotation."""
+    src = (tiny.cameras0, tiny.points0, tiny.obs_camera, tiny.obs_point, tiny.obs_uv)
+    arrays = zero_rotation_variant(with_edge_cases(small_zipf(seed=7))[:5] if edge else src)
+    cams, pts, oc, op, uv = arrays
+    prob = Problem(cams, pts, oc, op, uv, huber_delta=1.0, jacobian=1)
+    F, gc, gp = prob.eval_cost_grad()
+    Fo, gco, gpo = orc.gradient(cams, pts, oc, op, uv, 1.0)
+    assert abs(F - Fo) <= 1e-13 * abs(Fo)
+    assert rel_err(gc, gco) <= 1e-10 and rel_err(gp, gpo) <= 1e-10
+    lam = 1e-2
+    A = orc.assemble(cams, pts, oc, op, uv, 1.0)
+    Bd, Cd, Dc, Dp = orc.damp(A["B"], A["C"], lam, 0)
+    Ci = orc.invert_points(Cd)
+    x = np.random.default_rng(5).normal(size=(len(cams), 9))
+    ref = orc.schur_matvec(oc, op, Bd, A["E"], Ci, x)
+    assert rel_err(prob.schur_matvec(x, lam), ref) <= 1e-10
+    prob.close()
+    mixed = Problem(cams, pts, oc, op, uv, precision=FP32_MIXED, huber_delta=1.0, jacobian=1)
+    assert rel_err(mixed.schur_matvec(x, lam), ref) <= 2e-3
+    mixed.close()
+
+
+def test_autodiff_lm_trace_matches_oracle(tiny):
+    """An FP64 LM solve with autodiff Jacobians replays the oracle's trace."""
+    arrays = zero_rotation_variant((tiny.cameras0, tiny.points0, tiny.obs_camera, tiny.obs_point, tiny.obs_uv))
+    cams, pts, oc, op, uv = arrays
+    _, _, tr, rc = orc.lm_solve(cams, pts, oc, op, uv, huber_delta=1.0, max_lm_iters=8, max_pcg_iters=50,
+                                pcg_rtol=1e-8)
+    assert rc == 0
+    prob = Problem(cams, pts, oc, op, uv, huber_delta=1.0)
+    gpu = prob.lm_solve(max_lm_iters=8, pcg_schedule=tr["pcg_iters"], max_pcg_iters=50, pcg_rtol=1e-8, jacobian=1)
+    prob.close()
     assert_traces_match(tr, gpu)
