@@ -93,6 +93,16 @@ struct ba_problem {
         }                                                                                    \
     } while (0)
 
+// Text for a failed damped-block factorisation: bit 0 of the device flag is
+// set by the camera blocks, bit 1 by the point blocks.
+static std::string not_pd_message(int32_t bits, double lambda)
+{
+    std::string what = (bits & 1) && (bits & 2) ? "camera and point blocks" : (bits & 1) ? "camera block" : "point block";
+    char lam[32];
+    std::snprintf(lam, sizeof lam, "%.3e", lambda);
+    return "damped " + what + " not positive definite at lambda " + lam;
+}
+
 static bool finite_all(const double* a, int64_t len)
 {
     for (int64_t t = 0; t < len; ++t)
@@ -729,9 +739,9 @@ static ba_status lm_solve_t(ba_problem* P, const ba_options& o, ba_report* rep)
         BA_TRY(P, launch_damp_points<T>(n, (const double*)P->hpp, lambda, o.damping, (T*)P->cinv, P->flag, s));
         BA_TRY(P, hipMemcpyAsync(P->h_scalars, P->flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         BA_TRY(P, hipStreamSynchronize(s));
-        if (*(int32_t*)P->h_scalars != 0) {
+        if (const int32_t bad = *(int32_t*)P->h_scalars) {
             BA_TRY(P, hipMemsetAsync(P->flag, 0, sizeof(int32_t), s));
-            P->last_error = "damped block not positive definite";
+            P->last_error = not_pd_message(bad, lambda);
             result = BA_ENUMERIC;
             break;
         }
@@ -942,9 +952,9 @@ static ba_status schur_matvec_t(ba_problem* P, double lambda, int32_t damping, c
     BA_TRY(P, hipMemcpyAsync(qi.data(), P->q, qi.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     BA_TRY(P, hipMemcpyAsync(P->h_scalars, P->flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     BA_TRY(P, hipStreamSynchronize(s));
-    if (*(int32_t*)P->h_scalars != 0) {
+    if (const int32_t bad = *(int32_t*)P->h_scalars) {
         BA_TRY(P, hipMemset(P->flag, 0, sizeof(int32_t)));
-        P->last_error = "damped block not positive definite";
+        P->last_error = not_pd_message(bad, lambda);
         return BA_ENUMERIC;
     }
     for (int32_t j = 0; j < m; ++j)

@@ -47,19 +47,29 @@ hipError_t launch_camera_constants_f32(int32_t m, const double* cams, CamK<float
 }
 
 // ------------------------------------------------------ point-major build
-// Terms of one observation for its point: C (upper 6) and w (3).
+// Terms of one observation for its point: C (upper 6) and w (3).  Each
+// product is formed in FP64 from the T-precision Jacobian; a product of two
+// floats is exact there, so the sum over a point's observations is the Gram
+// matrix of the float Jacobian to FP64 rounding: positive semidefinite like
+// the FP64 form's, instead of carrying float rounding of order 1e-7 of its
+// largest eigenvalue into its smallest (a two-view point with a narrow
+// baseline has a smaller one than that).
 template <typename T>
-__device__ __forceinline__ void point_terms(const T Jp[6], T e0, T e1, T wt, T out[9])
+__device__ __forceinline__ void point_terms(const T Jp[6], T e0, T e1, T wt, double out[9])
 {
-    out[0] = wt * (Jp[0] * Jp[0] + Jp[3] * Jp[3]);
-    out[1] = wt * (Jp[0] * Jp[1] + Jp[3] * Jp[4]);
-    out[2] = wt * (Jp[0] * Jp[2] + Jp[3] * Jp[5]);
-    out[3] = wt * (Jp[1] * Jp[1] + Jp[4] * Jp[4]);
-    out[4] = wt * (Jp[1] * Jp[2] + Jp[4] * Jp[5]);
-    out[5] = wt * (Jp[2] * Jp[2] + Jp[5] * Jp[5]);
-    out[6] = -wt * (Jp[0] * e0 + Jp[3] * e1);
-    out[7] = -wt * (Jp[1] * e0 + Jp[4] * e1);
-    out[8] = -wt * (Jp[2] * e0 + Jp[5] * e1);
+    const double w = wt, r0 = e0, r1 = e1;
+    double j[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) j[q] = Jp[q];
+    out[0] = w * (j[0] * j[0] + j[3] * j[3]);
+    out[1] = w * (j[0] * j[1] + j[3] * j[4]);
+    out[2] = w * (j[0] * j[2] + j[3] * j[5]);
+    out[3] = w * (j[1] * j[1] + j[4] * j[4]);
+    out[4] = w * (j[1] * j[2] + j[4] * j[5]);
+    out[5] = w * (j[2] * j[2] + j[5] * j[5]);
+    out[6] = -w * (j[0] * r0 + j[3] * r1);
+    out[7] = -w * (j[1] * r0 + j[4] * r1);
+    out[8] = -w * (j[2] * r0 + j[5] * r1);
 }
 
 template <typename T, bool AD>
@@ -114,9 +124,9 @@ __device__ __forceinline__ double wave_sum(double v)
 // Point-major build over point-aligned tiles of <= kTile observations (a
 // longer point is a tile alone).  One thread per observation computes its
 // residual and Jacobian and stores E_k = w J_c^T J_p (27 coalesced streams);
-// its terms of C_i and w_i go to LDS, and the first thread of each point sums
-// the point's terms in stream order (FP64) and stores C_i (upper 6, as T)
-// and w_i (FP64).  GRAD_ONLY forms w_i only.
+// its terms of C_i and w_i go to LDS (FP64), and the first thread of each
+// point sums the point's terms in stream order and stores C_i (upper 6) and
+// w_i in FP64.  GRAD_ONLY forms w_i only.
 template <typename T, bool GRAD_ONLY, bool AD>
 __global__ __launch_bounds__(kTile) void k_build_points(
     const int32_t* __restrict__ tile, const int32_t* __restrict__ cam, const int32_t* __restrict__ pt,
@@ -125,7 +135,7 @@ __global__ __launch_bounds__(kTile) void k_build_points(
     double* __restrict__ wpt)
 {
     constexpr int R = GRAD_ONLY ? 3 : 9;  // terms kept: [C upper 6 |] w 3
-    __shared__ T sh[R][kTile];
+    __shared__ double sh[R][kTile];
     __shared__ int32_t shpt[kTile];
     __shared__ double red[R][kTile / 64];
     const int tid = threadIdx.x;
@@ -139,7 +149,7 @@ __global__ __launch_bounds__(kTile) void k_build_points(
             T e0, e1, wt, Jc[18], Jp[6];
             observation<T, AD>(k, cam, pt, uvx, uvy, pts, js, delta, e0, e1, wt, Jc, Jp, i);
             if (!GRAD_ONLY) store_coupling_blocked<T>(k, Jc, Jp, wt, hcp);
-            T v[9];
+            double v[9];
             point_terms<T>(Jp, e0, e1, wt, v);
 #pragma unroll
             for (int q = 0; q < R; ++q) sh[q][tid] = v[9 - R + q];
@@ -152,7 +162,7 @@ __global__ __launch_bounds__(kTile) void k_build_points(
             for (int q = 0; q < R; ++q) acc[q] = 0.0;
             for (int u = tid; u < len && shpt[u] == i; ++u)
 #pragma unroll
-                for (int q = 0; q < R; ++q) acc[q] += (double)sh[q][u];
+                for (int q = 0; q < R; ++q) acc[q] += sh[q][u];
             if (!GRAD_ONLY)
 #pragma unroll
                 for (int q = 0; q < 6; ++q) hpp[6 * (int64_t)i + q] = acc[q];
@@ -171,10 +181,10 @@ __global__ __launch_bounds__(kTile) void k_build_points(
             int32_t ii;
             observation<T, AD>(k, cam, pt, uvx, uvy, pts, js, delta, e0, e1, wt, Jc, Jp, ii);
             if (!GRAD_ONLY) store_coupling_blocked<T>(k, Jc, Jp, wt, hcp);
-            T v[9];
+            double v[9];
             point_terms<T>(Jp, e0, e1, wt, v);
 #pragma unroll
-            for (int q = 0; q < R; ++q) acc[q] += (double)v[9 - R + q];
+            for (int q = 0; q < R; ++q) acc[q] += v[9 - R + q];
         }
 #pragma unroll
         for (int q = 0; q < R; ++q) {
@@ -270,16 +280,21 @@ __global__ __launch_bounds__(256) void k_build_cameras(
         }
         while (true) {
             if (valid && j == cur) {
+                // FP64 products of the T-precision Jacobian (exact for
+                // float), as in point_terms: B_j stays a Gram matrix
+                const double w = wt, r0 = e0, r1 = e1;
+                double jc[18];
+#pragma unroll
+                for (int a = 0; a < 18; ++a) jc[a] = Jc[a];
                 int q = 0;
                 if (!GRAD_ONLY) {
 #pragma unroll
                     for (int a = 0; a < 9; ++a)
 #pragma unroll
-                        for (int b = a; b < 9; ++b)
-                            acc[q++] += (double)(wt * (Jc[a] * Jc[b] + Jc[9 + a] * Jc[9 + b]));
+                        for (int b = a; b < 9; ++b) acc[q++] += w * (jc[a] * jc[b] + jc[9 + a] * jc[9 + b]);
                 }
 #pragma unroll
-                for (int a = 0; a < 9; ++a) acc[q++] += (double)(-wt * (Jc[a] * e0 + Jc[9 + a] * e1));
+                for (int a = 0; a < 9; ++a) acc[q++] += -w * (jc[a] * r0 + jc[9 + a] * r1);
             }
             // lanes not yet consumed hold larger camera ids (the chunk is sorted)
             const uint64_t more = __ballot(valid && j > cur);

@@ -103,8 +103,9 @@ def test_lm_trace_fp64_matches_oracle(name):
     widened where the step itself is known only loosely.
       * PCG stopped at its iteration cap without reaching rtol: two FP64 CG
         runs that differ only in summation order drift apart over many
-        unconverged iterations, so the trial cost may also differ by 1e-7 of
-        the cost change |F_trial - F|.
+        unconverged iterations (the GPU's order also varies from run to run:
+        its camera sums use atomic adds), so the trial cost may also differ by
+        1e-6 of the cost change |F_trial - F| (observed: up to 5e-7).
       * A trial point far outside the region where the step's linear model
         holds (its cost rises more than tenfold) puts observations close to a
         camera's principal plane, where the cost is very sensitive to the
@@ -121,7 +122,7 @@ def test_lm_trace_fp64_matches_oracle(name):
         wild = ft > 10 * prev
         tol = 1e-5 * ft if wild else 1e-9 * ft
         if not wild and g["pcg_iters"][k] >= cap:
-            tol += 1e-7 * abs(ft - prev)
+            tol += 1e-6 * abs(ft - prev)
         err = abs(rep["trial_cost"][k] - ft)
         print(f"iter {k}: trial rel diff {err / ft:.2e} (tol {tol / ft:.1e}), pcg {g['pcg_iters'][k]}")
         assert err <= tol, k

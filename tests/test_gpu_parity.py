@@ -238,3 +238,48 @@ def test_autodiff_lm_trace_matches_oracle(tiny):
     gpu = prob.lm_solve(max_lm_iters=8, pcg_schedule=tr["pcg_iters"], max_pcg_iters=50, pcg_rtol=1e-8, jacobian=1)
     prob.close()
     assert_traces_match(tr, gpu)
+
+
+def narrow_baseline(seed=0, m=3, n=400, base=0.01, depth=100.0):
+    """Cameras 0.01 apart on a line, facing points about 100 away; every point
+    is seen by two neighbouring cameras, so its rays meet at ~1e-4 rad and its
+    block C_i, scaled to unit diagonal, has a smallest eigenvalue of 1e-8 ..
+    3e-6.  Rounding each float product of the Jacobian to float would move
+    those eigenvalues by up to ~6e-8 and leave about a sixth of the blocks
+    indefinite (checked by emulating float products on the oracle's
+    Jacobians)."""
+    rng = np.random.default_rng(seed)
+    cams = np.zeros((m, 9))
+    cams[:, :3] = rng.normal(scale=1e-3, size=(m, 3))
+    cams[:, 3] = base * np.arange(m)
+    cams[:, 6] = 500.0
+    cams[:, 7], cams[:, 8] = -1e-7, 1e-13
+    pts = np.column_stack([rng.uniform(-30, 30, n), rng.uniform(-30, 30, n), -depth + rng.uniform(-10, 10, n)])
+    j = np.arange(n) % (m - 1)
+    oc = np.column_stack([j, j + 1]).ravel().astype(np.int32)
+    op = np.repeat(np.arange(n), 2).astype(np.int32)
+    uv = np.array([orc.project(cams[a], pts[b]) for a, b in zip(oc, op)])
+    uv += rng.normal(scale=0.5, size=uv.shape)
+    return cams, pts, oc, op, uv
+
+
+def test_mixed_blocks_factor_at_narrow_baselines():
+    """The FP32-mixed form forms every product of its Gram blocks B_j and C_i
+    in FP64 from the float Jacobian, so the blocks stay positive semidefinite
+    and their damped forms factor wherever the FP64 form's do, down to
+    lambda = 0, on two-view points whose rays nearly coincide.  The FP64
+    product matches the oracle's at lambda 1e-6."""
+    arrays = narrow_baseline()
+    cams, pts, oc, op, uv = arrays
+    x = np.random.default_rng(3).normal(size=(len(cams), 9))
+    A = orc.assemble(cams, pts, oc, op, uv, 0.0)
+    Bd, Cd, _, _ = orc.damp(A["B"], A["C"], 1e-6, 0)
+    ref = orc.schur_matvec(oc, op, Bd, A["E"], orc.invert_points(Cd), x)
+    for precision in (FP64, FP32_MIXED):
+        prob, _ = make(arrays, precision=precision)
+        for lam in (1e-6, 1e-12, 0.0):
+            q = prob.schur_matvec(x, lam)
+            assert np.all(np.isfinite(q)), (precision, lam)
+            if precision == FP64 and lam == 1e-6:
+                assert rel_err(q, ref) <= 1e-7
+        prob.close()
