@@ -33,6 +33,9 @@ WORKLOADS = {  # name -> synth config and solver settings
     # one GPU's share of the 29M workload split over 8 GPUs (point-aligned edge partition)
     "large_chunk8": dict(config="large", chunk=(0, 8), huber_delta=1.0, max_pcg_iters=100, pcg_rtol=1e-6),
     "tiny": dict(config="tiny", huber_delta=0.0, max_pcg_iters=50, pcg_rtol=1e-8),
+    # the paper's synthesised problem: 20,000 cameras, 80,000 points seen 1,000 times each
+    "synth20000": dict(config="synth20000", huber_delta=0.0, max_pcg_iters=100, pcg_rtol=1e-6),
+    "synth_small": dict(config="synth_small", huber_delta=0.0, max_pcg_iters=100, pcg_rtol=1e-6),
 }
 
 
@@ -255,7 +258,8 @@ def main():
         "config": {"workload": f"{args.workload}: {m} cameras, {n} points, {N} observations, "
                                + (f"point-aligned chunk {wl['chunk'][0]} of {wl['chunk'][1]} of '{wl['config']}', "
                                   if "chunk" in wl else "")
-                               + f"Zipf visibility, Huber delta={wl['huber_delta']}, {args.jacobian} Jacobians, PCG max "
+                               + ("uniform visibility, " if wl["config"] in synth.CIRCLE_CONFIGS else "Zipf visibility, ")
+                               + f"Huber delta={wl['huber_delta']}, {args.jacobian} Jacobians, PCG max "
                                f"{wl['max_pcg_iters']} rtol {wl['pcg_rtol']}",
                    "cameras": m, "points": n, "observations": N},
         "pcg_iter_per_s": s32["pcg_iter_per_s"],

@@ -396,8 +396,23 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     {
         int32_t kmax = P->is_f32() ? hot_max_cameras<float>((size_t)lds_limit)
                                    : hot_max_cameras<double>((size_t)lds_limit);
-        if (const char* env = std::getenv("BA_HOT_CAMERAS")) kmax = std::min(kmax, std::max(0, std::atoi(env)));
+        const char* env = std::getenv("BA_HOT_CAMERAS");
+        if (env) kmax = std::min(kmax, std::max(0, std::atoi(env)));
         sp.K = std::max(0, std::min(m, kmax));
+        if (sp.K > 0 && !env) {
+            // A point that reaches two tiles past the one it starts in is walked
+            // again for the hot side (its tiles once more, plus the tile the pass
+            // resumes at); with no hot camera that walk is skipped and the cold
+            // stream takes every observation.  Keep the hot set only when it
+            // reads fewer coupling blocks per product: N + rewalk + cold < 2N.
+            int64_t rewalk = 0, cold = 0;
+            for (int32_t i = 0; i < n; ++i) {
+                const int64_t a = poff[i], b = poff[(size_t)i + 1];
+                if (b - a > 0 && ((b - 1) >> 6) >= (a >> 6) + 2) rewalk += (((b - 1) >> 6) - (a >> 6) + 2) * 64;
+            }
+            for (int32_t j = sp.K; j < m; ++j) cold += coff[(size_t)j + 1] - coff[j];
+            if (rewalk + cold > N) sp.K = 0;
+        }
     }
     // line-aligned 64-observation tiles split evenly over the hot pass's
     // wavefronts; the point-major arrays end with one padding tile (point -1)

@@ -229,12 +229,13 @@ __global__ __launch_bounds__(HotThreads<T>::value) void k_schur_hot(
                             bcold[3 * (int64_t)s_pt + 1] = s1;
                             bcold[3 * (int64_t)s_pt + 2] = s2;
                         }
-                        for (int64_t v = t; v <= u; ++v) {
-                            int32_t j, i;
-                            T h[27];
-                            load_tile<T>(v, lane, cam, pt, hcp, j, i, h);
-                            if (i == s_pt && j < K) add_hot<T>(cl, j, h, s0, s1, s2);
-                        }
+                        if (K > 0)  // with no hot camera the cold pass does the camera side
+                            for (int64_t v = t; v <= u; ++v) {
+                                int32_t j, i;
+                                T h[27];
+                                load_tile<T>(v, lane, cam, pt, hcp, j, i, h);
+                                if (i == s_pt && j < K) add_hot<T>(cl, j, h, s0, s1, s2);
+                            }
                         // tiles t + 1 .. u - 1 hold only this point; go on at tile u
                         before = s_pt;
                         t = u;

@@ -23,6 +23,12 @@ benchmark configurations):
   large  : 13,700 / 4.5M / 29M, stand-in for BAL Final-13682, 5% outliers.
   diff   : 1,000 / 200k / 1M, Huber workload for the gradient checks.
   stress : 20,000 / 10M / 60M, 5% outliers.
+  synth20000 : the paper's synthesised production-like problem (Sec. 6,
+           large synthesised dataset): 20,000 cameras evenly on a circle of
+           radius 8, 80,000 points in a 0.2 x 0.2 x 0.06 slab at its centre,
+           each seen by 1,000 distinct uniformly chosen cameras (80M
+           observations, every point a long run).  synth_small is the same
+           recipe at 400 / 1,600 / 480k for oracle-sized checks.
 Zipf visibility: the number of views of a point follows a truncated power
 law on [2, V_max] whose exponent is solved so that the mean equals N/n; the
 cameras of a point are distinct and drawn with weights proportional to
@@ -36,7 +42,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-__all__ = ["Problem", "CONFIGS", "generate", "point_chunk", "ring_rotation", "rotvec_from_matrix"]
+__all__ = ["Problem", "CONFIGS", "CIRCLE_CONFIGS", "generate", "point_chunk", "ring_rotation", "rotvec_from_matrix"]
 
 
 @dataclass
@@ -79,6 +85,13 @@ CONFIGS = {
     "large":  dict(m=13_700, n=4_500_000, N=29_000_000, vmax=60, half=50.0, ring=150.0, outliers=0.05),
     "diff":   dict(m=1000, n=200_000, N=1_000_000, vmax=40, half=50.0, ring=150.0, outliers=0.05),
     "stress": dict(m=20_000, n=10_000_000, N=60_000_000, vmax=80, half=50.0, ring=150.0, outliers=0.05),
+}
+
+
+# name -> circle recipe: cameras, points, views per point, circle radius
+CIRCLE_CONFIGS = {
+    "synth20000": dict(m=20_000, n=80_000, views=1_000, radius=8.0),
+    "synth_small": dict(m=400, n=1_600, views=300, radius=8.0),
 }
 
 
@@ -210,7 +223,72 @@ def _distinct_weighted(rng, views, weights):
     return owner, rank
 
 
+def _render(Rs, cams, pts, obs_camera, obs_point) -> np.ndarray:
+    """Pixel coordinates of every observation under the sensor model."""
+    N = obs_point.shape[0]
+    uv = np.empty((N, 2), dtype=np.float64)
+    chunk = 1 << 22
+    for s in range(0, N, chunk):
+        e = min(N, s + chunk)
+        cj = obs_camera[s:e]
+        X = pts[obs_point[s:e]]
+        P = _apply_rows(Rs[cj], X) + cams[cj, 3:6]
+        px = -P[:, 0] / P[:, 2]
+        py = -P[:, 1] / P[:, 2]
+        r2 = px * px + py * py
+        d = 1.0 + cams[cj, 7] * r2 + cams[cj, 8] * r2 * r2
+        fd = cams[cj, 6] * d
+        uv[s:e, 0] = fd * px
+        uv[s:e, 1] = fd * py
+        assert np.all(P[:, 2] < 0.0), "point behind a camera"
+    return uv
+
+
+def _generate_circle(name: str, seed: int) -> Problem:
+    """The synthesised recipe of Sec. 6.  The paper fixes the counts, the
+    circle, the point box and the noise laws; where it is silent this takes:
+    the circle in the z = 0 plane with every camera looking at its centre (as
+    the ring rule of the other recipes), true intrinsics drawn as there
+    (f ~ U[490, 510], k1 and k2 normal with standard deviation 1e-3), views drawn uniformly without
+    replacement, observations rendered without pixel noise (the paper names
+    none, so the optimum has zero cost), and the noise laws read as the
+    perturbation of the start point: U(0, 0.01) added to every angle-axis
+    and translation component, U(0, 0.5) to f, k1 and k2, U(-0.1, 0.1) to
+    the x and y of every point."""
+    cfg = CIRCLE_CONFIGS[name]
+    m, n, views, radius = cfg["m"], cfg["n"], cfg["views"], cfg["radius"]
+    rng = np.random.default_rng(seed)
+    cams = np.zeros((m, 9), dtype=np.float64)
+    Rs = np.zeros((m, 3, 3), dtype=np.float64)
+    for j in range(m):
+        phi = 2.0 * math.pi * (j + 0.5) / m
+        R = ring_rotation(phi)
+        C = np.array([radius * math.cos(phi), radius * math.sin(phi), 0.0])
+        Rs[j] = R
+        cams[j, 0:3] = rotvec_from_matrix(R)
+        cams[j, 3:6] = -(R @ C)
+    cams[:, 6] = rng.uniform(490.0, 510.0, size=m)
+    cams[:, 7] = rng.normal(0.0, 1e-3, size=m)
+    cams[:, 8] = rng.normal(0.0, 1e-3, size=m)
+    pts = np.column_stack([rng.uniform(-0.1, 0.1, n), rng.uniform(-0.1, 0.1, n), rng.uniform(-0.03, 0.03, n)])
+    obs_camera = np.empty(n * views, dtype=np.int32)
+    for i in range(n):
+        obs_camera[i * views:(i + 1) * views] = rng.choice(m, size=views, replace=False)
+    obs_point = np.repeat(np.arange(n, dtype=np.int32), views)
+    uv = _render(Rs, cams, pts, obs_camera, obs_point)
+    cams0 = cams.copy()
+    cams0[:, 0:6] += rng.uniform(0.0, 0.01, size=(m, 6))
+    cams0[:, 6:9] += rng.uniform(0.0, 0.5, size=(m, 3))
+    pts0 = pts.copy()
+    pts0[:, 0:2] += rng.uniform(-0.1, 0.1, size=(n, 2))
+    meta = dict(config=name, seed=seed, power_law_exponent=None, outlier_fraction=0.0)
+    return Problem(name, cams, pts, cams0, pts0, obs_camera, obs_point, uv, np.zeros(n * views, dtype=bool), meta)
+
+
 def generate(name: str, seed: int = 0, outliers: float | None = None) -> Problem:
+    if name in CIRCLE_CONFIGS:
+        assert outliers is None, "the synthesised recipe has no outliers"
+        return _generate_circle(name, seed)
     cfg = CONFIGS[name]
     m, n, vmax, half, ring = cfg["m"], cfg["n"], cfg["vmax"], cfg["half"], cfg["ring"]
     out_frac = cfg["outliers"] if outliers is None else outliers
@@ -247,21 +325,7 @@ def generate(name: str, seed: int = 0, outliers: float | None = None) -> Problem
     N = obs_point.shape[0]
 
     # render with the sensor model (rotation matrix, not the angle-axis)
-    uv = np.empty((N, 2), dtype=np.float64)
-    chunk = 1 << 22
-    for s in range(0, N, chunk):
-        e = min(N, s + chunk)
-        cj = obs_camera[s:e]
-        X = pts[obs_point[s:e]]
-        P = _apply_rows(Rs[cj], X) + cams[cj, 3:6]
-        px = -P[:, 0] / P[:, 2]
-        py = -P[:, 1] / P[:, 2]
-        r2 = px * px + py * py
-        d = 1.0 + cams[cj, 7] * r2 + cams[cj, 8] * r2 * r2
-        fd = cams[cj, 6] * d
-        uv[s:e, 0] = fd * px
-        uv[s:e, 1] = fd * py
-        assert np.all(P[:, 2] < 0.0), "point behind a camera"
+    uv = _render(Rs, cams, pts, obs_camera, obs_point)
     noise = rng.normal(0.0, 1.0, size=(N, 2))
     flag = np.zeros(N, dtype=bool)
     if out_frac > 0.0:
@@ -297,7 +361,7 @@ def point_chunk(prob: Problem, k: int, K: int) -> Problem:
 def render_exact(prob: Problem) -> np.ndarray:
     """Noise-free rendering of the true scene (for zero-residual checks)."""
     m = prob.num_cameras
-    ring = CONFIGS[prob.name]["ring"]
+    ring = CIRCLE_CONFIGS[prob.name]["radius"] if prob.name in CIRCLE_CONFIGS else CONFIGS[prob.name]["ring"]
     Rs = np.stack([ring_rotation(2.0 * math.pi * (j + 0.5) / m) for j in range(m)])
     cj = prob.obs_camera
     X = prob.points_true[prob.obs_point]

@@ -193,6 +193,46 @@ def test_stress_cost_gradient_and_schur_rows():
     assert np.all(np.diff(costs) <= 0)
 
 
+def test_synthesised_20000_cost_gradient_and_schur_rows():
+    """The paper's synthesised problem at full size (20,000 cameras, 80,000
+    points seen 1,000 times each, 80M observations), in both precisions:
+    FP64 cost and sampled camera and point gradients against the oracle,
+    sampled rows of the reduced system against the oracle's rows computed
+    from scratch, and two LM iterations with non-increasing cost."""
+    prob = synth.generate("synth20000", seed=0)
+    args = (prob.cameras0, prob.points0, prob.obs_camera, prob.obs_point, prob.obs_uv)
+    Fo = orc.cost(*args, 0.0)
+    cam_csr = orc.csr(prob.obs_camera, prob.num_cameras)
+    pt_csr = orc.csr(prob.obs_point, prob.num_points)
+    rng = np.random.default_rng(9)
+    cams = [int(j) for j in rng.choice(prob.num_cameras, 3, replace=False)]
+    pts = [int(i) for i in rng.choice(prob.num_points, 20, replace=False)]
+    x = rng.normal(size=(prob.num_cameras, 9))
+    ref_rows = orc.schur_rows(cams, *args[:2], *args[2:], x, 1e-3, 0.0, cam_csr=cam_csr, pt_csr=pt_csr)
+    for precision in (FP64, FP32_MIXED):
+        gpu = Problem(*args, precision=precision)
+        F, gc, gp = gpu.eval_cost_grad()
+        assert abs(F - Fo) <= 1e-12 * Fo, precision
+        gtol = 1e-10 if precision == FP64 else 1e-3
+        off, order = cam_csr
+        for j in cams:
+            ref = -orc.subset_sums(order[off[j]:off[j + 1]], *args, 0.0)["v"]
+            assert np.max(np.abs(gc[j] - ref)) <= gtol * np.max(np.abs(ref)), (precision, j)
+        off, order = pt_csr
+        for i in pts:
+            ref = -orc.subset_sums(order[off[i]:off[i + 1]], *args, 0.0)["w"]
+            assert np.max(np.abs(gp[i] - ref)) <= gtol * np.max(np.abs(ref)), (precision, i)
+        q = gpu.schur_matvec(x, 1e-3)
+        qtol = 1e-9 if precision == FP64 else 2e-3
+        for t, j in enumerate(cams):
+            assert np.max(np.abs(q[j] - ref_rows[t])) <= qtol * np.max(np.abs(ref_rows[t])), (precision, j)
+        rep = gpu.lm_solve(max_lm_iters=2, max_pcg_iters=100, pcg_rtol=1e-6)
+        gpu.close()
+        assert rep["status"] == 0
+        costs = np.concatenate([[rep["initial_cost"]], rep["cost"]])
+        assert np.all(np.diff(costs) <= 0) and costs[-1] < costs[0], precision
+
+
 def test_chunk_of_eight_lm_matches_oracle():
     """One GPU's share of the 29M workload split over eight GPUs (all 13,700
     cameras, the first 1/8 of the observations at point boundaries): three

@@ -76,6 +76,43 @@ def test_zero_residual_at_truth(tiny):
         assert np.max(np.abs(uv - exact[k])) <= 1e-9
 
 
+def test_synthesised_recipe_structure_and_zero_cost_at_truth():
+    """The synthesised recipe (Sec. 6) at oracle size: every point has exactly
+    its number of distinct views, the points lie in the stated box, the
+    observations carry no pixel noise (the oracle's cost at the true
+    parameters is zero to rounding), and the start point differs from the
+    truth only where the recipe perturbs it, within the stated laws."""
+    prob = synth.generate("synth_small", seed=0)
+    cfg = synth.CIRCLE_CONFIGS["synth_small"]
+    assert prob.num_obs == cfg["n"] * cfg["views"]
+    for i in range(0, prob.num_points, 97):
+        cams = prob.obs_camera[prob.obs_point == i]
+        assert len(cams) == cfg["views"] and len(np.unique(cams)) == cfg["views"]
+    assert np.all(np.abs(prob.points_true[:, :2]) <= 0.1) and np.all(np.abs(prob.points_true[:, 2]) <= 0.03)
+    centres = -np.einsum("kji,kj->ki", np.stack([orc_rotation(w) for w in prob.cameras_true[:, :3]]),
+                         prob.cameras_true[:, 3:6])
+    np.testing.assert_allclose(np.hypot(centres[:, 0], centres[:, 1]), cfg["radius"], rtol=1e-12)
+    np.testing.assert_allclose(centres[:, 2], 0.0, atol=1e-12)
+    args = (prob.obs_camera, prob.obs_point, prob.obs_uv)
+    F0 = orc.cost(prob.cameras_true, prob.points_true, *args)
+    assert F0 <= 1e-18 * prob.num_obs
+    dc = prob.cameras0 - prob.cameras_true
+    assert np.all((dc[:, :6] >= 0) & (dc[:, :6] <= 0.01)) and np.all((dc[:, 6:] >= 0) & (dc[:, 6:] <= 0.5))
+    dp = prob.points0 - prob.points_true
+    assert np.all(np.abs(dp[:, :2]) <= 0.1) and np.all(dp[:, 2] == 0.0)
+
+
+def orc_rotation(w):
+    """Rotation matrix of an angle-axis vector (Rodrigues' formula), used only
+    to place the camera centres C = -R^T t of the recipe's circle."""
+    th = np.linalg.norm(w)
+    if th == 0.0:
+        return np.eye(3)
+    k = w / th
+    K = np.array([[0, -k[2], k[1]], [k[2], 0, -k[0]], [-k[1], k[0], 0]])
+    return np.eye(3) + np.sin(th) * K + (1 - np.cos(th)) * (K @ K)
+
+
 # ------------------------------------------------------------------- C3
 def test_jacobian_matches_central_differences(tiny):
     rng = np.random.default_rng(3)
