@@ -75,6 +75,8 @@ struct ba_problem {
     // PCG
     double *g = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *cacc = nullptr;
     void* pT = nullptr;
+    void* wobs = nullptr;  // [ld] of T: IRLS weight per point-major observation
+    void* xf = nullptr;    // [m][12] of T: camera vectors of the recomputing product
     double* dp = nullptr;
     double *partials = nullptr, *sums = nullptr;
     PcgScalars* sc = nullptr;
@@ -399,7 +401,9 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
         const char* env = std::getenv("BA_HOT_CAMERAS");
         if (env) kmax = std::min(kmax, std::max(0, std::atoi(env)));
         sp.K = std::max(0, std::min(m, kmax));
-        if (sp.K > 0 && !env) {
+        const char* stored = std::getenv("BA_SCHUR_STORED");
+        sp.recompute = !(stored && std::atoi(stored) != 0);
+        if (sp.K > 0 && !env && !sp.recompute) {
             // A point that reaches two tiles past the one it starts in is walked
             // again for the hot side (its tiles once more, plus the tile the pass
             // resumes at); with no hot camera that walk is skipped and the cold
@@ -426,6 +430,52 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     const int32_t num_waves = sp.num_wg * waves_per_wg;
     std::vector<int32_t> wrange((size_t)num_waves + 1, 0);
     for (int32_t w = 0; w <= num_waves; ++w) wrange[(size_t)w] = (int32_t)((int64_t)w * ntiles64 / num_waves);
+    // recomputing product: point-aligned segments, short (<= 64 observations of
+    // whole points) and long (one point of more observations); each kind is
+    // split over the wavefronts by observation count
+    const int32_t free_waves = num_waves;
+    std::vector<int2> sseg, lseg;
+    std::vector<int32_t> frange((size_t)free_waves + 1, 0), lrange((size_t)free_waves + 1, 0);
+    {
+        int64_t open = -1, open_len = 0;  // the short segment being filled
+        for (int32_t i = 0; i < n; ++i) {
+            const int64_t a = poff[i], b = poff[(size_t)i + 1];
+            if (b == a) continue;
+            if (b - a > 64) {
+                lseg.push_back(make_int2((int32_t)a, (int32_t)b));
+                continue;
+            }
+            if (open >= 0 && open_len + (b - a) > 64) {
+                sseg.push_back(make_int2((int32_t)open, (int32_t)(open + open_len)));
+                open = -1;
+            }
+            if (open < 0) {
+                open = a;
+                open_len = 0;
+            }
+            // points of one short segment are contiguous: a long point closes it
+            if (open + open_len != a) {
+                sseg.push_back(make_int2((int32_t)open, (int32_t)(open + open_len)));
+                open = a;
+                open_len = 0;
+            }
+            open_len += b - a;
+        }
+        if (open >= 0) sseg.push_back(make_int2((int32_t)open, (int32_t)(open + open_len)));
+        sp.num_short = (int32_t)sseg.size();
+        sp.num_long = (int32_t)lseg.size();
+        auto split = [&](const std::vector<int2>& v, std::vector<int32_t>& range) {
+            std::vector<int64_t> cum(v.size() + 1, 0);
+            for (size_t q = 0; q < v.size(); ++q) cum[q + 1] = cum[q] + (v[q].y - v[q].x);
+            for (int32_t w = 0; w <= free_waves; ++w) {
+                const int64_t target = cum.back() * w / std::max(1, free_waves);
+                range[(size_t)w] = (int32_t)(std::lower_bound(cum.begin(), cum.end(), target) - cum.begin());
+            }
+            range[(size_t)free_waves] = (int32_t)v.size();
+        };
+        split(sseg, frange);
+        split(lseg, lrange);
+    }
     // the build: 32 wavefronts per CU over the same tiles
     // cold stream: observations on cameras >= K, camera-major
     std::vector<int32_t> h_cold_cam, h_cold_pt;
@@ -440,9 +490,11 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     sp.cold.N = (int64_t)h_cold_cam.size();
     if (std::getenv("BA_VERBOSE"))
         std::fprintf(stderr,
-                     "[ba] m=%d n=%d N=%lld cus=%d lds/block=%d hot K=%d wg=%d tiles=%lld cold obs=%lld (%.2f%%)\n",
+                     "[ba] m=%d n=%d N=%lld cus=%d lds/block=%d hot K=%d wg=%d tiles=%lld cold obs=%lld (%.2f%%) "
+                     "product=%s segments=%d\n",
                      m, n, (long long)N, cus, lds_limit, sp.K, sp.num_wg, (long long)ntiles64, (long long)sp.cold.N,
-                     N > 0 ? 100.0 * (double)sp.cold.N / (double)N : 0.0);
+                     N > 0 ? 100.0 * (double)sp.cold.N / (double)N : 0.0, sp.recompute ? "recompute" : "stored",
+                     sp.num_short + sp.num_long);
     std::vector<int32_t> cold_chunk_slot, cold_cam_slot;
     sp.cold.num_slots = plan_slots(h_cold_cam, m, kColdChunk, cold_chunk_slot, cold_cam_slot);
     sp.cold.num_chunks = (int32_t)cold_chunk_slot.size() - 1;
@@ -487,6 +539,12 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     for (double** v : {&P->g, &P->x, &P->r, &P->z, &P->p, &P->q, &P->cacc}) *v = A.get<double>(9 * (int64_t)m);
     P->pT = A.get<char>(9 * (int64_t)m * (int64_t)tsz);
     sp.wrange = A.get<int32_t>((int64_t)wrange.size());
+    sp.sseg = A.get<int2>(std::max<int64_t>(1, (int64_t)sseg.size()));
+    sp.lseg = A.get<int2>(std::max<int64_t>(1, (int64_t)lseg.size()));
+    sp.frange = A.get<int32_t>((int64_t)frange.size());
+    sp.lrange = A.get<int32_t>((int64_t)lrange.size());
+    P->wobs = A.get<char>(P->pm.ld * (int64_t)tsz);
+    P->xf = A.get<char>(12 * (int64_t)m * (int64_t)tsz);
     sp.has_cold = A.get<uint8_t>(n);
     sp.hot_part = A.get<double>((int64_t)sp.num_wg * sp.K * 9);
     sp.hot_fold = A.get<double>((int64_t)kHotFold * sp.K * 9);
@@ -542,6 +600,12 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     if (e == hipSuccess) e = hipMemset(P->hcc, 0, sizeof(double) * 81 * (size_t)m);
     if (e == hipSuccess) e = hipMemset(P->vcam, 0, sizeof(double) * 9 * (size_t)m);
     if (e == hipSuccess) e = up(sp.wrange, wrange.data(), sizeof(int32_t) * wrange.size());
+    if (e == hipSuccess && !sseg.empty()) e = up(sp.sseg, sseg.data(), sizeof(int2) * sseg.size());
+    if (e == hipSuccess && !lseg.empty()) e = up(sp.lseg, lseg.data(), sizeof(int2) * lseg.size());
+    if (e == hipSuccess) e = up(sp.frange, frange.data(), sizeof(int32_t) * frange.size());
+    if (e == hipSuccess) e = up(sp.lrange, lrange.data(), sizeof(int32_t) * lrange.size());
+    if (e == hipSuccess) e = hipMemset(P->wobs, 0, (size_t)P->pm.ld * tsz);
+    if (e == hipSuccess) e = hipMemset(P->xf, 0, 12 * (size_t)m * tsz);
     if (e == hipSuccess) e = up(sp.has_cold, has_cold.data(), (size_t)n);
     if (e == hipSuccess) e = up(sp.cold.cam, h_cold_cam.data(), sizeof(int32_t) * h_cold_cam.size());
     if (e == hipSuccess) e = up(sp.cold.pt, h_cold_pt.data(), sizeof(int32_t) * h_cold_pt.size());
@@ -617,6 +681,22 @@ static ba_status cost_into_sums(ba_problem* P, const double* pts, const CamK<T>*
     return BA_OK;
 }
 
+// Camera constants of the current state in T (FP32: refreshed by each build).
+template <typename T>
+static const CamK<T>* state_ck(const ba_problem* P)
+{
+    if constexpr (sizeof(T) == 4)
+        return (const CamK<T>*)P->ck32;
+    else
+        return (const CamK<T>*)P->ck64;
+}
+
+template <typename T>
+static RecomputeInputs<T> recompute_inputs(const ba_problem* P)
+{
+    return RecomputeInputs<T>{(const T*)P->wobs, P->pts, state_ck<T>(P), (const T*)P->xf};
+}
+
 template <typename T>
 static ba_status build_system(ba_problem* P)
 {
@@ -630,7 +710,7 @@ static ba_status build_system(ba_problem* P)
     }
     const JacSource<T> js{ck, P->opt.jacobian == BA_JACOBIAN_AUTODIFF ? P->cams : nullptr};
     BA_TRY(P, launch_build_points<T>(P->pm, P->opt.huber_delta, false, P->pts, js, (T*)P->hcp, (double*)P->hpp,
-                                     P->wpt, s));
+                                     P->wpt, (T*)P->wobs, s));
     BA_TRY(P, launch_build_cameras<T>(P->cm, P->m, P->N, P->pts, js, P->opt.huber_delta, false, P->hcc, P->vcam,
                                       P->sp.cold.N, (T*)P->sp.cold.hcp, s));
     return BA_OK;
@@ -671,9 +751,11 @@ static ba_status run_pcg(ba_problem* P, const ba_options& o, int32_t fixed, int3
     const int32_t cap = fixed > 0 ? fixed : o.max_pcg_iters;
     BA_TRY(P, launch_pcg_reset(P->sc, o.pcg_rtol, o.max_pcg_iters, fixed, s));
     // b = v - E C^-1 w; x = 0; r = b; ||b||^2; then z = M^-1 r and the first test
-    BA_TRY(P, launch_schur_product<T>(1, P->sp, P->pm, P->N, (const T*)P->hcp, (const T*)P->cinv, P->wpt, nullptr, m,
-                                      P->bd, nullptr, P->vcam, P->g, P->x, P->r, P->partials, P->sc, nullptr, nullptr,
-                                      s));
+    BA_TRY(P, launch_schur_product<T>(1, P->sp, P->pm, P->N, (const T*)P->hcp, (const T*)P->cinv, P->wpt, nullptr,
+                                      nullptr, m, P->bd, nullptr, P->vcam, P->g, P->x, P->r, P->partials, P->sc,
+                                      nullptr, nullptr, s));
+    const RecomputeInputs<T> ri = recompute_inputs<T>(P);
+    T* xf = P->sp.recompute ? (T*)P->xf : nullptr;
     BA_TRY(P, launch_pcg_step(m, true, P->lfac, P->p, P->q, P->x, P->r, P->z, P->partials, P->sc, s));
     std::vector<std::array<hipEvent_t, 4>> marks;
     const int32_t batch = fixed > 0 ? std::max(1, cap) : 8;
@@ -681,7 +763,7 @@ static ba_status run_pcg(ba_problem* P, const ba_options& o, int32_t fixed, int3
     while (enqueued < cap) {
         const int32_t nb = std::min(batch, cap - enqueued);
         for (int32_t b = 0; b < nb; ++b) {
-            BA_TRY(P, launch_pcg_direction<T>(m, false, P->z, P->p, (T*)P->pT, P->sc, s));
+            BA_TRY(P, launch_pcg_direction<T>(m, false, P->z, P->p, (T*)P->pT, ri.ck, xf, P->sc, s));
             std::array<hipEvent_t, 4> ev{nullptr, nullptr, nullptr, nullptr};
             if (tm) {
                 BA_TRY(P, tm->next(&ev[0], &ev[1]));
@@ -689,7 +771,7 @@ static ba_status run_pcg(ba_problem* P, const ba_options& o, int32_t fixed, int3
                 BA_TRY(P, hipEventRecord(ev[0], s));
             }
             BA_TRY(P, launch_schur_product<T>(0, P->sp, P->pm, P->N, (const T*)P->hcp, (const T*)P->cinv, P->wpt,
-                                              (const T*)P->pT, m, P->bd, P->p, nullptr, P->q, nullptr, nullptr,
+                                              (const T*)P->pT, &ri, m, P->bd, P->p, nullptr, P->q, nullptr, nullptr,
                                               P->partials, P->sc, ev[2], ev[3], s));
             if (tm) {
                 BA_TRY(P, hipEventRecord(ev[1], s));
@@ -772,7 +854,7 @@ static ba_status lm_solve_t(ba_problem* P, const ba_options& o, ba_report* rep)
             break;
         }
         // dp = C~^-1 (w - E^T dc); trial state; F(x + dx); predicted decrease
-        BA_TRY(P, launch_pcg_direction<T>(m, true, P->x, P->p, (T*)P->pT, P->sc, s));  // pT = (T) dc
+        BA_TRY(P, launch_pcg_direction<T>(m, true, P->x, P->p, (T*)P->pT, nullptr, nullptr, P->sc, s));  // pT = (T) dc
         BA_TRY(P, launch_schur_tiles<T>(2, P->pm, nullptr, 0, P->pm.ld, (const T*)P->hcp, (const T*)P->cinv, P->wpt,
                                         (const T*)P->pT, nullptr, P->dp, s));
         BA_TRY(P, launch_trial_state(m, n, P->cams, P->x, P->pts, P->dp, P->cams_t, P->pts_t, s));
@@ -864,7 +946,7 @@ template <typename T>
 static ba_status grad_into(ba_problem* P, const double* cams, const double* pts, const CamK<T>* ck, hipStream_t s)
 {
     const JacSource<T> js{ck, P->opt.jacobian == BA_JACOBIAN_AUTODIFF ? cams : nullptr};
-    BA_TRY(P, launch_build_points<T>(P->pm, P->opt.huber_delta, true, pts, js, nullptr, nullptr, P->wpt, s));
+    BA_TRY(P, launch_build_points<T>(P->pm, P->opt.huber_delta, true, pts, js, nullptr, nullptr, P->wpt, nullptr, s));
     BA_TRY(P, launch_build_cameras<T>(P->cm, P->m, P->N, pts, js, P->opt.huber_delta, true, nullptr, P->vcam, 0,
                                       nullptr, s));
     return BA_OK;
@@ -960,9 +1042,11 @@ static ba_status schur_matvec_t(ba_problem* P, double lambda, int32_t damping, c
         std::memcpy(&xi[(size_t)9 * j], x + (size_t)9 * P->old_of_new[j], 9 * sizeof(double));
     BA_TRY(P, hipMemcpyAsync(P->x, xi.data(), xi.size() * sizeof(double), hipMemcpyHostToDevice, s));
     BA_TRY(P, launch_pcg_reset(P->sc, 0.0, 1, 0, s));
-    BA_TRY(P, launch_pcg_direction<T>(m, true, P->x, P->p, (T*)P->pT, P->sc, s));
+    const RecomputeInputs<T> ri = recompute_inputs<T>(P);
+    BA_TRY(P, launch_pcg_direction<T>(m, true, P->x, P->p, (T*)P->pT, ri.ck, P->sp.recompute ? (T*)P->xf : nullptr,
+                                      P->sc, s));
     BA_TRY(P, launch_schur_product<T>(0, P->sp, P->pm, P->N, (const T*)P->hcp, (const T*)P->cinv, P->wpt,
-                                      (const T*)P->pT, m, P->bd, P->p, nullptr, P->q, nullptr, nullptr, P->partials,
+                                      (const T*)P->pT, &ri, m, P->bd, P->p, nullptr, P->q, nullptr, nullptr, P->partials,
                                       P->sc, nullptr, nullptr, s));
     BA_TRY(P, hipMemcpyAsync(qi.data(), P->q, qi.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     BA_TRY(P, hipMemcpyAsync(P->h_scalars, P->flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));

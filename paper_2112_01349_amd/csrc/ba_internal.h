@@ -128,6 +128,24 @@ struct SchurPlan {
     double* hot_fold = nullptr;     // [kHotFold][K][9] FP64
     void* bcold = nullptr;          // [n][3] of T
     ColdStream cold;
+    // the recomputing product (mode 0 when set): point-aligned segments, short
+    // (<= 64 observations of whole points) and long (one longer point), as
+    // [begin, end) observation ranges, and their ranges per wavefront
+    bool recompute = false;
+    int32_t num_short = 0, num_long = 0;
+    int2* sseg = nullptr;           // [num_short]
+    int2* lseg = nullptr;           // [num_long]
+    int32_t* frange = nullptr;      // [num_wg * waves per workgroup + 1] short-segment ranges
+    int32_t* lrange = nullptr;      // [num_wg * waves per workgroup + 1] long-segment ranges
+};
+
+// What the recomputing product reads besides the streams of PointMajor.
+template <typename T>
+struct RecomputeInputs {
+    const T* wobs;       // [ld] IRLS weight per point-major observation
+    const double* pts;   // [n][3] point coordinates
+    const CamK<T>* ck;   // [m] camera constants
+    const T* xf;         // [m][12] camera vectors from launch_pcg_direction
 };
 
 // ---------------------------------------------------------------- launchers
@@ -144,11 +162,11 @@ struct JacSource {
     const double* cams;
 };
 
-// Point-major build: E_k into hcp (unless grad_only), C_i into hpp (unless
-// grad_only) and w_i into wpt.
+// Point-major build: E_k into hcp, C_i into hpp and each observation's IRLS
+// weight into wobs (all unless grad_only), and w_i into wpt.
 template <typename T>
 hipError_t launch_build_points(const PointMajor& pm, double delta, bool grad_only, const double* pts,
-                               JacSource<T> js, T* hcp, double* hpp, double* wpt, hipStream_t s);
+                               JacSource<T> js, T* hcp, double* hpp, double* wpt, T* wobs, hipStream_t s);
 // Camera-major build: B_j (unless grad_only) and v_j; the last Nc
 // observations of the camera-major stream (the cold cameras) also store E_k
 // into chcp[q * Nc + k - (N - Nc)].
@@ -175,14 +193,15 @@ hipError_t launch_schur_tiles(int mode, const PointMajor& pm, const int32_t* til
 // Full implicit Schur product.  mode 0: out = q = B~ x - E C~^-1 E^T x, then
 // p^T q, alpha and the matvec count into sc (skipped once sc->done);
 // mode 1: out = g = v - E C~^-1 w, r = g, x = 0 and ||g||^2 into sc.
-// xcam: x in T and pvec: x in FP64 (mode 0).  hot_begin/hot_end (nullable)
-// bracket the point-major pass.
+// xcam: x in T and pvec: x in FP64 (mode 0).  With sp.recompute and ri set,
+// mode 0 forms E from the Jacobian instead of reading hcp.  hot_begin/hot_end
+// (nullable) bracket the point-major pass.
 template <typename T>
 hipError_t launch_schur_product(int mode, const SchurPlan& sp, const PointMajor& pm, int64_t N, const T* hcp,
-                                const T* cinv, const double* wpt, const T* xcam, int32_t m, const double* bd,
-                                const double* pvec, const double* vcam, double* out, double* xvec, double* rvec,
-                                double* partials, PcgScalars* sc, hipEvent_t hot_begin, hipEvent_t hot_end,
-                                hipStream_t s);
+                                const T* cinv, const double* wpt, const T* xcam, const RecomputeInputs<T>* ri,
+                                int32_t m, const double* bd, const double* pvec, const double* vcam, double* out,
+                                double* xvec, double* rvec, double* partials, PcgScalars* sc, hipEvent_t hot_begin,
+                                hipEvent_t hot_end, hipStream_t s);
 template <typename T>
 size_t hot_lds_bytes(int32_t K);
 template <typename T>
@@ -199,11 +218,13 @@ hipError_t launch_pcg_reset(PcgScalars* sc, double rtol, int32_t max_iters, int3
 // z = M^-1 r; then rho, ||r||^2, the stopping test and beta (last block).
 hipError_t launch_pcg_step(int32_t m, bool first, const double* lfac, const double* p, const double* q,
                            double* x, double* r, double* z, double* partials, PcgScalars* sc, hipStream_t s);
-// p = z (first iteration) or z + beta p; pT = (T) p.  With force, runs even
-// after the loop stopped (used to hand x to the back-substitution).
+// p = z (first iteration) or z + beta p; pT = (T) p; with xf set also the
+// recomputing product's camera vectors [J_l p_w, p_t, p_f, p_k1, p_k2] (12
+// words per camera, J_l from ck).  With force, runs even after the loop
+// stopped (used to hand x to the back-substitution).
 template <typename T>
-hipError_t launch_pcg_direction(int32_t m, bool force, const double* z, double* p, T* pT, PcgScalars* sc,
-                                hipStream_t s);
+hipError_t launch_pcg_direction(int32_t m, bool force, const double* z, double* p, T* pT, const CamK<T>* ck, T* xf,
+                                PcgScalars* sc, hipStream_t s);
 hipError_t launch_trial_state(int32_t m, int32_t n, const double* cams, const double* dc, const double* pts,
                               const double* dp, double* cams_t, double* pts_t, hipStream_t s);
 hipError_t launch_cost(const PointMajor& pm, int64_t N, const double* pts, const CamK<double>* ck,

@@ -132,7 +132,7 @@ __global__ __launch_bounds__(kTile) void k_build_points(
     const int32_t* __restrict__ tile, const int32_t* __restrict__ cam, const int32_t* __restrict__ pt,
     const double* __restrict__ uvx, const double* __restrict__ uvy, const double* __restrict__ pts,
     JacSource<T> js, T delta, int64_t ld, T* __restrict__ hcp, double* __restrict__ hpp,
-    double* __restrict__ wpt)
+    double* __restrict__ wpt, T* __restrict__ wobs)
 {
     constexpr int R = GRAD_ONLY ? 3 : 9;  // terms kept: [C upper 6 |] w 3
     __shared__ double sh[R][kTile];
@@ -148,7 +148,10 @@ __global__ __launch_bounds__(kTile) void k_build_points(
             const int64_t k = s + tid;
             T e0, e1, wt, Jc[18], Jp[6];
             observation<T, AD>(k, cam, pt, uvx, uvy, pts, js, delta, e0, e1, wt, Jc, Jp, i);
-            if (!GRAD_ONLY) store_coupling_blocked<T>(k, Jc, Jp, wt, hcp);
+            if (!GRAD_ONLY) {
+                store_coupling_blocked<T>(k, Jc, Jp, wt, hcp);
+                wobs[k] = wt;
+            }
             double v[9];
             point_terms<T>(Jp, e0, e1, wt, v);
 #pragma unroll
@@ -180,7 +183,10 @@ __global__ __launch_bounds__(kTile) void k_build_points(
             T e0, e1, wt, Jc[18], Jp[6];
             int32_t ii;
             observation<T, AD>(k, cam, pt, uvx, uvy, pts, js, delta, e0, e1, wt, Jc, Jp, ii);
-            if (!GRAD_ONLY) store_coupling_blocked<T>(k, Jc, Jp, wt, hcp);
+            if (!GRAD_ONLY) {
+                store_coupling_blocked<T>(k, Jc, Jp, wt, hcp);
+                wobs[k] = wt;
+            }
             double v[9];
             point_terms<T>(Jp, e0, e1, wt, v);
 #pragma unroll
@@ -210,25 +216,25 @@ __global__ __launch_bounds__(kTile) void k_build_points(
 
 template <typename T, bool G, bool A>
 static void build_points_variant(const PointMajor& pm, const double* pts, JacSource<T> js, T delta, T* hcp,
-                                 double* hpp, double* wpt, hipStream_t s)
+                                 double* hpp, double* wpt, T* wobs, hipStream_t s)
 {
     hipLaunchKernelGGL((k_build_points<T, G, A>), dim3((unsigned)pm.num_tiles), dim3(kTile), 0, s, pm.tile, pm.cam,
-                       pm.pt, pm.uvx, pm.uvy, pts, js, delta, pm.ld, hcp, hpp, wpt);
+                       pm.pt, pm.uvx, pm.uvy, pts, js, delta, pm.ld, hcp, hpp, wpt, wobs);
 }
 
 template <typename T>
 hipError_t launch_build_points(const PointMajor& pm, double delta, bool grad_only, const double* pts,
-                               JacSource<T> js, T* hcp, double* hpp, double* wpt, hipStream_t s)
+                               JacSource<T> js, T* hcp, double* hpp, double* wpt, T* wobs, hipStream_t s)
 {
     if (pm.num_tiles <= 0) return hipGetLastError();
     const bool ad = js.cams != nullptr;
     const T d = (T)delta;
     if (grad_only) {
-        if (ad) build_points_variant<T, true, true>(pm, pts, js, d, nullptr, nullptr, wpt, s);
-        else build_points_variant<T, true, false>(pm, pts, js, d, nullptr, nullptr, wpt, s);
+        if (ad) build_points_variant<T, true, true>(pm, pts, js, d, nullptr, nullptr, wpt, nullptr, s);
+        else build_points_variant<T, true, false>(pm, pts, js, d, nullptr, nullptr, wpt, nullptr, s);
     } else {
-        if (ad) build_points_variant<T, false, true>(pm, pts, js, d, hcp, hpp, wpt, s);
-        else build_points_variant<T, false, false>(pm, pts, js, d, hcp, hpp, wpt, s);
+        if (ad) build_points_variant<T, false, true>(pm, pts, js, d, hcp, hpp, wpt, wobs, s);
+        else build_points_variant<T, false, false>(pm, pts, js, d, hcp, hpp, wpt, wobs, s);
     }
     return hipGetLastError();
 }
@@ -452,9 +458,9 @@ hipError_t launch_cost(const PointMajor& pm, int64_t N, const double* pts, const
 }
 
 template hipError_t launch_build_points<double>(const PointMajor&, double, bool, const double*, JacSource<double>,
-                                                double*, double*, double*, hipStream_t);
+                                                double*, double*, double*, double*, hipStream_t);
 template hipError_t launch_build_points<float>(const PointMajor&, double, bool, const double*, JacSource<float>,
-                                               float*, double*, double*, hipStream_t);
+                                               float*, double*, double*, float*, hipStream_t);
 template hipError_t launch_build_cameras<double>(const CameraMajor&, int32_t, int64_t, const double*,
                                                  JacSource<double>, double, bool, double*, double*, int64_t,
                                                  double*, hipStream_t);

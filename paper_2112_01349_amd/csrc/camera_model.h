@@ -25,15 +25,18 @@
 namespace ba {
 
 // Per-camera constants, computed once per state from the FP64 parameters.
+// The first 16 words are what an observation's geometry needs (one aligned
+// 64-byte piece in FP32, 128 bytes in FP64); the record is 32 words.
 template <typename T>
 struct CamK {
     T R[9];   // row-major rotation
     T t[3];
     T f, k1, k2;
-    T Jl[9];  // left Jacobian of SO(3) at w; identity in the first-order branch
     T small;  // 1 in the first-order branch (use X instead of R X for de/dw)
-    T pad[2];
+    T Jl[9];  // left Jacobian of SO(3) at w; identity in the first-order branch
+    T pad[7];
 };
+constexpr int kCamHead = 16;  // words of CamK read by observation_geometry
 
 template <typename T>
 __host__ __device__ inline void camera_constants(const double* c, CamK<T>& k)
@@ -74,7 +77,7 @@ __host__ __device__ inline void camera_constants(const double* c, CamK<T>& k)
     k.k1 = (T)c[7];
     k.k2 = (T)c[8];
     k.small = (T)small;
-    k.pad[0] = k.pad[1] = (T)0;
+    for (int q = 0; q < 7; ++q) k.pad[q] = (T)0;
 }
 
 // Residual only.
@@ -91,49 +94,81 @@ __device__ __forceinline__ void residual(const CamK<T>& k, T X0, T X1, T X2, T u
     e1 = fd * py - v;
 }
 
+// What the Jacobian of one observation is built from: de/dP (2x3), the
+// projection p, the intrinsic factors and the lever arm of de/dw.  In terms
+// of these, with J_l the camera's left Jacobian,
+//   J_c = [ D (-[a]x) J_l | D | d p | f |p|^2 p | f |p|^4 p ],  J_p = D R.
+template <typename T>
+struct ObsGeo {
+    T D[6];            // de/dP, row-major 2x3
+    T px, py;          // p
+    T fd;              // f d
+    T d, fr2, fr4;     // d, f |p|^2, f |p|^4
+    T a0, a1, a2;      // R X, or X in the first-order branch
+};
+
+// hd: the first kCamHead words of the camera's CamK (R, t, f, k1, k2, small).
+template <typename T>
+__device__ __forceinline__ void observation_geometry(const T* hd, T X0, T X1, T X2, ObsGeo<T>& o)
+{
+    const T RX0 = hd[0] * X0 + hd[1] * X1 + hd[2] * X2;
+    const T RX1 = hd[3] * X0 + hd[4] * X1 + hd[5] * X2;
+    const T RX2 = hd[6] * X0 + hd[7] * X1 + hd[8] * X2;
+    const T P0 = RX0 + hd[9], P1 = RX1 + hd[10], P2 = RX2 + hd[11];
+    const T f = hd[12], k1 = hd[13], k2 = hd[14];
+    const T iz = (T)1 / P2;
+    const T px = -(P0 * iz), py = -(P1 * iz);
+    const T r2 = px * px + py * py;
+    const T d = (T)1 + k1 * r2 + k2 * (r2 * r2);
+    const T fd = f * d;
+    const T g = (T)2 * f * (k1 + (T)2 * k2 * r2);
+    const T A00 = fd + g * px * px, A01 = g * px * py, A11 = fd + g * py * py;
+    o.D[0] = -iz * A00;
+    o.D[1] = -iz * A01;
+    o.D[2] = -iz * (A00 * px + A01 * py);
+    o.D[3] = -iz * A01;
+    o.D[4] = -iz * A11;
+    o.D[5] = -iz * (A01 * px + A11 * py);
+    o.px = px;
+    o.py = py;
+    o.fd = fd;
+    o.d = d;
+    o.fr2 = f * r2;
+    o.fr4 = o.fr2 * r2;
+    const bool sm = hd[15] != (T)0;
+    o.a0 = sm ? X0 : RX0;
+    o.a1 = sm ? X1 : RX1;
+    o.a2 = sm ? X2 : RX2;
+}
+
 // Residual and Jacobians: Jc row-major 2x9, Jp row-major 2x3.
 template <typename T>
 __device__ __forceinline__ void residual_jacobian(const CamK<T>& k, T X0, T X1, T X2, T u, T v,
                                                   T& e0, T& e1, T Jc[18], T Jp[6])
 {
-    const T RX0 = k.R[0] * X0 + k.R[1] * X1 + k.R[2] * X2;
-    const T RX1 = k.R[3] * X0 + k.R[4] * X1 + k.R[5] * X2;
-    const T RX2 = k.R[6] * X0 + k.R[7] * X1 + k.R[8] * X2;
-    const T P0 = RX0 + k.t[0], P1 = RX1 + k.t[1], P2 = RX2 + k.t[2];
-    const T iz = (T)1 / P2;
-    const T px = -(P0 * iz), py = -(P1 * iz);
-    const T r2 = px * px + py * py;
-    const T d = (T)1 + k.k1 * r2 + k.k2 * (r2 * r2);
-    const T fd = k.f * d;
-    e0 = fd * px - u;
-    e1 = fd * py - v;
-    const T g = (T)2 * k.f * (k.k1 + (T)2 * k.k2 * r2);
-    const T A00 = fd + g * px * px, A01 = g * px * py, A11 = fd + g * py * py;
-    // de/dP rows
-    const T D00 = -iz * A00, D01 = -iz * A01, D02 = -iz * (A00 * px + A01 * py);
-    const T D10 = -iz * A01, D11 = -iz * A11, D12 = -iz * (A01 * px + A11 * py);
-    // lever arm for de/dw: R X (or X in the first-order branch)
-    const bool sm = k.small != (T)0;
-    const T a0 = sm ? X0 : RX0, a1 = sm ? X1 : RX1, a2 = sm ? X2 : RX2;
+    ObsGeo<T> o;
+    observation_geometry<T>(k.R, X0, X1, X2, o);
+    e0 = o.fd * o.px - u;
+    e1 = o.fd * o.py - v;
+    const T* D = o.D;
     // y_r = a x D_r  (row r of de/dP (-[a]x)), then de/dw_r = y_r J_l
-    const T y00 = a1 * D02 - a2 * D01, y01 = a2 * D00 - a0 * D02, y02 = a0 * D01 - a1 * D00;
-    const T y10 = a1 * D12 - a2 * D11, y11 = a2 * D10 - a0 * D12, y12 = a0 * D11 - a1 * D10;
+    const T y00 = o.a1 * D[2] - o.a2 * D[1], y01 = o.a2 * D[0] - o.a0 * D[2], y02 = o.a0 * D[1] - o.a1 * D[0];
+    const T y10 = o.a1 * D[5] - o.a2 * D[4], y11 = o.a2 * D[3] - o.a0 * D[5], y12 = o.a0 * D[4] - o.a1 * D[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         Jc[c] = y00 * k.Jl[c] + y01 * k.Jl[3 + c] + y02 * k.Jl[6 + c];
         Jc[9 + c] = y10 * k.Jl[c] + y11 * k.Jl[3 + c] + y12 * k.Jl[6 + c];
-        Jp[c] = D00 * k.R[c] + D01 * k.R[3 + c] + D02 * k.R[6 + c];
-        Jp[3 + c] = D10 * k.R[c] + D11 * k.R[3 + c] + D12 * k.R[6 + c];
+        Jp[c] = D[0] * k.R[c] + D[1] * k.R[3 + c] + D[2] * k.R[6 + c];
+        Jp[3 + c] = D[3] * k.R[c] + D[4] * k.R[3 + c] + D[5] * k.R[6 + c];
     }
-    Jc[3] = D00; Jc[4] = D01; Jc[5] = D02;
-    Jc[12] = D10; Jc[13] = D11; Jc[14] = D12;
-    Jc[6] = d * px;
-    Jc[15] = d * py;
-    const T fr2 = k.f * r2;
-    Jc[7] = fr2 * px;
-    Jc[16] = fr2 * py;
-    Jc[8] = fr2 * r2 * px;
-    Jc[17] = fr2 * r2 * py;
+    Jc[3] = D[0]; Jc[4] = D[1]; Jc[5] = D[2];
+    Jc[12] = D[3]; Jc[13] = D[4]; Jc[14] = D[5];
+    Jc[6] = o.d * o.px;
+    Jc[15] = o.d * o.py;
+    Jc[7] = o.fr2 * o.px;
+    Jc[16] = o.fr2 * o.py;
+    Jc[8] = o.fr4 * o.px;
+    Jc[17] = o.fr4 * o.py;
 }
 
 // Huber on the 2-D residual norm, s = |e|^2: rho(s) = s for s <= delta^2,

@@ -273,6 +273,289 @@ __global__ __launch_bounds__(HotThreads<T>::value) void k_schur_hot(
     for (int q = threadIdx.x; q < K * 9; q += NT) out[q] = cl[q];
 }
 
+// ------------------------------------------------- product without stored E
+// The coupling block of an observation factors as E_k = w J_c^T J_p, and its
+// Jacobian costs ~100 arithmetic operations to form again from the camera
+// constants and the point, against 108 bytes (FP32) of HBM to read it.  In
+// terms of observation_geometry's D = de/dP, p and lever arm a:
+//   J_c x  = D (x_t + u x a) + p (d x_f + f|p|^2 x_k1 + f|p|^4 x_k2),
+//            u = J_l x_w (per camera, in xf);
+//   J_p^T z = R^T (D^T z);
+//   J_p b  = D (R b);
+//   J_c^T y = [J_l^T (a x g), g, d p.y, f|p|^2 p.y, f|p|^4 p.y],  g = D^T y.
+// So E_k^T x = J_p^T (w J_c x) and E_k b = J_c^T (w J_p b); the J_l^T of the
+// camera side is applied once per hot camera when the table is written out.
+
+template <typename T>
+__device__ __forceinline__ void load_head(const CamK<T>* __restrict__ ck, int32_t j, T hd[kCamHead])
+{
+    const T* src = reinterpret_cast<const T*>(ck + j);
+#pragma unroll
+    for (int q = 0; q < kCamHead; ++q) hd[q] = src[q];
+}
+
+// E_k^T x for one observation (3 values in the point's frame).
+template <typename T>
+__device__ __forceinline__ void free_et_x(const ObsGeo<T>& o, const T hd[kCamHead], const T xv[9], T w, T& e0,
+                                          T& e1, T& e2)
+{
+    const T v0 = xv[3] + (xv[1] * o.a2 - xv[2] * o.a1);
+    const T v1 = xv[4] + (xv[2] * o.a0 - xv[0] * o.a2);
+    const T v2 = xv[5] + (xv[0] * o.a1 - xv[1] * o.a0);
+    const T sc = o.d * xv[6] + o.fr2 * xv[7] + o.fr4 * xv[8];
+    const T z0 = w * (o.D[0] * v0 + o.D[1] * v1 + o.D[2] * v2 + o.px * sc);
+    const T z1 = w * (o.D[3] * v0 + o.D[4] * v1 + o.D[5] * v2 + o.py * sc);
+    const T h0 = o.D[0] * z0 + o.D[3] * z1, h1 = o.D[1] * z0 + o.D[4] * z1, h2 = o.D[2] * z0 + o.D[5] * z1;
+    e0 = hd[0] * h0 + hd[3] * h1 + hd[6] * h2;
+    e1 = hd[1] * h0 + hd[4] * h1 + hd[7] * h2;
+    e2 = hd[2] * h0 + hd[5] * h1 + hd[8] * h2;
+}
+
+// Camera side of E_k b for one observation, before J_l^T, added to the
+// workgroup's FP64 table of hot cameras.
+template <typename T>
+__device__ __forceinline__ void free_add_hot(double* __restrict__ cl, int32_t j, const ObsGeo<T>& o,
+                                             const T hd[kCamHead], T w, T b0, T b1, T b2)
+{
+    const T r0 = hd[0] * b0 + hd[1] * b1 + hd[2] * b2;
+    const T r1 = hd[3] * b0 + hd[4] * b1 + hd[5] * b2;
+    const T r2 = hd[6] * b0 + hd[7] * b1 + hd[8] * b2;
+    const T y0 = w * (o.D[0] * r0 + o.D[1] * r1 + o.D[2] * r2);
+    const T y1 = w * (o.D[3] * r0 + o.D[4] * r1 + o.D[5] * r2);
+    const T g0 = o.D[0] * y0 + o.D[3] * y1, g1 = o.D[1] * y0 + o.D[4] * y1, g2 = o.D[2] * y0 + o.D[5] * y1;
+    const T pyv = o.px * y0 + o.py * y1;
+    double* dst = cl + 9 * j;
+    atomicAdd(dst + 0, (double)(o.a1 * g2 - o.a2 * g1));
+    atomicAdd(dst + 1, (double)(o.a2 * g0 - o.a0 * g2));
+    atomicAdd(dst + 2, (double)(o.a0 * g1 - o.a1 * g0));
+    atomicAdd(dst + 3, (double)g0);
+    atomicAdd(dst + 4, (double)g1);
+    atomicAdd(dst + 5, (double)g2);
+    atomicAdd(dst + 6, (double)(o.d * pyv));
+    atomicAdd(dst + 7, (double)(o.fr2 * pyv));
+    atomicAdd(dst + 8, (double)(o.fr4 * pyv));
+}
+
+// Everything one observation needs: its camera's constants and vector, its
+// point and its weight.
+template <typename T>
+__device__ __forceinline__ void free_observation(int64_t k, const int32_t* __restrict__ cam,
+                                                 const int32_t* __restrict__ pt, const T* __restrict__ wobs,
+                                                 const double* __restrict__ pts, const CamK<T>* __restrict__ ck,
+                                                 const T* __restrict__ xf, int32_t& j, int32_t& i, T& w,
+                                                 T hd[kCamHead], T xv[9], ObsGeo<T>& o)
+{
+    j = cam[k];
+    i = pt[k];
+    w = wobs[k];
+    load_head<T>(ck, j, hd);
+    const T* x = xf + 12 * (int64_t)j;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) xv[a] = x[a];
+    const double* X = pts + 3 * (int64_t)i;
+    observation_geometry<T>(hd, (T)X[0], (T)X[1], (T)X[2], o);
+}
+
+// A short segment in flight: its streamed indices and weight (stage 1), then
+// what they point at (stage 2).
+template <typename T>
+struct FreeRow {
+    int32_t b, len;  // segment start and length (uniform)
+    int32_t j, i;
+    T w;
+};
+
+template <typename T>
+struct FreeData {
+    T hd[kCamHead];
+    T xv[9];
+    T X[3];
+    T c6[6];
+    bool hc;
+};
+
+template <typename T>
+__device__ __forceinline__ void free_stream(const int2* __restrict__ sseg, int32_t q, int lane,
+                                            const int32_t* __restrict__ cam, const int32_t* __restrict__ pt,
+                                            const T* __restrict__ wobs, FreeRow<T>& r)
+{
+    const int2 be = sseg[q];
+    r.b = __builtin_amdgcn_readfirstlane(be.x);
+    r.len = __builtin_amdgcn_readfirstlane(be.y) - r.b;
+    const int64_t k = r.b + (lane < r.len ? lane : 0);
+    r.j = cam[k];
+    r.i = pt[k];
+    r.w = wobs[k];
+}
+
+template <typename T>
+__device__ __forceinline__ void free_gather(const FreeRow<T>& r, const double* __restrict__ pts,
+                                            const CamK<T>* __restrict__ ck, const T* __restrict__ xf,
+                                            const T* __restrict__ cinv, const uint8_t* __restrict__ has_cold,
+                                            FreeData<T>& d)
+{
+    load_head<T>(ck, r.j, d.hd);
+    const T* x = xf + 12 * (int64_t)r.j;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) d.xv[a] = x[a];
+    const double* X = pts + 3 * (int64_t)r.i;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) d.X[a] = (T)X[a];
+    const T* c6 = cinv + 6 * (int64_t)r.i;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) d.c6[a] = c6[a];
+    d.hc = has_cold[r.i] != 0;
+}
+
+// One short segment: E^T x per lane, a_i per point run by a segmented scan,
+// b_i, then the camera side of the hot cameras.
+template <typename T>
+__device__ __forceinline__ void free_short(const FreeRow<T>& r, const FreeData<T>& d, int lane, uint64_t upto,
+                                           int32_t K, double* __restrict__ cl, T* __restrict__ bcold)
+{
+    const bool valid = lane < r.len;
+    ObsGeo<T> o;
+    observation_geometry<T>(d.hd, d.X[0], d.X[1], d.X[2], o);
+    T a0, a1, a2;
+    free_et_x<T>(o, d.hd, d.xv, r.w, a0, a1, a2);
+    if (!valid) a0 = a1 = a2 = (T)0;
+    const int32_t prev = __shfl_up(r.i, 1, 64);
+    const bool head = valid && (lane == 0 || r.i != prev);
+    const uint64_t hm = __ballot(head);
+    const int seg_s = 63 - __clzll((hm & upto) | 1ull);
+    const uint64_t above = hm & ~upto;
+    const int seg_e = above ? __ffsll((unsigned long long)above) - 2 : r.len - 1;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const T u0 = __shfl_up(a0, off, 64), u1 = __shfl_up(a1, off, 64), u2 = __shfl_up(a2, off, 64);
+        if (lane - off >= seg_s) {
+            a0 += u0;
+            a1 += u1;
+            a2 += u2;
+        }
+    }
+    a0 = __shfl(a0, seg_e, 64);
+    a1 = __shfl(a1, seg_e, 64);
+    a2 = __shfl(a2, seg_e, 64);
+    // formed on every lane, so the gathered C~^-1 is not sunk into a branch
+    // (a load there would be waited for on its own)
+    const T b0 = d.c6[0] * a0 + d.c6[1] * a1 + d.c6[2] * a2;
+    const T b1 = d.c6[1] * a0 + d.c6[3] * a1 + d.c6[4] * a2;
+    const T b2 = d.c6[2] * a0 + d.c6[4] * a1 + d.c6[5] * a2;
+    if (valid && lane == seg_e && d.hc) {
+        bcold[3 * (int64_t)r.i] = b0;
+        bcold[3 * (int64_t)r.i + 1] = b1;
+        bcold[3 * (int64_t)r.i + 2] = b2;
+    }
+    if (valid && r.j < K) free_add_hot<T>(cl, r.j, o, d.hd, r.w, b0, b1, b2);
+}
+
+// Pass 1 of the product (mode 0) without stored blocks.  Work units are
+// point-aligned segments: short ones (up to 64 observations of whole points,
+// one per lane) and long ones (one point of more than 64 observations, in
+// rows of 64, walked a second time for its camera side); each wavefront has
+// a range of each kind.  Short segments go two at a time: the loads of both
+// are issued before either is computed (loads complete in issue order, so
+// the first segment's wait leaves the second's loads in flight).  Hot
+// cameras accumulate in the workgroup's LDS
+// table as in k_schur_hot; b_i of points with cold observations is stored for
+// the cold pass, which reads its own stored blocks.
+template <typename T>
+__global__ __launch_bounds__(HotThreads<T>::value) void k_schur_free(
+    const int32_t* __restrict__ frange, const int2* __restrict__ sseg, const int32_t* __restrict__ lrange,
+    const int2* __restrict__ lseg, const int32_t* __restrict__ cam, const int32_t* __restrict__ pt,
+    const T* __restrict__ wobs, const double* __restrict__ pts, const CamK<T>* __restrict__ ck,
+    const T* __restrict__ xf, const T* __restrict__ cinv, int32_t K, double* __restrict__ hot_part,
+    T* __restrict__ bcold, const uint8_t* __restrict__ has_cold, const PcgScalars* __restrict__ sc)
+{
+    constexpr int NT = HotThreads<T>::value;
+    if (sc->done) return;  // uniform over the grid
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* cl = reinterpret_cast<double*>(smem);
+    for (int q = threadIdx.x; q < K * 9; q += NT) cl[q] = 0.0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int32_t gw = __builtin_amdgcn_readfirstlane(blockIdx.x * (NT / 64) + (threadIdx.x >> 6));
+    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+    {
+        const int32_t S0 = frange[gw], S1 = frange[gw + 1];
+        int32_t q = S0;
+        for (; q + 1 < S1; q += 2) {
+            FreeRow<T> ra, rb;
+            FreeData<T> da, db;
+            free_stream<T>(sseg, q, lane, cam, pt, wobs, ra);
+            free_stream<T>(sseg, q + 1, lane, cam, pt, wobs, rb);
+            __builtin_amdgcn_sched_barrier(0);
+            free_gather<T>(ra, pts, ck, xf, cinv, has_cold, da);
+            free_gather<T>(rb, pts, ck, xf, cinv, has_cold, db);
+            __builtin_amdgcn_sched_barrier(0);
+            free_short<T>(ra, da, lane, upto, K, cl, bcold);
+            free_short<T>(rb, db, lane, upto, K, cl, bcold);
+        }
+        if (q < S1) {
+            FreeRow<T> ra;
+            FreeData<T> da;
+            free_stream<T>(sseg, q, lane, cam, pt, wobs, ra);
+            free_gather<T>(ra, pts, ck, xf, cinv, has_cold, da);
+            free_short<T>(ra, da, lane, upto, K, cl, bcold);
+        }
+    }
+    const int32_t L0 = lrange[gw], L1 = lrange[gw + 1];
+    for (int32_t q = L0; q < L1; ++q) {
+        const int2 be = lseg[q];
+        const int32_t s0 = __builtin_amdgcn_readfirstlane(be.x), s1 = __builtin_amdgcn_readfirstlane(be.y);
+        const int32_t i = __builtin_amdgcn_readfirstlane(pt[s0]);
+        T s_0 = (T)0, s_1 = (T)0, s_2 = (T)0;
+        for (int32_t r = s0; r < s1; r += 64) {
+            const bool valid = r + lane < s1;
+            const int64_t k = valid ? r + lane : r;
+            int32_t j, ii;
+            T w, hd[kCamHead], xv[9];
+            ObsGeo<T> o;
+            free_observation<T>(k, cam, pt, wobs, pts, ck, xf, j, ii, w, hd, xv, o);
+            T e0, e1, e2;
+            free_et_x<T>(o, hd, xv, w, e0, e1, e2);
+            if (!valid) e0 = e1 = e2 = (T)0;
+            s_0 += wave_sum(e0);
+            s_1 += wave_sum(e1);
+            s_2 += wave_sum(e2);
+        }
+        const T* c6 = cinv + 6 * (int64_t)i;
+        const T b0 = c6[0] * s_0 + c6[1] * s_1 + c6[2] * s_2;
+        const T b1 = c6[1] * s_0 + c6[3] * s_1 + c6[4] * s_2;
+        const T b2 = c6[2] * s_0 + c6[4] * s_1 + c6[5] * s_2;
+        if (lane == 0 && has_cold[i]) {
+            bcold[3 * (int64_t)i] = b0;
+            bcold[3 * (int64_t)i + 1] = b1;
+            bcold[3 * (int64_t)i + 2] = b2;
+        }
+        if (K > 0)
+            for (int32_t r = s0; r < s1; r += 64) {
+                const bool valid = r + lane < s1;
+                const int64_t k = valid ? r + lane : r;
+                int32_t j, ii;
+                T w, hd[kCamHead], xv[9];
+                ObsGeo<T> o;
+                free_observation<T>(k, cam, pt, wobs, pts, ck, xf, j, ii, w, hd, xv, o);
+                if (valid && j < K) free_add_hot<T>(cl, j, o, hd, w, b0, b1, b2);
+            }
+    }
+    __syncthreads();
+    // out: the table with J_l^T applied to each camera's rotation part
+    double* out = hot_part + (int64_t)blockIdx.x * K * 9;
+    for (int q = threadIdx.x; q < K * 9; q += NT) {
+        const int32_t j = q / 9;
+        const int a = q - 9 * j;
+        double v = cl[q];
+        if (a < 3) {
+            const T* J = ck[j].Jl;
+            const double* g = cl + 9 * j;
+            v = (double)J[a] * g[0] + (double)J[3 + a] * g[1] + (double)J[6 + a] * g[2];
+        }
+        out[q] = v;
+    }
+}
+
 // Point-major pass of the reduced right-hand side: every observation adds
 // E_k C~_i^-1 w_i into its camera (hot cameras into the LDS table), and the
 // first lane of each point run in a tile stores b_i for the cold pass (runs
@@ -496,22 +779,28 @@ hipError_t prepare_schur_kernels(int32_t K)
     const int bytes = (int)hot_lds_bytes<T>(K);
     hipError_t e = hipFuncSetAttribute((const void*)k_schur_hot<T>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)k_schur_free<T>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void*)k_schur_rhs<T>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 template <typename T>
 hipError_t launch_schur_product(int mode, const SchurPlan& sp, const PointMajor& pm, int64_t N, const T* hcp,
-                                const T* cinv, const double* wpt, const T* xcam, int32_t m, const double* bd,
-                                const double* pvec, const double* vcam, double* out, double* xvec, double* rvec,
-                                double* partials, PcgScalars* sc, hipEvent_t hot_begin, hipEvent_t hot_end,
-                                hipStream_t s)
+                                const T* cinv, const double* wpt, const T* xcam, const RecomputeInputs<T>* ri,
+                                int32_t m, const double* bd, const double* pvec, const double* vcam, double* out,
+                                double* xvec, double* rvec, double* partials, PcgScalars* sc, hipEvent_t hot_begin,
+                                hipEvent_t hot_end, hipStream_t s)
 {
     hipError_t e;
     const size_t lds = hot_lds_bytes<T>(sp.K);
     if (hot_begin && (e = hipEventRecord(hot_begin, s)) != hipSuccess) return e;
     if (sp.num_wg > 0) {
         const dim3 g(sp.num_wg), b(HotThreads<T>::value);
-        if (mode == 0)
+        if (mode == 0 && sp.recompute && ri)
+            hipLaunchKernelGGL((k_schur_free<T>), g, b, lds, s, sp.frange, sp.sseg, sp.lrange,
+                               sp.lseg, pm.cam, pm.pt, ri->wobs, ri->pts, ri->ck, ri->xf, cinv, sp.K,
+                               (double*)sp.hot_part, (T*)sp.bcold, sp.has_cold, sc);
+        else if (mode == 0)
             hipLaunchKernelGGL((k_schur_hot<T>), g, b, lds, s, sp.wrange, N, pm.cam, pm.pt, hcp, cinv, xcam,
                                sp.K, (double*)sp.hot_part, (T*)sp.bcold, sp.has_cold, sc);
         else
@@ -550,11 +839,13 @@ template int32_t hot_max_cameras<double>(size_t);
 template hipError_t prepare_schur_kernels<float>(int32_t);
 template hipError_t prepare_schur_kernels<double>(int32_t);
 template hipError_t launch_schur_product<float>(int, const SchurPlan&, const PointMajor&, int64_t, const float*,
-                                                const float*, const double*, const float*, int32_t, const double*,
-                                                const double*, const double*, double*, double*, double*, double*,
-                                                PcgScalars*, hipEvent_t, hipEvent_t, hipStream_t);
+                                                const float*, const double*, const float*,
+                                                const RecomputeInputs<float>*, int32_t, const double*, const double*,
+                                                const double*, double*, double*, double*, double*, PcgScalars*,
+                                                hipEvent_t, hipEvent_t, hipStream_t);
 template hipError_t launch_schur_product<double>(int, const SchurPlan&, const PointMajor&, int64_t, const double*,
-                                                 const double*, const double*, const double*, int32_t, const double*,
+                                                 const double*, const double*, const double*,
+                                                 const RecomputeInputs<double>*, int32_t, const double*,
                                                  const double*, const double*, double*, double*, double*, double*,
                                                  PcgScalars*, hipEvent_t, hipEvent_t, hipStream_t);
 

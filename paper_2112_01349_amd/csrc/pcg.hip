@@ -201,29 +201,47 @@ hipError_t launch_pcg_step(int32_t m, bool first, const double* lfac, const doub
     return hipGetLastError();
 }
 
-// p = z (first iteration) or z + beta p; pT = (T) p
+// p = z (first iteration) or z + beta p; pT = (T) p.  With xf set, also the
+// camera vectors the recomputing Schur product reads: [J_l p_w, p_t, p_f,
+// p_k1, p_k2] in T (12 words per camera, the last three unused).  One thread
+// per camera.
 template <typename T>
-__global__ void k_pcg_direction(int64_t len, int force, const double* __restrict__ z, double* __restrict__ p,
-                                T* __restrict__ pT, const PcgScalars* __restrict__ sc)
+__global__ void k_pcg_direction(int32_t m, int force, const double* __restrict__ z, double* __restrict__ p,
+                                T* __restrict__ pT, const CamK<T>* __restrict__ ck, T* __restrict__ xf,
+                                const PcgScalars* __restrict__ sc)
 {
     if (!force && sc->done) return;
     const bool first = force || sc->iters == 0;
     const double beta = first ? 0.0 : sc->beta;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < len; t += (int64_t)gridDim.x * blockDim.x) {
-        const double v = first ? z[t] : z[t] + beta * p[t];
-        p[t] = v;
-        pT[t] = (T)v;
+    for (int32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < m; j += gridDim.x * blockDim.x) {
+        double v[9];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            const int64_t t = 9 * (int64_t)j + a;
+            v[a] = first ? z[t] : z[t] + beta * p[t];
+            p[t] = v[a];
+            pT[t] = (T)v[a];
+        }
+        if (xf) {
+            const T* J = ck[j].Jl;
+            T* o = xf + 12 * (int64_t)j;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                o[a] = (T)((double)J[3 * a] * v[0] + (double)J[3 * a + 1] * v[1] + (double)J[3 * a + 2] * v[2]);
+#pragma unroll
+            for (int a = 3; a < 9; ++a) o[a] = (T)v[a];
+        }
     }
 }
 
 template <typename T>
-hipError_t launch_pcg_direction(int32_t m, bool force, const double* z, double* p, T* pT, PcgScalars* sc,
-                                hipStream_t s)
+hipError_t launch_pcg_direction(int32_t m, bool force, const double* z, double* p, T* pT, const CamK<T>* ck, T* xf,
+                                PcgScalars* sc, hipStream_t s)
 {
-    const int64_t len = 9 * (int64_t)m;
-    int64_t b = (len + 255) / 256;
-    if (b > 1024) b = 1024;
-    hipLaunchKernelGGL((k_pcg_direction<T>), dim3((unsigned)b), dim3(256), 0, s, len, force ? 1 : 0, z, p, pT, sc);
+    int32_t b = (m + 255) / 256;
+    if (b < 1) b = 1;
+    hipLaunchKernelGGL((k_pcg_direction<T>), dim3((unsigned)b), dim3(256), 0, s, m, force ? 1 : 0, z, p, pT, ck, xf,
+                       sc);
     return hipGetLastError();
 }
 
@@ -372,10 +390,10 @@ hipError_t launch_store_cost(const double* sum, double* out, hipStream_t s)
     return hipGetLastError();
 }
 
-template hipError_t launch_pcg_direction<double>(int32_t, bool, const double*, double*, double*, PcgScalars*,
-                                                 hipStream_t);
-template hipError_t launch_pcg_direction<float>(int32_t, bool, const double*, double*, float*, PcgScalars*,
-                                                hipStream_t);
+template hipError_t launch_pcg_direction<double>(int32_t, bool, const double*, double*, double*,
+                                                 const CamK<double>*, double*, PcgScalars*, hipStream_t);
+template hipError_t launch_pcg_direction<float>(int32_t, bool, const double*, double*, float*, const CamK<float>*,
+                                                float*, PcgScalars*, hipStream_t);
 template hipError_t launch_pred<double>(int32_t, int32_t, const double*, const double*, const double*, const double*,
                                         const double*, const double*, double, int32_t, double*, int32_t*, hipStream_t);
 template hipError_t launch_pred<float>(int32_t, int32_t, const double*, const double*, const double*, const double*,

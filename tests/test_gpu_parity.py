@@ -45,8 +45,10 @@ def test_cost_and_gradient(tiny, delta):
     np.testing.assert_array_equal(p2, pts)
 
 
+@pytest.mark.parametrize("stored", [0, 1])
 @pytest.mark.parametrize("damping", [0, 1])
-def test_schur_matvec(tiny, damping):
+def test_schur_matvec(tiny, damping, stored, monkeypatch):
+    monkeypatch.setenv("BA_SCHUR_STORED", str(stored))
     prob, (cams, pts, oc, op, uv) = make(tiny)
     lam = 1e-3
     A = orc.assemble(cams, pts, oc, op, uv)
@@ -176,12 +178,16 @@ def test_lm_monotone_and_state_consistent(tiny):
         <= 1e-12 * gpu["final_cost"]
 
 
+@pytest.mark.parametrize("stored", [0, 1])
 @pytest.mark.parametrize("hot", [0, 3, 7])
-def test_hot_cold_split_matches_oracle(hot, monkeypatch):
+def test_hot_cold_split_matches_oracle(hot, stored, monkeypatch):
     """The Schur product splits cameras into an LDS-held hot set and a
     camera-major cold stream; every split gives the oracle's product and LM
-    trace (with a point longer than one tile in the problem)."""
+    trace (with a point longer than one tile in the problem), both for the
+    product that recomputes E from the Jacobian and for the one that reads
+    the stored blocks."""
     monkeypatch.setenv("BA_HOT_CAMERAS", str(hot))
+    monkeypatch.setenv("BA_SCHUR_STORED", str(stored))
     arrays = with_edge_cases(small_zipf(seed=13, m=14, n=300, N=1500))
     cams, pts, oc, op, uv, _ = arrays
     for precision in (FP64, FP32_MIXED):
