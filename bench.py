@@ -26,6 +26,10 @@ if ROOT not in sys.path:
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+# wavefront VALU instructions the chip can issue per second: 256 CUs x 4 SIMDs,
+# one wave64 instruction per SIMD every 4 cycles at 2.4 GHz
+VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4
 WORKLOADS = {  # name -> synth config and solver settings
     "large": dict(config="large", huber_delta=1.0, max_pcg_iters=100, pcg_rtol=1e-6),
     "medium": dict(config="medium", huber_delta=0.0, max_pcg_iters=100, pcg_rtol=1e-6),
@@ -57,26 +61,67 @@ def hot_pass_algorithmic_bytes(n, N, w):
     return N * (27 * w + 4) + n * (6 * w + 4)
 
 
-def counted_traffic(kernel="k_schur_hot<float>"):
-    """HBM bytes per launch of `kernel` from the committed counter summary
-    (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's reading),
-    or None when the kernel source has changed since the counters were taken."""
+def free_pass_algorithmic_flops(n, N):
+    """Arithmetic of the point-major pass when E is formed from the Jacobian
+    (an FMA counts 2): per observation the geometry (de/dP, projection, lever
+    arm: 57), E_k^T x in factored form (57), the camera side E_k b (51), the
+    point sum (3) and the camera sum (9); per point b_i = C~_i^-1 a_i (15)."""
+    return N * (57 + 57 + 51 + 3 + 9) + n * 15
+
+
+def schur_product_kind():
+    """The point-major kernel the library runs: it forms E from the Jacobian
+    unless BA_SCHUR_STORED=1 selects the stored blocks (read at creation)."""
+    return "stored" if os.environ.get("BA_SCHUR_STORED", "0") not in ("", "0") else "recompute"
+
+
+COUNTER_FILES = {"k_schur_hot<float>": "schur_hot_stored_29M_hbm_counters.md",
+                 "k_schur_free<float>": "schur_free_29M_counters.md"}
+
+
+def counted(kernel):
+    """Per-launch figures of `kernel` from its committed rocprofv3 counter
+    summary (HBM bytes from FETCH_SIZE and WRITE_SIZE scaled by a plain copy's
+    reading; VALU instructions where taken), or {} when the kernel sources have
+    changed since the counters were taken."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "schur_hot_29M_hbm_counters.md")
+    path = os.path.join(ROOT, "profiles", COUNTER_FILES[kernel])
     if not os.path.exists(path):
-        return None
+        return {}
     fields = {}
     for line in open(path):
         key, sep, val = line.strip().partition(": ")
         if sep:
             fields[key] = val
     h = hashlib.sha256()
-    for f in ("matvec.hip", "ba_internal.h"):
+    for f in ("matvec.hip", "ba_internal.h", "camera_model.h"):
         h.update(open(os.path.join(ROOT, "paper_2112_01349_amd", "csrc", f), "rb").read())
     if fields.get("kernel") != kernel or fields.get("source_sha256") != h.hexdigest()[:16]:
-        return None
-    return float(fields["traffic_bytes_per_launch"])
+        return {}
+    return {k: float(v) for k, v in fields.items() if k.endswith("_per_launch")}
+
+
+def roofline(s32, m, n, N, counters_apply):
+    """Roofline entry of the dominant kernel (the FP32 point-major pass)."""
+    ms = s32["hot_kernel_ms"]
+    stored_bytes = hot_pass_algorithmic_bytes(n, N, 4)
+    if schur_product_kind() == "stored":
+        c = counted("k_schur_hot<float>") if counters_apply else {}
+        return {"bound": "hbm", "achieved": s32["hot_kernel_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": s32["hot_kernel_frac"], "traffic": c.get("traffic_bytes_per_launch"),
+                "kernel": "k_schur_hot<float> (point-major pass of the implicit Schur matvec, stored E)",
+                "bytes_per_launch": stored_bytes, "avg_ms": ms}
+    c = counted("k_schur_free<float>") if counters_apply else {}
+    flops = free_pass_algorithmic_flops(n, N)
+    tflops = flops / (ms * 1e-3) / 1e12
+    insts = c.get("valu_insts_per_launch")
+    return {"bound": "alu", "achieved": tflops, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": tflops / FP32_VECTOR_PEAK_TFLOPS, "traffic": c.get("traffic_bytes_per_launch"),
+            "kernel": "k_schur_free<float> (point-major pass of the implicit Schur matvec, E formed from the Jacobian)",
+            "flops_per_launch": flops, "avg_ms": ms,
+            "valu_issue_frac": (insts / VALU_ISSUE_PER_S) / (ms * 1e-3) if insts else None,
+            "stored_e_hbm_floor_ms": stored_bytes / (HBM_PEAK_GBS * 1e9) * 1e3}
 
 
 def run_precision(prob_data, precision, wl, steps, warmup, jacobian=0):
@@ -263,11 +308,7 @@ def main():
                                f"{wl['max_pcg_iters']} rtol {wl['pcg_rtol']}",
                    "cameras": m, "points": n, "observations": N},
         "pcg_iter_per_s": s32["pcg_iter_per_s"],
-        "roofline": {"bound": "hbm", "achieved": s32["hot_kernel_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": s32["hot_kernel_frac"],
-                     "traffic": counted_traffic() if args.workload == "large" else None,
-                     "kernel": "k_schur_hot<float> (point-major pass of the implicit Schur matvec)",
-                     "bytes_per_launch": s32["hot_kernel_bytes"], "avg_ms": s32["hot_kernel_ms"]},
+        "roofline": roofline(s32, m, n, N, args.workload == "large"),
         "fp32_mixed": s32,
     }
     if "fp64" in res:

@@ -527,7 +527,8 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     P->cm.cam_seg = A.get<int32_t>((int64_t)m + 1);
     P->cm.seg_part = A.get<double>((int64_t)P->cm.num_segs * kCamSlotWords);
     P->cm.arrive = A.get<uint32_t>(m);
-    P->hcp = A.get<char>(27 * P->pm.ld * (int64_t)tsz);
+    // point-major E is stored only for the stored-block product
+    P->hcp = sp.recompute ? nullptr : A.get<char>(27 * P->pm.ld * (int64_t)tsz);
     P->hpp = A.get<char>(6 * (int64_t)n * (int64_t)sizeof(double));
     P->cinv = A.get<char>(6 * (int64_t)n * (int64_t)tsz);
     P->wpt = A.get<double>(3 * (int64_t)n);
@@ -583,7 +584,7 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     h_pm_pt.resize((size_t)P->pm.ld, -1);
     if (e == hipSuccess) e = up(P->pm.cam, h_pm_cam.data(), sizeof(int32_t) * (size_t)P->pm.ld);
     if (e == hipSuccess) e = up(P->pm.pt, h_pm_pt.data(), sizeof(int32_t) * (size_t)P->pm.ld);
-    if (e == hipSuccess) e = hipMemset(P->hcp, 0, 27 * (size_t)P->pm.ld * tsz);
+    if (e == hipSuccess && P->hcp) e = hipMemset(P->hcp, 0, 27 * (size_t)P->pm.ld * tsz);
     if (e == hipSuccess) e = up(P->pm.uvx, h_uvx.data(), sizeof(double) * N);
     if (e == hipSuccess) e = up(P->pm.uvy, h_uvy.data(), sizeof(double) * N);
     if (e == hipSuccess) e = up(P->pm.tile, tiles.data(), sizeof(int32_t) * tiles.size());
@@ -751,11 +752,11 @@ static ba_status run_pcg(ba_problem* P, const ba_options& o, int32_t fixed, int3
     const int32_t cap = fixed > 0 ? fixed : o.max_pcg_iters;
     BA_TRY(P, launch_pcg_reset(P->sc, o.pcg_rtol, o.max_pcg_iters, fixed, s));
     // b = v - E C^-1 w; x = 0; r = b; ||b||^2; then z = M^-1 r and the first test
-    BA_TRY(P, launch_schur_product<T>(1, P->sp, P->pm, P->N, (const T*)P->hcp, (const T*)P->cinv, P->wpt, nullptr,
-                                      nullptr, m, P->bd, nullptr, P->vcam, P->g, P->x, P->r, P->partials, P->sc,
-                                      nullptr, nullptr, s));
     const RecomputeInputs<T> ri = recompute_inputs<T>(P);
     T* xf = P->sp.recompute ? (T*)P->xf : nullptr;
+    BA_TRY(P, launch_schur_product<T>(1, P->sp, P->pm, P->N, (const T*)P->hcp, (const T*)P->cinv, P->wpt, nullptr,
+                                      &ri, m, P->bd, nullptr, P->vcam, P->g, P->x, P->r, P->partials, P->sc,
+                                      nullptr, nullptr, s));
     BA_TRY(P, launch_pcg_step(m, true, P->lfac, P->p, P->q, P->x, P->r, P->z, P->partials, P->sc, s));
     std::vector<std::array<hipEvent_t, 4>> marks;
     const int32_t batch = fixed > 0 ? std::max(1, cap) : 8;
@@ -854,9 +855,15 @@ static ba_status lm_solve_t(ba_problem* P, const ba_options& o, ba_report* rep)
             break;
         }
         // dp = C~^-1 (w - E^T dc); trial state; F(x + dx); predicted decrease
-        BA_TRY(P, launch_pcg_direction<T>(m, true, P->x, P->p, (T*)P->pT, nullptr, nullptr, P->sc, s));  // pT = (T) dc
-        BA_TRY(P, launch_schur_tiles<T>(2, P->pm, nullptr, 0, P->pm.ld, (const T*)P->hcp, (const T*)P->cinv, P->wpt,
-                                        (const T*)P->pT, nullptr, P->dp, s));
+        if (P->sp.recompute) {
+            const RecomputeInputs<T> ri = recompute_inputs<T>(P);
+            BA_TRY(P, launch_pcg_direction<T>(m, true, P->x, P->p, (T*)P->pT, ri.ck, (T*)P->xf, P->sc, s));
+            BA_TRY(P, launch_backsub_free<T>(P->sp, P->pm, ri, (const T*)P->cinv, P->wpt, P->dp, s));
+        } else {
+            BA_TRY(P, launch_pcg_direction<T>(m, true, P->x, P->p, (T*)P->pT, nullptr, nullptr, P->sc, s));
+            BA_TRY(P, launch_schur_tiles<T>(2, P->pm, nullptr, 0, P->pm.ld, (const T*)P->hcp, (const T*)P->cinv,
+                                            P->wpt, (const T*)P->pT, nullptr, P->dp, s));
+        }
         BA_TRY(P, launch_trial_state(m, n, P->cams, P->x, P->pts, P->dp, P->cams_t, P->pts_t, s));
         BA_TRY(P, launch_camera_constants_f64(m, P->cams_t, P->ck64_t, s));
         if ((st = cost_into_sums<double>(P, P->pts_t, P->ck64_t, s)) != BA_OK) return st;

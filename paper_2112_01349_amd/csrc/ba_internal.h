@@ -202,6 +202,11 @@ hipError_t launch_schur_product(int mode, const SchurPlan& sp, const PointMajor&
                                 int32_t m, const double* bd, const double* pvec, const double* vcam, double* out,
                                 double* xvec, double* rvec, double* partials, PcgScalars* sc, hipEvent_t hot_begin,
                                 hipEvent_t hot_end, hipStream_t s);
+// Back-substitution without stored blocks (sp.recompute): dp_i =
+// C~_i^-1 (w_i - sum_k E_k^T dc_j), with dc in ri.xf (launch_pcg_direction).
+template <typename T>
+hipError_t launch_backsub_free(const SchurPlan& sp, const PointMajor& pm, const RecomputeInputs<T>& ri, const T* cinv,
+                               const double* wpt, double* dp, hipStream_t s);
 template <typename T>
 size_t hot_lds_bytes(int32_t K);
 template <typename T>

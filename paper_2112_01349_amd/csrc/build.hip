@@ -123,7 +123,8 @@ __device__ __forceinline__ double wave_sum(double v)
 
 // Point-major build over point-aligned tiles of <= kTile observations (a
 // longer point is a tile alone).  One thread per observation computes its
-// residual and Jacobian and stores E_k = w J_c^T J_p (27 coalesced streams);
+// residual and Jacobian, stores its IRLS weight and, when hcp is given,
+// E_k = w J_c^T J_p (27 coalesced streams);
 // its terms of C_i and w_i go to LDS (FP64), and the first thread of each
 // point sums the point's terms in stream order and stores C_i (upper 6) and
 // w_i in FP64.  GRAD_ONLY forms w_i only.
@@ -149,7 +150,7 @@ __global__ __launch_bounds__(kTile) void k_build_points(
             T e0, e1, wt, Jc[18], Jp[6];
             observation<T, AD>(k, cam, pt, uvx, uvy, pts, js, delta, e0, e1, wt, Jc, Jp, i);
             if (!GRAD_ONLY) {
-                store_coupling_blocked<T>(k, Jc, Jp, wt, hcp);
+                if (hcp) store_coupling_blocked<T>(k, Jc, Jp, wt, hcp);
                 wobs[k] = wt;
             }
             double v[9];
@@ -184,7 +185,7 @@ __global__ __launch_bounds__(kTile) void k_build_points(
             int32_t ii;
             observation<T, AD>(k, cam, pt, uvx, uvy, pts, js, delta, e0, e1, wt, Jc, Jp, ii);
             if (!GRAD_ONLY) {
-                store_coupling_blocked<T>(k, Jc, Jp, wt, hcp);
+                if (hcp) store_coupling_blocked<T>(k, Jc, Jp, wt, hcp);
                 wobs[k] = wt;
             }
             double v[9];
