@@ -403,16 +403,22 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
         sp.K = std::max(0, std::min(m, kmax));
         const char* stored = std::getenv("BA_SCHUR_STORED");
         sp.recompute = !(stored && std::atoi(stored) != 0);
-        if (sp.K > 0 && !env && !sp.recompute) {
-            // A point that reaches two tiles past the one it starts in is walked
-            // again for the hot side (its tiles once more, plus the tile the pass
-            // resumes at); with no hot camera that walk is skipped and the cold
-            // stream takes every observation.  Keep the hot set only when it
-            // reads fewer coupling blocks per product: N + rewalk + cold < 2N.
+        if (sp.K > 0 && !env) {
+            // Keep the hot set only when it costs fewer observation visits per
+            // product than none: N + rewalk + cold < 2N.  With a hot set, a long
+            // point is walked again for its camera side: the stored-block pass
+            // re-reads every tile it touches (plus the tile it resumes at); the
+            // recomputing pass walks a point of more than 64 observations twice.
+            // With none, that walk is skipped and the cold pass takes every
+            // observation.
             int64_t rewalk = 0, cold = 0;
             for (int32_t i = 0; i < n; ++i) {
                 const int64_t a = poff[i], b = poff[(size_t)i + 1];
-                if (b - a > 0 && ((b - 1) >> 6) >= (a >> 6) + 2) rewalk += (((b - 1) >> 6) - (a >> 6) + 2) * 64;
+                if (sp.recompute) {
+                    if (b - a > 64) rewalk += b - a;
+                } else if (b - a > 0 && ((b - 1) >> 6) >= (a >> 6) + 2) {
+                    rewalk += (((b - 1) >> 6) - (a >> 6) + 2) * 64;
+                }
             }
             for (int32_t j = sp.K; j < m; ++j) cold += coff[(size_t)j + 1] - coff[j];
             if (rewalk + cold > N) sp.K = 0;
@@ -552,7 +558,8 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     sp.bcold = A.get<char>(3 * (int64_t)n * (int64_t)tsz);
     sp.cold.cam = A.get<int32_t>(sp.cold.N);
     sp.cold.pt = A.get<int32_t>(sp.cold.N);
-    sp.cold.hcp = A.get<char>(27 * sp.cold.N * (int64_t)tsz);
+    sp.cold.hcp = sp.recompute ? nullptr : A.get<char>(27 * sp.cold.N * (int64_t)tsz);
+    sp.cold.w = sp.recompute ? A.get<char>(sp.cold.N * (int64_t)tsz) : nullptr;
     sp.cold.chunk_slot = A.get<int32_t>((int64_t)sp.cold.num_chunks + 1);
     sp.cold.cam_slot = A.get<int32_t>((int64_t)m + 1);
     sp.cold.slots = A.get<double>((int64_t)sp.cold.num_slots * 9);
@@ -713,7 +720,7 @@ static ba_status build_system(ba_problem* P)
     BA_TRY(P, launch_build_points<T>(P->pm, P->opt.huber_delta, false, P->pts, js, (T*)P->hcp, (double*)P->hpp,
                                      P->wpt, (T*)P->wobs, s));
     BA_TRY(P, launch_build_cameras<T>(P->cm, P->m, P->N, P->pts, js, P->opt.huber_delta, false, P->hcc, P->vcam,
-                                      P->sp.cold.N, (T*)P->sp.cold.hcp, s));
+                                      P->sp.cold.N, (T*)P->sp.cold.hcp, (T*)P->sp.cold.w, s));
     return BA_OK;
 }
 
@@ -955,7 +962,7 @@ static ba_status grad_into(ba_problem* P, const double* cams, const double* pts,
     const JacSource<T> js{ck, P->opt.jacobian == BA_JACOBIAN_AUTODIFF ? cams : nullptr};
     BA_TRY(P, launch_build_points<T>(P->pm, P->opt.huber_delta, true, pts, js, nullptr, nullptr, P->wpt, nullptr, s));
     BA_TRY(P, launch_build_cameras<T>(P->cm, P->m, P->N, pts, js, P->opt.huber_delta, true, nullptr, P->vcam, 0,
-                                      nullptr, s));
+                                      nullptr, nullptr, s));
     return BA_OK;
 }
 

@@ -109,7 +109,8 @@ struct ColdStream {
     int64_t N = 0;
     int32_t* cam = nullptr;         // [N]
     int32_t* pt = nullptr;          // [N]
-    void* hcp = nullptr;            // [27][N] of T
+    void* hcp = nullptr;            // [27][N] of T (stored-block product)
+    void* w = nullptr;              // [N] of T: IRLS weights (recomputing product)
     int32_t* chunk_slot = nullptr;  // [num_chunks + 1]
     int32_t* cam_slot = nullptr;    // [m + 1]
     int32_t num_chunks = 0;
@@ -167,13 +168,14 @@ struct JacSource {
 template <typename T>
 hipError_t launch_build_points(const PointMajor& pm, double delta, bool grad_only, const double* pts,
                                JacSource<T> js, T* hcp, double* hpp, double* wpt, T* wobs, hipStream_t s);
-// Camera-major build: B_j (unless grad_only) and v_j; the last Nc
-// observations of the camera-major stream (the cold cameras) also store E_k
-// into chcp[q * Nc + k - (N - Nc)].
+// Camera-major build: B_j (unless grad_only) and v_j; for the last Nc
+// observations of the camera-major stream (the cold cameras) also, when
+// given, E_k into chcp[q * Nc + k - (N - Nc)] and the weight into
+// cw[k - (N - Nc)].
 template <typename T>
 hipError_t launch_build_cameras(const CameraMajor& cm, int32_t m, int64_t N, const double* pts,
                                 JacSource<T> js, double delta, bool grad_only, double* hcc,
-                                double* vcam, int64_t Nc, T* chcp, hipStream_t s);
+                                double* vcam, int64_t Nc, T* chcp, T* cw, hipStream_t s);
 
 hipError_t launch_damp_cameras(int32_t m, const double* hcc, double lambda, int32_t damping,
                                double* bd, double* lfac, double* dcam, int32_t* flag, hipStream_t s);

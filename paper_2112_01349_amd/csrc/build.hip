@@ -259,7 +259,7 @@ __global__ __launch_bounds__(256) void k_build_cameras(
     int64_t N, int32_t num_chunks, const int32_t* __restrict__ cam, const int32_t* __restrict__ pt,
     const double* __restrict__ uvx, const double* __restrict__ uvy, const double* __restrict__ pts,
     JacSource<T> js, T delta, const int32_t* __restrict__ chunk_slot, double* __restrict__ slots,
-    int64_t Nc, T* __restrict__ chcp)
+    int64_t Nc, T* __restrict__ chcp, T* __restrict__ cw)
 {
     constexpr int W = GRAD_ONLY ? 9 : kCamSlotWords;
     const int64_t cold0 = N - Nc;  // the cold cameras' observations are the stream's tail
@@ -283,7 +283,10 @@ __global__ __launch_bounds__(256) void k_build_cameras(
             int32_t i;
             j = cam[k];
             observation<T, AD>(k, cam, pt, uvx, uvy, pts, js, delta, e0, e1, wt, Jc, Jp, i);
-            if (!GRAD_ONLY && k >= cold0) store_coupling<T>(k - cold0, Nc, Jc, Jp, wt, chcp);
+            if (!GRAD_ONLY && k >= cold0) {
+                if (chcp) store_coupling<T>(k - cold0, Nc, Jc, Jp, wt, chcp);
+                if (cw) cw[k - cold0] = wt;
+            }
         }
         while (true) {
             if (valid && j == cur) {
@@ -371,26 +374,26 @@ __global__ __launch_bounds__(256) void k_reduce_slots(int32_t num_segs, const in
 
 template <typename T, bool G, bool A>
 static void build_cameras_variant(const CameraMajor& cm, int64_t N, const double* pts, JacSource<T> js, T delta,
-                                  int64_t Nc, T* chcp, hipStream_t s)
+                                  int64_t Nc, T* chcp, T* cw, hipStream_t s)
 {
     hipLaunchKernelGGL((k_build_cameras<T, G, A>), dim3((cm.num_chunks + 3) / 4), dim3(256), 0, s, N, cm.num_chunks,
-                       cm.cam, cm.pt, cm.uvx, cm.uvy, pts, js, delta, cm.chunk_slot, cm.slots, Nc, chcp);
+                       cm.cam, cm.pt, cm.uvx, cm.uvy, pts, js, delta, cm.chunk_slot, cm.slots, Nc, chcp, cw);
 }
 
 template <typename T>
 hipError_t launch_build_cameras(const CameraMajor& cm, int32_t m, int64_t N, const double* pts, JacSource<T> js,
                                 double delta, bool grad_only, double* hcc, double* vcam, int64_t Nc, T* chcp,
-                                hipStream_t s)
+                                T* cw, hipStream_t s)
 {
     if (cm.num_chunks > 0) {
         const bool ad = js.cams != nullptr;
         const T d = (T)delta;
         if (grad_only) {
-            if (ad) build_cameras_variant<T, true, true>(cm, N, pts, js, d, 0, nullptr, s);
-            else build_cameras_variant<T, true, false>(cm, N, pts, js, d, 0, nullptr, s);
+            if (ad) build_cameras_variant<T, true, true>(cm, N, pts, js, d, 0, nullptr, nullptr, s);
+            else build_cameras_variant<T, true, false>(cm, N, pts, js, d, 0, nullptr, nullptr, s);
         } else {
-            if (ad) build_cameras_variant<T, false, true>(cm, N, pts, js, d, Nc, chcp, s);
-            else build_cameras_variant<T, false, false>(cm, N, pts, js, d, Nc, chcp, s);
+            if (ad) build_cameras_variant<T, false, true>(cm, N, pts, js, d, Nc, chcp, cw, s);
+            else build_cameras_variant<T, false, false>(cm, N, pts, js, d, Nc, chcp, cw, s);
         }
     }
     if (cm.num_segs > 0) {
@@ -464,10 +467,10 @@ template hipError_t launch_build_points<float>(const PointMajor&, double, bool, 
                                                float*, double*, double*, float*, hipStream_t);
 template hipError_t launch_build_cameras<double>(const CameraMajor&, int32_t, int64_t, const double*,
                                                  JacSource<double>, double, bool, double*, double*, int64_t,
-                                                 double*, hipStream_t);
+                                                 double*, double*, hipStream_t);
 template hipError_t launch_build_cameras<float>(const CameraMajor&, int32_t, int64_t, const double*,
                                                 JacSource<float>, double, bool, double*, double*, int64_t, float*,
-                                                hipStream_t);
+                                                float*, hipStream_t);
 template hipError_t launch_cost_t<float>(const PointMajor&, int64_t, const double*, const CamK<float>*, double,
                                          double*, int32_t*, hipStream_t);
 

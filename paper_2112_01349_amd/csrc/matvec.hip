@@ -311,11 +311,10 @@ __device__ __forceinline__ void free_et_x(const ObsGeo<T>& o, const T hd[kCamHea
     e2 = hd[2] * h0 + hd[5] * h1 + hd[8] * h2;
 }
 
-// Camera side of E_k b for one observation, before J_l^T, added to the
-// workgroup's FP64 table of hot cameras.
+// Camera side of E_k b for one observation, before J_l^T.
 template <typename T>
-__device__ __forceinline__ void free_add_hot(double* __restrict__ cl, int32_t j, const ObsGeo<T>& o,
-                                             const T hd[kCamHead], T w, T b0, T b1, T b2)
+__device__ __forceinline__ void free_camera_side(const ObsGeo<T>& o, const T hd[kCamHead], T w, T b0, T b1, T b2,
+                                                 T c[9])
 {
     const T r0 = hd[0] * b0 + hd[1] * b1 + hd[2] * b2;
     const T r1 = hd[3] * b0 + hd[4] * b1 + hd[5] * b2;
@@ -324,16 +323,27 @@ __device__ __forceinline__ void free_add_hot(double* __restrict__ cl, int32_t j,
     const T y1 = w * (o.D[3] * r0 + o.D[4] * r1 + o.D[5] * r2);
     const T g0 = o.D[0] * y0 + o.D[3] * y1, g1 = o.D[1] * y0 + o.D[4] * y1, g2 = o.D[2] * y0 + o.D[5] * y1;
     const T pyv = o.px * y0 + o.py * y1;
+    c[0] = o.a1 * g2 - o.a2 * g1;
+    c[1] = o.a2 * g0 - o.a0 * g2;
+    c[2] = o.a0 * g1 - o.a1 * g0;
+    c[3] = g0;
+    c[4] = g1;
+    c[5] = g2;
+    c[6] = o.d * pyv;
+    c[7] = o.fr2 * pyv;
+    c[8] = o.fr4 * pyv;
+}
+
+// ... added to the workgroup's FP64 table of hot cameras.
+template <typename T>
+__device__ __forceinline__ void free_add_hot(double* __restrict__ cl, int32_t j, const ObsGeo<T>& o,
+                                             const T hd[kCamHead], T w, T b0, T b1, T b2)
+{
+    T c[9];
+    free_camera_side<T>(o, hd, w, b0, b1, b2, c);
     double* dst = cl + 9 * j;
-    atomicAdd(dst + 0, (double)(o.a1 * g2 - o.a2 * g1));
-    atomicAdd(dst + 1, (double)(o.a2 * g0 - o.a0 * g2));
-    atomicAdd(dst + 2, (double)(o.a0 * g1 - o.a1 * g0));
-    atomicAdd(dst + 3, (double)g0);
-    atomicAdd(dst + 4, (double)g1);
-    atomicAdd(dst + 5, (double)g2);
-    atomicAdd(dst + 6, (double)(o.d * pyv));
-    atomicAdd(dst + 7, (double)(o.fr2 * pyv));
-    atomicAdd(dst + 8, (double)(o.fr4 * pyv));
+#pragma unroll
+    for (int a = 0; a < 9; ++a) atomicAdd(dst + a, (double)c[a]);
 }
 
 // Everything one observation needs: its camera's constants and vector, its
@@ -712,6 +722,78 @@ __global__ __launch_bounds__(256) void k_schur_cold(int64_t Nc, int32_t num_chun
     }
 }
 
+// Cold observations without stored blocks: as k_schur_cold, with E_k b
+// formed from the camera constants, the point and the observation's weight
+// (cw, in cold-stream order).  The camera is uniform over a slot, so J_l^T of
+// the rotation part is applied once per slot.
+template <typename T>
+__global__ __launch_bounds__(256) void k_schur_cold_free(int64_t Nc, int32_t num_chunks,
+                                                         const int32_t* __restrict__ ccam,
+                                                         const int32_t* __restrict__ cpt, const T* __restrict__ cw,
+                                                         const double* __restrict__ pts,
+                                                         const CamK<T>* __restrict__ ck, const T* __restrict__ bcold,
+                                                         const int32_t* __restrict__ chunk_slot,
+                                                         double* __restrict__ slots, const PcgScalars* __restrict__ sc,
+                                                         int skip_if_done)
+{
+    if (skip_if_done && sc->done) return;
+    const int lane = threadIdx.x & 63;
+    const int32_t chunk = (int32_t)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
+    if (chunk >= num_chunks) return;
+    const int64_t start = (int64_t)chunk * kColdChunk;
+    const int64_t end = start + kColdChunk < Nc ? start + kColdChunk : Nc;
+    int32_t slot = chunk_slot[chunk];
+    int32_t cur = ccam[start];
+    double acc[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) acc[a] = 0.0;
+    auto flush = [&](int32_t camj) {
+        double v[9];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            v[a] = wave_sum(acc[a]);
+            acc[a] = 0.0;
+        }
+        if (lane == 0) {
+            const T* J = ck[camj].Jl;
+            double* o = slots + (int64_t)slot * 9;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) o[a] = (double)J[a] * v[0] + (double)J[3 + a] * v[1] + (double)J[6 + a] * v[2];
+#pragma unroll
+            for (int a = 3; a < 9; ++a) o[a] = v[a];
+        }
+    };
+    for (int row = 0; row < kColdRows; ++row) {
+        if (start + (int64_t)row * 64 >= end) break;
+        const int64_t k = start + (int64_t)row * 64 + lane;
+        const bool valid = k < end;
+        int32_t j = 0x7fffffff;
+        T c[9];
+        if (valid) {
+            j = ccam[k];
+            const int32_t i = cpt[k];
+            T hd[kCamHead];
+            load_head<T>(ck, j, hd);
+            const double* X = pts + 3 * (int64_t)i;
+            ObsGeo<T> o;
+            observation_geometry<T>(hd, (T)X[0], (T)X[1], (T)X[2], o);
+            free_camera_side<T>(o, hd, cw[k], bcold[3 * (int64_t)i], bcold[3 * (int64_t)i + 1],
+                                bcold[3 * (int64_t)i + 2], c);
+        }
+        while (true) {
+            if (valid && j == cur)
+#pragma unroll
+                for (int a = 0; a < 9; ++a) acc[a] += (double)c[a];
+            const uint64_t more = __ballot(valid && j > cur);
+            if (more == 0) break;
+            flush(cur);
+            ++slot;
+            cur = __shfl(j, __ffsll((unsigned long long)more) - 1, 64);
+        }
+    }
+    flush(cur);
+}
+
 // Folds the per-workgroup hot partials [G][K*9] into kHotFold slices, each
 // the sum of a contiguous range of workgroups in order.
 __global__ __launch_bounds__(256) void k_hot_fold(int32_t K9, int32_t G, const double* __restrict__ hot_part,
@@ -869,9 +951,16 @@ hipError_t launch_schur_product(int mode, const SchurPlan& sp, const PointMajor&
     }
     if (hot_end && (e = hipEventRecord(hot_end, s)) != hipSuccess) return e;
     if (sp.cold.num_chunks > 0) {
-        hipLaunchKernelGGL((k_schur_cold<T>), dim3((sp.cold.num_chunks + 3) / 4), dim3(256), 0, s, sp.cold.N,
-                           sp.cold.num_chunks, sp.cold.cam, sp.cold.pt, (const T*)sp.cold.hcp, (const T*)sp.bcold,
-                           sp.cold.chunk_slot, sp.cold.slots, (const PcgScalars*)sc, mode == 0 ? 1 : 0);
+        if (sp.recompute && ri)
+            hipLaunchKernelGGL((k_schur_cold_free<T>), dim3((sp.cold.num_chunks + 3) / 4), dim3(256), 0, s,
+                               sp.cold.N, sp.cold.num_chunks, sp.cold.cam, sp.cold.pt, (const T*)sp.cold.w, ri->pts,
+                               ri->ck, (const T*)sp.bcold, sp.cold.chunk_slot, sp.cold.slots, (const PcgScalars*)sc,
+                               mode == 0 ? 1 : 0);
+        else
+            hipLaunchKernelGGL((k_schur_cold<T>), dim3((sp.cold.num_chunks + 3) / 4), dim3(256), 0, s, sp.cold.N,
+                               sp.cold.num_chunks, sp.cold.cam, sp.cold.pt, (const T*)sp.cold.hcp,
+                               (const T*)sp.bcold, sp.cold.chunk_slot, sp.cold.slots, (const PcgScalars*)sc,
+                               mode == 0 ? 1 : 0);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (sp.K > 0 && sp.num_wg > 0) {

@@ -300,10 +300,9 @@ def test_mixed_blocks_factor_at_narrow_baselines():
 @pytest.mark.parametrize("hot", [None, 400])
 def test_synthesised_recipe_matches_oracle(hot, monkeypatch):
     """The synthesised recipe at oracle size (400 cameras, 1,600 points seen
-    300 times each: every point spans five or six tiles).  By default the
-    library keeps no hot camera here (walking every long point twice would
-    read more than a second pass); forcing all 400 hot exercises that walk.
-    Both give the oracle's product and FP64 LM trace.  The trace is compared
+    300 times each: every point spans five or six tiles), with the library's
+    own choice of hot set and with all 400 cameras forced hot (every long
+    point walked twice).  Both give the oracle's product and FP64 LM trace.  The trace is compared
     at 1e-8: the scene spans 0.025 rad of every camera's view, so the camera
     blocks scaled to unit diagonal have smallest eigenvalues near 4e-5 (5e-3
     on the tiny workload) and the PCG step carries about 1e-9 relative
