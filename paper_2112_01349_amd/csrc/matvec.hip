@@ -763,32 +763,51 @@ __global__ __launch_bounds__(256) void k_schur_cold_free(int64_t Nc, int32_t num
             for (int a = 3; a < 9; ++a) o[a] = v[a];
         }
     };
-    for (int row = 0; row < kColdRows; ++row) {
+    // rows two at a time: both rows' loads are issued before either is used
+    for (int row = 0; row < kColdRows; row += 2) {
         if (start + (int64_t)row * 64 >= end) break;
-        const int64_t k = start + (int64_t)row * 64 + lane;
-        const bool valid = k < end;
-        int32_t j = 0x7fffffff;
-        T c[9];
-        if (valid) {
-            j = ccam[k];
-            const int32_t i = cpt[k];
-            T hd[kCamHead];
-            load_head<T>(ck, j, hd);
-            const double* X = pts + 3 * (int64_t)i;
-            ObsGeo<T> o;
-            observation_geometry<T>(hd, (T)X[0], (T)X[1], (T)X[2], o);
-            free_camera_side<T>(o, hd, cw[k], bcold[3 * (int64_t)i], bcold[3 * (int64_t)i + 1],
-                                bcold[3 * (int64_t)i + 2], c);
-        }
-        while (true) {
-            if (valid && j == cur)
+        int32_t j[2], i[2];
+        T w[2], hd[2][kCamHead], X[2][3], b[2][3];
+        bool valid[2];
 #pragma unroll
-                for (int a = 0; a < 9; ++a) acc[a] += (double)c[a];
-            const uint64_t more = __ballot(valid && j > cur);
-            if (more == 0) break;
-            flush(cur);
-            ++slot;
-            cur = __shfl(j, __ffsll((unsigned long long)more) - 1, 64);
+        for (int u = 0; u < 2; ++u) {
+            const int64_t k = start + (int64_t)(row + u) * 64 + lane;
+            valid[u] = k < end;
+            const int64_t kk = valid[u] ? k : start;
+            j[u] = ccam[kk];
+            i[u] = cpt[kk];
+            w[u] = cw[kk];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            load_head<T>(ck, j[u], hd[u]);
+            const double* Xp = pts + 3 * (int64_t)i[u];
+            const T* bp = bcold + 3 * (int64_t)i[u];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                X[u][a] = (T)Xp[a];
+                b[u][a] = bp[a];
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            ObsGeo<T> o;
+            observation_geometry<T>(hd[u], X[u][0], X[u][1], X[u][2], o);
+            T c[9];
+            free_camera_side<T>(o, hd[u], w[u], b[u][0], b[u][1], b[u][2], c);
+            const int32_t jj = valid[u] ? j[u] : 0x7fffffff;
+            while (true) {
+                if (valid[u] && jj == cur)
+#pragma unroll
+                    for (int a = 0; a < 9; ++a) acc[a] += (double)c[a];
+                const uint64_t more = __ballot(valid[u] && jj > cur);
+                if (more == 0) break;
+                flush(cur);
+                ++slot;
+                cur = __shfl(jj, __ffsll((unsigned long long)more) - 1, 64);
+            }
         }
     }
     flush(cur);
