@@ -95,14 +95,37 @@ struct ba_problem {
         }                                                                                    \
     } while (0)
 
-// Text for a failed damped-block factorisation: bit 0 of the device flag is
-// set by the camera blocks, bit 1 by the point blocks.
-static std::string not_pd_message(int32_t bits, double lambda)
+// Text for a failed damped-block factorisation from the device flag words:
+// bit 0 of flag[0] is set by the camera blocks, bit 1 by the point blocks;
+// flag[1] and flag[2] name one failing camera and point, whose undamped block
+// diagonal is quoted.
+static std::string not_pd_message(ba_problem* P, const int32_t* flag, double lambda)
 {
-    std::string what = (bits & 1) && (bits & 2) ? "camera and point blocks" : (bits & 1) ? "camera block" : "point block";
-    char lam[32];
-    std::snprintf(lam, sizeof lam, "%.3e", lambda);
-    return "damped " + what + " not positive definite at lambda " + lam;
+    char buf[256];
+    std::string msg = "damped";
+    if (flag[0] & 1) {
+        double d[81] = {0};
+        const int32_t j = flag[1];
+        if (j >= 0 && j < P->m && hipMemcpy(d, P->hcc + 81 * (int64_t)j, sizeof d, hipMemcpyDeviceToHost) == hipSuccess)
+            std::snprintf(buf, sizeof buf, " camera block %d (diagonal %.3e .. %.3e)", (int)P->old_of_new[j],
+                          *std::min_element(d, d + 81, [](double a, double b) { return a < b; }),
+                          *std::max_element(d, d + 81, [](double a, double b) { return a < b; }));
+        else
+            std::snprintf(buf, sizeof buf, " camera block");
+        msg += buf;
+    }
+    if (flag[0] & 2) {
+        double c[6] = {0};
+        const int32_t i = flag[2];
+        if (i >= 0 && i < P->n && hipMemcpy(c, (const double*)P->hpp + 6 * (int64_t)i, sizeof c, hipMemcpyDeviceToHost) == hipSuccess)
+            std::snprintf(buf, sizeof buf, "%s point block %d (C = %.3e %.3e %.3e %.3e %.3e %.3e)",
+                          (flag[0] & 1) ? " and" : "", (int)i, c[0], c[1], c[2], c[3], c[4], c[5]);
+        else
+            std::snprintf(buf, sizeof buf, "%s point block", (flag[0] & 1) ? " and" : "");
+        msg += buf;
+    }
+    std::snprintf(buf, sizeof buf, " not positive definite at lambda %.3e", lambda);
+    return msg + buf;
 }
 
 static bool finite_all(const double* a, int64_t len)
@@ -567,7 +590,7 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     P->partials = A.get<double>(2 * 2048);
     P->sums = A.get<double>(8);
     P->sc = A.get<PcgScalars>(1);
-    P->flag = A.get<int32_t>(1);
+    P->flag = A.get<int32_t>(4);  // [failure bits, a failing camera, a failing point, unused]
     if (A.err != hipSuccess) {
         g_create_error = std::string("device allocation failed: ") + hipGetErrorString(A.err);
         const bool oom = A.err == hipErrorOutOfMemory || A.err == hipErrorMemoryAllocation;
@@ -624,7 +647,7 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     if (e == hipSuccess) e = hipMemset(P->hpp, 0, 6 * (size_t)(n > 0 ? n : 1) * sizeof(double));
     if (e == hipSuccess) e = hipMemset(P->wpt, 0, 3 * (size_t)(n > 0 ? n : 1) * sizeof(double));
     if (e == hipSuccess) e = hipMemset(P->sc, 0, sizeof(PcgScalars));
-    if (e == hipSuccess) e = hipMemset(P->flag, 0, sizeof(int32_t));
+    if (e == hipSuccess) e = hipMemset(P->flag, 0, 4 * sizeof(int32_t));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         g_create_error = std::string("device upload failed: ") + hipGetErrorString(e);
@@ -842,11 +865,11 @@ static ba_status lm_solve_t(ba_problem* P, const ba_options& o, ba_report* rep)
         }
         BA_TRY(P, launch_damp_cameras(m, P->hcc, lambda, o.damping, P->bd, P->lfac, P->dcam, P->flag, s));
         BA_TRY(P, launch_damp_points<T>(n, (const double*)P->hpp, lambda, o.damping, (T*)P->cinv, P->flag, s));
-        BA_TRY(P, hipMemcpyAsync(P->h_scalars, P->flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        BA_TRY(P, hipMemcpyAsync(P->h_scalars, P->flag, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         BA_TRY(P, hipStreamSynchronize(s));
         if (const int32_t bad = *(int32_t*)P->h_scalars) {
-            BA_TRY(P, hipMemsetAsync(P->flag, 0, sizeof(int32_t), s));
-            P->last_error = not_pd_message(bad, lambda);
+            P->last_error = not_pd_message(P, (const int32_t*)P->h_scalars, lambda);
+            BA_TRY(P, hipMemsetAsync(P->flag, 0, 4 * sizeof(int32_t), s));
             result = BA_ENUMERIC;
             break;
         }
@@ -1063,11 +1086,11 @@ static ba_status schur_matvec_t(ba_problem* P, double lambda, int32_t damping, c
                                       (const T*)P->pT, &ri, m, P->bd, P->p, nullptr, P->q, nullptr, nullptr, P->partials,
                                       P->sc, nullptr, nullptr, s));
     BA_TRY(P, hipMemcpyAsync(qi.data(), P->q, qi.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-    BA_TRY(P, hipMemcpyAsync(P->h_scalars, P->flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    BA_TRY(P, hipMemcpyAsync(P->h_scalars, P->flag, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     BA_TRY(P, hipStreamSynchronize(s));
     if (const int32_t bad = *(int32_t*)P->h_scalars) {
-        BA_TRY(P, hipMemset(P->flag, 0, sizeof(int32_t)));
-        P->last_error = not_pd_message(bad, lambda);
+        P->last_error = not_pd_message(P, (const int32_t*)P->h_scalars, lambda);
+        BA_TRY(P, hipMemset(P->flag, 0, 4 * sizeof(int32_t)));
         return BA_ENUMERIC;
     }
     for (int32_t j = 0; j < m; ++j)

@@ -107,6 +107,20 @@ struct ObsGeo {
     T a0, a1, a2;      // R X, or X in the first-order branch
 };
 
+// FP32 can resolve P = R X + t only to ~1e-7 of |R X| + |t|: a point within
+// that of its camera's centre (a degenerate placement LM can drift into when
+// a point's other views are outliers) has a depth made of rounding, and its
+// FP32 Jacobian of overflow and NaN.  Such an observation gets a zero
+// Jacobian in FP32 (it then adds nothing to the blocks or the gradient; the
+// FP64 cost still counts it): its depth must exceed 2^-10 of the terms it is
+// formed from.  FP64 needs no such guard.
+template <typename T>
+__device__ __forceinline__ bool depth_resolved(T RX2, T t2, T P2)
+{
+    if (sizeof(T) == 8) return true;
+    return fabs(P2) > (T)(1.0 / 1024.0) * (fabs(RX2) + fabs(t2));
+}
+
 // hd: the first kCamHead words of the camera's CamK (R, t, f, k1, k2, small).
 template <typename T>
 __device__ __forceinline__ void observation_geometry(const T* hd, T X0, T X1, T X2, ObsGeo<T>& o)
@@ -114,9 +128,11 @@ __device__ __forceinline__ void observation_geometry(const T* hd, T X0, T X1, T 
     const T RX0 = hd[0] * X0 + hd[1] * X1 + hd[2] * X2;
     const T RX1 = hd[3] * X0 + hd[4] * X1 + hd[5] * X2;
     const T RX2 = hd[6] * X0 + hd[7] * X1 + hd[8] * X2;
-    const T P0 = RX0 + hd[9], P1 = RX1 + hd[10], P2 = RX2 + hd[11];
+    T P0 = RX0 + hd[9], P1 = RX1 + hd[10];
+    const T P2 = RX2 + hd[11];
     const T f = hd[12], k1 = hd[13], k2 = hd[14];
-    const T iz = (T)1 / P2;
+    T iz = (T)1 / P2;
+    if (!depth_resolved<T>(RX2, hd[11], P2)) P0 = P1 = iz = (T)0;  // all derivatives vanish
     const T px = -(P0 * iz), py = -(P1 * iz);
     const T r2 = px * px + py * py;
     const T d = (T)1 + k1 * r2 + k2 * (r2 * r2);

@@ -64,7 +64,10 @@ __global__ void k_damp_cameras(int32_t m, const double* __restrict__ hcc, double
         }
     }
     for (int q = 0; q < 45; ++q) lfac[45 * (int64_t)j + q] = L[q];
-    if (!ok) atomicOr(flag, 1);
+    if (!ok) {
+        atomicOr(flag, 1);
+        flag[1] = j;  // one of the failing cameras (for the error message)
+    }
 }
 
 hipError_t launch_damp_cameras(int32_t m, const double* hcc, double lambda, int32_t damping, double* bd,
@@ -117,7 +120,10 @@ __global__ void k_damp_points(int32_t n, const double* __restrict__ hpp, double 
     o[3] = (T)(m11 * m11 + m21 * m21);
     o[4] = (T)(m21 * m22);
     o[5] = (T)(m22 * m22);
-    if (!ok) atomicOr(flag, 2);
+    if (!ok) {
+        atomicOr(flag, 2);
+        flag[2] = i;  // one of the failing points (for the error message)
+    }
 }
 
 template <typename T>

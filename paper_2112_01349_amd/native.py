@@ -208,7 +208,8 @@ class Problem:
         out.update(iters_run=n_it, initial_cost=rep.initial_cost, final_cost=rep.final_cost,
                    total_ms=rep.total_ms, pcg_ms=rep.pcg_ms, pcg_iters_total=rep.pcg_iters_total,
                    matvec_ms=rep.matvec_ms, matvec_launches=rep.matvec_launches,
-                   schur_hot_ms=rep.schur_hot_ms, status=st)
+                   schur_hot_ms=rep.schur_hot_ms, status=st,
+                   error=lib().ba_last_error(self._h).decode() if st != BA_OK else "")
         if st not in (BA_OK, BA_ENUMERIC):
             self._check(st)
         return out

@@ -59,8 +59,13 @@ def test_large_cost_gradient_fp64(large):
         assert np.max(np.abs(gp[i] - ref)) <= 1e-10 * np.max(np.abs(ref)) + 1e-300, i
 
 
+@pytest.mark.parametrize("stored", [0, 1])
 @pytest.mark.parametrize("precision", [FP64, FP32_MIXED])
-def test_large_schur_rows(large, precision):
+def test_large_schur_rows(large, precision, stored, monkeypatch):
+    """Sampled rows of the reduced-system product at full size, from the
+    recomputing product and from the stored-block one, against the oracle's
+    rows computed from scratch."""
+    monkeypatch.setenv("BA_SCHUR_STORED", str(stored))
     prob = large["prob"]
     gpu = Problem(*large["args"], precision=precision, huber_delta=DELTA)
     lam = 1e-3
@@ -151,7 +156,7 @@ def test_lm_mixed_reaches_oracle_final_cost():
     rep = gpu.lm_solve(max_lm_iters=30, max_pcg_iters=g["options"]["max_pcg_iters"],
                        pcg_rtol=g["options"]["pcg_rtol"])
     gpu.close()
-    assert rep["status"] == 0
+    assert rep["status"] == 0, (rep["error"], rep["lambda"].tolist(), rep["cost"].tolist())
     costs = np.concatenate([[rep["initial_cost"]], rep["cost"]])
     assert np.all(np.diff(costs) <= 0)
     target = g["final_cost"] * (1 + 1e-4)

@@ -324,3 +324,33 @@ def test_synthesised_recipe_matches_oracle(hot, monkeypatch):
         gpu.close()
     tr, rep, _, _ = lm_pair(arrays, iters=4, max_pcg=30, rtol=1e-8)
     assert_traces_match(tr, rep, tol=1e-8)
+
+
+def test_mixed_point_at_camera_centre():
+    """A point within FP32 resolution of a camera's centre (LM can drift there
+    when a point's other views are outliers: every projection is available
+    from the centre) has a depth made of rounding in FP32.  The FP32-mixed
+    form gives that observation a zero Jacobian, so the blocks, the product
+    and the LM step stay finite; the FP64 form keeps its exact Jacobian."""
+    from scipy.spatial.transform import Rotation
+
+    prob = synth.generate("tiny", seed=0)
+    cams, pts = prob.cameras0.copy(), prob.points0.copy()
+    R = Rotation.from_rotvec(cams[0, :3]).as_matrix()
+    centre = -R.T @ cams[0, 3:6]
+    X = centre - 1e-7 * R[2]  # just in front of camera 0, on its optical axis
+    pts = np.vstack([pts, X])
+    i = len(pts) - 1
+    oc = np.concatenate([prob.obs_camera, [0, 1]]).astype(np.int32)
+    op = np.concatenate([prob.obs_point, [i, i]]).astype(np.int32)
+    uv = np.vstack([prob.obs_uv, [[12.0, -7.0], orc.project(cams[1], X) + 0.3]])
+    x = np.random.default_rng(2).normal(size=(len(cams), 9))
+    for precision in (FP64, FP32_MIXED):
+        gpu, _ = make((cams, pts, oc, op, uv), precision=precision, huber_delta=1.0)
+        F, gc, gp = gpu.eval_cost_grad()
+        assert np.isfinite(F) and np.all(np.isfinite(gc)) and np.all(np.isfinite(gp)), precision
+        assert np.all(np.isfinite(gpu.schur_matvec(x, 1e-3))), precision
+        rep = gpu.lm_solve(max_lm_iters=3, max_pcg_iters=30, pcg_rtol=1e-6)
+        assert rep["status"] == 0, (precision, rep["error"])
+        assert np.all(np.diff(np.concatenate([[rep["initial_cost"]], rep["cost"]])) <= 0)
+        gpu.close()
