@@ -725,7 +725,8 @@ static const CamK<T>* state_ck(const ba_problem* P)
 template <typename T>
 static RecomputeInputs<T> recompute_inputs(const ba_problem* P)
 {
-    return RecomputeInputs<T>{(const T*)P->wobs, P->pts, state_ck<T>(P), (const T*)P->xf};
+    return RecomputeInputs<T>{(const T*)P->wobs, P->pts, state_ck<T>(P), (const T*)P->xf,
+                              sizeof(T) == 4 ? P->ck64 : nullptr};
 }
 
 template <typename T>
@@ -739,7 +740,8 @@ static ba_status build_system(ba_problem* P)
     } else {
         ck = (const CamK<T>*)P->ck64;
     }
-    const JacSource<T> js{ck, P->opt.jacobian == BA_JACOBIAN_AUTODIFF ? P->cams : nullptr};
+    const JacSource<T> js{ck, P->opt.jacobian == BA_JACOBIAN_AUTODIFF ? P->cams : nullptr,
+                          sizeof(T) == 4 ? P->ck64 : nullptr};
     BA_TRY(P, launch_build_points<T>(P->pm, P->opt.huber_delta, false, P->pts, js, (T*)P->hcp, (double*)P->hpp,
                                      P->wpt, (T*)P->wobs, s));
     BA_TRY(P, launch_build_cameras<T>(P->cm, P->m, P->N, P->pts, js, P->opt.huber_delta, false, P->hcc, P->vcam,
@@ -980,9 +982,10 @@ extern "C" ba_status ba_lm_solve(ba_problem* P, const ba_options* opt, ba_report
 
 // --------------------------------------------------- cost and gradients
 template <typename T>
-static ba_status grad_into(ba_problem* P, const double* cams, const double* pts, const CamK<T>* ck, hipStream_t s)
+static ba_status grad_into(ba_problem* P, const double* cams, const double* pts, const CamK<T>* ck,
+                           const CamK<double>* ck64, hipStream_t s)
 {
-    const JacSource<T> js{ck, P->opt.jacobian == BA_JACOBIAN_AUTODIFF ? cams : nullptr};
+    const JacSource<T> js{ck, P->opt.jacobian == BA_JACOBIAN_AUTODIFF ? cams : nullptr, ck64};
     BA_TRY(P, launch_build_points<T>(P->pm, P->opt.huber_delta, true, pts, js, nullptr, nullptr, P->wpt, nullptr, s));
     BA_TRY(P, launch_build_cameras<T>(P->cm, P->m, P->N, pts, js, P->opt.huber_delta, true, nullptr, P->vcam, 0,
                                       nullptr, nullptr, s));
@@ -1000,7 +1003,7 @@ extern "C" ba_status ba_eval_cost_grad(ba_problem* P, double* cost, double* grad
         *cost = P->h_scalars[0];
     }
     if (grad_cameras || grad_points) {
-        if ((st = grad_into<double>(P, P->cams, P->pts, P->ck64, s)) != BA_OK) return st;
+        if ((st = grad_into<double>(P, P->cams, P->pts, P->ck64, nullptr, s)) != BA_OK) return st;
         // gradients land in cams_t / pts_t (caller order), then to the host
         BA_TRY(P, launch_scatter_grad(P->m, P->n, 0, 1.0, P->vcam, P->wpt, P->d_old_of_new,
                                       grad_cameras ? (void*)P->cams_t : nullptr,
@@ -1021,11 +1024,11 @@ static ba_status device_form(ba_problem* P, int32_t dtype, const void* d_cams, c
     BA_TRY(P, launch_gather_cameras(P->m, dtype, d_cams, P->d_old_of_new, P->cams_t, s));
     BA_TRY(P, launch_convert_points(P->n, dtype, d_pts, P->pts_t, s));
     const CamK<T>* ck;
+    BA_TRY(P, launch_camera_constants_f64(P->m, P->cams_t, P->ck64_t, s));
     if constexpr (sizeof(T) == 4) {
         BA_TRY(P, launch_camera_constants_f32(P->m, P->cams_t, P->ck32, s));
         ck = (const CamK<T>*)P->ck32;
     } else {
-        BA_TRY(P, launch_camera_constants_f64(P->m, P->cams_t, P->ck64_t, s));
         ck = (const CamK<T>*)P->ck64_t;
     }
     ba_status st;
@@ -1034,7 +1037,8 @@ static ba_status device_form(ba_problem* P, int32_t dtype, const void* d_cams, c
         BA_TRY(P, launch_store_cost(P->sums, (double*)d_cost, s));
         return BA_OK;
     }
-    if ((st = grad_into<T>(P, P->cams_t, P->pts_t, ck, s)) != BA_OK) return st;
+    if ((st = grad_into<T>(P, P->cams_t, P->pts_t, ck, sizeof(T) == 4 ? P->ck64_t : nullptr, s)) != BA_OK)
+        return st;
     BA_TRY(P, launch_scatter_grad(P->m, P->n, dtype, gout, P->vcam, P->wpt, P->d_old_of_new, d_gc, d_gp, s));
     return BA_OK;
 }

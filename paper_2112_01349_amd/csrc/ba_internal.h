@@ -147,6 +147,7 @@ struct RecomputeInputs {
     const double* pts;   // [n][3] point coordinates
     const CamK<T>* ck;   // [m] camera constants
     const T* xf;         // [m][12] camera vectors from launch_pcg_direction
+    const CamK<double>* ck64;  // [m] FP64 constants (FP32 form: unresolved depths), nullable
 };
 
 // ---------------------------------------------------------------- launchers
@@ -157,10 +158,13 @@ hipError_t launch_camera_constants_f32(int32_t m, const double* cams, CamK<float
 // Where the build's Jacobians come from: the per-camera constants of the
 // analytic form (ck), or, when cams is set, forward-mode differentiation of
 // the residual at the FP64 camera parameters cams [m][9] (internal order).
+// ck64 (nullable): FP64 constants of the same cameras, for the FP32 form's
+// observations whose depth FP32 cannot resolve.
 template <typename T>
 struct JacSource {
     const CamK<T>* ck;
     const double* cams;
+    const CamK<double>* ck64;
 };
 
 // Point-major build: E_k into hcp, C_i into hpp and each observation's IRLS

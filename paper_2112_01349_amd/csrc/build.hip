@@ -80,24 +80,23 @@ __device__ __forceinline__ void observation(int64_t k, const int32_t* __restrict
 {
     const int32_t j = cam[k];
     i = pt[k];
-    const T X0 = (T)pts[3 * (int64_t)i], X1 = (T)pts[3 * (int64_t)i + 1], X2 = (T)pts[3 * (int64_t)i + 2];
+    const double* Xd = pts + 3 * (int64_t)i;
+    const T X0 = (T)Xd[0], X1 = (T)Xd[1], X2 = (T)Xd[2];
+    const CamK<T>& kk = js.ck[j];
     if (AD) {
         residual_jacobian_ad<T>(js.cams + 9 * (int64_t)j, X0, X1, X2, (T)uvx[k], (T)uvy[k], e0, e1, Jc, Jp);
-        if (sizeof(T) == 4) {  // the analytic form's guard against a depth made of rounding
-            const T* R = js.ck[j].R;
-            const T RX2 = R[6] * X0 + R[7] * X1 + R[8] * X2, t2 = js.ck[j].t[2];
-            if (!depth_resolved<T>(RX2, t2, RX2 + t2)) {
-                e0 = -(T)uvx[k];
-                e1 = -(T)uvy[k];
-#pragma unroll
-                for (int q = 0; q < 18; ++q) Jc[q] = (T)0;
-#pragma unroll
-                for (int q = 0; q < 6; ++q) Jp[q] = (T)0;
+        if (sizeof(T) == 4) {  // an unresolved FP32 depth: the analytic form from the FP64 geometry
+            const T RX2 = kk.R[6] * X0 + kk.R[7] * X1 + kk.R[8] * X2;
+            if (!depth_resolved<T>(RX2, kk.t[2], RX2 + kk.t[2])) {
+                ObsGeo<T> o;
+                observation_geometry_checked<T>(kk.R, js.ck64, j, Xd, o);
+                jacobian_from_geometry<T>(kk, o, (T)uvx[k], (T)uvy[k], e0, e1, Jc, Jp);
             }
         }
     } else {
-        const CamK<T> kk = js.ck[j];
-        residual_jacobian<T>(kk, X0, X1, X2, (T)uvx[k], (T)uvy[k], e0, e1, Jc, Jp);
+        ObsGeo<T> o;
+        observation_geometry_checked<T>(kk.R, js.ck64, j, Xd, o);
+        jacobian_from_geometry<T>(kk, o, (T)uvx[k], (T)uvy[k], e0, e1, Jc, Jp);
     }
     wt = huber_weight<T>(e0 * e0 + e1 * e1, delta);
 }

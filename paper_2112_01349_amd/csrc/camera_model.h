@@ -107,13 +107,13 @@ struct ObsGeo {
     T a0, a1, a2;      // R X, or X in the first-order branch
 };
 
-// FP32 can resolve P = R X + t only to ~1e-7 of |R X| + |t|: a point within
-// that of its camera's centre (a degenerate placement LM can drift into when
-// a point's other views are outliers) has a depth made of rounding, and its
-// FP32 Jacobian of overflow and NaN.  Such an observation gets a zero
-// Jacobian in FP32 (it then adds nothing to the blocks or the gradient; the
-// FP64 cost still counts it): its depth must exceed 2^-10 of the terms it is
-// formed from.  FP64 needs no such guard.
+// FP32 resolves P = R X + t only to ~1e-7 of |R X| + |t|: for a point within
+// that of its camera's centre (a placement LM can drift into when a point's
+// other views are outliers: from the centre every projection is available)
+// the FP32 depth is made of rounding and the FP32 Jacobian overflows.  A
+// depth is taken as resolved when it exceeds 2^-10 of the terms it is formed
+// from; an unresolved one is formed again in FP64 (observation_geometry_f64).
+// FP64 needs no such test.
 template <typename T>
 __device__ __forceinline__ bool depth_resolved(T RX2, T t2, T P2)
 {
@@ -122,8 +122,10 @@ __device__ __forceinline__ bool depth_resolved(T RX2, T t2, T P2)
 }
 
 // hd: the first kCamHead words of the camera's CamK (R, t, f, k1, k2, small).
+// Returns false for an unresolved FP32 depth, with every derivative set to
+// zero (the caller forms the geometry in FP64 instead where it can).
 template <typename T>
-__device__ __forceinline__ void observation_geometry(const T* hd, T X0, T X1, T X2, ObsGeo<T>& o)
+__device__ __forceinline__ bool observation_geometry(const T* hd, T X0, T X1, T X2, ObsGeo<T>& o)
 {
     const T RX0 = hd[0] * X0 + hd[1] * X1 + hd[2] * X2;
     const T RX1 = hd[3] * X0 + hd[4] * X1 + hd[5] * X2;
@@ -132,7 +134,8 @@ __device__ __forceinline__ void observation_geometry(const T* hd, T X0, T X1, T 
     const T P2 = RX2 + hd[11];
     const T f = hd[12], k1 = hd[13], k2 = hd[14];
     T iz = (T)1 / P2;
-    if (!depth_resolved<T>(RX2, hd[11], P2)) P0 = P1 = iz = (T)0;  // all derivatives vanish
+    const bool resolved = depth_resolved<T>(RX2, hd[11], P2);
+    if (!resolved) P0 = P1 = iz = (T)0;  // all derivatives vanish
     const T px = -(P0 * iz), py = -(P1 * iz);
     const T r2 = px * px + py * py;
     const T d = (T)1 + k1 * r2 + k2 * (r2 * r2);
@@ -155,15 +158,49 @@ __device__ __forceinline__ void observation_geometry(const T* hd, T X0, T X1, T 
     o.a0 = sm ? X0 : RX0;
     o.a1 = sm ? X1 : RX1;
     o.a2 = sm ? X2 : RX2;
+    return resolved;
 }
 
-// Residual and Jacobians: Jc row-major 2x9, Jp row-major 2x3.
+// The geometry formed in FP64 from the camera's FP64 constants and the FP64
+// point, stored in T: the FP32 form's path for an unresolved depth (rare, so
+// kept out of line).
 template <typename T>
-__device__ __forceinline__ void residual_jacobian(const CamK<T>& k, T X0, T X1, T X2, T u, T v,
-                                                  T& e0, T& e1, T Jc[18], T Jp[6])
+__device__ __attribute__((noinline)) ObsGeo<T> observation_geometry_f64(const CamK<double>* __restrict__ ck64,
+                                                                        int32_t j, const double* __restrict__ X)
 {
+    ObsGeo<double> g;
+    observation_geometry<double>(ck64[j].R, X[0], X[1], X[2], g);
     ObsGeo<T> o;
-    observation_geometry<T>(k.R, X0, X1, X2, o);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) o.D[q] = (T)g.D[q];
+    o.px = (T)g.px;
+    o.py = (T)g.py;
+    o.fd = (T)g.fd;
+    o.d = (T)g.d;
+    o.fr2 = (T)g.fr2;
+    o.fr4 = (T)g.fr4;
+    o.a0 = (T)g.a0;
+    o.a1 = (T)g.a1;
+    o.a2 = (T)g.a2;
+    return o;
+}
+
+// The geometry of one observation in T; an unresolved FP32 depth is formed in
+// FP64 when the FP64 constants are at hand (ck64), else left with zero
+// derivatives.
+template <typename T>
+__device__ __forceinline__ void observation_geometry_checked(const T* hd, const CamK<double>* __restrict__ ck64,
+                                                             int32_t j, const double* __restrict__ X, ObsGeo<T>& o)
+{
+    if (!observation_geometry<T>(hd, (T)X[0], (T)X[1], (T)X[2], o) && ck64) o = observation_geometry_f64<T>(ck64, j, X);
+}
+
+// Residual and Jacobians from the geometry: Jc row-major 2x9, Jp row-major
+// 2x3.
+template <typename T>
+__device__ __forceinline__ void jacobian_from_geometry(const CamK<T>& k, const ObsGeo<T>& o, T u, T v, T& e0, T& e1,
+                                                       T Jc[18], T Jp[6])
+{
     e0 = o.fd * o.px - u;
     e1 = o.fd * o.py - v;
     const T* D = o.D;
@@ -185,6 +222,15 @@ __device__ __forceinline__ void residual_jacobian(const CamK<T>& k, T X0, T X1, 
     Jc[16] = o.fr2 * o.py;
     Jc[8] = o.fr4 * o.px;
     Jc[17] = o.fr4 * o.py;
+}
+
+template <typename T>
+__device__ __forceinline__ void residual_jacobian(const CamK<T>& k, T X0, T X1, T X2, T u, T v,
+                                                  T& e0, T& e1, T Jc[18], T Jp[6])
+{
+    ObsGeo<T> o;
+    observation_geometry<T>(k.R, X0, X1, X2, o);
+    jacobian_from_geometry<T>(k, o, u, v, e0, e1, Jc, Jp);
 }
 
 // Huber on the 2-D residual norm, s = |e|^2: rho(s) = s for s <= delta^2,

@@ -352,8 +352,8 @@ template <typename T>
 __device__ __forceinline__ void free_observation(int64_t k, const int32_t* __restrict__ cam,
                                                  const int32_t* __restrict__ pt, const T* __restrict__ wobs,
                                                  const double* __restrict__ pts, const CamK<T>* __restrict__ ck,
-                                                 const T* __restrict__ xf, int32_t& j, int32_t& i, T& w,
-                                                 T hd[kCamHead], T xv[9], ObsGeo<T>& o)
+                                                 const CamK<double>* __restrict__ ck64, const T* __restrict__ xf,
+                                                 int32_t& j, int32_t& i, T& w, T hd[kCamHead], T xv[9], ObsGeo<T>& o)
 {
     j = cam[k];
     i = pt[k];
@@ -362,8 +362,7 @@ __device__ __forceinline__ void free_observation(int64_t k, const int32_t* __res
     const T* x = xf + 12 * (int64_t)j;
 #pragma unroll
     for (int a = 0; a < 9; ++a) xv[a] = x[a];
-    const double* X = pts + 3 * (int64_t)i;
-    observation_geometry<T>(hd, (T)X[0], (T)X[1], (T)X[2], o);
+    observation_geometry_checked<T>(hd, ck64, j, pts + 3 * (int64_t)i, o);
 }
 
 // A short segment in flight: its streamed indices and weight (stage 1), then
@@ -433,11 +432,13 @@ __device__ __forceinline__ void free_gather(const FreeRow<T>& r, const double* _
 template <typename T, int MODE>
 __device__ __forceinline__ void free_short(const FreeRow<T>& r, const FreeData<T>& d, int lane, uint64_t upto,
                                            int32_t K, double* __restrict__ cl, T* __restrict__ bcold,
-                                           double* __restrict__ dp)
+                                           double* __restrict__ dp, const double* __restrict__ pts,
+                                           const CamK<double>* __restrict__ ck64)
 {
     const bool valid = lane < r.len;
     ObsGeo<T> o;
-    observation_geometry<T>(d.hd, d.X[0], d.X[1], d.X[2], o);
+    if (!observation_geometry<T>(d.hd, d.X[0], d.X[1], d.X[2], o) && ck64)
+        o = observation_geometry_f64<T>(ck64, r.j, pts + 3 * (int64_t)r.i);
     T a0, a1, a2;
     int seg_e = lane;
     if (MODE == 1) {
@@ -508,9 +509,9 @@ __global__ __launch_bounds__(HotThreads<T>::value) void k_schur_free(
     const int32_t* __restrict__ frange, const int2* __restrict__ sseg, const int32_t* __restrict__ lrange,
     const int2* __restrict__ lseg, const int32_t* __restrict__ cam, const int32_t* __restrict__ pt,
     const T* __restrict__ wobs, const double* __restrict__ pts, const CamK<T>* __restrict__ ck,
-    const T* __restrict__ xf, const T* __restrict__ cinv, const double* __restrict__ wpt, int32_t K,
-    double* __restrict__ hot_part, T* __restrict__ bcold, const uint8_t* __restrict__ has_cold,
-    double* __restrict__ dp, const PcgScalars* __restrict__ sc)
+    const CamK<double>* __restrict__ ck64, const T* __restrict__ xf, const T* __restrict__ cinv,
+    const double* __restrict__ wpt, int32_t K, double* __restrict__ hot_part, T* __restrict__ bcold,
+    const uint8_t* __restrict__ has_cold, double* __restrict__ dp, const PcgScalars* __restrict__ sc)
 {
     constexpr int NT = HotThreads<T>::value;
     if (MODE == 0 && sc->done) return;  // uniform over the grid
@@ -538,14 +539,14 @@ __global__ __launch_bounds__(HotThreads<T>::value) void k_schur_free(
             for (int u = 0; u < NB; ++u) free_gather<T, MODE>(r[u], pts, ck, xf, cinv, has_cold, wpt, d[u]);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int u = 0; u < NB; ++u) free_short<T, MODE>(r[u], d[u], lane, upto, K, cl, bcold, dp);
+            for (int u = 0; u < NB; ++u) free_short<T, MODE>(r[u], d[u], lane, upto, K, cl, bcold, dp, pts, ck64);
         }
         for (int32_t q = S0 + NB * nbat; q < S1; ++q) {
             FreeRow<T> r;
             FreeData<T> d;
             free_stream<T>(sseg, q, lane, cam, pt, wobs, r);
             free_gather<T, MODE>(r, pts, ck, xf, cinv, has_cold, wpt, d);
-            free_short<T, MODE>(r, d, lane, upto, K, cl, bcold, dp);
+            free_short<T, MODE>(r, d, lane, upto, K, cl, bcold, dp, pts, ck64);
         }
     }
     const int32_t L0 = lrange[gw], L1 = lrange[gw + 1];
@@ -561,7 +562,7 @@ __global__ __launch_bounds__(HotThreads<T>::value) void k_schur_free(
                 int32_t j, ii;
                 T w, hd[kCamHead], xv[9];
                 ObsGeo<T> o;
-                free_observation<T>(k, cam, pt, wobs, pts, ck, xf, j, ii, w, hd, xv, o);
+                free_observation<T>(k, cam, pt, wobs, pts, ck, ck64, xf, j, ii, w, hd, xv, o);
                 T e0, e1, e2;
                 free_et_x<T>(o, hd, xv, w, e0, e1, e2);
                 if (!valid) e0 = e1 = e2 = (T)0;
@@ -599,7 +600,7 @@ __global__ __launch_bounds__(HotThreads<T>::value) void k_schur_free(
                 int32_t j, ii;
                 T w, hd[kCamHead], xv[9];
                 ObsGeo<T> o;
-                free_observation<T>(k, cam, pt, wobs, pts, ck, xf, j, ii, w, hd, xv, o);
+                free_observation<T>(k, cam, pt, wobs, pts, ck, ck64, xf, j, ii, w, hd, xv, o);
                 if (valid && j < K) free_add_hot<T>(cl, j, o, hd, w, b0, b1, b2);
             }
     }
@@ -731,7 +732,9 @@ __global__ __launch_bounds__(256) void k_schur_cold_free(int64_t Nc, int32_t num
                                                          const int32_t* __restrict__ ccam,
                                                          const int32_t* __restrict__ cpt, const T* __restrict__ cw,
                                                          const double* __restrict__ pts,
-                                                         const CamK<T>* __restrict__ ck, const T* __restrict__ bcold,
+                                                         const CamK<T>* __restrict__ ck,
+                                                         const CamK<double>* __restrict__ ck64,
+                                                         const T* __restrict__ bcold,
                                                          const int32_t* __restrict__ chunk_slot,
                                                          double* __restrict__ slots, const PcgScalars* __restrict__ sc,
                                                          int skip_if_done)
@@ -794,7 +797,8 @@ __global__ __launch_bounds__(256) void k_schur_cold_free(int64_t Nc, int32_t num
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             ObsGeo<T> o;
-            observation_geometry<T>(hd[u], X[u][0], X[u][1], X[u][2], o);
+            if (!observation_geometry<T>(hd[u], X[u][0], X[u][1], X[u][2], o) && ck64)
+                o = observation_geometry_f64<T>(ck64, j[u], pts + 3 * (int64_t)i[u]);
             T c[9];
             free_camera_side<T>(o, hd[u], w[u], b[u][0], b[u][1], b[u][2], c);
             const int32_t jj = valid[u] ? j[u] : 0x7fffffff;
@@ -954,11 +958,11 @@ hipError_t launch_schur_product(int mode, const SchurPlan& sp, const PointMajor&
         const dim3 g(sp.num_wg), b(HotThreads<T>::value);
         if (mode == 0 && sp.recompute && ri)
             hipLaunchKernelGGL((k_schur_free<T, 0>), g, b, lds, s, sp.frange, sp.sseg, sp.lrange, sp.lseg, pm.cam,
-                               pm.pt, ri->wobs, ri->pts, ri->ck, ri->xf, cinv, nullptr, sp.K, (double*)sp.hot_part,
+                               pm.pt, ri->wobs, ri->pts, ri->ck, ri->ck64, ri->xf, cinv, nullptr, sp.K, (double*)sp.hot_part,
                                (T*)sp.bcold, sp.has_cold, nullptr, sc);
         else if (mode == 1 && sp.recompute && ri)
             hipLaunchKernelGGL((k_schur_free<T, 1>), g, b, lds, s, sp.frange, sp.sseg, sp.lrange, sp.lseg, pm.cam,
-                               pm.pt, ri->wobs, ri->pts, ri->ck, nullptr, cinv, wpt, sp.K, (double*)sp.hot_part,
+                               pm.pt, ri->wobs, ri->pts, ri->ck, ri->ck64, nullptr, cinv, wpt, sp.K, (double*)sp.hot_part,
                                (T*)sp.bcold, sp.has_cold, nullptr, nullptr);
         else if (mode == 0)
             hipLaunchKernelGGL((k_schur_hot<T>), g, b, lds, s, sp.wrange, N, pm.cam, pm.pt, hcp, cinv, xcam,
@@ -973,7 +977,7 @@ hipError_t launch_schur_product(int mode, const SchurPlan& sp, const PointMajor&
         if (sp.recompute && ri)
             hipLaunchKernelGGL((k_schur_cold_free<T>), dim3((sp.cold.num_chunks + 3) / 4), dim3(256), 0, s,
                                sp.cold.N, sp.cold.num_chunks, sp.cold.cam, sp.cold.pt, (const T*)sp.cold.w, ri->pts,
-                               ri->ck, (const T*)sp.bcold, sp.cold.chunk_slot, sp.cold.slots, (const PcgScalars*)sc,
+                               ri->ck, ri->ck64, (const T*)sp.bcold, sp.cold.chunk_slot, sp.cold.slots, (const PcgScalars*)sc,
                                mode == 0 ? 1 : 0);
         else
             hipLaunchKernelGGL((k_schur_cold<T>), dim3((sp.cold.num_chunks + 3) / 4), dim3(256), 0, s, sp.cold.N,
@@ -1011,7 +1015,7 @@ hipError_t launch_backsub_free(const SchurPlan& sp, const PointMajor& pm, const 
 {
     if (sp.num_wg <= 0) return hipGetLastError();
     hipLaunchKernelGGL((k_schur_free<T, 2>), dim3(sp.num_wg), dim3(HotThreads<T>::value), 0, s, sp.frange, sp.sseg,
-                       sp.lrange, sp.lseg, pm.cam, pm.pt, ri.wobs, ri.pts, ri.ck, ri.xf, cinv, wpt, 0, nullptr,
+                       sp.lrange, sp.lseg, pm.cam, pm.pt, ri.wobs, ri.pts, ri.ck, ri.ck64, ri.xf, cinv, wpt, 0, nullptr,
                        nullptr, sp.has_cold, dp, nullptr);
     return hipGetLastError();
 }
