@@ -5,9 +5,11 @@
  * e_k per observation (graph edge) between a camera and a point, with the
  * Levenberg-Marquardt method.  Each LM iteration runs, on one GPU:
  *   - the per-observation residual and Jacobian (Alg. 1, first step);
- *   - Schur block assembly B (camera 9x9), C (point 3x3), E (camera-point 9x3
- *     per observation) and the vectors v, w (Alg. 1, second step; Eq.
- *     schur_complement);
+ *   - Schur block assembly B (camera 9x9), C (point 3x3) and the vectors v, w
+ *     (Alg. 1, second step; Eq. schur_complement); the camera-point blocks E
+ *     (9x3 per observation) are formed again from the Jacobian inside every
+ *     product that uses them rather than stored (BA_SCHUR_STORED=1 in the
+ *     environment at ba_create stores and streams them instead);
  *   - the reduced camera system (Eq. schur_x_c) solved by block-Jacobi PCG
  *     (Alg. 2) whose matrix-vector products are implicit Schur products
  *     (Alg. 3);
@@ -51,8 +53,11 @@ typedef enum {
     BA_FP64 = 0,       /* every step in FP64 */
     BA_FP32_MIXED = 1  /* Jacobians, coupling blocks E, C~^-1 and matvecs in FP32;
                           cost sums, PCG vectors/dots/scalars, the 9x9 camera-block
-                          factorisations and the 3x3 point-block sums and
-                          inversions in FP64 (paper Sec. 6, Table float) */
+                          factorisations, the 3x3 point-block sums and inversions
+                          and the products forming B and C in FP64 (paper Sec. 6,
+                          Table float); an observation whose point sits within
+                          FP32 resolution of its camera's centre has its
+                          geometry formed in FP64 */
 } ba_precision;
 
 typedef enum {
