@@ -893,8 +893,8 @@ static ba_status lm_solve_t(ba_problem* P, const ba_options& o, ba_report* rep)
             BA_TRY(P, launch_backsub_free<T>(P->sp, P->pm, ri, (const T*)P->cinv, P->wpt, P->dp, s));
         } else {
             BA_TRY(P, launch_pcg_direction<T>(m, true, P->x, P->p, (T*)P->pT, nullptr, nullptr, P->sc, s));
-            BA_TRY(P, launch_schur_tiles<T>(2, P->pm, nullptr, 0, P->pm.ld, (const T*)P->hcp, (const T*)P->cinv,
-                                            P->wpt, (const T*)P->pT, nullptr, P->dp, s));
+            BA_TRY(P, launch_backsub_stored<T>(P->pm, (const T*)P->hcp, (const T*)P->cinv, P->wpt,
+                                               (const T*)P->pT, P->dp, s));
         }
         BA_TRY(P, launch_trial_state(m, n, P->cams, P->x, P->pts, P->dp, P->cams_t, P->pts_t, s));
         BA_TRY(P, launch_camera_constants_f64(m, P->cams_t, P->ck64_t, s));

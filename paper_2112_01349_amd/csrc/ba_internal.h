@@ -187,14 +187,11 @@ template <typename T>
 hipError_t launch_damp_points(int32_t n, const double* hpp, double lambda, int32_t damping, T* cinv,
                               int32_t* flag, hipStream_t s);
 
-// mode 0: c = E C^-1 E^T x    (implicit Schur product without the B term)
-// mode 1: c = E C^-1 w        (reduced right-hand side)
-// mode 2: dp = C^-1 (w - E^T x)  (back-substitution)
-// tile_list (nullable = every tile) selects the tiles; count = its length.
+// Back-substitution from the stored blocks (BA_SCHUR_STORED=1):
+// dp = C~^-1 (w - E^T x), x in T (xcam).
 template <typename T>
-hipError_t launch_schur_tiles(int mode, const PointMajor& pm, const int32_t* tile_list, int32_t count, int64_t N,
-                              const T* hcp, const T* cinv, const double* wpt, const T* xcam, double* cacc,
-                              double* dp, hipStream_t s);
+hipError_t launch_backsub_stored(const PointMajor& pm, const T* hcp, const T* cinv, const double* wpt,
+                                 const T* xcam, double* dp, hipStream_t s);
 
 // Full implicit Schur product.  mode 0: out = q = B~ x - E C~^-1 E^T x, then
 // p^T q, alpha and the matvec count into sc (skipped once sc->done);

@@ -1,18 +1,13 @@
-// Damping, block inverses and the implicit Schur products.
+// Damping, block inverses and the back-substitution from stored blocks.
 //
 //   * k_damp_cameras: B~_j = B_j + lambda D_j and its Cholesky factor, FP64
 //     (the block-Jacobi preconditioner of Alg. 2 and the B x term of Alg. 3).
 //   * k_damp_points:  C~_i = C_i + lambda D_i and its explicit inverse (Alg. 3
 //     b = C^-1 a, Eq. schur_x_p), one lane per point.
-//   * k_schur_tiles: the observation pass of Alg. 3 (DSE) with one partition,
-//     and its two relatives, over point-aligned tiles of <= 256 observations:
-//       mode 0  c = E C~^-1 E^T x   (a = E^T x per point, b = C~^-1 a,
-//                                    then c_j += E_k b per observation)
-//       mode 1  c = E C~^-1 w       (reduced right-hand side, Eq. schur_x_c)
-//       mode 2  dp = C~^-1 (w - E^T x)   (back-substitution, Eq. schur_x_p)
-//     E is read as 27 coalesced streams.  The per-point sums a_i run over the
-//     point's contiguous segment in LDS; each observation then scatters its
-//     nine-word camera contribution with a hardware float atomic add.
+//   * k_backsub_stored: dp = C~^-1 (w - E^T x) (Eq. schur_x_p) over
+//     point-aligned tiles of <= 256 observations, reading E as 27 coalesced
+//     streams, for the stored-block product; the per-point sums run over the
+//     point's contiguous segment in LDS.
 // Damping (Reading of Sec. 3 and supplementary Sec. C): D = clamp(diag, 1e-6,
 // 1e32) (Marquardt, Ceres-like) or D = I (as printed in Sec. 3).
 #include "ba_internal.h"
@@ -136,7 +131,7 @@ hipError_t launch_damp_points(int32_t n, const double* hpp, double lambda, int32
     return hipGetLastError();
 }
 
-// ----------------------------------------------------------- Schur tiles
+// ------------------------------------------- back-substitution (stored E)
 template <typename T>
 __device__ __forceinline__ void sym3_apply(const T* __restrict__ ci, T a0, T a1, T a2, T& b0, T& b1, T& b2)
 {
@@ -146,182 +141,110 @@ __device__ __forceinline__ void sym3_apply(const T* __restrict__ ci, T a0, T a1,
     b2 = c02 * a0 + c12 * a1 + c22 * a2;
 }
 
-__device__ __forceinline__ void atomic_add_f64(double* p, double v) { unsafeAtomicAdd(p, v); }
-
-template <typename T, int MODE>
-__global__ __launch_bounds__(kTile) void k_schur_tiles(const int32_t* __restrict__ tile,
-                                                       const int32_t* __restrict__ tile_list,
-                                                       const int32_t* __restrict__ cam,
-                                                       const int32_t* __restrict__ pt, int64_t N,
-                                                       const T* __restrict__ hcp, const T* __restrict__ cinv,
-                                                       const double* __restrict__ wpt, const T* __restrict__ xcam,
-                                                       double* __restrict__ cacc, double* __restrict__ dp)
+// dp_i = C~_i^-1 (w_i - sum_k E_k^T dc_j) from the stored blocks, one
+// workgroup per point-aligned tile (a point longer than the tile is one tile,
+// summed by a tree in LDS).
+template <typename T>
+__global__ __launch_bounds__(kTile) void k_backsub_stored(const int32_t* __restrict__ tile,
+                                                          const int32_t* __restrict__ cam,
+                                                          const int32_t* __restrict__ pt, const T* __restrict__ hcp,
+                                                          const T* __restrict__ cinv, const double* __restrict__ wpt,
+                                                          const T* __restrict__ xcam, double* __restrict__ dp)
 {
     __shared__ T sha[3][kTile];
-    __shared__ T shb[3][kTile];
     __shared__ int32_t shpt[kTile];
     const int tid = threadIdx.x;
-    const int32_t tix = tile_list ? tile_list[blockIdx.x] : (int32_t)blockIdx.x;
-    const int32_t s = tile[tix], e = tile[tix + 1];
+    const int32_t s = tile[blockIdx.x], e = tile[blockIdx.x + 1];
     const int32_t len = e - s;
     if (len <= kTile) {
         const bool valid = tid < len;
         const int64_t k = s + tid;
-        int32_t i = -1, j = 0;
-        T h[27];
+        int32_t i = -1;
         if (valid) {
-            j = cam[k];
+            const int32_t j = cam[k];
             i = pt[k];
+            T x[9];
 #pragma unroll
-            for (int q = 0; q < 27; ++q) h[q] = hcp[eidx(k, q)];
-            if (MODE != 1) {
-                T x[9];
+            for (int a = 0; a < 9; ++a) x[a] = xcam[9 * (int64_t)j + a];
 #pragma unroll
-                for (int a = 0; a < 9; ++a) x[a] = xcam[9 * (int64_t)j + a];
+            for (int b = 0; b < 3; ++b) {
+                T acc = 0;
 #pragma unroll
-                for (int b = 0; b < 3; ++b) {
-                    T acc = 0;
-#pragma unroll
-                    for (int a = 0; a < 9; ++a) acc += h[a * 3 + b] * x[a];
-                    sha[b][tid] = acc;
-                }
+                for (int a = 0; a < 9; ++a) acc += hcp[eidx(k, a * 3 + b)] * x[a];
+                sha[b][tid] = acc;
             }
         }
         shpt[tid] = i;
         __syncthreads();
         if (valid && (tid == 0 || shpt[tid - 1] != i)) {
+            T a0 = 0, a1 = 0, a2 = 0;
+            for (int u = tid; u < len && shpt[u] == i; ++u) {
+                a0 += sha[0][u];
+                a1 += sha[1][u];
+                a2 += sha[2][u];
+            }
             T b0, b1, b2;
-            const T* ci = cinv + 6 * (int64_t)i;
-            if (MODE == 1) {
-                sym3_apply<T>(ci, (T)wpt[3 * (int64_t)i], (T)wpt[3 * (int64_t)i + 1], (T)wpt[3 * (int64_t)i + 2],
-                              b0, b1, b2);
-            } else {
-                T a0 = 0, a1 = 0, a2 = 0;
-                for (int u = tid; u < len && shpt[u] == i; ++u) {
-                    a0 += sha[0][u];
-                    a1 += sha[1][u];
-                    a2 += sha[2][u];
-                }
-                if (MODE == 2) {
-                    a0 = (T)wpt[3 * (int64_t)i] - a0;
-                    a1 = (T)wpt[3 * (int64_t)i + 1] - a1;
-                    a2 = (T)wpt[3 * (int64_t)i + 2] - a2;
-                }
-                sym3_apply<T>(ci, a0, a1, a2, b0, b1, b2);
-            }
-            if (MODE == 2) {
-                dp[3 * (int64_t)i] = (double)b0;
-                dp[3 * (int64_t)i + 1] = (double)b1;
-                dp[3 * (int64_t)i + 2] = (double)b2;
-            } else {
-                shb[0][tid] = b0;
-                shb[1][tid] = b1;
-                shb[2][tid] = b2;
-            }
-        }
-        if (MODE == 2) return;
-        __syncthreads();
-        if (valid) {
-            int hd = tid;
-            while (hd > 0 && shpt[hd - 1] == i) --hd;
-            const T b0 = shb[0][hd], b1 = shb[1][hd], b2 = shb[2][hd];
-#pragma unroll
-            for (int a = 0; a < 9; ++a)
-                atomic_add_f64(cacc + 9 * (int64_t)j + a, (double)(h[a * 3] * b0 + h[a * 3 + 1] * b1 + h[a * 3 + 2] * b2));
+            sym3_apply<T>(cinv + 6 * (int64_t)i, (T)wpt[3 * (int64_t)i] - a0, (T)wpt[3 * (int64_t)i + 1] - a1,
+                          (T)wpt[3 * (int64_t)i + 2] - a2, b0, b1, b2);
+            dp[3 * (int64_t)i] = (double)b0;
+            dp[3 * (int64_t)i + 1] = (double)b1;
+            dp[3 * (int64_t)i + 2] = (double)b2;
         }
     } else {
         // one point with more than kTile observations
         const int32_t i = pt[s];
         T a0 = 0, a1 = 0, a2 = 0;
-        if (MODE != 1) {
-            for (int32_t base = s; base < e; base += kTile) {
-                const int64_t k = base + tid;
-                if (k < e) {
-                    const int32_t j = cam[k];
-#pragma unroll
-                    for (int b = 0; b < 3; ++b) {
-                        T acc = 0;
-#pragma unroll
-                        for (int a = 0; a < 9; ++a) acc += hcp[eidx(k, a * 3 + b)] * xcam[9 * (int64_t)j + a];
-                        if (b == 0) a0 += acc;
-                        if (b == 1) a1 += acc;
-                        if (b == 2) a2 += acc;
-                    }
-                }
-            }
-            sha[0][tid] = a0;
-            sha[1][tid] = a1;
-            sha[2][tid] = a2;
-            __syncthreads();
-            for (int stride = kTile / 2; stride > 0; stride >>= 1) {
-                if (tid < stride)
-                    for (int b = 0; b < 3; ++b) sha[b][tid] += sha[b][tid + stride];
-                __syncthreads();
-            }
-        }
-        if (tid == 0) {
-            const T* ci = cinv + 6 * (int64_t)i;
-            T b0, b1, b2;
-            if (MODE == 1) {
-                sym3_apply<T>(ci, (T)wpt[3 * (int64_t)i], (T)wpt[3 * (int64_t)i + 1], (T)wpt[3 * (int64_t)i + 2],
-                              b0, b1, b2);
-            } else if (MODE == 2) {
-                sym3_apply<T>(ci, (T)wpt[3 * (int64_t)i] - sha[0][0], (T)wpt[3 * (int64_t)i + 1] - sha[1][0],
-                              (T)wpt[3 * (int64_t)i + 2] - sha[2][0], b0, b1, b2);
-                dp[3 * (int64_t)i] = (double)b0;
-                dp[3 * (int64_t)i + 1] = (double)b1;
-                dp[3 * (int64_t)i + 2] = (double)b2;
-            } else {
-                sym3_apply<T>(ci, sha[0][0], sha[1][0], sha[2][0], b0, b1, b2);
-            }
-            shb[0][0] = b0;
-            shb[1][0] = b1;
-            shb[2][0] = b2;
-        }
-        if (MODE == 2) return;
-        __syncthreads();
-        const T b0 = shb[0][0], b1 = shb[1][0], b2 = shb[2][0];
         for (int32_t base = s; base < e; base += kTile) {
             const int64_t k = base + tid;
             if (k < e) {
                 const int32_t j = cam[k];
 #pragma unroll
-                for (int a = 0; a < 9; ++a)
-                    atomic_add_f64(cacc + 9 * (int64_t)j + a,
-                                   (double)(hcp[eidx(k, a * 3)] * b0 + hcp[eidx(k, a * 3 + 1)] * b1 +
-                                            hcp[eidx(k, a * 3 + 2)] * b2));
+                for (int b = 0; b < 3; ++b) {
+                    T acc = 0;
+#pragma unroll
+                    for (int a = 0; a < 9; ++a) acc += hcp[eidx(k, a * 3 + b)] * xcam[9 * (int64_t)j + a];
+                    if (b == 0) a0 += acc;
+                    if (b == 1) a1 += acc;
+                    if (b == 2) a2 += acc;
+                }
             }
+        }
+        sha[0][tid] = a0;
+        sha[1][tid] = a1;
+        sha[2][tid] = a2;
+        __syncthreads();
+        for (int stride = kTile / 2; stride > 0; stride >>= 1) {
+            if (tid < stride)
+                for (int b = 0; b < 3; ++b) sha[b][tid] += sha[b][tid + stride];
+            __syncthreads();
+        }
+        if (tid == 0) {
+            T b0, b1, b2;
+            sym3_apply<T>(cinv + 6 * (int64_t)i, (T)wpt[3 * (int64_t)i] - sha[0][0],
+                          (T)wpt[3 * (int64_t)i + 1] - sha[1][0], (T)wpt[3 * (int64_t)i + 2] - sha[2][0], b0, b1,
+                          b2);
+            dp[3 * (int64_t)i] = (double)b0;
+            dp[3 * (int64_t)i + 1] = (double)b1;
+            dp[3 * (int64_t)i + 2] = (double)b2;
         }
     }
 }
 
 template <typename T>
-hipError_t launch_schur_tiles(int mode, const PointMajor& pm, const int32_t* tile_list, int32_t count, int64_t N,
-                              const T* hcp, const T* cinv, const double* wpt, const T* xcam, double* cacc,
-                              double* dp, hipStream_t s)
+hipError_t launch_backsub_stored(const PointMajor& pm, const T* hcp, const T* cinv, const double* wpt,
+                                 const T* xcam, double* dp, hipStream_t s)
 {
-    if (!tile_list) count = pm.num_tiles;
-    if (count <= 0) return hipGetLastError();
-    const dim3 g(count), b(kTile);
-    if (mode == 0)
-        hipLaunchKernelGGL((k_schur_tiles<T, 0>), g, b, 0, s, pm.tile, tile_list, pm.cam, pm.pt, N, hcp, cinv, wpt,
-                           xcam, cacc, dp);
-    else if (mode == 1)
-        hipLaunchKernelGGL((k_schur_tiles<T, 1>), g, b, 0, s, pm.tile, tile_list, pm.cam, pm.pt, N, hcp, cinv, wpt,
-                           xcam, cacc, dp);
-    else
-        hipLaunchKernelGGL((k_schur_tiles<T, 2>), g, b, 0, s, pm.tile, tile_list, pm.cam, pm.pt, N, hcp, cinv, wpt,
-                           xcam, cacc, dp);
+    if (pm.num_tiles > 0)
+        hipLaunchKernelGGL((k_backsub_stored<T>), dim3(pm.num_tiles), dim3(kTile), 0, s, pm.tile, pm.cam, pm.pt, hcp,
+                           cinv, wpt, xcam, dp);
     return hipGetLastError();
 }
 
 template hipError_t launch_damp_points<double>(int32_t, const double*, double, int32_t, double*, int32_t*, hipStream_t);
 template hipError_t launch_damp_points<float>(int32_t, const double*, double, int32_t, float*, int32_t*, hipStream_t);
-template hipError_t launch_schur_tiles<double>(int, const PointMajor&, const int32_t*, int32_t, int64_t,
-                                               const double*, const double*, const double*, const double*, double*,
-                                               double*, hipStream_t);
-template hipError_t launch_schur_tiles<float>(int, const PointMajor&, const int32_t*, int32_t, int64_t, const float*,
-                                              const float*, const double*, const float*, double*, double*,
-                                              hipStream_t);
+template hipError_t launch_backsub_stored<double>(const PointMajor&, const double*, const double*, const double*,
+                                                  const double*, double*, hipStream_t);
+template hipError_t launch_backsub_stored<float>(const PointMajor&, const float*, const float*, const double*,
+                                                 const float*, double*, hipStream_t);
 
 }  // namespace ba
