@@ -553,6 +553,88 @@ void orc_schur_jacobi(int32_t m, int64_t N, const int32_t *oc, const int32_t *op
     }
 }
 
+/* The reduced camera system written out, dense [9m][9m] row-major (Eq.
+ * schur_x_c): S = blockdiag(B~_j) - sum over points i of E_a C~_i^-1 E_b^T for
+ * every ordered pair (a, b) of the point's observations, placed at the block
+ * of cameras (cam(a), cam(b)).  This is the matrix the direct option for small
+ * problems factors (Sec. 3, direct against iterative solvers). */
+int orc_schur_dense(int32_t m, int32_t n, int64_t N, const int32_t *oc, const int32_t *op,
+                    const double *Bd, const double *E, const double *Cinv, double *S)
+{
+    const int64_t nd = 9 * (int64_t)m;
+    memset(S, 0, sizeof(double) * (size_t)(nd * nd));
+    for (int64_t j = 0; j < m; ++j)
+        for (int a = 0; a < 9; ++a)
+            for (int b = 0; b < 9; ++b) S[(9 * j + a) * nd + 9 * j + b] = Bd[81 * j + a * 9 + b];
+    /* the observations of each point, in observation order */
+    int64_t *start = calloc((size_t)n + 1, sizeof(int64_t));
+    int64_t *list = malloc(sizeof(int64_t) * (size_t)(N > 0 ? N : 1));
+    int64_t *fill = malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!start || !list || !fill) {
+        free(start); free(list); free(fill);
+        return ORC_ENUMERIC;
+    }
+    for (int64_t k = 0; k < N; ++k) start[op[k] + 1]++;
+    for (int32_t i = 0; i < n; ++i) start[i + 1] += start[i];
+    for (int32_t i = 0; i < n; ++i) fill[i] = start[i];
+    for (int64_t k = 0; k < N; ++k) list[fill[op[k]]++] = k;
+    for (int32_t i = 0; i < n; ++i) {
+        const double *Ci = Cinv + 9 * (int64_t)i;
+        for (int64_t u = start[i]; u < start[i + 1]; ++u) {
+            const int64_t ka = list[u];
+            const double *Ea = E + 27 * ka;
+            double T[27]; /* E_a C~^-1 */
+            for (int a = 0; a < 9; ++a)
+                for (int c = 0; c < 3; ++c) {
+                    double t = 0.0;
+                    for (int d = 0; d < 3; ++d) t += Ea[a * 3 + d] * Ci[d * 3 + c];
+                    T[a * 3 + c] = t;
+                }
+            for (int64_t v = start[i]; v < start[i + 1]; ++v) {
+                const int64_t kb = list[v];
+                const double *Eb = E + 27 * kb;
+                double *blk = S + (9 * (int64_t)oc[ka]) * nd + 9 * (int64_t)oc[kb];
+                for (int a = 0; a < 9; ++a)
+                    for (int b = 0; b < 9; ++b) {
+                        double t = 0.0;
+                        for (int c = 0; c < 3; ++c) t += T[a * 3 + c] * Eb[b * 3 + c];
+                        blk[a * nd + b] -= t;
+                    }
+            }
+        }
+    }
+    free(start); free(list); free(fill);
+    return ORC_OK;
+}
+
+/* x = A^-1 b for a dense symmetric positive definite A [nd][nd] (row-major)
+ * by its Cholesky factor and two triangular solves; ORC_ENUMERIC when A is
+ * not positive definite. */
+int orc_dense_solve(int64_t nd, const double *A, const double *b, double *x)
+{
+    double *L = malloc(sizeof(double) * (size_t)(nd * nd > 0 ? nd * nd : 1));
+    double *y = malloc(sizeof(double) * (size_t)(nd > 0 ? nd : 1));
+    if (!L || !y) {
+        free(L); free(y);
+        return ORC_ENUMERIC;
+    }
+    int status = cholesky(A, (int)nd, L) ? ORC_ENUMERIC : ORC_OK;
+    if (status == ORC_OK) {
+        for (int64_t r = 0; r < nd; ++r) {
+            double t = b[r];
+            for (int64_t c = 0; c < r; ++c) t -= L[r * nd + c] * y[c];
+            y[r] = t / L[r * nd + r];
+        }
+        for (int64_t r = nd - 1; r >= 0; --r) {
+            double t = y[r];
+            for (int64_t c = r + 1; c < nd; ++c) t -= L[c * nd + r] * x[c];
+            x[r] = t / L[r * nd + r];
+        }
+    }
+    free(L); free(y);
+    return status;
+}
+
 /* PCG of Alg. 2 with the preconditioner blocks Mblk (Bd for Alg. 2 itself). */
 int orc_pcg_m(int32_t m, int32_t n, int64_t N, const int32_t *oc, const int32_t *op,
               const double *Bd, const double *E, const double *Cinv, const double *Mblk,
@@ -688,10 +770,20 @@ int orc_lm_solve(int32_t m, int32_t n, int64_t N, double *cams, double *pts,
         orc_reduced_rhs(m, n, N, oc, op, v, w, E, Ci, g, wb);
         int32_t fixed = opt->pcg_schedule ? opt->pcg_schedule[it] : 0;
         int32_t npcg = 0;
-        if (opt->preconditioner == 1) orc_schur_jacobi(m, N, oc, op, Bd, E, Ci, Mj);
-        /* a breakdown leaves dc at the last iterate, which is still a step */
-        int pst = orc_pcg_m(m, n, N, oc, op, Bd, E, Ci, opt->preconditioner == 1 ? Mj : Bd, g, opt->pcg_rtol,
+        int pst;
+        if (opt->solver == 1) {
+            /* the reduced camera system written out and factored */
+            const int64_t nd = 9 * (int64_t)m;
+            double *S = malloc(sizeof(double) * (size_t)(nd * nd));
+            pst = S ? orc_schur_dense(m, n, N, oc, op, Bd, E, Ci, S) : ORC_ENUMERIC;
+            if (pst == ORC_OK) pst = orc_dense_solve(nd, S, g, dc);
+            free(S);
+        } else {
+            if (opt->preconditioner == 1) orc_schur_jacobi(m, N, oc, op, Bd, E, Ci, Mj);
+            /* a breakdown leaves dc at the last iterate, which is still a step */
+            pst = orc_pcg_m(m, n, N, oc, op, Bd, E, Ci, opt->preconditioner == 1 ? Mj : Bd, g, opt->pcg_rtol,
                             opt->max_pcg_iters, fixed, dc, &npcg);
+        }
         if (pst != ORC_OK && pst != ORC_BREAKDOWN) {
             trace->pcg_iters[it] = npcg;
             status = ORC_ENUMERIC;

@@ -35,6 +35,8 @@ typedef struct {
     double lambda_init;
     double min_relative_decrease;
     int32_t preconditioner;    /* 0: damped camera blocks B~_j (Alg. 2); 1: Schur-Jacobi */
+    int32_t solver;            /* 0: PCG (Alg. 2); 1: the reduced camera system written out
+                                  and factored (the direct option for small problems) */
 } orc_options;
 
 typedef struct {               /* caller-owned arrays of length max_lm_iters */
@@ -91,6 +93,9 @@ void orc_back_substitute(int32_t n, int64_t N, const int32_t *oc, const int32_t 
                          const double *E, const double *Cinv, const double *w,
                          const double *dc, double *dp);
 
+int orc_schur_dense(int32_t m, int32_t n, int64_t N, const int32_t *oc, const int32_t *op,
+                    const double *Bd, const double *E, const double *Cinv, double *S);
+int orc_dense_solve(int64_t nd, const double *A, const double *b, double *x);
 int orc_lm_solve(int32_t m, int32_t n, int64_t N, double *cams, double *pts,
                  const int32_t *oc, const int32_t *op, const double *uv,
                  const orc_options *opt, orc_trace *trace);

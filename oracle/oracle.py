@@ -33,7 +33,7 @@ class Options(C.Structure):
                 ("max_lm_iters", C.c_int32), ("max_pcg_iters", C.c_int32),
                 ("pcg_rtol", C.c_double), ("pcg_schedule", C.c_void_p),
                 ("lambda_init", C.c_double), ("min_relative_decrease", C.c_double),
-                ("preconditioner", C.c_int32)]
+                ("preconditioner", C.c_int32), ("solver", C.c_int32)]
 
 
 class Trace(C.Structure):
@@ -96,6 +96,9 @@ def lib():
                                     C.c_double, C.c_int32, _i64p, _i64p, _i64p, _i64p, _f64p,
                                     _f64p]
         L.orc_schur_row.restype = C.c_double
+        L.orc_schur_dense.argtypes = [C.c_int32, C.c_int32, C.c_int64, _i32p, _i32p, _f64p, _f64p,
+                                      _f64p, _f64p]
+        L.orc_dense_solve.argtypes = [C.c_int64, _f64p, _f64p, _f64p]
         _lib = L
     return _lib
 
@@ -221,11 +224,32 @@ def back_substitute(oc, op, E, Ci, w, dc):
     return dp
 
 
+def schur_dense(oc, op, Bd, E, Ci):
+    """The reduced camera system written out: dense [9m][9m] S."""
+    m, n, N = len(Bd), len(Ci), len(oc)
+    S = np.zeros((9 * m, 9 * m))
+    rc = lib().orc_schur_dense(m, n, N, _i(oc), _i(op), _f(Bd), _f(E), _f(Ci), S)
+    if rc:
+        raise MemoryError("orc_schur_dense")
+    return S
+
+
+def dense_solve(A, b):
+    """A^-1 b through the Cholesky factor of a dense SPD A."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    x = np.zeros(len(A))
+    rc = lib().orc_dense_solve(len(A), A, _f(b), x)
+    if rc:
+        raise FloatingPointError("matrix not positive definite")
+    return x
+
+
 def lm_solve(cams, pts, oc, op, uv, huber_delta=0.0, damping=0, max_lm_iters=10,
              max_pcg_iters=50, pcg_rtol=1e-8, pcg_schedule=None, lambda_init=1e-4,
-             min_relative_decrease=1e-3, preconditioner=0):
+             min_relative_decrease=1e-3, preconditioner=0, solver=0):
     """Runs the LM loop; returns (cams, pts, trace dict, status).  preconditioner:
-    0 = the damped camera blocks (Alg. 2), 1 = Schur-Jacobi blocks."""
+    0 = the damped camera blocks (Alg. 2), 1 = Schur-Jacobi blocks; solver: 0 =
+    PCG, 1 = the reduced camera system written out and factored."""
     cams = np.array(cams, dtype=np.float64, order="C", copy=True)
     pts = np.array(pts, dtype=np.float64, order="C", copy=True)
     K = int(max_lm_iters)
@@ -235,7 +259,7 @@ def lm_solve(cams, pts, oc, op, uv, huber_delta=0.0, damping=0, max_lm_iters=10,
         assert len(sched) >= K
     opt = Options(float(huber_delta), int(damping), K, int(max_pcg_iters), float(pcg_rtol),
                   sched.ctypes.data if sched is not None else None, float(lambda_init),
-                  float(min_relative_decrease), int(preconditioner))
+                  float(min_relative_decrease), int(preconditioner), int(solver))
     arrs = dict(cost=np.zeros(K), trial_cost=np.zeros(K), lambda_=np.zeros(K), pred=np.zeros(K),
                 pcg_iters=np.zeros(K, np.int32), accepted=np.zeros(K, np.int32))
     tr = Trace(0, 0.0, 0.0, *(arrs[k].ctypes.data for k in

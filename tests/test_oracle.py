@@ -16,7 +16,7 @@ import scipy.linalg
 import scipy.sparse.linalg
 from scipy.spatial.transform import Rotation
 
-from helpers import small_zipf
+from helpers import small_zipf, with_edge_cases
 from oracle import oracle as orc
 from paper_2112_01349_amd import synth
 
@@ -522,3 +522,60 @@ def test_schur_jacobi_needs_fewer_iterations(tiny):
     ref = scipy.linalg.cho_solve(scipy.linalg.cho_factor(S), b.ravel())
     for x in (x1, x2):
         assert np.abs(x.ravel() - ref).max() <= 1e-6 * np.abs(ref).max()
+
+
+# ------------------------------------------------- the direct option (dense S)
+@pytest.mark.parametrize("lam", [1e-4, 1e-1])
+def test_schur_dense_is_explicit_s(tiny, lam):
+    """The written-out reduced camera system equals the explicit dense
+    S = B~ - E C~^-1 E^T built from dense block matrices in numpy."""
+    A, Bd, Cd, Dc, Dp, Ci = damped_problem(tiny, lam=lam)
+    S_ref, _ = explicit_schur(tiny, A, Bd, Ci)
+    S = orc.schur_dense(tiny.obs_camera, tiny.obs_point, Bd, A["E"], Ci)
+    np.testing.assert_allclose(S, S_ref, rtol=0, atol=1e-12 * np.abs(S_ref).max())
+
+
+def test_schur_dense_with_repeated_pairs():
+    """A duplicated (camera, point) pair adds its blocks, so the dense S still
+    equals the explicit one (edge-case problem with a repeated pair and a
+    point longer than a tile)."""
+    cams, pts, oc, op, uv, _ = with_edge_cases(small_zipf(seed=5, m=9, n=60, N=300))
+    A = orc.assemble(cams, pts, oc, op, uv, 1.0)
+    Bd, Cd, _, _ = orc.damp(A["B"], A["C"], 1e-3, 0)
+    Ci = orc.invert_points(Cd)
+    m, n = len(cams), len(pts)
+    Ed = np.zeros((9 * m, 3 * n))
+    for k in range(len(oc)):
+        Ed[9 * oc[k]:9 * oc[k] + 9, 3 * op[k]:3 * op[k] + 3] += A["E"][k]
+    Cid = np.zeros((3 * n, 3 * n))
+    for i in range(n):
+        Cid[3 * i:3 * i + 3, 3 * i:3 * i + 3] = Ci[i]
+    Bdd = np.zeros((9 * m, 9 * m))
+    for j in range(m):
+        Bdd[9 * j:9 * j + 9, 9 * j:9 * j + 9] = Bd[j]
+    S_ref = Bdd - Ed @ Cid @ Ed.T
+    S = orc.schur_dense(oc, op, Bd, A["E"], Ci)
+    np.testing.assert_allclose(S, S_ref, rtol=0, atol=1e-12 * np.abs(S_ref).max())
+
+
+def test_dense_solve_matches_numpy_and_rejects_indefinite():
+    rng = np.random.default_rng(4)
+    G = rng.normal(size=(40, 40))
+    A = G @ G.T + 0.1 * np.eye(40)
+    b = rng.normal(size=40)
+    np.testing.assert_allclose(orc.dense_solve(A, b), np.linalg.solve(A, b), rtol=1e-10, atol=1e-12)
+    A[5, 5] = -1.0
+    with pytest.raises(FloatingPointError):
+        orc.dense_solve(A, b)
+
+
+def test_lm_dense_solver_matches_converged_pcg(tiny):
+    """With the reduced system factored, every LM step is PCG's limit: the
+    trace equals that of PCG run to convergence (rtol 1e-15)."""
+    args = (tiny.cameras0, tiny.points0, tiny.obs_camera, tiny.obs_point, tiny.obs_uv)
+    _, _, tr_d, rc_d = orc.lm_solve(*args, huber_delta=1.0, max_lm_iters=6, solver=1)
+    _, _, tr_p, rc_p = orc.lm_solve(*args, huber_delta=1.0, max_lm_iters=6, max_pcg_iters=5000, pcg_rtol=1e-15)
+    assert rc_d == 0 and rc_p == 0
+    assert list(tr_d["pcg_iters"]) == [0] * 6
+    np.testing.assert_allclose(tr_d["trial_cost"], tr_p["trial_cost"], rtol=1e-10)
+    assert list(tr_d["accepted"]) == list(tr_p["accepted"])
