@@ -46,7 +46,8 @@ typedef enum {
     BA_EINVAL = 1,   /* bad count, index out of range, non-finite input, bad option */
     BA_ENOMEM = 2,   /* device workspace does not fit */
     BA_EDEVICE = 3,  /* HIP runtime error (message in ba_last_error) */
-    BA_ENUMERIC = 4  /* a damped block that is not positive definite */
+    BA_ENUMERIC = 4  /* a damped block (or, with BA_SOLVER_DENSE, the damped reduced
+                        camera system) that is not positive definite */
 } ba_status;
 
 typedef enum {
@@ -71,6 +72,16 @@ typedef enum {
                                  (the paper's "-a" variant, Sec. 5 JetVector) */
 } ba_jacobian;
 
+typedef enum {
+    BA_SOLVER_PCG = 0,   /* block-Jacobi PCG on implicit Schur products (Alg. 2 and 3) */
+    BA_SOLVER_DENSE = 1  /* the reduced camera system (Eq. schur_x_c) written out as a dense
+                            FP64 [9m][9m] matrix and solved through its Cholesky factor, the
+                            direct route of Sec. 3, for m <= BA_DENSE_MAX_CAMERAS; needs
+                            (9m)^2 * 8 bytes more device memory, allocated at ba_create */
+} ba_solver;
+
+#define BA_DENSE_MAX_CAMERAS 2048
+
 typedef struct {
     uint32_t struct_size;          /* sizeof(ba_options) */
     int32_t precision;             /* ba_precision; fixed at ba_create */
@@ -86,7 +97,10 @@ typedef struct {
     double lambda_init;            /* initial LM damping, default 1e-4 */
     double min_relative_decrease;  /* accept a step iff gain ratio > this, default 1e-3 */
     int32_t time_kernels;          /* != 0: time every Schur matvec with HIP events */
-    int32_t reserved1;
+    int32_t solver;                /* ba_solver; fixed at ba_create.  With BA_SOLVER_DENSE
+                                      the PCG fields are ignored and pcg_iters reports 0;
+                                      a reduced system that is not positive definite
+                                      ends the solve with BA_ENUMERIC */
 } ba_options;
 
 typedef struct {
@@ -127,7 +141,8 @@ ba_status ba_options_default(ba_options *opt);
  * the whole workspace here (the paper's memory pool, Sec. 5.2); later calls
  * allocate nothing.  Duplicate (camera, point) pairs are allowed (their terms
  * add); points with fewer than two observations and cameras with none are
- * allowed.  Errors: BA_EINVAL (handle not created), BA_ENOMEM, BA_EDEVICE. */
+ * allowed.  Errors: BA_EINVAL (handle not created; also for BA_SOLVER_DENSE
+ * with m > BA_DENSE_MAX_CAMERAS), BA_ENOMEM, BA_EDEVICE. */
 ba_status ba_create(int32_t num_cameras, int32_t num_points, int64_t num_obs,
                     const double *cameras, const double *points,
                     const int32_t *obs_camera, const int32_t *obs_point,
@@ -148,8 +163,8 @@ ba_status ba_eval_cost_grad(ba_problem *prob, double *cost, double *grad_cameras
 
 /* Runs the LM loop from the current state (Alg. 1 with one partition inside
  * the trust-region wrapper) and leaves the last accepted state in the handle.
- * opt: NULL = the create-time options; opt->precision must equal the
- * create-time precision.  rep: nullable.  A PCG breakdown (p^T q <= 0 or
+ * opt: NULL = the create-time options; opt->precision and opt->solver must
+ * equal the create-time values.  rep: nullable.  A PCG breakdown (p^T q <= 0 or
  * non-finite, possible in the FP32 products near a gauge direction once
  * lambda is small) ends that PCG run with its last iterate as the step
  * (truncated CG) and the loop goes on.  BA_ENUMERIC stops the loop and keeps

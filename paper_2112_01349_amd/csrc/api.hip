@@ -81,6 +81,9 @@ struct ba_problem {
     double *partials = nullptr, *sums = nullptr;
     PcgScalars* sc = nullptr;
     int32_t* flag = nullptr;
+    // direct option: S [9m][9m] FP64 factored in place, a solve buffer, row pairs
+    double *S = nullptr, *ybuf = nullptr;
+    DensePlan dense{};
     // pinned host scratch
     double* h_scalars = nullptr;
     bool is_f32() const { return opt.precision == BA_FP32_MIXED; }
@@ -153,6 +156,10 @@ static ba_status check_options(const ba_options* o, std::string& msg)
         msg = "unknown jacobian";
         return BA_EINVAL;
     }
+    if (o->solver != BA_SOLVER_PCG && o->solver != BA_SOLVER_DENSE) {
+        msg = "unknown solver";
+        return BA_EINVAL;
+    }
     if (o->max_lm_iters < 0 || o->max_pcg_iters < 0 || o->pcg_fixed_iters < 0 || !std::isfinite(o->pcg_rtol) ||
         !(o->lambda_init > 0.0) || !std::isfinite(o->lambda_init) || !std::isfinite(o->min_relative_decrease) ||
         !std::isfinite(o->huber_delta)) {
@@ -187,6 +194,7 @@ ba_status ba_options_default(ba_options* opt)
     opt->min_relative_decrease = 1e-3;
     opt->time_kernels = 0;
     opt->jacobian = BA_JACOBIAN_ANALYTIC;
+    opt->solver = BA_SOLVER_PCG;
     return BA_OK;
 }
 
@@ -292,6 +300,10 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     }
     if (m < 1 || n < 0 || N < 0 || N >= ((int64_t)1 << 31)) {
         g_create_error = "invalid counts";
+        return BA_EINVAL;
+    }
+    if (opt.solver == BA_SOLVER_DENSE && m > BA_DENSE_MAX_CAMERAS) {
+        g_create_error = "the dense solver takes at most " + std::to_string(BA_DENSE_MAX_CAMERAS) + " cameras";
         return BA_EINVAL;
     }
     if (!cameras || (n > 0 && !points) || (N > 0 && (!obs_camera || !obs_point || !obs_uv))) {
@@ -505,6 +517,17 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
         split(sseg, frange);
         split(lseg, lrange);
     }
+    // direct option: the row pairs whose observations share points (a short
+    // segment with itself; every pair of the 64-observation rows of a long point)
+    std::vector<int4> dense_rows;
+    if (opt.solver == BA_SOLVER_DENSE) {
+        for (const int2& g : sseg) dense_rows.push_back(make_int4(g.x, g.y - g.x, g.x, g.y - g.x));
+        for (const int2& g : lseg)
+            for (int32_t a = g.x; a < g.y; a += 64)
+                for (int32_t b = g.x; b < g.y; b += 64)
+                    dense_rows.push_back(make_int4(a, std::min(64, g.y - a), b, std::min(64, g.y - b)));
+        P->dense.num_rows = (int32_t)dense_rows.size();
+    }
     // the build: 32 wavefronts per CU over the same tiles
     // cold stream: observations on cameras >= K, camera-major
     std::vector<int32_t> h_cold_cam, h_cold_pt;
@@ -591,6 +614,11 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     P->sums = A.get<double>(8);
     P->sc = A.get<PcgScalars>(1);
     P->flag = A.get<int32_t>(4);  // [failure bits, a failing camera, a failing point, unused]
+    if (opt.solver == BA_SOLVER_DENSE) {
+        P->S = A.get<double>(81 * (int64_t)m * m);
+        P->ybuf = A.get<double>(9 * (int64_t)m);
+        P->dense.rows = A.get<int4>(std::max<int64_t>(1, (int64_t)dense_rows.size()));
+    }
     if (A.err != hipSuccess) {
         g_create_error = std::string("device allocation failed: ") + hipGetErrorString(A.err);
         const bool oom = A.err == hipErrorOutOfMemory || A.err == hipErrorMemoryAllocation;
@@ -635,6 +663,8 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     if (e == hipSuccess && !lseg.empty()) e = up(sp.lseg, lseg.data(), sizeof(int2) * lseg.size());
     if (e == hipSuccess) e = up(sp.frange, frange.data(), sizeof(int32_t) * frange.size());
     if (e == hipSuccess) e = up(sp.lrange, lrange.data(), sizeof(int32_t) * lrange.size());
+    if (e == hipSuccess && !dense_rows.empty())
+        e = up(P->dense.rows, dense_rows.data(), sizeof(int4) * dense_rows.size());
     if (e == hipSuccess) e = hipMemset(P->wobs, 0, (size_t)P->pm.ld * tsz);
     if (e == hipSuccess) e = hipMemset(P->xf, 0, 12 * (size_t)m * tsz);
     if (e == hipSuccess) e = up(sp.has_cold, has_cold.data(), (size_t)n);
@@ -836,6 +866,32 @@ static ba_status run_pcg(ba_problem* P, const ba_options& o, int32_t fixed, int3
     return BA_OK;
 }
 
+// The direct option: g = v - E C~^-1 w by the same product as PCG's right-hand
+// side, then dc = x = S^-1 g with S written out and factored.  A reduced system
+// that is not positive definite ends the solve (BA_ENUMERIC).
+template <typename T>
+static ba_status run_dense(ba_problem* P, double lambda)
+{
+    hipStream_t s = P->stream;
+    const RecomputeInputs<T> ri = recompute_inputs<T>(P);
+    BA_TRY(P, launch_pcg_reset(P->sc, 0.0, 0, 0, s));
+    BA_TRY(P, launch_schur_product<T>(1, P->sp, P->pm, P->N, (const T*)P->hcp, (const T*)P->cinv, P->wpt, nullptr,
+                                      &ri, P->m, P->bd, nullptr, P->vcam, P->g, P->x, P->r, P->partials, P->sc,
+                                      nullptr, nullptr, s));
+    BA_TRY(P, launch_dense_solve<T>(P->dense, P->pm, ri, (const T*)P->cinv, P->m, P->bd, P->g, P->x, P->S, P->ybuf,
+                                    P->flag, s));
+    BA_TRY(P, hipMemcpyAsync(P->h_scalars, P->flag, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    BA_TRY(P, hipStreamSynchronize(s));
+    if (*(const int32_t*)P->h_scalars & 4) {
+        char buf[128];
+        std::snprintf(buf, sizeof buf, "damped reduced camera system not positive definite at lambda %.3e", lambda);
+        P->last_error = buf;
+        BA_TRY(P, hipMemsetAsync(P->flag, 0, 4 * sizeof(int32_t), s));
+        return BA_ENUMERIC;
+    }
+    return BA_OK;
+}
+
 template <typename T>
 static ba_status lm_solve_t(ba_problem* P, const ba_options& o, ba_report* rep)
 {
@@ -869,7 +925,7 @@ static ba_status lm_solve_t(ba_problem* P, const ba_options& o, ba_report* rep)
         BA_TRY(P, launch_damp_points<T>(n, (const double*)P->hpp, lambda, o.damping, (T*)P->cinv, P->flag, s));
         BA_TRY(P, hipMemcpyAsync(P->h_scalars, P->flag, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         BA_TRY(P, hipStreamSynchronize(s));
-        if (const int32_t bad = *(int32_t*)P->h_scalars) {
+        if (*(const int32_t*)P->h_scalars != 0) {
             P->last_error = not_pd_message(P, (const int32_t*)P->h_scalars, lambda);
             BA_TRY(P, hipMemsetAsync(P->flag, 0, 4 * sizeof(int32_t), s));
             result = BA_ENUMERIC;
@@ -878,7 +934,10 @@ static ba_status lm_solve_t(ba_problem* P, const ba_options& o, ba_report* rep)
         const int32_t fixed = o.pcg_schedule ? o.pcg_schedule[it] : o.pcg_fixed_iters;
         int32_t npcg = 0;
         const auto t_pcg = clock::now();
-        st = run_pcg<T>(P, o, fixed, &npcg, o.time_kernels ? &timer : nullptr, &matvec_ms, &hot_ms, &launches);
+        if (P->opt.solver == BA_SOLVER_DENSE)
+            st = run_dense<T>(P, lambda);
+        else
+            st = run_pcg<T>(P, o, fixed, &npcg, o.time_kernels ? &timer : nullptr, &matvec_ms, &hot_ms, &launches);
         pcg_ms += std::chrono::duration<double, std::milli>(clock::now() - t_pcg).count();
         pcg_total += npcg;
         if (st != BA_OK) {
@@ -964,6 +1023,10 @@ extern "C" ba_status ba_lm_solve(ba_problem* P, const ba_options* opt, ba_report
     }
     if (o.precision != P->opt.precision) {
         P->last_error = "precision differs from the create-time precision";
+        return BA_EINVAL;
+    }
+    if (o.solver != P->opt.solver) {
+        P->last_error = "solver differs from the create-time solver";
         return BA_EINVAL;
     }
     if (rep && rep->capacity < 0) {
@@ -1092,7 +1155,7 @@ static ba_status schur_matvec_t(ba_problem* P, double lambda, int32_t damping, c
     BA_TRY(P, hipMemcpyAsync(qi.data(), P->q, qi.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     BA_TRY(P, hipMemcpyAsync(P->h_scalars, P->flag, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     BA_TRY(P, hipStreamSynchronize(s));
-    if (const int32_t bad = *(int32_t*)P->h_scalars) {
+    if (*(const int32_t*)P->h_scalars != 0) {
         P->last_error = not_pd_message(P, (const int32_t*)P->h_scalars, lambda);
         BA_TRY(P, hipMemset(P->flag, 0, 4 * sizeof(int32_t)));
         return BA_ENUMERIC;

@@ -187,6 +187,22 @@ template <typename T>
 hipError_t launch_damp_points(int32_t n, const double* hpp, double lambda, int32_t damping, T* cinv,
                               int32_t* flag, hipStream_t s);
 
+// The direct option: pairs of observation rows (64 observations each) whose
+// points meet, {start of row a, its length, start of row b, its length}, for
+// forming the dense reduced camera system.
+struct DensePlan {
+    int32_t num_rows = 0;
+    int4* rows = nullptr;
+};
+
+// x = S^-1 g for the reduced camera system written out (S [9m][9m] FP64,
+// factored in place; ybuf [9m] scratch); flag bit 2 when S is not positive
+// definite.
+template <typename T>
+hipError_t launch_dense_solve(const DensePlan& dp, const PointMajor& pm, const RecomputeInputs<T>& ri,
+                              const T* cinv, int32_t m, const double* bd, const double* g, double* x, double* S,
+                              double* ybuf, int32_t* flag, hipStream_t s);
+
 // Back-substitution from the stored blocks (BA_SCHUR_STORED=1):
 // dp = C~^-1 (w - E^T x), x in T (xcam).
 template <typename T>

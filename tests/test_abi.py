@@ -86,6 +86,16 @@ def test_invalid_inputs_are_rejected_on_the_host(native):
     o.jacobian = 2
     st, h = _create(native, cams, pts, oc, op, uv, C.byref(o))
     assert st == native.BA_EINVAL and b"jacobian" in native.lib().ba_last_error(None)
+    native.lib().ba_options_default(C.byref(o))
+    assert o.solver == native.SOLVER_PCG
+    o.solver = 2
+    st, h = _create(native, cams, pts, oc, op, uv, C.byref(o))
+    assert st == native.BA_EINVAL and b"solver" in native.lib().ba_last_error(None)
+    # the dense reduced system is limited to BA_DENSE_MAX_CAMERAS cameras
+    o.solver = native.SOLVER_DENSE
+    many = np.tile(cams[:1], (native.DENSE_MAX_CAMERAS + 1, 1))
+    st, h = _create(native, many, pts, oc, op, uv, C.byref(o))
+    assert st == native.BA_EINVAL and b"at most 2048 cameras" in native.lib().ba_last_error(None)
     assert native.lib().ba_status_str(4) == b"BA_ENUMERIC"
 
 

@@ -13,6 +13,7 @@ import pytest
 from helpers import rel_err, small_zipf, with_edge_cases
 from oracle import oracle as orc
 from paper_2112_01349_amd import FP32_MIXED, FP64, Problem, synth
+from paper_2112_01349_amd.native import SOLVER_DENSE
 
 pytestmark = pytest.mark.gpu
 
@@ -354,3 +355,69 @@ def test_mixed_point_at_camera_centre():
         assert rep["status"] == 0, (precision, rep["error"])
         assert np.all(np.diff(np.concatenate([[rep["initial_cost"]], rep["cost"]])) <= 0)
         gpu.close()
+
+
+def dense_pair(arrays, delta=0.0, iters=6, precision=FP64):
+    """The oracle's LM trace with the reduced camera system written out and
+    factored, beside the library's direct option on the same problem."""
+    cams, pts, oc, op, uv = arrays[:5]
+    _, _, tr, rc = orc.lm_solve(cams, pts, oc, op, uv, huber_delta=delta, max_lm_iters=iters, solver=1)
+    assert rc == 0
+    prob, _ = make(arrays[:5], precision=precision, huber_delta=delta, solver=SOLVER_DENSE)
+    gpu = prob.lm_solve(max_lm_iters=iters)
+    return tr, gpu, prob
+
+
+def test_dense_solver_trace_tiny(tiny):
+    """Direct option on the tiny problem: 9m = 144 rows, two full tiles of
+    the factorisation and a ragged one."""
+    arrays = (tiny.cameras0, tiny.points0, tiny.obs_camera, tiny.obs_point, tiny.obs_uv)
+    tr, gpu, prob = dense_pair(arrays, iters=10)
+    assert np.all(gpu["pcg_iters"] == 0)
+    assert_traces_match(tr, gpu)
+    co, po = orc.lm_solve(*arrays, max_lm_iters=10, solver=1)[:2]
+    c, p = prob.get_params()
+    assert rel_err(c, co) <= 1e-6 and rel_err(p, po) <= 1e-6
+
+
+@pytest.mark.parametrize("stored", [0, 1])
+def test_dense_solver_trace_edge_cases(stored, monkeypatch):
+    """Huber loss, an unseen camera, single-view points, a duplicated pair
+    and a point of 300 views (whose Schur terms span 5 x 5 row pairs), for
+    either right-hand-side product."""
+    monkeypatch.setenv("BA_SCHUR_STORED", str(stored))
+    arrays = with_edge_cases(small_zipf(seed=13, m=14, n=300, N=1500))
+    tr, gpu, _ = dense_pair(arrays, delta=1.0, iters=6)
+    assert_traces_match(tr, gpu)
+
+
+def test_dense_solver_trace_many_tiles():
+    """150 cameras: 9m = 1350 rows, 21 full 64-row tiles and a ragged one,
+    so every step of the tiled factorisation runs many times."""
+    arrays = small_zipf(seed=5, m=150, n=2500, N=15000)
+    arrays = (arrays.cameras0, arrays.points0, arrays.obs_camera, arrays.obs_point, arrays.obs_uv)
+    tr, gpu, _ = dense_pair(arrays, delta=1.0, iters=4)
+    assert_traces_match(tr, gpu)
+
+
+def test_dense_solver_mixed_reaches_oracle_cost(tiny):
+    arrays = (tiny.cameras0, tiny.points0, tiny.obs_camera, tiny.obs_point, tiny.obs_uv)
+    tr, gpu, _ = dense_pair(arrays, iters=10, precision=FP32_MIXED)
+    assert gpu["status"] == 0, gpu["error"]
+    assert np.all(np.diff(np.concatenate([[gpu["initial_cost"]], gpu["cost"]])) <= 0)
+    assert gpu["final_cost"] <= tr["final_cost"] * (1 + 1e-4)
+
+
+def test_dense_solver_matches_converged_pcg(tiny):
+    """The direct step is the limit of PCG: with a tight tolerance and
+    enough iterations the two options follow the same LM path."""
+    arrays = (tiny.cameras0, tiny.points0, tiny.obs_camera, tiny.obs_point, tiny.obs_uv)
+    dense, _ = make(arrays, solver=SOLVER_DENSE)
+    pcg, _ = make(arrays)
+    a = dense.lm_solve(max_lm_iters=5)
+    b = pcg.lm_solve(max_lm_iters=5, max_pcg_iters=500, pcg_rtol=1e-14)
+    assert a["status"] == 0 and b["status"] == 0
+    np.testing.assert_array_equal(a["accepted"], b["accepted"])
+    np.testing.assert_allclose(a["cost"], b["cost"], rtol=1e-8)
+    with pytest.raises(Exception, match="solver differs"):
+        dense.lm_solve(max_lm_iters=1, solver=0)
