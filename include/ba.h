@@ -82,6 +82,14 @@ typedef enum {
 
 #define BA_DENSE_MAX_CAMERAS 2048
 
+typedef enum {
+    BA_PRECOND_CAMERA_BLOCKS = 0, /* M_j = B~_j, the damped camera blocks (Alg. 2) */
+    BA_PRECOND_SCHUR_JACOBI = 1   /* M_j = B~_j - sum_{k in obs(j)} E_k C~^-1 E_k^T: the block
+                                     diagonal of the reduced system (Eq. schur_x_c), summed
+                                     per observation (a repeated (camera, point) pair adds no
+                                     cross term); formed once per LM iteration */
+} ba_preconditioner;
+
 typedef struct {
     uint32_t struct_size;          /* sizeof(ba_options) */
     int32_t precision;             /* ba_precision; fixed at ba_create */
@@ -101,6 +109,7 @@ typedef struct {
                                       the PCG fields are ignored and pcg_iters reports 0;
                                       a reduced system that is not positive definite
                                       ends the solve with BA_ENUMERIC */
+    int32_t preconditioner;        /* ba_preconditioner of PCG; may change between solves */
 } ba_options;
 
 typedef struct {

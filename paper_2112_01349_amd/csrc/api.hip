@@ -72,6 +72,7 @@ struct ba_problem {
     void* cinv = nullptr;  // [n][6] of T
     double* wpt = nullptr; // [n][3]
     double *hcc = nullptr, *vcam = nullptr, *bd = nullptr, *lfac = nullptr, *dcam = nullptr;
+    double* mj = nullptr;  // [m][81]: Schur-Jacobi terms (preconditioner option)
     // PCG
     double *g = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *cacc = nullptr;
     void* pT = nullptr;
@@ -102,11 +103,12 @@ struct ba_problem {
 // bit 0 of flag[0] is set by the camera blocks, bit 1 by the point blocks;
 // flag[1] and flag[2] name one failing camera and point, whose undamped block
 // diagonal is quoted.
-static std::string not_pd_message(ba_problem* P, const int32_t* flag, double lambda)
+static std::string not_pd_message(ba_problem* P, const int32_t* flag, double lambda, bool schur_jacobi = false)
 {
     char buf[256];
     std::string msg = "damped";
     if (flag[0] & 1) {
+        if (schur_jacobi) msg += " Schur-Jacobi";
         double d[81] = {0};
         const int32_t j = flag[1];
         if (j >= 0 && j < P->m && hipMemcpy(d, P->hcc + 81 * (int64_t)j, sizeof d, hipMemcpyDeviceToHost) == hipSuccess)
@@ -160,6 +162,10 @@ static ba_status check_options(const ba_options* o, std::string& msg)
         msg = "unknown solver";
         return BA_EINVAL;
     }
+    if (o->preconditioner != BA_PRECOND_CAMERA_BLOCKS && o->preconditioner != BA_PRECOND_SCHUR_JACOBI) {
+        msg = "unknown preconditioner";
+        return BA_EINVAL;
+    }
     if (o->max_lm_iters < 0 || o->max_pcg_iters < 0 || o->pcg_fixed_iters < 0 || !std::isfinite(o->pcg_rtol) ||
         !(o->lambda_init > 0.0) || !std::isfinite(o->lambda_init) || !std::isfinite(o->min_relative_decrease) ||
         !std::isfinite(o->huber_delta)) {
@@ -195,6 +201,7 @@ ba_status ba_options_default(ba_options* opt)
     opt->time_kernels = 0;
     opt->jacobian = BA_JACOBIAN_ANALYTIC;
     opt->solver = BA_SOLVER_PCG;
+    opt->preconditioner = BA_PRECOND_CAMERA_BLOCKS;
     return BA_OK;
 }
 
@@ -588,6 +595,7 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     P->vcam = A.get<double>(9 * (int64_t)m);
     P->bd = A.get<double>(81 * (int64_t)m);
     P->lfac = A.get<double>(45 * (int64_t)m);
+    P->mj = A.get<double>(81 * (int64_t)m);
     P->dcam = A.get<double>(9 * (int64_t)m);
     for (double** v : {&P->g, &P->x, &P->r, &P->z, &P->p, &P->q, &P->cacc}) *v = A.get<double>(9 * (int64_t)m);
     P->pT = A.get<char>(9 * (int64_t)m * (int64_t)tsz);
@@ -657,6 +665,7 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     if (e == hipSuccess) e = up(P->cm.cam_seg, cam_seg.data(), sizeof(int32_t) * cam_seg.size());
     if (e == hipSuccess) e = hipMemset(P->cm.arrive, 0, sizeof(uint32_t) * (size_t)m);
     if (e == hipSuccess) e = hipMemset(P->hcc, 0, sizeof(double) * 81 * (size_t)m);
+    if (e == hipSuccess) e = hipMemset(P->mj, 0, sizeof(double) * 81 * (size_t)m);  // unseen cameras: no term
     if (e == hipSuccess) e = hipMemset(P->vcam, 0, sizeof(double) * 9 * (size_t)m);
     if (e == hipSuccess) e = up(sp.wrange, wrange.data(), sizeof(int32_t) * wrange.size());
     if (e == hipSuccess && !sseg.empty()) e = up(sp.sseg, sseg.data(), sizeof(int2) * sseg.size());
@@ -757,6 +766,15 @@ static RecomputeInputs<T> recompute_inputs(const ba_problem* P)
 {
     return RecomputeInputs<T>{(const T*)P->wobs, P->pts, state_ck<T>(P), (const T*)P->xf,
                               sizeof(T) == 4 ? P->ck64 : nullptr};
+}
+
+// Where the Jacobian comes from at the current state (the build refreshes
+// the FP32 camera constants first).
+template <typename T>
+static JacSource<T> jac_source(const ba_problem* P)
+{
+    return JacSource<T>{state_ck<T>(P), P->opt.jacobian == BA_JACOBIAN_AUTODIFF ? P->cams : nullptr,
+                        sizeof(T) == 4 ? P->ck64 : nullptr};
 }
 
 template <typename T>
@@ -923,10 +941,16 @@ static ba_status lm_solve_t(ba_problem* P, const ba_options& o, ba_report* rep)
         }
         BA_TRY(P, launch_damp_cameras(m, P->hcc, lambda, o.damping, P->bd, P->lfac, P->dcam, P->flag, s));
         BA_TRY(P, launch_damp_points<T>(n, (const double*)P->hpp, lambda, o.damping, (T*)P->cinv, P->flag, s));
+        if (P->opt.solver == BA_SOLVER_PCG && o.preconditioner == BA_PRECOND_SCHUR_JACOBI) {
+            BA_TRY(P, launch_schur_jacobi_terms<T>(P->cm, P->N, P->pts, jac_source<T>(P), o.huber_delta,
+                                                   (const T*)P->cinv, P->mj, s));
+            BA_TRY(P, launch_factor_schur_jacobi(m, P->bd, P->mj, P->lfac, P->flag, s));
+        }
         BA_TRY(P, hipMemcpyAsync(P->h_scalars, P->flag, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         BA_TRY(P, hipStreamSynchronize(s));
         if (*(const int32_t*)P->h_scalars != 0) {
-            P->last_error = not_pd_message(P, (const int32_t*)P->h_scalars, lambda);
+            P->last_error = not_pd_message(P, (const int32_t*)P->h_scalars, lambda,
+                                           P->opt.solver == BA_SOLVER_PCG && o.preconditioner == BA_PRECOND_SCHUR_JACOBI);
             BA_TRY(P, hipMemsetAsync(P->flag, 0, 4 * sizeof(int32_t), s));
             result = BA_ENUMERIC;
             break;

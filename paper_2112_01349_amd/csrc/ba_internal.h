@@ -181,6 +181,15 @@ hipError_t launch_build_cameras(const CameraMajor& cm, int32_t m, int64_t N, con
                                 JacSource<T> js, double delta, bool grad_only, double* hcc,
                                 double* vcam, int64_t Nc, T* chcp, T* cw, hipStream_t s);
 
+// Schur-Jacobi preconditioner option: mj [m][81] = -sum_k E_k C~^-1 E_k^T per
+// camera (camera-major pass at the current state and damping), then
+// lfac = chol(B~_j + mj_j) with failure flags as launch_damp_cameras.
+template <typename T>
+hipError_t launch_schur_jacobi_terms(const CameraMajor& cm, int64_t N, const double* pts, JacSource<T> js,
+                                     double delta, const T* cinv, double* mj, hipStream_t s);
+hipError_t launch_factor_schur_jacobi(int32_t m, const double* bd, const double* mj, double* lfac, int32_t* flag,
+                                      hipStream_t s);
+
 hipError_t launch_damp_cameras(int32_t m, const double* hcc, double lambda, int32_t damping,
                                double* bd, double* lfac, double* dcam, int32_t* flag, hipStream_t s);
 template <typename T>

@@ -18,6 +18,9 @@
 //     balances the Zipf-skewed camera segments (the most-seen camera holds
 //     about 60% of all points) over the whole chip, as the paper's equal-edge
 //     partition (Sec. 4.1) does over GPUs.
+//   * camera-major again (k_schur_jacobi_cameras), for the Schur-Jacobi
+//     preconditioner option: the same slots sum -E_k C~^-1 E_k^T per camera
+//     at the damping of the current LM iteration.
 #include "ba_internal.h"
 #include "autodiff.h"
 
@@ -253,10 +256,10 @@ hipError_t launch_build_points(const PointMajor& pm, double delta, bool grad_onl
 
 // ----------------------------------------------------- camera-major build
 
-template <bool GRAD_ONLY>
+// Wave sums of the W accumulated words into one slot.
+template <int W>
 __device__ __forceinline__ void flush_slot(double* acc, double* __restrict__ slots, int32_t slot, int lane)
 {
-    constexpr int W = GRAD_ONLY ? 9 : kCamSlotWords;
 #pragma unroll
     for (int q = 0; q < W; ++q) {
         const double v = wave_sum(acc[q]);
@@ -320,20 +323,22 @@ __global__ __launch_bounds__(256) void k_build_cameras(
             // lanes not yet consumed hold larger camera ids (the chunk is sorted)
             const uint64_t more = __ballot(valid && j > cur);
             if (more == 0) break;
-            flush_slot<GRAD_ONLY>(acc, slots, slot, lane);
+            flush_slot<W>(acc, slots, slot, lane);
             ++slot;
             const int first = __ffsll((unsigned long long)more) - 1;
             cur = __shfl(j, first, 64);  // strictly larger: the loop ends
         }
     }
-    flush_slot<GRAD_ONLY>(acc, slots, slot, lane);
+    flush_slot<W>(acc, slots, slot, lane);
 }
 
 // One wavefront per segment of <= kSlotSeg consecutive slots of one camera
 // (lanes = the 54 terms).  A camera with one segment is written directly;
 // otherwise the last of its segments to finish (device-scope counter) adds
 // the segment sums in segment order, so the result is deterministic.
-template <bool GRAD_ONLY>
+// MODE 0: the 45 upper-triangle B terms and the 9 v terms into hcc and vcam;
+// MODE 1: the 9 v terms only; MODE 2: 45 upper-triangle terms only, into hcc.
+template <int MODE>
 __global__ __launch_bounds__(256) void k_reduce_slots(int32_t num_segs, const int32_t* __restrict__ seg_cam,
                                                       const int32_t* __restrict__ seg_slot,
                                                       const int32_t* __restrict__ cam_slot,
@@ -348,7 +353,7 @@ __global__ __launch_bounds__(256) void k_reduce_slots(int32_t num_segs, const in
     const int32_t j = seg_cam[sg];
     const int32_t s0 = seg_slot[sg];
     const int32_t s1 = min(s0 + kSlotSeg, cam_slot[j + 1]);
-    const int W = GRAD_ONLY ? 9 : kCamSlotWords;
+    const int W = MODE == 1 ? 9 : (MODE == 2 ? 45 : kCamSlotWords);
     double acc = 0.0;
     if (lane < W)
         for (int32_t sl = s0; sl < s1; ++sl) acc += slots[(int64_t)sl * kCamSlotWords + lane];
@@ -367,7 +372,7 @@ __global__ __launch_bounds__(256) void k_reduce_slots(int32_t num_segs, const in
         if (lane == 0) arrive[j] = 0u;
     }
     if (lane >= W) return;
-    const int q = GRAD_ONLY ? 45 + lane : lane;
+    const int q = MODE == 1 ? 45 + lane : lane;
     if (q < 45) {
         // upper-triangle index q -> (a, b), a <= b
         int a = 0, rem = q;
@@ -410,10 +415,10 @@ hipError_t launch_build_cameras(const CameraMajor& cm, int32_t m, int64_t N, con
     if (cm.num_segs > 0) {
         const int blocks = (cm.num_segs + 3) / 4;
         if (grad_only)
-            hipLaunchKernelGGL((k_reduce_slots<true>), dim3(blocks), dim3(256), 0, s, cm.num_segs, cm.seg_cam,
+            hipLaunchKernelGGL((k_reduce_slots<1>), dim3(blocks), dim3(256), 0, s, cm.num_segs, cm.seg_cam,
                                cm.seg_slot, cm.cam_slot, cm.cam_seg, cm.slots, cm.seg_part, cm.arrive, hcc, vcam);
         else
-            hipLaunchKernelGGL((k_reduce_slots<false>), dim3(blocks), dim3(256), 0, s, cm.num_segs, cm.seg_cam,
+            hipLaunchKernelGGL((k_reduce_slots<0>), dim3(blocks), dim3(256), 0, s, cm.num_segs, cm.seg_cam,
                                cm.seg_slot, cm.cam_slot, cm.cam_seg, cm.slots, cm.seg_part, cm.arrive, hcc, vcam);
     }
     return hipGetLastError();
@@ -472,6 +477,98 @@ hipError_t launch_cost(const PointMajor& pm, int64_t N, const double* pts, const
     return launch_cost_t<double>(pm, N, pts, ck, delta, partials, nblocks, s);
 }
 
+// Schur-Jacobi preconditioner terms: per camera, the sum over its
+// observations of E_k C~_i^-1 E_k^T (E_k = w J_c^T J_p, the damped point
+// inverse of the current lambda), negated, camera-major as the B_j build.
+// Products in FP64 from the T-precision Jacobian.
+template <typename T, bool AD>
+__global__ __launch_bounds__(256) void k_schur_jacobi_cameras(
+    int64_t N, int32_t num_chunks, const int32_t* __restrict__ cam, const int32_t* __restrict__ pt,
+    const double* __restrict__ uvx, const double* __restrict__ uvy, const double* __restrict__ pts,
+    JacSource<T> js, T delta, const T* __restrict__ cinv, const int32_t* __restrict__ chunk_slot,
+    double* __restrict__ slots)
+{
+    constexpr int W = 45;
+    const int lane = threadIdx.x & 63;
+    const int32_t chunk = (int32_t)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
+    if (chunk >= num_chunks) return;  // whole wavefront leaves together
+    const int64_t start = (int64_t)chunk * kCmChunk;
+    const int64_t end = start + kCmChunk < N ? start + kCmChunk : N;
+    int32_t slot = chunk_slot[chunk];
+    int32_t cur = cam[start];
+    double acc[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) acc[q] = 0.0;
+    for (int row = 0; row < kCmRows; ++row) {
+        const int64_t k = start + (int64_t)row * 64 + lane;
+        if (start + (int64_t)row * 64 >= end) break;
+        const bool valid = k < end;
+        T e0 = 0, e1 = 0, wt = 0, Jc[18], Jp[6];
+        int32_t j = 0x7fffffff, i = 0;
+        if (valid) {
+            j = cam[k];
+            observation<T, AD>(k, cam, pt, uvx, uvy, pts, js, delta, e0, e1, wt, Jc, Jp, i);
+        }
+        while (true) {
+            if (valid && j == cur) {
+                const double w = wt;
+                double E[27], Tm[27];
+#pragma unroll
+                for (int a = 0; a < 9; ++a)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        E[a * 3 + c] = w * ((double)Jc[a] * (double)Jp[c] + (double)Jc[9 + a] * (double)Jp[3 + c]);
+                const T* c6 = cinv + 6 * (int64_t)i;
+                const double C[9] = {(double)c6[0], (double)c6[1], (double)c6[2], (double)c6[1], (double)c6[3],
+                                     (double)c6[4], (double)c6[2], (double)c6[4], (double)c6[5]};
+#pragma unroll
+                for (int a = 0; a < 9; ++a)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        Tm[a * 3 + c] = E[a * 3] * C[c] + E[a * 3 + 1] * C[3 + c] + E[a * 3 + 2] * C[6 + c];
+                int q = 0;
+#pragma unroll
+                for (int a = 0; a < 9; ++a)
+#pragma unroll
+                    for (int b = a; b < 9; ++b)
+                        acc[q++] -= Tm[a * 3] * E[b * 3] + Tm[a * 3 + 1] * E[b * 3 + 1] + Tm[a * 3 + 2] * E[b * 3 + 2];
+            }
+            const uint64_t more = __ballot(valid && j > cur);
+            if (more == 0) break;
+            flush_slot<W>(acc, slots, slot, lane);
+            ++slot;
+            const int first = __ffsll((unsigned long long)more) - 1;
+            cur = __shfl(j, first, 64);
+        }
+    }
+    flush_slot<W>(acc, slots, slot, lane);
+}
+
+template <typename T>
+hipError_t launch_schur_jacobi_terms(const CameraMajor& cm, int64_t N, const double* pts, JacSource<T> js,
+                                     double delta, const T* cinv, double* mj, hipStream_t s)
+{
+    if (cm.num_chunks > 0) {
+        const dim3 grid((cm.num_chunks + 3) / 4);
+        if (js.cams)
+            hipLaunchKernelGGL((k_schur_jacobi_cameras<T, true>), grid, dim3(256), 0, s, N, cm.num_chunks, cm.cam,
+                               cm.pt, cm.uvx, cm.uvy, pts, js, (T)delta, cinv, cm.chunk_slot, cm.slots);
+        else
+            hipLaunchKernelGGL((k_schur_jacobi_cameras<T, false>), grid, dim3(256), 0, s, N, cm.num_chunks, cm.cam,
+                               cm.pt, cm.uvx, cm.uvy, pts, js, (T)delta, cinv, cm.chunk_slot, cm.slots);
+    }
+    if (cm.num_segs > 0)
+        hipLaunchKernelGGL((k_reduce_slots<2>), dim3((cm.num_segs + 3) / 4), dim3(256), 0, s, cm.num_segs,
+                           cm.seg_cam, cm.seg_slot, cm.cam_slot, cm.cam_seg, cm.slots, cm.seg_part, cm.arrive, mj,
+                           (double*)nullptr);
+    return hipGetLastError();
+}
+
+template hipError_t launch_schur_jacobi_terms<double>(const CameraMajor&, int64_t, const double*,
+                                                      JacSource<double>, double, const double*, double*,
+                                                      hipStream_t);
+template hipError_t launch_schur_jacobi_terms<float>(const CameraMajor&, int64_t, const double*, JacSource<float>,
+                                                     double, const float*, double*, hipStream_t);
 template hipError_t launch_build_points<double>(const PointMajor&, double, bool, const double*, JacSource<double>,
                                                 double*, double*, double*, double*, hipStream_t);
 template hipError_t launch_build_points<float>(const PointMajor&, double, bool, const double*, JacSource<float>,

@@ -2,6 +2,8 @@
 //
 //   * k_damp_cameras: B~_j = B_j + lambda D_j and its Cholesky factor, FP64
 //     (the block-Jacobi preconditioner of Alg. 2 and the B x term of Alg. 3).
+//   * k_factor_schur_jacobi: the Schur-Jacobi option's preconditioner blocks
+//     M_j = S_jj (per-observation terms) and their factors, replacing B~_j's.
 //   * k_damp_points:  C~_i = C_i + lambda D_i and its explicit inverse (Alg. 3
 //     b = C^-1 a, Eq. schur_x_p), one lane per point.
 //   * k_backsub_stored: dp = C~^-1 (w - E^T x) (Eq. schur_x_p) over
@@ -21,6 +23,29 @@ __device__ __forceinline__ double clamp_diag(double h)
 
 // packed lower-triangular index (r >= c)
 __host__ __device__ constexpr int tri(int r, int c) { return r * (r + 1) / 2 + c; }
+
+// In-place Cholesky factor of a packed lower-triangular 9x9 block; false
+// (with unit pivots substituted) when it is not positive definite.
+__device__ __forceinline__ bool cholesky9(double L[45])
+{
+    bool ok = true;
+    for (int c = 0; c < 9; ++c) {
+        double sd = L[tri(c, c)];
+        for (int t = 0; t < c; ++t) sd -= L[tri(c, t)] * L[tri(c, t)];
+        if (!(sd > 0.0)) {
+            ok = false;
+            sd = 1.0;
+        }
+        const double d = sqrt(sd);
+        L[tri(c, c)] = d;
+        for (int r = c + 1; r < 9; ++r) {
+            double x = L[tri(r, c)];
+            for (int t = 0; t < c; ++t) x -= L[tri(r, t)] * L[tri(c, t)];
+            L[tri(r, c)] = x / d;
+        }
+    }
+    return ok;
+}
 
 __global__ void k_damp_cameras(int32_t m, const double* __restrict__ hcc, double lambda, int32_t damping,
                                double* __restrict__ bd, double* __restrict__ lfac, double* __restrict__ dcam,
@@ -42,27 +67,39 @@ __global__ void k_damp_cameras(int32_t m, const double* __restrict__ hcc, double
             const double v = r >= c ? L[tri(r, c)] : L[tri(c, r)];
             bd[81 * (int64_t)j + r * 9 + c] = v;
         }
-    bool ok = true;
-    for (int c = 0; c < 9; ++c) {
-        double sd = L[tri(c, c)];
-        for (int t = 0; t < c; ++t) sd -= L[tri(c, t)] * L[tri(c, t)];
-        if (!(sd > 0.0)) {
-            ok = false;
-            sd = 1.0;
-        }
-        const double d = sqrt(sd);
-        L[tri(c, c)] = d;
-        for (int r = c + 1; r < 9; ++r) {
-            double x = L[tri(r, c)];
-            for (int t = 0; t < c; ++t) x -= L[tri(r, t)] * L[tri(c, t)];
-            L[tri(r, c)] = x / d;
-        }
-    }
+    const bool ok = cholesky9(L);
     for (int q = 0; q < 45; ++q) lfac[45 * (int64_t)j + q] = L[q];
     if (!ok) {
         atomicOr(flag, 1);
         flag[1] = j;  // one of the failing cameras (for the error message)
     }
+}
+
+// Schur-Jacobi preconditioner: M_j = B~_j + mj_j (mj holding the negated
+// per-camera sums of E C~^-1 E^T) and its Cholesky factor into lfac, in
+// place of the factor of B~_j.  Failure flags as the camera blocks.
+__global__ void k_factor_schur_jacobi(int32_t m, const double* __restrict__ bd, const double* __restrict__ mj,
+                                      double* __restrict__ lfac, int32_t* __restrict__ flag)
+{
+    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    double L[45];
+    for (int r = 0; r < 9; ++r)
+        for (int c = 0; c <= r; ++c) L[tri(r, c)] = bd[81 * (int64_t)j + r * 9 + c] + mj[81 * (int64_t)j + r * 9 + c];
+    const bool ok = cholesky9(L);
+    for (int q = 0; q < 45; ++q) lfac[45 * (int64_t)j + q] = L[q];
+    if (!ok) {
+        atomicOr(flag, 1);
+        flag[1] = j;
+    }
+}
+
+hipError_t launch_factor_schur_jacobi(int32_t m, const double* bd, const double* mj, double* lfac, int32_t* flag,
+                                      hipStream_t s)
+{
+    if (m > 0)
+        hipLaunchKernelGGL(k_factor_schur_jacobi, dim3((m + 63) / 64), dim3(64), 0, s, m, bd, mj, lfac, flag);
+    return hipGetLastError();
 }
 
 hipError_t launch_damp_cameras(int32_t m, const double* hcc, double lambda, int32_t damping, double* bd,

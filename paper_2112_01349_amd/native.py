@@ -18,6 +18,7 @@ BA_OK, BA_EINVAL, BA_ENOMEM, BA_EDEVICE, BA_ENUMERIC = 0, 1, 2, 3, 4
 FP64, FP32_MIXED = 0, 1
 DAMP_MARQUARDT, DAMP_IDENTITY = 0, 1
 SOLVER_PCG, SOLVER_DENSE = 0, 1
+PRECOND_CAMERA_BLOCKS, PRECOND_SCHUR_JACOBI = 0, 1
 DENSE_MAX_CAMERAS = 2048
 
 EXPORTED = ("ba_options_default", "ba_create", "ba_set_params", "ba_get_params", "ba_eval_cost_grad",
@@ -37,7 +38,7 @@ class Options(C.Structure):
                 ("pcg_rtol", C.c_double), ("pcg_fixed_iters", C.c_int32), ("jacobian", C.c_int32),
                 ("pcg_schedule", C.c_void_p), ("lambda_init", C.c_double),
                 ("min_relative_decrease", C.c_double), ("time_kernels", C.c_int32),
-                ("solver", C.c_int32)]
+                ("solver", C.c_int32), ("preconditioner", C.c_int32)]
 
 
 class Report(C.Structure):
@@ -98,7 +99,7 @@ def _ptr(a):
 def make_options(precision=FP64, damping=DAMP_MARQUARDT, huber_delta=0.0, max_lm_iters=10,
                  max_pcg_iters=50, pcg_rtol=1e-8, pcg_fixed_iters=0, pcg_schedule=None,
                  lambda_init=1e-4, min_relative_decrease=1e-3, time_kernels=False, jacobian=0,
-                 solver=0):
+                 solver=0, preconditioner=0):
     o = Options()
     lib().ba_options_default(C.byref(o))
     o.precision = int(precision)
@@ -119,6 +120,7 @@ def make_options(precision=FP64, damping=DAMP_MARQUARDT, huber_delta=0.0, max_lm
     o.time_kernels = 1 if time_kernels else 0
     o.jacobian = int(jacobian)
     o.solver = int(solver)
+    o.preconditioner = int(preconditioner)
     return o, keep
 
 

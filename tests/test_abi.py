@@ -35,12 +35,12 @@ def test_every_declared_symbol_is_exported(native):
 
 
 def test_struct_sizes_match_header(native):
-    # ba_options: 80 bytes, ba_report: 128 bytes on LP64 (natural alignment)
-    assert C.sizeof(native.Options) == 80
+    # ba_options: 88 bytes, ba_report: 128 bytes on LP64 (natural alignment)
+    assert C.sizeof(native.Options) == 88
     assert C.sizeof(native.Report) == 128
     o = native.Options()
     assert native.lib().ba_options_default(C.byref(o)) == 0
-    assert o.struct_size == 80 and o.max_lm_iters == 10 and o.pcg_rtol == 1e-8 and o.lambda_init == 1e-4
+    assert o.struct_size == 88 and o.max_lm_iters == 10 and o.pcg_rtol == 1e-8 and o.lambda_init == 1e-4
 
 
 def _create(native, cams, pts, oc, op, uv, opt=None):
@@ -96,6 +96,11 @@ def test_invalid_inputs_are_rejected_on_the_host(native):
     many = np.tile(cams[:1], (native.DENSE_MAX_CAMERAS + 1, 1))
     st, h = _create(native, many, pts, oc, op, uv, C.byref(o))
     assert st == native.BA_EINVAL and b"at most 2048 cameras" in native.lib().ba_last_error(None)
+    native.lib().ba_options_default(C.byref(o))
+    assert o.preconditioner == native.PRECOND_CAMERA_BLOCKS
+    o.preconditioner = 2
+    st, h = _create(native, cams, pts, oc, op, uv, C.byref(o))
+    assert st == native.BA_EINVAL and b"preconditioner" in native.lib().ba_last_error(None)
     assert native.lib().ba_status_str(4) == b"BA_ENUMERIC"
 
 

@@ -13,7 +13,7 @@ import pytest
 from helpers import rel_err, small_zipf, with_edge_cases
 from oracle import oracle as orc
 from paper_2112_01349_amd import FP32_MIXED, FP64, Problem, synth
-from paper_2112_01349_amd.native import SOLVER_DENSE
+from paper_2112_01349_amd.native import PRECOND_SCHUR_JACOBI, SOLVER_DENSE
 
 pytestmark = pytest.mark.gpu
 
@@ -421,3 +421,60 @@ def test_dense_solver_matches_converged_pcg(tiny):
     np.testing.assert_allclose(a["cost"], b["cost"], rtol=1e-8)
     with pytest.raises(Exception, match="solver differs"):
         dense.lm_solve(max_lm_iters=1, solver=0)
+
+
+def schur_jacobi_pair(arrays, delta=0.0, iters=8, max_pcg=60, rtol=1e-8, precision=FP64, **opts):
+    """Oracle and library LM traces with the Schur-Jacobi preconditioner; the
+    library replays the oracle's PCG counts."""
+    cams, pts, oc, op, uv = arrays[:5]
+    _, _, tr, rc = orc.lm_solve(cams, pts, oc, op, uv, huber_delta=delta, max_lm_iters=iters,
+                                max_pcg_iters=max_pcg, pcg_rtol=rtol, preconditioner=1)
+    assert rc == 0
+    prob, _ = make(arrays[:5], precision=precision, huber_delta=delta, preconditioner=PRECOND_SCHUR_JACOBI,
+                   **opts)
+    gpu = prob.lm_solve(max_lm_iters=iters, pcg_schedule=tr["pcg_iters"], max_pcg_iters=max_pcg, pcg_rtol=rtol)
+    return tr, gpu, prob
+
+
+def test_schur_jacobi_trace_tiny(tiny):
+    arrays = (tiny.cameras0, tiny.points0, tiny.obs_camera, tiny.obs_point, tiny.obs_uv)
+    tr, gpu, _ = schur_jacobi_pair(arrays, iters=10, max_pcg=50)
+    assert_traces_match(tr, gpu)
+
+
+@pytest.mark.parametrize("jacobian", [0, 1])
+def test_schur_jacobi_trace_edge_cases(jacobian):
+    """Huber loss, an unseen camera (no Schur term: M_j = B~_j), a repeated
+    pair (no cross term) and a point of 300 views; analytic and
+    forward-mode Jacobians."""
+    arrays = with_edge_cases(small_zipf(seed=13, m=14, n=300, N=1500))
+    tr, gpu, _ = schur_jacobi_pair(arrays, delta=1.0, iters=6, jacobian=jacobian)
+    assert_traces_match(tr, gpu)
+
+
+def test_schur_jacobi_changes_the_preconditioner(tiny):
+    """The option reaches the solver: in tolerance mode the PCG counts follow
+    the oracle's with Schur-Jacobi blocks, not with the camera blocks."""
+    arrays = (tiny.cameras0, tiny.points0, tiny.obs_camera, tiny.obs_point, tiny.obs_uv)
+    cams, pts, oc, op, uv = arrays
+    sj = orc.lm_solve(cams, pts, oc, op, uv, max_lm_iters=1, max_pcg_iters=200, pcg_rtol=1e-8, preconditioner=1)[2]
+    cb = orc.lm_solve(cams, pts, oc, op, uv, max_lm_iters=1, max_pcg_iters=200, pcg_rtol=1e-8)[2]
+    prob, _ = make(arrays)
+    a = prob.lm_solve(max_lm_iters=1, max_pcg_iters=200, pcg_rtol=1e-8, preconditioner=PRECOND_SCHUR_JACOBI)
+    prob.close()
+    prob, _ = make(arrays)
+    b = prob.lm_solve(max_lm_iters=1, max_pcg_iters=200, pcg_rtol=1e-8)
+    assert abs(int(a["pcg_iters"][0]) - int(sj["pcg_iters"][0])) <= 1
+    assert abs(int(b["pcg_iters"][0]) - int(cb["pcg_iters"][0])) <= 1
+
+
+def test_schur_jacobi_mixed_reaches_oracle_cost(tiny):
+    arrays = (tiny.cameras0, tiny.points0, tiny.obs_camera, tiny.obs_point, tiny.obs_uv)
+    cams, pts, oc, op, uv = arrays
+    _, _, tr, rc = orc.lm_solve(cams, pts, oc, op, uv, max_lm_iters=10, max_pcg_iters=50, pcg_rtol=1e-8,
+                                preconditioner=1)
+    prob, _ = make(arrays, precision=FP32_MIXED, preconditioner=PRECOND_SCHUR_JACOBI)
+    gpu = prob.lm_solve(max_lm_iters=10, max_pcg_iters=50, pcg_rtol=1e-8)
+    assert gpu["status"] == 0, gpu["error"]
+    assert np.all(np.diff(np.concatenate([[gpu["initial_cost"]], gpu["cost"]])) <= 0)
+    assert gpu["final_cost"] <= tr["final_cost"] * (1 + 1e-4)
