@@ -125,7 +125,7 @@ def roofline(s32, m, n, N, counters_apply):
             "stored_e_hbm_floor_ms": stored_bytes / (HBM_PEAK_GBS * 1e9) * 1e3}
 
 
-def run_precision(prob_data, precision, wl, steps, warmup, jacobian=0):
+def run_precision(prob_data, precision, wl, steps, warmup, jacobian=0, solver=0, preconditioner=0):
     import torch
 
     from paper_2112_01349_amd import Problem
@@ -133,7 +133,8 @@ def run_precision(prob_data, precision, wl, steps, warmup, jacobian=0):
     cams, pts, oc, op, uv = prob_data
     t0 = time.perf_counter()
     prob = Problem(cams, pts, oc, op, uv, precision=precision, huber_delta=wl["huber_delta"],
-                   max_pcg_iters=wl["max_pcg_iters"], pcg_rtol=wl["pcg_rtol"], jacobian=jacobian)
+                   max_pcg_iters=wl["max_pcg_iters"], pcg_rtol=wl["pcg_rtol"], jacobian=jacobian, solver=solver,
+                   preconditioner=preconditioner)
     device_bytes = prob.memory_bytes()
     log(f"[bench] precision={precision} create {time.perf_counter() - t0:.1f}s "
         f"device bytes {device_bytes / 1e9:.2f} GB")
@@ -234,6 +235,11 @@ def main():
     ap.add_argument("--autograd", type=int, default=1, help="also time the autograd Function (1M observations)")
     ap.add_argument("--jacobian", default="analytic", choices=["analytic", "autodiff"],
                     help="analytic Jacobians (the paper's -m) or forward-mode autodiff (-a)")
+    ap.add_argument("--solver", default="pcg", choices=["pcg", "dense"],
+                    help="PCG on implicit Schur products, or the reduced system written out and factored "
+                         "(at most 2048 cameras)")
+    ap.add_argument("--preconditioner", default="camera-blocks", choices=["camera-blocks", "schur-jacobi"],
+                    help="PCG preconditioner: damped camera blocks (Alg. 2) or the Schur-Jacobi blocks")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (scale reference for HBM byte counters)")
     args = ap.parse_args()
@@ -268,12 +274,14 @@ def main():
     m, n, N = prob.num_cameras, prob.num_points, prob.num_obs
 
     jac = 1 if args.jacobian == "autodiff" else 0
-    rep32, wall32 = run_precision(data, FP32_MIXED, wl, args.steps, args.warmup, jac)
+    variant = dict(solver=1 if args.solver == "dense" else 0,
+                   preconditioner=1 if args.preconditioner == "schur-jacobi" else 0)
+    rep32, wall32 = run_precision(data, FP32_MIXED, wl, args.steps, args.warmup, jac, **variant)
     res = {}
     for name, rep, wall, w in [("fp32_mixed", rep32, wall32, 4)]:
         res[name] = rep, wall, w
     if args.fp64:
-        rep64, wall64 = run_precision(data, FP64, wl, args.steps, args.warmup, jac)
+        rep64, wall64 = run_precision(data, FP64, wl, args.steps, args.warmup, jac, **variant)
         res["fp64"] = rep64, wall64, 8
 
     def summary(rep, wall, w):
@@ -293,7 +301,8 @@ def main():
         else:
             # arithmetic rate of the recomputing pass; the bytes the stored design moves are not moved
             flops = free_pass_algorithmic_flops(n, N)
-            out.update(hot_kernel_flops=flops, hot_kernel_tflops=flops / (hot_ms * 1e-3) / 1e12)
+            out.update(hot_kernel_flops=flops,
+                       hot_kernel_tflops=flops / (hot_ms * 1e-3) / 1e12 if hot_ms > 0 else None)
         out.update(initial_cost=rep["initial_cost"], final_cost=rep["final_cost"],
                    device_bytes=int(rep["device_bytes"]),
                    pcg_per_lm=rep["pcg_iters"].tolist(), accepted=rep["accepted"].tolist())
@@ -312,11 +321,13 @@ def main():
                                + (f"point-aligned chunk {wl['chunk'][0]} of {wl['chunk'][1]} of '{wl['config']}', "
                                   if "chunk" in wl else "")
                                + ("uniform visibility, " if wl["config"] in synth.CIRCLE_CONFIGS else "Zipf visibility, ")
-                               + f"Huber delta={wl['huber_delta']}, {args.jacobian} Jacobians, PCG max "
-                               f"{wl['max_pcg_iters']} rtol {wl['pcg_rtol']}",
+                               + f"Huber delta={wl['huber_delta']}, {args.jacobian} Jacobians, "
+                               + ("dense reduced system, Cholesky" if args.solver == "dense" else
+                                  f"PCG ({args.preconditioner}) max {wl['max_pcg_iters']} rtol {wl['pcg_rtol']}"),
                    "cameras": m, "points": n, "observations": N},
         "pcg_iter_per_s": s32["pcg_iter_per_s"],
-        "roofline": roofline(s32, m, n, N, args.workload == "large"),
+        # the roofline entry describes the PCG path's dominant kernel
+        "roofline": roofline(s32, m, n, N, args.workload == "large") if args.solver == "pcg" else None,
         "fp32_mixed": s32,
     }
     if "fp64" in res:
@@ -326,7 +337,7 @@ def main():
         out["mixed_speedup_equal_cost"] = equal_cost_speedup(res["fp32_mixed"][0], res["fp64"][0])
     if args.autograd:
         out["autograd"] = autograd_throughput()
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.solver == "pcg":
         out["cpu_baseline"] = cpu_baseline(prob, wl, s32["pcg_iters"] / max(1, args.steps))
     print(json.dumps(out), flush=True)
 

@@ -82,8 +82,8 @@ struct ba_problem {
     double *partials = nullptr, *sums = nullptr;
     PcgScalars* sc = nullptr;
     int32_t* flag = nullptr;
-    // direct option: S [9m][9m] FP64 factored in place, a solve buffer, row pairs
-    double *S = nullptr, *ybuf = nullptr;
+    // direct option: S [9m][9m] FP64 factored in place and the formation plan
+    double* S = nullptr;
     DensePlan dense{};
     // pinned host scratch
     double* h_scalars = nullptr;
@@ -524,17 +524,6 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
         split(sseg, frange);
         split(lseg, lrange);
     }
-    // direct option: the row pairs whose observations share points (a short
-    // segment with itself; every pair of the 64-observation rows of a long point)
-    std::vector<int4> dense_rows;
-    if (opt.solver == BA_SOLVER_DENSE) {
-        for (const int2& g : sseg) dense_rows.push_back(make_int4(g.x, g.y - g.x, g.x, g.y - g.x));
-        for (const int2& g : lseg)
-            for (int32_t a = g.x; a < g.y; a += 64)
-                for (int32_t b = g.x; b < g.y; b += 64)
-                    dense_rows.push_back(make_int4(a, std::min(64, g.y - a), b, std::min(64, g.y - b)));
-        P->dense.num_rows = (int32_t)dense_rows.size();
-    }
     // the build: 32 wavefronts per CU over the same tiles
     // cold stream: observations on cameras >= K, camera-major
     std::vector<int32_t> h_cold_cam, h_cold_pt;
@@ -624,8 +613,15 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     P->flag = A.get<int32_t>(4);  // [failure bits, a failing camera, a failing point, unused]
     if (opt.solver == BA_SOLVER_DENSE) {
         P->S = A.get<double>(81 * (int64_t)m * m);
-        P->ybuf = A.get<double>(9 * (int64_t)m);
-        P->dense.rows = A.get<int4>(std::max<int64_t>(1, (int64_t)dense_rows.size()));
+        int64_t np = 0;
+        for (int32_t j = 0; j < m; ++j)
+            np += std::max<int64_t>(1, (coff[(size_t)j + 1] - coff[j] + kDensePiece - 1) / kDensePiece);
+        P->dense.num_pieces = (int32_t)np;
+        P->dense.pieces = A.get<int4>(np);
+        P->dense.coff = A.get<int32_t>((int64_t)m + 1);
+        P->dense.cm_pm = A.get<int32_t>(N);
+        P->dense.poff = A.get<int32_t>((int64_t)n + 1);
+        P->dense.E = A.get<double>(27 * N);
     }
     if (A.err != hipSuccess) {
         g_create_error = std::string("device allocation failed: ") + hipGetErrorString(A.err);
@@ -672,8 +668,25 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     if (e == hipSuccess && !lseg.empty()) e = up(sp.lseg, lseg.data(), sizeof(int2) * lseg.size());
     if (e == hipSuccess) e = up(sp.frange, frange.data(), sizeof(int32_t) * frange.size());
     if (e == hipSuccess) e = up(sp.lrange, lrange.data(), sizeof(int32_t) * lrange.size());
-    if (e == hipSuccess && !dense_rows.empty())
-        e = up(P->dense.rows, dense_rows.data(), sizeof(int4) * dense_rows.size());
+    if (e == hipSuccess && opt.solver == BA_SOLVER_DENSE) {
+        // camera-major entry d holds point-major observation cm_pm[d]
+        std::vector<int32_t> h_coff((size_t)m + 1), h_cm_pm((size_t)N), h_poff((size_t)n + 1);
+        for (int32_t j = 0; j <= m; ++j) h_coff[(size_t)j] = (int32_t)coff[(size_t)j];
+        for (int32_t i = 0; i <= n; ++i) h_poff[(size_t)i] = (int32_t)poff[(size_t)i];
+        std::vector<int64_t> fill(coff.begin(), coff.end() - 1);
+        for (int64_t t = 0; t < N; ++t) h_cm_pm[(size_t)fill[h_pm_cam[(size_t)t]]++] = (int32_t)t;
+        std::vector<int4> h_pieces;
+        for (int32_t j = 0; j < m; ++j) {
+            const int32_t a = h_coff[(size_t)j], b = h_coff[(size_t)j + 1];
+            const int32_t np = std::max(1, (b - a + kDensePiece - 1) / kDensePiece);
+            for (int32_t q = 0; q < np; ++q)
+                h_pieces.push_back(make_int4(j, a + q * kDensePiece, std::min(b, a + (q + 1) * kDensePiece), np));
+        }
+        e = up(P->dense.coff, h_coff.data(), sizeof(int32_t) * h_coff.size());
+        if (e == hipSuccess) e = up(P->dense.pieces, h_pieces.data(), sizeof(int4) * h_pieces.size());
+        if (e == hipSuccess) e = up(P->dense.cm_pm, h_cm_pm.data(), sizeof(int32_t) * h_cm_pm.size());
+        if (e == hipSuccess) e = up(P->dense.poff, h_poff.data(), sizeof(int32_t) * h_poff.size());
+    }
     if (e == hipSuccess) e = hipMemset(P->wobs, 0, (size_t)P->pm.ld * tsz);
     if (e == hipSuccess) e = hipMemset(P->xf, 0, 12 * (size_t)m * tsz);
     if (e == hipSuccess) e = up(sp.has_cold, has_cold.data(), (size_t)n);
@@ -896,8 +909,11 @@ static ba_status run_dense(ba_problem* P, double lambda)
     BA_TRY(P, launch_schur_product<T>(1, P->sp, P->pm, P->N, (const T*)P->hcp, (const T*)P->cinv, P->wpt, nullptr,
                                       &ri, P->m, P->bd, nullptr, P->vcam, P->g, P->x, P->r, P->partials, P->sc,
                                       nullptr, nullptr, s));
-    BA_TRY(P, launch_dense_solve<T>(P->dense, P->pm, ri, (const T*)P->cinv, P->m, P->bd, P->g, P->x, P->S, P->ybuf,
-                                    P->flag, s));
+    // the per-observation (diagonal) terms come from the camera-major pass
+    BA_TRY(P, launch_schur_jacobi_terms<T>(P->cm, P->N, P->pts, jac_source<T>(P), P->opt.huber_delta,
+                                           (const T*)P->cinv, P->mj, s));
+    BA_TRY(P, launch_dense_solve<T>(P->dense, P->pm, P->N, ri, (const T*)P->cinv, P->m, P->bd, P->mj, P->g, P->x,
+                                    P->S, P->flag, s));
     BA_TRY(P, hipMemcpyAsync(P->h_scalars, P->flag, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     BA_TRY(P, hipStreamSynchronize(s));
     if (*(const int32_t*)P->h_scalars & 4) {

@@ -196,21 +196,29 @@ template <typename T>
 hipError_t launch_damp_points(int32_t n, const double* hpp, double lambda, int32_t damping, T* cinv,
                               int32_t* flag, hipStream_t s);
 
-// The direct option: pairs of observation rows (64 observations each) whose
-// points meet, {start of row a, its length, start of row b, its length}, for
-// forming the dense reduced camera system.
+// The direct option's plan: the camera-major walk (pieces of at most
+// kDensePiece observations of one camera, and per camera-major entry its
+// point-major index), the point
+// offsets of the point-major stream, and an FP64 scratch stream of E_k.
+constexpr int32_t kDensePiece = 4096;  // camera-major observations per piece of a block row
+
 struct DensePlan {
-    int32_t num_rows = 0;
-    int4* rows = nullptr;
+    int32_t num_pieces = 0;
+    int4* pieces = nullptr;    // {camera, first, end, pieces of this camera}, camera order
+    int32_t* coff = nullptr;   // [m + 1]
+    int32_t* cm_pm = nullptr;  // [N]
+    int32_t* poff = nullptr;   // [n + 1]
+    double* E = nullptr;       // [N][27]
 };
 
 // x = S^-1 g for the reduced camera system written out (S [9m][9m] FP64,
-// factored in place; ybuf [9m] scratch); flag bit 2 when S is not positive
+// formed from B~ (bd), the per-camera self terms mj and the cross terms of
+// shared points, then factored in place); flag bit 2 when S is not positive
 // definite.
 template <typename T>
-hipError_t launch_dense_solve(const DensePlan& dp, const PointMajor& pm, const RecomputeInputs<T>& ri,
-                              const T* cinv, int32_t m, const double* bd, const double* g, double* x, double* S,
-                              double* ybuf, int32_t* flag, hipStream_t s);
+hipError_t launch_dense_solve(const DensePlan& dp, const PointMajor& pm, int64_t N, const RecomputeInputs<T>& ri,
+                              const T* cinv, int32_t m, const double* bd, const double* mj, const double* g,
+                              double* x, double* S, int32_t* flag, hipStream_t s);
 
 // Back-substitution from the stored blocks (BA_SCHUR_STORED=1):
 // dp = C~^-1 (w - E^T x), x in T (xcam).

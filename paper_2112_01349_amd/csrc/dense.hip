@@ -3,187 +3,224 @@
 // its Cholesky factor, in place of PCG, for problems with few cameras (the
 // direct route the paper sets against iterative solvers in Sec. 3).
 //
-//   * k_dense_init: S = blockdiag(B~_j).
-//   * k_dense_schur: for every point, S[cam(a), cam(b)] -= E_a C~^-1 E_b^T over
-//     all pairs of its observations; E is formed from the Jacobian as in the
-//     recomputing products, one observation per lane, the partner blocks
-//     fetched by shuffles, the 81 terms of a block added with FP64 atomics.
+//   * k_dense_coupling: E_k = w J_c^T J_p of every observation (FP64, from
+//     the T-precision Jacobian), point-major, into a scratch stream.
+//   * k_dense_rows: one workgroup per piece of a block row (camera a, at most
+//     kPiece of its observations) and chunk of kChunk block columns.  It
+//     walks the piece's observations; for each, the other observations of
+//     the same point whose camera falls in the chunk add -E_a C~^-1 E_b^T to
+//     an LDS copy of the chunk (LDS atomics).  The blocks touched are then
+//     stored, or added with global atomics when the camera has several
+//     pieces (the few most-seen cameras), which splits the hottest rows over
+//     many workgroups.  The diagonal block starts from B~_a plus
+//     the per-observation terms -sum E_k C~^-1 E_k^T (the Schur-Jacobi
+//     camera-major pass), so an observation never pairs with itself here.
 //   * Cholesky, right-looking over 64 x 64 tiles: k_potrf_tile factors the
-//     diagonal tile in LDS, k_trsm_tiles forms the panel below it, and
-//     k_syrk_tiles updates the trailing lower tiles.
-//   * k_dense_trsv: L y = g, then L^T x = y, by one workgroup, a tile at a
-//     time.
+//     diagonal tile (one wavefront, a row per lane), k_trsm_tiles forms the
+//     panel below it (a row per lane), and k_syrk_tiles updates the trailing
+//     lower tiles on the FP64 matrix cores.
+//   * k_trsv_diag / k_trsv_panel: L y = g and L^T x = y a tile at a time, the
+//     tile's triangle by one wavefront and the coupling to the remaining rows
+//     by many workgroups.
 #include "ba_internal.h"
 
 namespace ba {
 
 namespace {
-constexpr int kT = 64;  // tile edge
-}
+constexpr int kT = 64;       // factorisation tile edge
+constexpr int kChunk = 64;  // block columns per workgroup in k_dense_rows (41.5 KB of LDS)
+}  // namespace
 
-__global__ void k_dense_init(int32_t m, const double* __restrict__ bd, double* __restrict__ S)
-{
-    const int64_t nd = 9 * (int64_t)m;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nd * nd;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = e / nd, c = e - r * nd;
-        const int64_t jr = r / 9, jc = c / 9;
-        S[e] = jr == jc ? bd[81 * jr + (r - 9 * jr) * 9 + (c - 9 * jc)] : 0.0;
-    }
-}
-
-// E_k (9x3 row-major, FP64) of one observation from the geometry: E = w J_c^T J_p.
+// E_k of every observation, [N][27] row-major 9x3.
 template <typename T>
-__device__ __forceinline__ void coupling_block(const CamK<T>& k, const ObsGeo<T>& o, T w, double E[27])
+__global__ __launch_bounds__(256) void k_dense_coupling(int64_t N, const int32_t* __restrict__ cam,
+                                                        const int32_t* __restrict__ pt, const T* __restrict__ wobs,
+                                                        const double* __restrict__ pts,
+                                                        const CamK<T>* __restrict__ ck,
+                                                        const CamK<double>* __restrict__ ck64,
+                                                        double* __restrict__ E)
 {
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const int32_t j = cam[k];
+    const CamK<T>& kk = ck[j];
+    ObsGeo<T> o;
+    observation_geometry_checked<T>(kk.R, ck64, j, pts + 3 * (int64_t)pt[k], o);
     T e0, e1, Jc[18], Jp[6];
-    jacobian_from_geometry<T>(k, o, (T)0, (T)0, e0, e1, Jc, Jp);
+    jacobian_from_geometry<T>(kk, o, (T)0, (T)0, e0, e1, Jc, Jp);
+    const double w = (double)wobs[k];
+    double* out = E + 27 * k;
 #pragma unroll
     for (int a = 0; a < 9; ++a)
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-            E[a * 3 + c] = (double)w * ((double)Jc[a] * (double)Jp[c] + (double)Jc[9 + a] * (double)Jp[3 + c]);
+            out[a * 3 + c] = w * ((double)Jc[a] * (double)Jp[c] + (double)Jc[9 + a] * (double)Jp[3 + c]);
 }
 
-// One wavefront per row of 64 observations of a segment (a short segment is a
-// row; a long one, a point, is cut into rows).  Lane a pairs with every lane
-// of the partner row holding the same point.
-template <typename T>
-__global__ __launch_bounds__(256) void k_dense_schur(int32_t num_rows, const int4* __restrict__ rows,
-                                                     const int32_t* __restrict__ cam, const int32_t* __restrict__ pt,
-                                                     const T* __restrict__ wobs, const double* __restrict__ pts,
-                                                     const CamK<T>* __restrict__ ck,
-                                                     const CamK<double>* __restrict__ ck64,
-                                                     const T* __restrict__ cinv, int32_t m, double* __restrict__ S)
+__global__ void k_dense_zero(int64_t len, double* __restrict__ S)
 {
-    const int lane = threadIdx.x & 63;
-    const int32_t rw = (int32_t)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
-    if (rw >= num_rows) return;  // whole wavefront leaves together
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < len; e += (int64_t)gridDim.x * blockDim.x)
+        S[e] = 0.0;
+}
+
+// One workgroup per (piece, chunk): piece = {camera a, first and end
+// camera-major observation, number of pieces of camera a}.  S is zero
+// beforehand; blocks that received a term are stored (a camera walked by one
+// piece) or added atomically (several pieces).
+template <typename T>
+__global__ __launch_bounds__(256) void k_dense_rows(int32_t m, int32_t nchunk, const int4* __restrict__ pieces,
+                                                    const int32_t* __restrict__ cm_pm,
+                                                    const int32_t* __restrict__ poff,
+                                                    const int32_t* __restrict__ pm_cam,
+                                                    const int32_t* __restrict__ pm_pt, const double* __restrict__ E,
+                                                    const T* __restrict__ cinv, const double* __restrict__ bd,
+                                                    const double* __restrict__ mj, double* __restrict__ S)
+{
+    __shared__ double acc[kChunk * 81];
+    __shared__ int touched[kChunk];
+    const int32_t pc = blockIdx.x / nchunk;
+    const int4 pe = pieces[pc];
+    const int32_t ja = pe.x;
+    const bool first = pc == 0 || pieces[pc - 1].x != ja;  // the piece that adds the diagonal terms
+    const int32_t c0 = (blockIdx.x - pc * nchunk) * kChunk;
+    const int32_t cw = min(kChunk, m - c0);
     const int64_t nd = 9 * (int64_t)m;
-    // rows[rw] = {start of this row, its length, start of the partner row, its length}
-    const int4 rr = rows[rw];
-    const int32_t a0 = __builtin_amdgcn_readfirstlane(rr.x), alen = __builtin_amdgcn_readfirstlane(rr.y);
-    const int32_t b0 = __builtin_amdgcn_readfirstlane(rr.z), blen = __builtin_amdgcn_readfirstlane(rr.w);
-    const bool va = lane < alen, vb = lane < blen;
-    double Ta[27], Eb[27];
-    int32_t ia = -1, ja = 0, ib = -2, jb = 0;
-    {
-        const int64_t k = a0 + (va ? lane : 0);
-        ja = cam[k];
-        ia = va ? pt[k] : -1;
-        const CamK<T>& kk = ck[ja];
-        ObsGeo<T> o;
-        observation_geometry_checked<T>(kk.R, ck64, ja, pts + 3 * (int64_t)pt[k], o);
-        double E[27];
-        coupling_block<T>(kk, o, wobs[k], E);
-        const T* c6 = cinv + 6 * (int64_t)pt[k];
-        const double C[9] = {(double)c6[0], (double)c6[1], (double)c6[2], (double)c6[1], (double)c6[3],
-                             (double)c6[4], (double)c6[2], (double)c6[4], (double)c6[5]};
-#pragma unroll
-        for (int a = 0; a < 9; ++a)
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                Ta[a * 3 + c] = E[a * 3] * C[c] + E[a * 3 + 1] * C[3 + c] + E[a * 3 + 2] * C[6 + c];
+    for (int e = threadIdx.x; e < cw * 81; e += blockDim.x) {
+        const int32_t jb = c0 + e / 81;
+        const int q = e % 81;
+        acc[e] = (first && jb == ja) ? bd[81 * (int64_t)ja + q] + mj[81 * (int64_t)ja + q] : 0.0;
     }
-    {
-        const int64_t k = b0 + (vb ? lane : 0);
-        jb = cam[k];
-        ib = vb ? pt[k] : -2;
-        const CamK<T>& kk = ck[jb];
-        ObsGeo<T> o;
-        observation_geometry_checked<T>(kk.R, ck64, jb, pts + 3 * (int64_t)pt[k], o);
-        coupling_block<T>(kk, o, wobs[k], Eb);
-    }
-    for (int32_t t = 0; t < blen; ++t) {  // uniform: every lane takes part in the shuffles
-        const int32_t it = __shfl(ib, t, 64), jt = __shfl(jb, t, 64);
-        double E[27];
+    for (int c = threadIdx.x; c < kChunk; c += blockDim.x) touched[c] = (first && c0 + c == ja) ? 1 : 0;
+    __syncthreads();
+    for (int32_t a = pe.y + threadIdx.x; a < pe.z; a += blockDim.x) {
+        const int32_t ka = cm_pm[a];
+        const int32_t i = pm_pt[ka];
+        const int32_t p0 = poff[i], p1 = poff[i + 1];
+        bool have = false;
+        double Ta[27];
+        for (int32_t kb = p0; kb < p1; ++kb) {
+            const int32_t jb = pm_cam[kb];
+            if (kb == ka || jb < c0 || jb >= c0 + cw) continue;
+            if (!have) {  // T_a = E_a C~_i^-1, formed at the first partner in the chunk
+                const T* c6 = cinv + 6 * (int64_t)i;
+                const double C[9] = {(double)c6[0], (double)c6[1], (double)c6[2], (double)c6[1], (double)c6[3],
+                                     (double)c6[4], (double)c6[2], (double)c6[4], (double)c6[5]};
+                const double* Ea = E + 27 * (int64_t)ka;
 #pragma unroll
-        for (int q = 0; q < 27; ++q) E[q] = __shfl(Eb[q], t, 64);
-        if (va && ia == it) {
-            double* blk = S + (9 * (int64_t)ja) * nd + 9 * (int64_t)jt;
+                for (int r = 0; r < 9; ++r) {
+                    const double x0 = Ea[r * 3], x1 = Ea[r * 3 + 1], x2 = Ea[r * 3 + 2];
 #pragma unroll
-            for (int a = 0; a < 9; ++a)
-#pragma unroll
-                for (int b = 0; b < 9; ++b) {
-                    const double v = Ta[a * 3] * E[b * 3] + Ta[a * 3 + 1] * E[b * 3 + 1] + Ta[a * 3 + 2] * E[b * 3 + 2];
-                    unsafeAtomicAdd(blk + a * nd + b, -v);
+                    for (int c = 0; c < 3; ++c) Ta[r * 3 + c] = x0 * C[c] + x1 * C[3 + c] + x2 * C[6 + c];
                 }
+                have = true;
+            }
+            const double* Eb = E + 27 * (int64_t)kb;
+            double eb[27];
+#pragma unroll
+            for (int q = 0; q < 27; ++q) eb[q] = Eb[q];
+            touched[jb - c0] = 1;
+            double* blk = acc + (jb - c0) * 81;
+#pragma unroll
+            for (int r = 0; r < 9; ++r)
+#pragma unroll
+                for (int c = 0; c < 9; ++c)
+                    unsafeAtomicAdd(blk + r * 9 + c,
+                                    -(Ta[r * 3] * eb[c * 3] + Ta[r * 3 + 1] * eb[c * 3 + 1] +
+                                      Ta[r * 3 + 2] * eb[c * 3 + 2]));
         }
     }
+    __syncthreads();
+    // rows 9 ja .. 9 ja + 8, columns 9 c0 .. 9 (c0 + cw) - 1: contiguous per row
+    const bool shared_row = pe.w > 1;
+    const int rowlen = 9 * cw;
+    for (int e = threadIdx.x; e < 9 * rowlen; e += blockDim.x) {
+        const int r = e / rowlen, rem = e - r * rowlen;
+        const int c = rem / 9, col = rem - c * 9;
+        if (!touched[c]) continue;
+        double* dst = S + (9 * (int64_t)ja + r) * nd + 9 * (int64_t)c0 + rem;
+        const double v = acc[c * 81 + r * 9 + col];
+        if (shared_row) unsafeAtomicAdd(dst, v);
+        else *dst = v;
+    }
 }
 
-// Factor the diagonal tile (kb, kb) in place: L L^T = A; flag on failure.
-__global__ __launch_bounds__(256) void k_potrf_tile(int64_t nd, int32_t kb, double* __restrict__ S,
-                                                    int32_t* __restrict__ flag)
+// Factor the diagonal tile (kb, kb) in place, L L^T = A, by one wavefront
+// (lane r owns row r in LDS); flag bit 2 on failure.
+__global__ __launch_bounds__(64) void k_potrf_tile(int64_t nd, int32_t kb, double* __restrict__ S,
+                                                   int32_t* __restrict__ flag)
 {
     __shared__ double L[kT][kT + 1];
+    __shared__ double col[kT];  // column c of the factor, apart from L so loads and stores do not alias
+    const int r = threadIdx.x;
     const int64_t o = (int64_t)kb * kT;
     const int w = (int)(nd - o < kT ? nd - o : kT);
-    for (int e = threadIdx.x; e < kT * kT; e += blockDim.x) {
-        const int r = e / kT, c = e % kT;
-        L[r][c] = (r < w && c < w) ? S[(o + r) * nd + o + c] : (r == c ? 1.0 : 0.0);
-    }
+    for (int c = 0; c < kT; ++c) L[r][c] = (r < w && c < w) ? S[(o + r) * nd + o + c] : (r == c ? 1.0 : 0.0);
     __syncthreads();
-    __shared__ int bad;
-    if (threadIdx.x == 0) bad = 0;
-    __syncthreads();
+    bool bad = false;
     for (int c = 0; c < w; ++c) {
-        if (threadIdx.x == 0) {
-            const double d = L[c][c];
-            if (!(d > 0.0) || !isfinite(d)) bad = 1;
-            L[c][c] = sqrt(d > 0.0 ? d : 1.0);
+        const double dd = L[c][c];  // final: every update of column c has been applied
+        if (!(dd > 0.0) || !isfinite(dd)) bad = true;
+        const double d = sqrt(dd > 0.0 ? dd : 1.0);
+        __syncthreads();
+        double lrc = 0.0;
+        if (r == c) L[c][c] = d;
+        if (r > c) {
+            lrc = L[r][c] / d;
+            L[r][c] = lrc;
         }
+        col[r] = lrc;
         __syncthreads();
-        const double d = L[c][c];
-        for (int r = c + 1 + threadIdx.x; r < w; r += blockDim.x) L[r][c] /= d;
-        __syncthreads();
-        // trailing update of columns c+1.. within the tile
-        for (int e = threadIdx.x; e < (w - c - 1) * (w - c - 1); e += blockDim.x) {
-            const int r = c + 1 + e / (w - c - 1), q = c + 1 + e % (w - c - 1);
-            if (q <= r) L[r][q] -= L[r][c] * L[q][c];
+        if (r > c) {
+#pragma unroll 8
+            for (int q = c + 1; q <= r; ++q) L[r][q] -= lrc * col[q];
         }
         __syncthreads();
     }
-    for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
-        const int r = e / w, c = e % w;
-        S[(o + r) * nd + o + c] = c <= r ? L[r][c] : 0.0;
-    }
-    if (threadIdx.x == 0 && bad) atomicOr(flag, 4);
+    if (r < w)
+        for (int c = 0; c < w; ++c) S[(o + r) * nd + o + c] = c <= r ? L[r][c] : 0.0;
+    if (r == 0 && bad) atomicOr(flag, 4);
 }
 
-// Panel below the diagonal tile: A[ib][kb] = A[ib][kb] L11^-T, one workgroup
-// per tile row ib > kb.
-__global__ __launch_bounds__(256) void k_trsm_tiles(int64_t nd, int32_t kb, double* __restrict__ S)
+// Panel below the diagonal tile: A[ib][kb] = A[ib][kb] L11^-T, one wavefront
+// per tile row ib > kb, each lane solving its own row.
+__global__ __launch_bounds__(64) void k_trsm_tiles(int64_t nd, int32_t kb, double* __restrict__ S)
 {
     __shared__ double L[kT][kT + 1];
     __shared__ double X[kT][kT + 1];
+    const int r = threadIdx.x;
     const int64_t o = (int64_t)kb * kT;
     const int w = (int)(nd - o < kT ? nd - o : kT);
     const int64_t ro = o + kT * (int64_t)(1 + blockIdx.x);
     const int h = (int)(nd - ro < kT ? nd - ro : kT);
-    for (int e = threadIdx.x; e < kT * kT; e += blockDim.x) {
-        const int r = e / kT, c = e % kT;
+    for (int c = 0; c < kT; ++c) {
         L[r][c] = (r < w && c < w) ? S[(o + r) * nd + o + c] : 0.0;
         X[r][c] = (r < h && c < w) ? S[(ro + r) * nd + o + c] : 0.0;
     }
     __syncthreads();
-    // X L^T = A: column c of X from columns < c; each thread owns rows
-    for (int c = 0; c < w; ++c) {
-        for (int r = threadIdx.x; r < h; r += blockDim.x) {
-            double v = X[r][c];
-            for (int t = 0; t < c; ++t) v -= X[r][t] * L[c][t];
-            X[r][c] = v / L[c][c];
+    if (r < h) {
+        for (int c = 0; c < w; ++c) {
+            double v0 = X[r][c], v1 = 0.0, v2 = 0.0, v3 = 0.0;  // four chains for latency
+            int t = 0;
+            for (; t + 4 <= c; t += 4) {
+                v0 -= X[r][t] * L[c][t];
+                v1 -= X[r][t + 1] * L[c][t + 1];
+                v2 -= X[r][t + 2] * L[c][t + 2];
+                v3 -= X[r][t + 3] * L[c][t + 3];
+            }
+            for (; t < c; ++t) v0 -= X[r][t] * L[c][t];
+            X[r][c] = ((v0 + v1) + (v2 + v3)) / L[c][c];
         }
-        __syncthreads();
-    }
-    for (int e = threadIdx.x; e < h * w; e += blockDim.x) {
-        const int r = e / w, c = e % w;
-        S[(ro + r) * nd + o + c] = X[r][c];
+        for (int c = 0; c < w; ++c) S[(ro + r) * nd + o + c] = X[r][c];
     }
 }
 
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
 // Trailing update A[ib][jb] -= A[ib][kb] A[jb][kb]^T for kb < jb <= ib: one
-// workgroup per lower tile, 16 outputs per thread.
+// workgroup per lower tile, on the FP64 matrix cores.  Each wavefront forms a
+// 32 x 32 quarter as 2 x 2 products of 16 x 16 x 4 (v_mfma_f64_16x16x4f64:
+// lane l holds A[l % 16][l / 16] and B[l / 16][l % 16] of a step, and
+// D[4 q + l / 16][l % 16] in item q).
 __global__ __launch_bounds__(256) void k_syrk_tiles(int64_t nd, int32_t kb, double* __restrict__ S)
 {
     __shared__ double P[kT][kT + 1];
@@ -207,120 +244,137 @@ __global__ __launch_bounds__(256) void k_syrk_tiles(int64_t nd, int32_t kb, doub
         Q[r][c] = (r < wc && c < w) ? S[(co + r) * nd + o + c] : 0.0;
     }
     __syncthreads();
-    const int tr = threadIdx.x / 16, tc = threadIdx.x % 16;  // 16 x 16 threads, 4 x 4 outputs each
-    double acc[4][4] = {};
-    for (int t = 0; t < w; ++t) {
-        double p[4], q[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            p[u] = P[tr * 4 + u][t];
-            q[u] = Q[tc * 4 + u][t];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc[u][v] += p[u] * q[v];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r0 = (wave >> 1) * 32, c0 = (wave & 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+    dbl4 acc00 = {0.0, 0.0, 0.0, 0.0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
+    for (int t = 0; t < w; t += 4) {  // columns beyond w are zero in LDS
+        const double a0 = P[r0 + li][t + lk], a1 = P[r0 + 16 + li][t + lk];
+        const double b0 = Q[c0 + li][t + lk], b1 = Q[c0 + 16 + li][t + lk];
+        acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc00, 0, 0, 0);
+        acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc01, 0, 0, 0);
+        acc10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc10, 0, 0, 0);
+        acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc11, 0, 0, 0);
     }
+    const dbl4 acc[2][2] = {{acc00, acc01}, {acc10, acc11}};
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = tr * 4 + u, c = tc * 4 + v;
-            if (r < h && c < wc && (ib != jb || c <= r)) S[(ro + r) * nd + co + c] -= acc[u][v];
-        }
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = r0 + 16 * u + 4 * q + lk, c = c0 + 16 * v + li;
+                if (r < h && c < wc && (ib != jb || c <= r)) S[(ro + r) * nd + co + c] -= acc[u][v][q];
+            }
 }
 
-// x = S^-1 g with S = L L^T factored in place (lower triangle): forward then
-// backward substitution by one workgroup, a tile at a time (the tile's own
-// triangle by one wavefront, the coupling to the remaining rows by all).
-__global__ __launch_bounds__(1024) void k_dense_trsv(int64_t nd, const double* __restrict__ L,
-                                                     const double* __restrict__ g, double* __restrict__ x,
-                                                     double* __restrict__ y)
+// The triangle of tile kb: forward (L11 y1 = y1) or backward (L11^T x1 = x1)
+// in place on v[o .. o + w), one wavefront.
+template <bool FORWARD>
+__global__ __launch_bounds__(64) void k_trsv_diag(int64_t nd, int32_t kb, const double* __restrict__ L,
+                                                  double* __restrict__ v)
 {
-    for (int64_t r = threadIdx.x; r < nd; r += blockDim.x) y[r] = g[r];
+    __shared__ double A[kT][kT + 1];
+    const int lane = threadIdx.x;
+    const int64_t o = (int64_t)kb * kT;
+    const int w = (int)(nd - o < kT ? nd - o : kT);
+    for (int r = 0; r < w; ++r)  // coalesced: row r of the tile
+        A[r][lane] = lane < w ? L[(o + r) * nd + o + lane] : 0.0;
     __syncthreads();
-    const int32_t nb = (int32_t)((nd + kT - 1) / kT);
-    // forward: L y = g
-    for (int32_t kb = 0; kb < nb; ++kb) {
-        const int64_t o = (int64_t)kb * kT;
-        const int w = (int)(nd - o < kT ? nd - o : kT);
-        if (threadIdx.x < 64) {
-            const int lane = threadIdx.x;
-            double v = lane < w ? y[o + lane] : 0.0;
-            for (int c = 0; c < w; ++c) {
-                const double yc = __shfl(v, c, 64) / L[(o + c) * nd + o + c];
-                if (lane == c) v = yc;
-                if (lane > c && lane < w) v -= L[(o + lane) * nd + o + c] * yc;
-            }
-            if (lane < w) y[o + lane] = v;
+    double x = lane < w ? v[o + lane] : 0.0;
+    if (FORWARD) {
+        for (int c = 0; c < w; ++c) {
+            const double yc = __shfl(x, c, 64) / A[c][c];
+            if (lane == c) x = yc;
+            if (lane > c && lane < w) x -= A[lane][c] * yc;
         }
-        __syncthreads();
-        for (int64_t r = o + w + threadIdx.x; r < nd; r += blockDim.x) {
-            double s = 0.0;
-            for (int c = 0; c < w; ++c) s += L[r * nd + o + c] * y[o + c];
-            y[r] -= s;
+    } else {
+        for (int c = w - 1; c >= 0; --c) {
+            const double xc = __shfl(x, c, 64) / A[c][c];
+            if (lane == c) x = xc;
+            if (lane < c) x -= A[c][lane] * xc;
         }
-        __syncthreads();
     }
-    // backward: L^T x = y
-    for (int64_t r = threadIdx.x; r < nd; r += blockDim.x) x[r] = y[r];
+    if (lane < w) v[o + lane] = x;
+}
+
+// The coupling of tile kb to the remaining rows: forward, v[r] -= L[r][o..]
+// v[o..] for the rows below the tile; backward, v[r] -= L[o..][r] v[o..] for
+// the rows above it.  A thread per row.
+template <bool FORWARD>
+__global__ __launch_bounds__(256) void k_trsv_panel(int64_t nd, int32_t kb, const double* __restrict__ L,
+                                                    double* __restrict__ v)
+{
+    __shared__ double t[kT];
+    const int64_t o = (int64_t)kb * kT;
+    const int w = (int)(nd - o < kT ? nd - o : kT);
+    if (threadIdx.x < kT) t[threadIdx.x] = threadIdx.x < w ? v[o + threadIdx.x] : 0.0;
     __syncthreads();
-    for (int32_t kb = nb - 1; kb >= 0; --kb) {
-        const int64_t o = (int64_t)kb * kT;
-        const int w = (int)(nd - o < kT ? nd - o : kT);
-        if (threadIdx.x < 64) {
-            const int lane = threadIdx.x;
-            double v = lane < w ? x[o + lane] : 0.0;
-            for (int c = w - 1; c >= 0; --c) {
-                const double xc = __shfl(v, c, 64) / L[(o + c) * nd + o + c];
-                if (lane == c) v = xc;
-                if (lane < c) v -= L[(o + c) * nd + o + lane] * xc;
-            }
-            if (lane < w) x[o + lane] = v;
-        }
-        __syncthreads();
-        for (int64_t r = threadIdx.x; r < o; r += blockDim.x) {
-            double s = 0.0;
-            for (int c = 0; c < w; ++c) s += L[(o + c) * nd + r] * x[o + c];
-            x[r] -= s;
-        }
-        __syncthreads();
+    const int64_t r = (FORWARD ? o + w : 0) + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= (FORWARD ? nd : o)) return;
+    double s = 0.0;
+    if (FORWARD) {
+        const double* row = L + r * nd + o;
+        for (int c = 0; c < w; ++c) s += row[c] * t[c];
+    } else {
+        for (int c = 0; c < w; ++c) s += L[(o + c) * nd + r] * t[c];
     }
+    v[r] -= s;
 }
 
 template <typename T>
-hipError_t launch_dense_solve(const DensePlan& dp, const PointMajor& pm, const RecomputeInputs<T>& ri,
-                              const T* cinv, int32_t m, const double* bd, const double* g, double* x, double* S,
-                              double* ybuf, int32_t* flag, hipStream_t s)
+hipError_t launch_dense_solve(const DensePlan& dp, const PointMajor& pm, int64_t N, const RecomputeInputs<T>& ri,
+                              const T* cinv, int32_t m, const double* bd, const double* mj, const double* g,
+                              double* x, double* S, int32_t* flag, hipStream_t s)
 {
     const int64_t nd = 9 * (int64_t)m;
-    hipLaunchKernelGGL(k_dense_init, dim3(1024), dim3(256), 0, s, m, bd, S);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (dp.num_rows > 0) {
-        hipLaunchKernelGGL((k_dense_schur<T>), dim3((dp.num_rows + 3) / 4), dim3(256), 0, s, dp.num_rows, dp.rows,
-                           pm.cam, pm.pt, ri.wobs, ri.pts, ri.ck, ri.ck64, cinv, m, S);
+    hipError_t e;
+    if (N > 0) {
+        hipLaunchKernelGGL((k_dense_coupling<T>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N, pm.cam,
+                           pm.pt, ri.wobs, ri.pts, ri.ck, ri.ck64, dp.E);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
+    const int32_t nchunk = (m + kChunk - 1) / kChunk;
+    hipLaunchKernelGGL(k_dense_zero, dim3(2048), dim3(256), 0, s, nd * nd, S);
+    hipLaunchKernelGGL((k_dense_rows<T>), dim3((unsigned)(dp.num_pieces * nchunk)), dim3(256), 0, s, m, nchunk,
+                       dp.pieces, dp.cm_pm, dp.poff, pm.cam, pm.pt, dp.E, cinv, bd, mj, S);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     const int32_t nb = (int32_t)((nd + kT - 1) / kT);
     for (int32_t kb = 0; kb < nb; ++kb) {
-        hipLaunchKernelGGL(k_potrf_tile, dim3(1), dim3(256), 0, s, nd, kb, S, flag);
+        hipLaunchKernelGGL(k_potrf_tile, dim3(1), dim3(64), 0, s, nd, kb, S, flag);
         const int32_t rem = nb - kb - 1;
         if (rem > 0) {
-            hipLaunchKernelGGL(k_trsm_tiles, dim3(rem), dim3(256), 0, s, nd, kb, S);
+            hipLaunchKernelGGL(k_trsm_tiles, dim3(rem), dim3(64), 0, s, nd, kb, S);
             hipLaunchKernelGGL(k_syrk_tiles, dim3(rem * (rem + 1) / 2), dim3(256), 0, s, nd, kb, S);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_dense_trsv, dim3(1), dim3(1024), 0, s, nd, S, g, x, ybuf);
+    // x = S^-1 g: forward into x, then backward in place
+    if ((e = hipMemcpyAsync(x, g, sizeof(double) * nd, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+    for (int32_t kb = 0; kb < nb; ++kb) {
+        hipLaunchKernelGGL((k_trsv_diag<true>), dim3(1), dim3(64), 0, s, nd, kb, S, x);
+        const int64_t below = nd - (int64_t)(kb + 1) * kT;
+        if (below > 0)
+            hipLaunchKernelGGL((k_trsv_panel<true>), dim3((unsigned)((below + 255) / 256)), dim3(256), 0, s, nd, kb,
+                               S, x);
+    }
+    for (int32_t kb = nb - 1; kb >= 0; --kb) {
+        hipLaunchKernelGGL((k_trsv_diag<false>), dim3(1), dim3(64), 0, s, nd, kb, S, x);
+        const int64_t above = (int64_t)kb * kT;
+        if (above > 0)
+            hipLaunchKernelGGL((k_trsv_panel<false>), dim3((unsigned)((above + 255) / 256)), dim3(256), 0, s, nd,
+                               kb, S, x);
+    }
     return hipGetLastError();
 }
 
-template hipError_t launch_dense_solve<float>(const DensePlan&, const PointMajor&, const RecomputeInputs<float>&,
-                                              const float*, int32_t, const double*, const double*, double*, double*,
-                                              double*, int32_t*, hipStream_t);
-template hipError_t launch_dense_solve<double>(const DensePlan&, const PointMajor&, const RecomputeInputs<double>&,
-                                               const double*, int32_t, const double*, const double*, double*,
-                                               double*, double*, int32_t*, hipStream_t);
+template hipError_t launch_dense_solve<float>(const DensePlan&, const PointMajor&, int64_t,
+                                              const RecomputeInputs<float>&, const float*, int32_t, const double*,
+                                              const double*, const double*, double*, double*, int32_t*,
+                                              hipStream_t);
+template hipError_t launch_dense_solve<double>(const DensePlan&, const PointMajor&, int64_t,
+                                               const RecomputeInputs<double>&, const double*, int32_t,
+                                               const double*, const double*, const double*, double*, double*,
+                                               int32_t*, hipStream_t);
 
 }  // namespace ba
