@@ -15,10 +15,12 @@
 //     many workgroups.  The diagonal block starts from B~_a plus
 //     the per-observation terms -sum E_k C~^-1 E_k^T (the Schur-Jacobi
 //     camera-major pass), so an observation never pairs with itself here.
-//   * Cholesky, right-looking over 64 x 64 tiles: k_potrf_tile factors the
-//     diagonal tile (one wavefront, a row per lane), k_trsm_tiles forms the
-//     panel below it (a row per lane), and k_syrk_tiles updates the trailing
-//     lower tiles on the FP64 matrix cores.
+//   * Cholesky, blocked right-looking over 64 x 64 tiles: k_potrf_tile factors
+//     the diagonal tile (one wavefront, a row per lane), k_trsm_tiles forms
+//     the panel below it (a row per lane), and k_syrk_tiles updates lower
+//     tiles on the FP64 matrix cores: within a super-panel of 4 tile columns
+//     by each column as it is done, beyond it once per super-panel with rank
+//     256, so the trailing matrix is read and written a quarter as often.
 //   * k_trsv_diag / k_trsv_panel: L y = g and L^T x = y a tile at a time, the
 //     tile's triangle by one wavefront and the coupling to the remaining rows
 //     by many workgroups.
@@ -28,6 +30,7 @@ namespace ba {
 
 namespace {
 constexpr int kT = 64;       // factorisation tile edge
+constexpr int kSuper = 4;    // tile columns per super-panel (rank of the trailing update: 64 kSuper)
 constexpr int kChunk = 64;  // block columns per workgroup in k_dense_rows (41.5 KB of LDS)
 }  // namespace
 
@@ -216,45 +219,50 @@ __global__ __launch_bounds__(64) void k_trsm_tiles(int64_t nd, int32_t kb, doubl
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-// Trailing update A[ib][jb] -= A[ib][kb] A[jb][kb]^T for kb < jb <= ib: one
-// workgroup per lower tile, on the FP64 matrix cores.  Each wavefront forms a
-// 32 x 32 quarter as 2 x 2 products of 16 x 16 x 4 (v_mfma_f64_16x16x4f64:
-// lane l holds A[l % 16][l / 16] and B[l / 16][l % 16] of a step, and
-// D[4 q + l / 16][l % 16] in item q).
-__global__ __launch_bounds__(256) void k_syrk_tiles(int64_t nd, int32_t kb, double* __restrict__ S)
+// Trailing update of the lower tiles (ib, jb) with j0 <= jb < j1 and
+// ib >= jb by the tile columns k0 .. k0 + kw - 1 of the factor:
+// A[ib][jb] -= sum_kc A[ib][kc] A[jb][kc]^T (rank 64 kw).  One workgroup per
+// tile, on the FP64 matrix cores: each wavefront forms a 32 x 32 quarter as
+// 2 x 2 products of 16 x 16 x 4 (v_mfma_f64_16x16x4f64: lane l holds
+// A[l % 16][l / 16] and B[l / 16][l % 16] of a step, and D[4 q + l / 16][l % 16]
+// in item q), accumulating over all kw panel tiles before the one
+// read-modify-write of the output tile.
+__global__ __launch_bounds__(256) void k_syrk_tiles(int64_t nd, int32_t k0, int32_t kw, int32_t j0,
+                                                    double* __restrict__ S)
 {
     __shared__ double P[kT][kT + 1];
     __shared__ double Q[kT][kT + 1];
-    // blockIdx.x enumerates the lower tiles (ib, jb) of the trailing matrix
-    const int32_t rem = (int32_t)((nd + kT - 1) / kT) - kb - 1;
-    int32_t idx = blockIdx.x, ib = 0;
-    while (idx >= ib + 1) {  // row ib holds ib + 1 tiles
-        idx -= ib + 1;
-        ++ib;
+    const int32_t nb = (int32_t)((nd + kT - 1) / kT);
+    // blockIdx.x enumerates the tiles column by column: column jb holds nb - jb tiles
+    int32_t idx = blockIdx.x, jb = j0;
+    while (idx >= nb - jb) {
+        idx -= nb - jb;
+        ++jb;
     }
-    const int32_t jb = idx;
-    if (ib >= rem) return;
-    const int64_t o = (int64_t)kb * kT;
-    const int64_t ro = o + kT * (int64_t)(1 + ib), co = o + kT * (int64_t)(1 + jb);
+    const int32_t ib = jb + idx;
+    const int64_t ro = kT * (int64_t)ib, co = kT * (int64_t)jb;
     const int h = (int)(nd - ro < kT ? nd - ro : kT), wc = (int)(nd - co < kT ? nd - co : kT);
-    const int w = (int)(nd - o < kT ? nd - o : kT);
-    for (int e = threadIdx.x; e < kT * kT; e += blockDim.x) {
-        const int r = e / kT, c = e % kT;
-        P[r][c] = (r < h && c < w) ? S[(ro + r) * nd + o + c] : 0.0;
-        Q[r][c] = (r < wc && c < w) ? S[(co + r) * nd + o + c] : 0.0;
-    }
-    __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r0 = (wave >> 1) * 32, c0 = (wave & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
     dbl4 acc00 = {0.0, 0.0, 0.0, 0.0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
-    for (int t = 0; t < w; t += 4) {  // columns beyond w are zero in LDS
-        const double a0 = P[r0 + li][t + lk], a1 = P[r0 + 16 + li][t + lk];
-        const double b0 = Q[c0 + li][t + lk], b1 = Q[c0 + 16 + li][t + lk];
-        acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc00, 0, 0, 0);
-        acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc01, 0, 0, 0);
-        acc10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc10, 0, 0, 0);
-        acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc11, 0, 0, 0);
+    for (int32_t kc = k0; kc < k0 + kw; ++kc) {  // panel tiles are full: kc < jb <= nb - 1
+        const int64_t o = kT * (int64_t)kc;
+        __syncthreads();  // the previous panel tile has been consumed
+        for (int e = threadIdx.x; e < kT * kT; e += blockDim.x) {
+            const int r = e / kT, c = e % kT;
+            P[r][c] = r < h ? S[(ro + r) * nd + o + c] : 0.0;
+            Q[r][c] = r < wc ? S[(co + r) * nd + o + c] : 0.0;
+        }
+        __syncthreads();
+        for (int t = 0; t < kT; t += 4) {
+            const double a0 = P[r0 + li][t + lk], a1 = P[r0 + 16 + li][t + lk];
+            const double b0 = Q[c0 + li][t + lk], b1 = Q[c0 + 16 + li][t + lk];
+            acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc00, 0, 0, 0);
+            acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc01, 0, 0, 0);
+            acc10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc10, 0, 0, 0);
+            acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc11, 0, 0, 0);
+        }
     }
     const dbl4 acc[2][2] = {{acc00, acc01}, {acc10, acc11}};
 #pragma unroll
@@ -266,6 +274,14 @@ __global__ __launch_bounds__(256) void k_syrk_tiles(int64_t nd, int32_t kb, doub
                 const int r = r0 + 16 * u + 4 * q + lk, c = c0 + 16 * v + li;
                 if (r < h && c < wc && (ib != jb || c <= r)) S[(ro + r) * nd + co + c] -= acc[u][v][q];
             }
+}
+
+// Blocks of the lower triangle in tile columns j0 .. j1 - 1 (nb tile rows).
+static unsigned column_tiles(int32_t nb, int32_t j0, int32_t j1)
+{
+    int64_t t = 0;
+    for (int32_t j = j0; j < j1; ++j) t += nb - j;
+    return (unsigned)t;
 }
 
 // The triangle of tile kb: forward (L11 y1 = y1) or backward (L11^T x1 = x1)
@@ -339,15 +355,26 @@ hipError_t launch_dense_solve(const DensePlan& dp, const PointMajor& pm, int64_t
     hipLaunchKernelGGL((k_dense_rows<T>), dim3((unsigned)(dp.num_pieces * nchunk)), dim3(256), 0, s, m, nchunk,
                        dp.pieces, dp.cm_pm, dp.poff, pm.cam, pm.pt, dp.E, cinv, bd, mj, S);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    // Blocked right-looking Cholesky: super-panels of kSuper tile columns are
+    // factored column by column (each column updating only the rest of its
+    // super-panel), then the trailing matrix takes one rank-64 kSuper update.
     const int32_t nb = (int32_t)((nd + kT - 1) / kT);
-    for (int32_t kb = 0; kb < nb; ++kb) {
-        hipLaunchKernelGGL(k_potrf_tile, dim3(1), dim3(64), 0, s, nd, kb, S, flag);
-        const int32_t rem = nb - kb - 1;
-        if (rem > 0) {
-            hipLaunchKernelGGL(k_trsm_tiles, dim3(rem), dim3(64), 0, s, nd, kb, S);
-            hipLaunchKernelGGL(k_syrk_tiles, dim3(rem * (rem + 1) / 2), dim3(256), 0, s, nd, kb, S);
+    for (int32_t sb = 0; sb < nb; sb += kSuper) {
+        const int32_t se = min(sb + kSuper, nb);
+        for (int32_t kb = sb; kb < se; ++kb) {
+            hipLaunchKernelGGL(k_potrf_tile, dim3(1), dim3(64), 0, s, nd, kb, S, flag);
+            const int32_t rem = nb - kb - 1;
+            if (rem > 0) hipLaunchKernelGGL(k_trsm_tiles, dim3(rem), dim3(64), 0, s, nd, kb, S);
+            if (kb + 1 < se)
+                hipLaunchKernelGGL(k_syrk_tiles, dim3(column_tiles(nb, kb + 1, se)), dim3(256), 0, s, nd, kb, 1,
+                                   kb + 1, S);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
         }
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (se < nb) {
+            hipLaunchKernelGGL(k_syrk_tiles, dim3(column_tiles(nb, se, nb)), dim3(256), 0, s, nd, sb, se - sb, se,
+                               S);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
     }
     // x = S^-1 g: forward into x, then backward in place
     if ((e = hipMemcpyAsync(x, g, sizeof(double) * nd, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
