@@ -1,0 +1,65 @@
+"""Host-side checks of bench.py's measurement arithmetic (no GPU): the
+algorithmic byte and flop counts the roofline divides by, the time-to-cost
+comparison, the counter-summary parser and the one-GPU guard."""
+import os
+import shutil
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_algorithmic_counts_at_29m():
+    n, N, m = 4_500_000, 29_000_000, 13_700
+    # stored design: 27 words of E and a camera index per observation, 6 words and an offset per point
+    assert bench.hot_pass_algorithmic_bytes(n, N, 4) == N * (27 * 4 + 4) + n * (6 * 4 + 4)
+    assert abs(bench.hot_pass_algorithmic_bytes(n, N, 4) / 1e9 - 3.374) < 1e-3
+    # the whole matvec adds the camera vectors in and out and the damped camera blocks
+    assert bench.matvec_algorithmic_bytes(m, n, N, 8) - bench.hot_pass_algorithmic_bytes(n, N, 8) == \
+        m * (9 * 8 * 2 + 45 * 8)
+    # recomputing pass: 177 flops per observation and 15 per point
+    assert bench.free_pass_algorithmic_flops(n, N) == 177 * N + 15 * n
+    assert abs(bench.VALU_ISSUE_PER_S - 614.4e9) < 1.0
+
+
+def test_time_to_cost_and_equal_cost_speedup():
+    rep64 = dict(cost=np.array([10.0, 5.0, 2.0, 1.0]), ms=np.array([4.0, 4.0, 4.0, 4.0]), final_cost=1.0)
+    rep32 = dict(cost=np.array([9.0, 4.0, 1.00005, 0.9]), ms=np.array([2.0, 2.0, 2.0, 2.0]), final_cost=0.9)
+    assert bench.time_to_cost(rep64, 2.0) == 12.0
+    assert bench.time_to_cost(rep64, 0.5) is None
+    sp = bench.equal_cost_speedup(rep32, rep64)
+    # target 1.0001: FP64 reaches it after 4 iterations (16 ms), FP32-mixed after 3 (6 ms)
+    assert sp["fp64_ms"] == 16.0 and sp["fp32_mixed_ms"] == 6.0 and sp["speedup"] == pytest.approx(16.0 / 6.0)
+
+
+def test_counter_summary_is_read_only_for_matching_sources(tmp_path, monkeypatch):
+    kernel = "k_schur_free<float>"
+    summary = os.path.join(ROOT, "profiles", bench.COUNTER_FILES[kernel])
+    fake = tmp_path / "repo"
+    (fake / "profiles").mkdir(parents=True)
+    csrc = fake / "paper_2112_01349_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    for f in ("matvec.hip", "ba_internal.h", "camera_model.h"):
+        shutil.copy(os.path.join(ROOT, "paper_2112_01349_amd", "csrc", f), csrc / f)
+    shutil.copy(summary, fake / "profiles" / os.path.basename(summary))
+    monkeypatch.setattr(bench, "ROOT", str(fake))
+    got = bench.counted(kernel)
+    fields = dict(line.strip().partition(": ")[::2] for line in open(summary) if ": " in line)
+    if got:  # the committed summary was taken from these sources
+        assert got["traffic_bytes_per_launch"] == float(fields["traffic_bytes_per_launch"])
+    # any change to a kernel source makes the figures stale
+    with open(csrc / "matvec.hip", "a") as fh:
+        fh.write("\n// edited\n")
+    assert bench.counted(kernel) == {}
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
