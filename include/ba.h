@@ -12,7 +12,8 @@
  *     environment at ba_create stores and streams them instead);
  *   - the reduced camera system (Eq. schur_x_c) solved by block-Jacobi PCG
  *     (Alg. 2) whose matrix-vector products are implicit Schur products
- *     (Alg. 3);
+ *     (Alg. 3); options: the Schur-Jacobi blocks as the preconditioner, or
+ *     the system written out and Cholesky-factored (ba_options.solver);
  *   - point back-substitution (Eq. schur_x_p) and the additive update
  *     (Alg. 1, last step), inside a trust-region accept/reject loop
  *     (supplementary Sec. C: LM with a Ceres-like trust region).
