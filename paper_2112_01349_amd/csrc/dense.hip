@@ -18,9 +18,9 @@
 //   * Cholesky, blocked right-looking over 64 x 64 tiles: k_potrf_tile factors
 //     the diagonal tile (one wavefront, a row per lane), k_trsm_tiles forms
 //     the panel below it (a row per lane), and k_syrk_tiles updates lower
-//     tiles on the FP64 matrix cores: within a super-panel of 4 tile columns
+//     tiles on the FP64 matrix cores: within a super-panel of 8 tile columns
 //     by each column as it is done, beyond it once per super-panel with rank
-//     256, so the trailing matrix is read and written a quarter as often.
+//     512, so the trailing matrix is read and written an eighth as often.
 //   * k_trsv_diag / k_trsv_panel: L y = g and L^T x = y a tile at a time, the
 //     tile's triangle by one wavefront and the coupling to the remaining rows
 //     by many workgroups.
@@ -30,7 +30,7 @@ namespace ba {
 
 namespace {
 constexpr int kT = 64;       // factorisation tile edge
-constexpr int kSuper = 4;    // tile columns per super-panel (rank of the trailing update: 64 kSuper)
+constexpr int kSuper = 8;    // tile columns per super-panel (rank of the trailing update: 64 kSuper)
 constexpr int kChunk = 64;  // block columns per workgroup in k_dense_rows (41.5 KB of LDS)
 }  // namespace
 
