@@ -157,7 +157,15 @@ __global__ __launch_bounds__(64) void k_potrf_tile(int64_t nd, int32_t kb, doubl
     const int r = threadIdx.x;
     const int64_t o = (int64_t)kb * kT;
     const int w = (int)(nd - o < kT ? nd - o : kT);
-    for (int c = 0; c < kT; ++c) L[r][c] = (r < w && c < w) ? S[(o + r) * nd + o + c] : (r == c ? 1.0 : 0.0);
+    // row by row, lane = column; every load reads a valid (clamped) address
+    // and is selected afterwards, so the loads are issued back to back
+    const int rc = r < w ? r : w - 1;
+#pragma unroll 16
+    for (int q = 0; q < w; ++q) {
+        const double v = S[(o + q) * nd + o + rc];
+        L[q][r] = r < w ? v : 0.0;  // q < w <= r: off the diagonal
+    }
+    for (int q = w; q < kT; ++q) L[q][r] = q == r ? 1.0 : 0.0;
     __syncthreads();
     bool bad = false;
     for (int c = 0; c < w; ++c) {
@@ -179,8 +187,8 @@ __global__ __launch_bounds__(64) void k_potrf_tile(int64_t nd, int32_t kb, doubl
         }
         __syncthreads();
     }
-    if (r < w)
-        for (int c = 0; c < w; ++c) S[(o + r) * nd + o + c] = c <= r ? L[r][c] : 0.0;
+    for (int q = 0; q < w; ++q)
+        if (r < w) S[(o + q) * nd + o + r] = r <= q ? L[q][r] : 0.0;
     if (r == 0 && bad) atomicOr(flag, 4);
 }
 
@@ -195,10 +203,19 @@ __global__ __launch_bounds__(64) void k_trsm_tiles(int64_t nd, int32_t kb, doubl
     const int w = (int)(nd - o < kT ? nd - o : kT);
     const int64_t ro = o + kT * (int64_t)(1 + blockIdx.x);
     const int h = (int)(nd - ro < kT ? nd - ro : kT);
-    for (int c = 0; c < kT; ++c) {
-        L[r][c] = (r < w && c < w) ? S[(o + r) * nd + o + c] : 0.0;
-        X[r][c] = (r < h && c < w) ? S[(ro + r) * nd + o + c] : 0.0;
+    const int rc = r < w ? r : w - 1;  // row by row, lane = column, clamped loads as in k_potrf_tile
+#pragma unroll 16
+    for (int q = 0; q < w; ++q) {
+        const double v = S[(o + q) * nd + o + rc];
+        L[q][r] = r < w ? v : 0.0;
     }
+#pragma unroll 16
+    for (int q = 0; q < h; ++q) {
+        const double v = S[(ro + q) * nd + o + rc];
+        X[q][r] = r < w ? v : 0.0;
+    }
+    for (int q = w; q < kT; ++q) L[q][r] = 0.0;
+    for (int q = h; q < kT; ++q) X[q][r] = 0.0;
     __syncthreads();
     if (r < h) {
         for (int c = 0; c < w; ++c) {
@@ -213,8 +230,10 @@ __global__ __launch_bounds__(64) void k_trsm_tiles(int64_t nd, int32_t kb, doubl
             for (; t < c; ++t) v0 -= X[r][t] * L[c][t];
             X[r][c] = ((v0 + v1) + (v2 + v3)) / L[c][c];
         }
-        for (int c = 0; c < w; ++c) S[(ro + r) * nd + o + c] = X[r][c];
     }
+    __syncthreads();
+    for (int q = 0; q < h; ++q)
+        if (r < w) S[(ro + q) * nd + o + r] = X[q][r];
 }
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
@@ -294,8 +313,13 @@ __global__ __launch_bounds__(64) void k_trsv_diag(int64_t nd, int32_t kb, const 
     const int lane = threadIdx.x;
     const int64_t o = (int64_t)kb * kT;
     const int w = (int)(nd - o < kT ? nd - o : kT);
-    for (int r = 0; r < w; ++r)  // coalesced: row r of the tile
-        A[r][lane] = lane < w ? L[(o + r) * nd + o + lane] : 0.0;
+    const int lc = lane < w ? lane : w - 1;
+#pragma unroll 16
+    for (int r = 0; r < w; ++r) {  // row r of the tile, lane = column, clamped loads
+        const double v = L[(o + r) * nd + o + lc];
+        A[r][lane] = lane < w ? v : 0.0;
+    }
+    for (int r = w; r < kT; ++r) A[r][lane] = 0.0;
     __syncthreads();
     double x = lane < w ? v[o + lane] : 0.0;
     if (FORWARD) {
