@@ -598,7 +598,7 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     sp.has_cold = A.get<uint8_t>(n);
     sp.hot_part = A.get<double>((int64_t)sp.num_wg * sp.K * 9);
     sp.hot_fold = A.get<double>((int64_t)kHotFold * sp.K * 9);
-    sp.bcold = A.get<char>(3 * (int64_t)n * (int64_t)tsz);
+    sp.bcold = A.get<char>(kBcold * (int64_t)n * (int64_t)tsz);
     sp.cold.cam = A.get<int32_t>(sp.cold.N);
     sp.cold.pt = A.get<int32_t>(sp.cold.N);
     sp.cold.hcp = sp.recompute ? nullptr : A.get<char>(27 * sp.cold.N * (int64_t)tsz);
@@ -807,6 +807,7 @@ static ba_status build_system(ba_problem* P)
                                      P->wpt, (T*)P->wobs, s));
     BA_TRY(P, launch_build_cameras<T>(P->cm, P->m, P->N, P->pts, js, P->opt.huber_delta, false, P->hcc, P->vcam,
                                       P->sp.cold.N, (T*)P->sp.cold.hcp, (T*)P->sp.cold.w, s));
+    if (P->sp.recompute) BA_TRY(P, launch_cold_points<T>(P->sp, P->n, P->pts, s));
     return BA_OK;
 }
 

@@ -18,6 +18,7 @@ constexpr int kRedBlock = 256;  // threads of reduction blocks
 constexpr int kCamSlotWords = 54;  // 45 upper-triangle B terms + 9 v terms
 constexpr int kSlotSeg = 32;       // slots summed by one wavefront before the per-camera combine
 constexpr int kHotFold = 8;        // slices the per-workgroup hot partials are folded into
+constexpr int kBcold = 8;          // words of T per point record read by the cold pass
 
 // Scalars of one PCG run, kept on the device.  Kernels of the PCG loop read
 // `done` first and do nothing once it is set, so the host can enqueue
@@ -127,7 +128,8 @@ struct SchurPlan {
     uint8_t* has_cold = nullptr;    // [n] point has an observation in the cold stream
     void* hot_part = nullptr;       // [num_wg][K][9] FP64
     double* hot_fold = nullptr;     // [kHotFold][K][9] FP64
-    void* bcold = nullptr;          // [n][3] of T
+    void* bcold = nullptr;          // [n][kBcold] of T: b_i for the cold pass, and (recomputing
+                                    // product) the point cast to T, one record per point
     ColdStream cold;
     // the recomputing product (mode 0 when set): point-aligned segments, short
     // (<= 64 observations of whole points) and long (one longer point), as
@@ -225,6 +227,11 @@ hipError_t launch_dense_solve(const DensePlan& dp, const PointMajor& pm, int64_t
 template <typename T>
 hipError_t launch_backsub_stored(const PointMajor& pm, const T* hcp, const T* cinv, const double* wpt,
                                  const T* xcam, double* dp, hipStream_t s);
+
+// Writes the point half of the cold pass's per-point records (the point cast
+// to T) for the current state; run whenever the points change.
+template <typename T>
+hipError_t launch_cold_points(const SchurPlan& sp, int32_t n, const double* pts, hipStream_t s);
 
 // Full implicit Schur product.  mode 0: out = q = B~ x - E C~^-1 E^T x, then
 // p^T q, alpha and the matvec count into sc (skipped once sc->done);

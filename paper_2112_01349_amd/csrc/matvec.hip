@@ -181,9 +181,9 @@ __global__ __launch_bounds__(HotThreads<T>::value) void k_schur_hot(
                     const T b1 = c6[1] * a0 + c6[3] * a1 + c6[4] * a2;
                     const T b2 = c6[2] * a0 + c6[4] * a1 + c6[5] * a2;
                     if (lane == seg_e && hc) {
-                        bcold[3 * ii] = b0;
-                        bcold[3 * ii + 1] = b1;
-                        bcold[3 * ii + 2] = b2;
+                        bcold[kBcold * ii] = b0;
+                        bcold[kBcold * ii + 1] = b1;
+                        bcold[kBcold * ii + 2] = b2;
                     }
                     if (cj < K) add_hot<T>(cl, cj, ch, b0, b1, b2);
                 }
@@ -225,9 +225,9 @@ __global__ __launch_bounds__(HotThreads<T>::value) void k_schur_hot(
                         const T s1 = q6[1] * p0 + q6[3] * p1 + q6[4] * p2;
                         const T s2 = q6[2] * p0 + q6[4] * p1 + q6[5] * p2;
                         if (lane == 0 && has_cold[s_pt]) {
-                            bcold[3 * (int64_t)s_pt] = s0;
-                            bcold[3 * (int64_t)s_pt + 1] = s1;
-                            bcold[3 * (int64_t)s_pt + 2] = s2;
+                            bcold[kBcold * (int64_t)s_pt] = s0;
+                            bcold[kBcold * (int64_t)s_pt + 1] = s1;
+                            bcold[kBcold * (int64_t)s_pt + 2] = s2;
                         }
                         if (K > 0)  // with no hot camera the cold pass does the camera side
                             for (int64_t v = t; v <= u; ++v) {
@@ -248,9 +248,9 @@ __global__ __launch_bounds__(HotThreads<T>::value) void k_schur_hot(
                         b1 = c6[1] * a0 + c6[3] * a1 + c6[4] * a2;
                         b2 = c6[2] * a0 + c6[4] * a1 + c6[5] * a2;
                         if (lane == 63 && hc) {
-                            bcold[3 * ii] = b0;
-                            bcold[3 * ii + 1] = b1;
-                            bcold[3 * ii + 2] = b2;
+                            bcold[kBcold * ii] = b0;
+                            bcold[kBcold * ii + 1] = b1;
+                            bcold[kBcold * ii + 2] = b2;
                         }
                         if (cj < K) add_hot<T>(cl, cj, ch, b0, b1, b2);
                     }
@@ -488,9 +488,9 @@ __device__ __forceinline__ void free_short(const FreeRow<T>& r, const FreeData<T
         return;
     }
     if (valid && lane == seg_e && d.hc) {
-        bcold[3 * (int64_t)r.i] = b0;
-        bcold[3 * (int64_t)r.i + 1] = b1;
-        bcold[3 * (int64_t)r.i + 2] = b2;
+        bcold[kBcold * (int64_t)r.i] = b0;
+        bcold[kBcold * (int64_t)r.i + 1] = b1;
+        bcold[kBcold * (int64_t)r.i + 2] = b2;
     }
     if (valid && r.j < K) free_add_hot<T>(cl, r.j, o, d.hd, r.w, b0, b1, b2);
 }
@@ -589,9 +589,9 @@ __global__ __launch_bounds__(HotThreads<T>::value) void k_schur_free(
             continue;
         }
         if (lane == 0 && has_cold[i]) {
-            bcold[3 * (int64_t)i] = b0;
-            bcold[3 * (int64_t)i + 1] = b1;
-            bcold[3 * (int64_t)i + 2] = b2;
+            bcold[kBcold * (int64_t)i] = b0;
+            bcold[kBcold * (int64_t)i + 1] = b1;
+            bcold[kBcold * (int64_t)i + 2] = b2;
         }
         if (K > 0)
             for (int32_t r = s0; r < s1; r += 64) {
@@ -652,9 +652,9 @@ __global__ __launch_bounds__(HotThreads<T>::value) void k_schur_rhs(
             const T b1 = c6[1] * w0 + c6[3] * w1 + c6[4] * w2;
             const T b2 = c6[2] * w0 + c6[4] * w1 + c6[5] * w2;
             if ((lane == 0 || prev != i) && has_cold[i]) {
-                bcold[3 * (int64_t)i] = b0;
-                bcold[3 * (int64_t)i + 1] = b1;
-                bcold[3 * (int64_t)i + 2] = b2;
+                bcold[kBcold * (int64_t)i] = b0;
+                bcold[kBcold * (int64_t)i + 1] = b1;
+                bcold[kBcold * (int64_t)i + 2] = b2;
             }
             if (j < K) add_hot<T>(cl, j, h, b0, b1, b2);
         }
@@ -693,7 +693,7 @@ __global__ __launch_bounds__(256) void k_schur_cold(int64_t Nc, int32_t num_chun
         if (valid) {
             j = ccam[k];
             const int32_t i = cpt[k];
-            const T b0 = bcold[3 * (int64_t)i], b1 = bcold[3 * (int64_t)i + 1], b2 = bcold[3 * (int64_t)i + 2];
+            const T b0 = bcold[kBcold * (int64_t)i], b1 = bcold[kBcold * (int64_t)i + 1], b2 = bcold[kBcold * (int64_t)i + 2];
 #pragma unroll
             for (int a = 0; a < 9; ++a)
                 c[a] = __builtin_nontemporal_load(chcp + (int64_t)(a * 3) * Nc + k) * b0 +
@@ -785,12 +785,11 @@ __global__ __launch_bounds__(256) void k_schur_cold_free(int64_t Nc, int32_t num
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             load_head<T>(ck, j[u], hd[u]);
-            const double* Xp = pts + 3 * (int64_t)i[u];
-            const T* bp = bcold + 3 * (int64_t)i[u];
+            const T* bp = bcold + kBcold * (int64_t)i[u];  // b_i and the point: one record
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                X[u][a] = (T)Xp[a];
                 b[u][a] = bp[a];
+                X[u][a] = bp[4 + a];
             }
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -943,6 +942,33 @@ hipError_t prepare_schur_kernels(int32_t K)
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void*)k_schur_rhs<T>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
+
+// The point half of the cold pass's per-point records: the point cast to T,
+// for points with a cold observation.  Points change only with the state, so
+// this runs with the build; the product passes write the b_i half.
+template <typename T>
+__global__ void k_cold_points(int32_t n, const double* __restrict__ pts, const uint8_t* __restrict__ has_cold,
+                              T* __restrict__ bcold)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !has_cold[i]) return;
+    T* rec = bcold + kBcold * (int64_t)i;
+    rec[4] = (T)pts[3 * (int64_t)i];
+    rec[5] = (T)pts[3 * (int64_t)i + 1];
+    rec[6] = (T)pts[3 * (int64_t)i + 2];
+}
+
+template <typename T>
+hipError_t launch_cold_points(const SchurPlan& sp, int32_t n, const double* pts, hipStream_t s)
+{
+    if (n > 0 && sp.cold.N > 0)
+        hipLaunchKernelGGL((k_cold_points<T>), dim3((n + 255) / 256), dim3(256), 0, s, n, pts, sp.has_cold,
+                           (T*)sp.bcold);
+    return hipGetLastError();
+}
+
+template hipError_t launch_cold_points<float>(const SchurPlan&, int32_t, const double*, hipStream_t);
+template hipError_t launch_cold_points<double>(const SchurPlan&, int32_t, const double*, hipStream_t);
 
 template <typename T>
 hipError_t launch_schur_product(int mode, const SchurPlan& sp, const PointMajor& pm, int64_t N, const T* hcp,
