@@ -286,6 +286,23 @@ __global__ __launch_bounds__(HotThreads<T>::value) void k_schur_hot(
 // So E_k^T x = J_p^T (w J_c x) and E_k b = J_c^T (w J_p b); the J_l^T of the
 // camera side is applied once per hot camera when the table is written out.
 
+// Slice f of the fold of the per-workgroup hot partials [G][K*9]: the sum of a
+// contiguous range of workgroups, in order, for entry t.
+__device__ __forceinline__ void fold_slice(int32_t t, int32_t f, int32_t K9, int32_t G,
+                                           const double* __restrict__ hot_part, double* __restrict__ fold)
+{
+    if (t >= K9) return;
+    const int32_t w0 = (int32_t)((int64_t)f * G / kHotFold), w1 = (int32_t)((int64_t)(f + 1) * G / kHotFold);
+    double c0 = 0.0, c1 = 0.0;
+    int32_t w = w0;
+    for (; w + 2 <= w1; w += 2) {
+        c0 += hot_part[(int64_t)w * K9 + t];
+        c1 += hot_part[(int64_t)(w + 1) * K9 + t];
+    }
+    if (w < w1) c0 += hot_part[(int64_t)w * K9 + t];
+    fold[(int64_t)f * K9 + t] = c0 + c1;
+}
+
 template <typename T>
 __device__ __forceinline__ void load_head(const CamK<T>* __restrict__ ck, int32_t j, T hd[kCamHead])
 {
@@ -737,9 +754,18 @@ __global__ __launch_bounds__(256) void k_schur_cold_free(int64_t Nc, int32_t num
                                                          const T* __restrict__ bcold,
                                                          const int32_t* __restrict__ chunk_slot,
                                                          double* __restrict__ slots, const PcgScalars* __restrict__ sc,
-                                                         int skip_if_done)
+                                                         int skip_if_done, int32_t cold_blocks, int32_t K9,
+                                                         int32_t G, const double* __restrict__ hot_part,
+                                                         double* __restrict__ hot_fold)
 {
     if (skip_if_done && sc->done) return;
+    if ((int32_t)blockIdx.x >= cold_blocks) {  // trailing blocks fold the hot partials meanwhile
+        const int32_t fx = (K9 + 255) / 256;
+        const int32_t fb = (int32_t)blockIdx.x - cold_blocks;
+        const int32_t f = fb / fx;
+        fold_slice((fb - f * fx) * 256 + (int32_t)threadIdx.x, f, K9, G, hot_part, hot_fold);
+        return;
+    }
     const int lane = threadIdx.x & 63;
     const int32_t chunk = (int32_t)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
     if (chunk >= num_chunks) return;
@@ -823,18 +849,7 @@ __global__ __launch_bounds__(256) void k_hot_fold(int32_t K9, int32_t G, const d
                                                   int skip_if_done)
 {
     if (skip_if_done && sc->done) return;
-    const int32_t t = blockIdx.x * 256 + threadIdx.x;
-    const int32_t f = blockIdx.y;
-    if (t >= K9) return;
-    const int32_t w0 = (int32_t)((int64_t)f * G / kHotFold), w1 = (int32_t)((int64_t)(f + 1) * G / kHotFold);
-    double c0 = 0.0, c1 = 0.0;
-    int32_t w = w0;
-    for (; w + 2 <= w1; w += 2) {
-        c0 += hot_part[(int64_t)w * K9 + t];
-        c1 += hot_part[(int64_t)(w + 1) * K9 + t];
-    }
-    if (w < w1) c0 += hot_part[(int64_t)w * K9 + t];
-    fold[(int64_t)f * K9 + t] = c0 + c1;
+    fold_slice(blockIdx.x * 256 + threadIdx.x, blockIdx.y, K9, G, hot_part, fold);
 }
 
 // q = B~ x - c (mode 0) or g = v - c, r = g, x = 0 (mode 1); c from the hot
@@ -999,21 +1014,28 @@ hipError_t launch_schur_product(int mode, const SchurPlan& sp, const PointMajor&
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (hot_end && (e = hipEventRecord(hot_end, s)) != hipSuccess) return e;
+    const int32_t K9 = sp.K * 9;
+    const bool fold = sp.K > 0 && sp.num_wg > 0;
+    bool folded = false;
     if (sp.cold.num_chunks > 0) {
-        if (sp.recompute && ri)
-            hipLaunchKernelGGL((k_schur_cold_free<T>), dim3((sp.cold.num_chunks + 3) / 4), dim3(256), 0, s,
-                               sp.cold.N, sp.cold.num_chunks, sp.cold.cam, sp.cold.pt, (const T*)sp.cold.w, ri->pts,
-                               ri->ck, ri->ck64, (const T*)sp.bcold, sp.cold.chunk_slot, sp.cold.slots, (const PcgScalars*)sc,
-                               mode == 0 ? 1 : 0);
-        else
+        if (sp.recompute && ri) {
+            // the fold of the hot partials rides in the same launch as extra blocks
+            const int32_t cold_blocks = (sp.cold.num_chunks + 3) / 4;
+            const int32_t fold_blocks = fold ? (K9 + 255) / 256 * kHotFold : 0;
+            hipLaunchKernelGGL((k_schur_cold_free<T>), dim3(cold_blocks + fold_blocks), dim3(256), 0, s, sp.cold.N,
+                               sp.cold.num_chunks, sp.cold.cam, sp.cold.pt, (const T*)sp.cold.w, ri->pts, ri->ck,
+                               ri->ck64, (const T*)sp.bcold, sp.cold.chunk_slot, sp.cold.slots,
+                               (const PcgScalars*)sc, mode == 0 ? 1 : 0, cold_blocks, K9, sp.num_wg,
+                               (const double*)sp.hot_part, sp.hot_fold);
+            folded = fold;
+        } else
             hipLaunchKernelGGL((k_schur_cold<T>), dim3((sp.cold.num_chunks + 3) / 4), dim3(256), 0, s, sp.cold.N,
                                sp.cold.num_chunks, sp.cold.cam, sp.cold.pt, (const T*)sp.cold.hcp,
                                (const T*)sp.bcold, sp.cold.chunk_slot, sp.cold.slots, (const PcgScalars*)sc,
                                mode == 0 ? 1 : 0);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if (sp.K > 0 && sp.num_wg > 0) {
-        const int32_t K9 = sp.K * 9;
+    if (fold && !folded) {
         hipLaunchKernelGGL(k_hot_fold, dim3((K9 + 255) / 256, kHotFold), dim3(256), 0, s, K9, sp.num_wg,
                            (const double*)sp.hot_part, sp.hot_fold, (const PcgScalars*)sc, mode == 0 ? 1 : 0);
         if ((e = hipGetLastError()) != hipSuccess) return e;
