@@ -413,14 +413,6 @@ static void chol_solve(const double *L, int k, const double *rhs, double *x)
     }
 }
 
-int orc_chol9_solve(const double A[81], const double rhs[9], double x[9])
-{
-    double L[81];
-    if (cholesky(A, 9, L)) return ORC_ENUMERIC;
-    chol_solve(L, 9, rhs, x);
-    return ORC_OK;
-}
-
 /* C~_i^{-1} formed explicitly per point through its Cholesky factor (used by
  * Alg. 3's b = C^{-1} a and Eq. schur_x_p). */
 int orc_invert_points(int32_t n, const double *Cd, double *Cinv)
@@ -788,6 +780,14 @@ int orc_lm_solve(int32_t m, int32_t n, int64_t N, double *cams, double *pts,
             trace->pcg_iters[it] = npcg;
             status = ORC_ENUMERIC;
             break;
+        }
+        if (trace->pcg_stop) {
+            int32_t stop;
+            if (opt->solver == 1) stop = ORC_PCG_DIRECT;
+            else if (pst == ORC_BREAKDOWN) stop = ORC_PCG_BREAKDOWN;
+            else if (fixed > 0) stop = ORC_PCG_FIXED;
+            else stop = npcg >= opt->max_pcg_iters ? ORC_PCG_CAP : ORC_PCG_CONVERGED;
+            trace->pcg_stop[it] = stop;
         }
         orc_back_substitute(n, N, oc, op, E, Ci, w, dc, dp);
         for (size_t t = 0; t < 9 * (size_t)m; ++t) cams_t[t] = cams[t] + dc[t];

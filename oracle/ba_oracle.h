@@ -39,11 +39,19 @@ typedef struct {
                                   and factored (the direct option for small problems) */
 } orc_options;
 
+/* How a PCG solve ended (Alg. 2 with the stopping readings): */
+#define ORC_PCG_CONVERGED 0   /* ||r|| <= rtol ||b|| before a matvec */
+#define ORC_PCG_CAP 1         /* the matvec cap was reached first */
+#define ORC_PCG_BREAKDOWN 2   /* p^T q <= 0 or non-finite; x holds the last iterate */
+#define ORC_PCG_FIXED 3       /* a fixed count (schedule) was run to its end */
+#define ORC_PCG_DIRECT 4      /* no PCG: the reduced system was factored */
+
 typedef struct {               /* caller-owned arrays of length max_lm_iters */
     int32_t iters_run;
     double initial_cost, final_cost;
     double *cost, *trial_cost, *lambda, *pred;
     int32_t *pcg_iters, *accepted;
+    int32_t *pcg_stop;         /* nullable: ORC_PCG_* per iteration */
 } orc_trace;
 
 int orc_project(const double cam[9], const double X[3], double uv[2]);
@@ -72,7 +80,6 @@ void orc_subset_sums(const int64_t *list, int64_t count, const double *cams,
 void orc_damp(int32_t m, int32_t n, const double *B, const double *C, double lambda,
               int32_t damping, double *Bd, double *Cd, double *Dc, double *Dp);
 int orc_invert_points(int32_t n, const double *Cd, double *Cinv);
-int orc_chol9_solve(const double A[81], const double rhs[9], double x[9]);
 
 void orc_schur_matvec(int32_t m, int32_t n, int64_t N, const int32_t *oc, const int32_t *op,
                       const double *Bd, const double *E, const double *Cinv,

@@ -22,9 +22,11 @@ _i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
 
 def build(force: bool = True) -> str:
     if force or not os.path.exists(LIB):
+        tmp = LIB + ".tmp"
         cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
-               "-fno-fast-math", "-Wall", "-o", LIB, SRC, "-lm"]
+               "-fno-fast-math", "-Wall", "-o", tmp, SRC, "-lm"]
         subprocess.run(cmd, check=True)
+        os.replace(tmp, LIB)   # a process that has the old library loaded keeps it
     return LIB
 
 
@@ -40,7 +42,11 @@ class Trace(C.Structure):
     _fields_ = [("iters_run", C.c_int32), ("initial_cost", C.c_double),
                 ("final_cost", C.c_double), ("cost", C.c_void_p), ("trial_cost", C.c_void_p),
                 ("lambda_", C.c_void_p), ("pred", C.c_void_p), ("pcg_iters", C.c_void_p),
-                ("accepted", C.c_void_p)]
+                ("accepted", C.c_void_p), ("pcg_stop", C.c_void_p)]
+
+
+# how each PCG solve ended (trace["pcg_stop"])
+PCG_CONVERGED, PCG_CAP, PCG_BREAKDOWN, PCG_FIXED, PCG_DIRECT = 0, 1, 2, 3, 4
 
 
 _lib = None
@@ -75,7 +81,6 @@ def lib():
         L.orc_damp.argtypes = [C.c_int32, C.c_int32, _f64p, _f64p, C.c_double, C.c_int32,
                                _f64p, _f64p, _f64p, _f64p]
         L.orc_invert_points.argtypes = [C.c_int32, _f64p, _f64p]
-        L.orc_chol9_solve.argtypes = [_f64p, _f64p, _f64p]
         L.orc_schur_matvec.argtypes = [C.c_int32, C.c_int32, C.c_int64, _i32p, _i32p, _f64p,
                                        _f64p, _f64p, _f64p, _f64p, _f64p, _f64p]
         L.orc_reduced_rhs.argtypes = [C.c_int32, C.c_int32, C.c_int64, _i32p, _i32p, _f64p,
@@ -261,9 +266,10 @@ def lm_solve(cams, pts, oc, op, uv, huber_delta=0.0, damping=0, max_lm_iters=10,
                   sched.ctypes.data if sched is not None else None, float(lambda_init),
                   float(min_relative_decrease), int(preconditioner), int(solver))
     arrs = dict(cost=np.zeros(K), trial_cost=np.zeros(K), lambda_=np.zeros(K), pred=np.zeros(K),
-                pcg_iters=np.zeros(K, np.int32), accepted=np.zeros(K, np.int32))
+                pcg_iters=np.zeros(K, np.int32), accepted=np.zeros(K, np.int32),
+                pcg_stop=np.zeros(K, np.int32))
     tr = Trace(0, 0.0, 0.0, *(arrs[k].ctypes.data for k in
-                              ("cost", "trial_cost", "lambda_", "pred", "pcg_iters", "accepted")))
+                              ("cost", "trial_cost", "lambda_", "pred", "pcg_iters", "accepted", "pcg_stop")))
     rc = lib().orc_lm_solve(len(cams), len(pts), len(oc), cams, pts, _i(oc), _i(op), _f(uv),
                             C.byref(opt), C.byref(tr))
     n_it = tr.iters_run

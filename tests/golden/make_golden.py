@@ -1,15 +1,28 @@
 """Writes the oracle's LM traces for the medium and large synthetic workloads.
 
 Calls only the FP64 CPU oracle (oracle/) and the seeded input generator.
-Usage: python tests/golden/make_golden.py {medium|large} [iters]
+Usage: python tests/golden/make_golden.py {medium|large} [iters] [--permuted SEED]
+
 Output: tests/golden/lm_trace_<name>.json with the generator digest, the
 solver options, the per-iteration trace (trial cost, cost, lambda,
-predicted decrease, PCG iterations, accepted) and the oracle's wall time.
+predicted decrease, PCG iterations, how each PCG solve ended, accepted)
+and the oracle's wall time,
+and tests/golden/lm_params_<name>.npz with the final parameters: every
+camera, and a seeded sample of 10,000 points (indices and values).
+
+With --permuted SEED the oracle runs on the same problem with its
+observations in a seeded random order, replaying the stored trace's PCG
+counts, and writes tests/golden/order_spread_<name>.json: the per-iteration
+trace of that run.  Two FP64 runs that differ only in summation order
+measure how far rounding alone moves each iteration's costs; the parity
+tolerances for the GPU are set from this spread.
 """
 import json
 import os
 import sys
 import time
+
+import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
@@ -22,20 +35,45 @@ SETTINGS = {
     "medium": dict(huber_delta=0.0, max_pcg_iters=100, pcg_rtol=1e-6),
     "large": dict(huber_delta=1.0, max_pcg_iters=100, pcg_rtol=1e-6),
 }
+POINT_SAMPLE = 10_000
+
+
+def trace_fields(tr):
+    return {"initial_cost": tr["initial_cost"], "final_cost": tr["final_cost"], "iters_run": tr["iters_run"],
+            "trial_cost": tr["trial_cost"].tolist(), "cost": tr["cost"].tolist(), "lambda": tr["lambda"].tolist(),
+            "pred": tr["pred"].tolist(), "pcg_iters": tr["pcg_iters"].tolist(),
+            "accepted": tr["accepted"].tolist(), "pcg_stop": tr["pcg_stop"].tolist()}
+
+
+def point_sample(n):
+    return np.sort(np.random.default_rng(10).choice(n, min(n, POINT_SAMPLE), replace=False)).astype(np.int64)
 
 
 def main():
-    name = sys.argv[1]
-    iters = int(sys.argv[2]) if len(sys.argv) > 2 else 20
+    args = [a for a in sys.argv[1:]]
+    permuted = None
+    if "--permuted" in args:
+        k = args.index("--permuted")
+        permuted = int(args[k + 1])
+        del args[k:k + 2]
+    name = args[0]
+    iters = int(args[1]) if len(args) > 1 else 20
     opts = SETTINGS[name]
     t0 = time.time()
     prob = synth.generate(name, seed=0)
     t_gen = time.time() - t0
     print(f"[golden] {name}: generated {prob.num_obs} observations in {t_gen:.1f}s digest {prob.digest()}",
           flush=True)
+    oc, op, uv = prob.obs_camera, prob.obs_point, prob.obs_uv
+    kw = dict(max_lm_iters=iters, **opts)
+    if permuted is not None:
+        ref = json.load(open(os.path.join(HERE, f"lm_trace_{name}.json")))
+        assert ref["digest"] == prob.digest()
+        perm = np.random.default_rng(permuted).permutation(prob.num_obs)
+        oc, op, uv = oc[perm], op[perm], uv[perm]
+        kw["pcg_schedule"] = ref["pcg_iters"]
     t0 = time.time()
-    _, _, tr, rc = orc.lm_solve(prob.cameras0, prob.points0, prob.obs_camera, prob.obs_point, prob.obs_uv,
-                                max_lm_iters=iters, **opts)
+    cams, pts, tr, rc = orc.lm_solve(prob.cameras0, prob.points0, oc, op, uv, **kw)
     wall = time.time() - t0
     out = {
         "description": "FP64 CPU oracle LM trace (single thread) on the seeded synthetic workload; "
@@ -43,12 +81,18 @@ def main():
         "workload": name, "seed": 0, "digest": prob.digest(),
         "shape": [prob.num_cameras, prob.num_points, prob.num_obs],
         "options": dict(opts, max_lm_iters=iters, lambda_init=1e-4, min_relative_decrease=1e-3, damping=0),
-        "status": rc, "oracle_seconds": wall,
-        "initial_cost": tr["initial_cost"], "final_cost": tr["final_cost"], "iters_run": tr["iters_run"],
-        "trial_cost": tr["trial_cost"].tolist(), "cost": tr["cost"].tolist(), "lambda": tr["lambda"].tolist(),
-        "pred": tr["pred"].tolist(), "pcg_iters": tr["pcg_iters"].tolist(), "accepted": tr["accepted"].tolist(),
+        "status": rc, "oracle_seconds": wall, **trace_fields(tr),
     }
-    path = os.path.join(HERE, f"lm_trace_{name}.json")
+    if permuted is not None:
+        out["description"] = ("FP64 CPU oracle LM trace with the observations in a seeded random order "
+                              "(numpy default_rng(%d).permutation), replaying the PCG counts of "
+                              "lm_trace_%s.json; written by tests/golden/make_golden.py" % (permuted, name))
+        out["permutation_seed"] = permuted
+        path = os.path.join(HERE, f"order_spread_{name}.json")
+    else:
+        path = os.path.join(HERE, f"lm_trace_{name}.json")
+        idx = point_sample(prob.num_points)
+        np.savez(os.path.join(HERE, f"lm_params_{name}.npz"), cameras=cams, point_index=idx, points=pts[idx])
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     print(f"[golden] {name}: {tr['iters_run']} iterations in {wall:.0f}s, final cost {tr['final_cost']:.10g} "

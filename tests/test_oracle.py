@@ -293,21 +293,6 @@ def explicit_schur(prob, A, Bd, Ci):
     return S - Edense @ Cinv_dense @ Edense.T, Edense
 
 
-@pytest.mark.parametrize("damping", [0, 1])
-def test_damping_definition(tiny, damping):
-    A = orc.assemble(tiny.cameras0, tiny.points0, tiny.obs_camera, tiny.obs_point, tiny.obs_uv)
-    lam = 0.37
-    Bd, Cd, Dc, Dp = orc.damp(A["B"], A["C"], lam, damping)
-    for j in range(len(Bd)):
-        diag = np.diag(A["B"][j])
-        D = np.clip(diag, 1e-6, 1e32) if damping == 0 else np.ones(9)
-        np.testing.assert_array_equal(Dc[j], D)
-        np.testing.assert_allclose(Bd[j], A["B"][j] + lam * np.diag(D), rtol=1e-15)
-    for i in range(0, len(Cd), 37):
-        D = np.clip(np.diag(A["C"][i]), 1e-6, 1e32) if damping == 0 else np.ones(3)
-        np.testing.assert_allclose(Cd[i], A["C"][i] + lam * np.diag(D), rtol=1e-15)
-
-
 def test_point_inverse(tiny):
     _, _, Cd, _, _, Ci = damped_problem(tiny)
     for i in range(0, len(Cd), 11):
