@@ -91,6 +91,16 @@ typedef enum {
                                      cross term); formed once per LM iteration */
 } ba_preconditioner;
 
+/* How one iteration's PCG solve ended (Alg. 2 with the stopping rule of
+ * ba_options; the paper leaves the stopping rule open). */
+typedef enum {
+    BA_PCG_CONVERGED = 0, /* ||r|| <= pcg_rtol ||b|| before a matvec */
+    BA_PCG_CAP = 1,       /* max_pcg_iters matvecs ran (the residual test may also hold there) */
+    BA_PCG_BREAKDOWN = 2, /* p^T q <= 0 or non-finite: the last iterate is the step */
+    BA_PCG_FIXED = 3,     /* a fixed count (pcg_fixed_iters or pcg_schedule) ran to its end */
+    BA_PCG_DIRECT = 4     /* BA_SOLVER_DENSE: no PCG */
+} ba_pcg_stop;
+
 typedef struct {
     uint32_t struct_size;          /* sizeof(ba_options) */
     int32_t precision;             /* ba_precision; fixed at ba_create */
@@ -126,6 +136,7 @@ typedef struct {
     double *ms;                    /* wall time of each iteration, ms */
     int32_t *pcg_iters;            /* Schur matvecs of each iteration */
     int32_t *accepted;             /* 1 if the step was accepted */
+    int32_t *pcg_stop;             /* ba_pcg_stop of each iteration's solve */
     /* totals, always filled */
     double total_ms;               /* whole solve */
     double pcg_ms;                 /* time inside the PCG loops */

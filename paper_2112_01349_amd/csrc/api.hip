@@ -838,8 +838,8 @@ struct PcgTimer {
 // the host enqueues iterations in batches and reads the `done` flag between
 // batches.  With a fixed count everything is enqueued at once.
 template <typename T>
-static ba_status run_pcg(ba_problem* P, const ba_options& o, int32_t fixed, int32_t* iters, PcgTimer* tm,
-                         double* matvec_ms, double* hot_ms, int64_t* launches)
+static ba_status run_pcg(ba_problem* P, const ba_options& o, int32_t fixed, int32_t* iters, int32_t* stop,
+                         PcgTimer* tm, double* matvec_ms, double* hot_ms, int64_t* launches)
 {
     hipStream_t s = P->stream;
     const int32_t m = P->m;
@@ -883,6 +883,12 @@ static ba_status run_pcg(ba_problem* P, const ba_options& o, int32_t fixed, int3
     if (st != BA_OK) return st;
     const PcgScalars* h = (const PcgScalars*)P->h_scalars;
     *iters = h->iters;
+    if (h->breakdown)
+        *stop = BA_PCG_BREAKDOWN;
+    else if (fixed > 0)
+        *stop = BA_PCG_FIXED;
+    else
+        *stop = h->iters >= o.max_pcg_iters ? BA_PCG_CAP : BA_PCG_CONVERGED;
     // A breakdown (p^T q <= 0 or non-finite) stops the loop before that
     // update, so x holds the last iterate: it is used as the step (truncated CG).
     // matvecs run in order: the first `iters` marks timed real work
@@ -973,12 +979,13 @@ static ba_status lm_solve_t(ba_problem* P, const ba_options& o, ba_report* rep)
             break;
         }
         const int32_t fixed = o.pcg_schedule ? o.pcg_schedule[it] : o.pcg_fixed_iters;
-        int32_t npcg = 0;
+        int32_t npcg = 0, stop = BA_PCG_DIRECT;
         const auto t_pcg = clock::now();
         if (P->opt.solver == BA_SOLVER_DENSE)
             st = run_dense<T>(P, lambda);
         else
-            st = run_pcg<T>(P, o, fixed, &npcg, o.time_kernels ? &timer : nullptr, &matvec_ms, &hot_ms, &launches);
+            st = run_pcg<T>(P, o, fixed, &npcg, &stop, o.time_kernels ? &timer : nullptr, &matvec_ms, &hot_ms,
+                            &launches);
         pcg_ms += std::chrono::duration<double, std::milli>(clock::now() - t_pcg).count();
         pcg_total += npcg;
         if (st != BA_OK) {
@@ -1015,6 +1022,7 @@ static ba_status lm_solve_t(ba_problem* P, const ba_options& o, ba_report* rep)
                 if (rep->pred) rep->pred[it] = pred;
                 if (rep->pcg_iters) rep->pcg_iters[it] = npcg;
                 if (rep->accepted) rep->accepted[it] = acc ? 1 : 0;
+                if (rep->pcg_stop) rep->pcg_stop[it] = stop;
             }
         }
         if (acc) {

@@ -19,6 +19,9 @@ FP64, FP32_MIXED = 0, 1
 DAMP_MARQUARDT, DAMP_IDENTITY = 0, 1
 SOLVER_PCG, SOLVER_DENSE = 0, 1
 PRECOND_CAMERA_BLOCKS, PRECOND_SCHUR_JACOBI = 0, 1
+# how each iteration's PCG solve ended (report["pcg_stop"])
+PCG_CONVERGED, PCG_CAP, PCG_BREAKDOWN, PCG_FIXED, PCG_DIRECT = 0, 1, 2, 3, 4
+PCG_STOP_NAMES = ("converged", "cap", "breakdown", "fixed", "direct")
 DENSE_MAX_CAMERAS = 2048
 
 EXPORTED = ("ba_options_default", "ba_create", "ba_set_params", "ba_get_params", "ba_eval_cost_grad",
@@ -45,7 +48,8 @@ class Report(C.Structure):
     _fields_ = [("capacity", C.c_int32), ("iters_run", C.c_int32), ("initial_cost", C.c_double),
                 ("final_cost", C.c_double), ("cost", C.c_void_p), ("trial_cost", C.c_void_p),
                 ("lambda_", C.c_void_p), ("pred", C.c_void_p), ("ms", C.c_void_p),
-                ("pcg_iters", C.c_void_p), ("accepted", C.c_void_p), ("total_ms", C.c_double),
+                ("pcg_iters", C.c_void_p), ("accepted", C.c_void_p), ("pcg_stop", C.c_void_p),
+                ("total_ms", C.c_double),
                 ("pcg_ms", C.c_double), ("pcg_iters_total", C.c_int64), ("matvec_ms", C.c_double),
                 ("matvec_launches", C.c_int64), ("schur_hot_ms", C.c_double)]
 
@@ -202,7 +206,8 @@ class Problem:
         opt, keep = make_options(precision=self.precision, **merged)
         K = max(opt.max_lm_iters, 1)
         arrs = dict(cost=np.zeros(K), trial_cost=np.zeros(K), lambda_=np.zeros(K), pred=np.zeros(K),
-                    ms=np.zeros(K), pcg_iters=np.zeros(K, np.int32), accepted=np.zeros(K, np.int32))
+                    ms=np.zeros(K), pcg_iters=np.zeros(K, np.int32), accepted=np.zeros(K, np.int32),
+                    pcg_stop=np.zeros(K, np.int32))
         rep = Report()
         rep.capacity = K
         for k, a in arrs.items():

@@ -35,9 +35,9 @@ def test_every_declared_symbol_is_exported(native):
 
 
 def test_struct_sizes_match_header(native):
-    # ba_options: 88 bytes, ba_report: 128 bytes on LP64 (natural alignment)
+    # ba_options: 88 bytes, ba_report: 136 bytes on LP64 (natural alignment)
     assert C.sizeof(native.Options) == 88
-    assert C.sizeof(native.Report) == 128
+    assert C.sizeof(native.Report) == 136
     o = native.Options()
     assert native.lib().ba_options_default(C.byref(o)) == 0
     assert o.struct_size == 88 and o.max_lm_iters == 10 and o.pcg_rtol == 1e-8 and o.lambda_init == 1e-4

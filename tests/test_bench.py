@@ -63,3 +63,38 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_equal_cost_speedup_uses_the_oracle_target_and_splits_the_ratio():
+    rep64 = dict(cost=np.array([10.0, 5.0, 2.0, 1.0]), ms=np.array([4.0, 4.0, 4.0, 4.0]), final_cost=1.0,
+                 pcg_iters=np.array([10, 20, 30, 40]), matvec_ms=300.0, matvec_launches=100)
+    rep32 = dict(cost=np.array([9.0, 4.0, 1.9, 0.9]), ms=np.array([2.0, 2.0, 2.0, 2.0]), final_cost=0.9,
+                 pcg_iters=np.array([10, 20, 5, 5]), matvec_ms=100.0, matvec_launches=50)
+    sp = bench.equal_cost_speedup(rep32, rep64, oracle_final=1.95)
+    # target 1.95 x (1 + 1e-4): FP64 after 4 iterations (16 ms, 100 matvecs), FP32-mixed after 3 (6 ms, 35)
+    assert sp["target_from"] == "oracle" and sp["fp64_lm_iters"] == 4 and sp["fp32_mixed_lm_iters"] == 3
+    assert sp["speedup"] == pytest.approx(16.0 / 6.0)
+    assert sp["matvec_speed_ratio"] == pytest.approx(3.0 / 2.0)
+    assert sp["fp64_matvecs"] == 100 and sp["fp32_mixed_matvecs"] == 35
+
+
+def test_oracle_errors_and_roofline_fractions():
+    golden = dict(iters_run=3, cost=[5.0, 4.0, 2.0],
+                  params=dict(cameras=np.ones((4, 9)), point_index=np.array([1, 3]), points=np.ones((2, 3))))
+    cams = np.ones((4, 9))
+    cams[0, 0] = 1.0 + 6.0   # |delta| = 6 over |ref| = 6
+    pts = np.ones((5, 3))
+    e = bench.oracle_errors(dict(final_cost=2.002), (cams, pts), golden, 3)
+    assert e["final_cost_rel_err"] == pytest.approx(1e-3)
+    assert e["cameras_rel_err"] == pytest.approx(1.0) and e["points_rel_err"] == 0.0
+    assert bench.oracle_errors(dict(final_cost=4.0), None, golden, 2)["final_cost_rel_err"] == 0.0
+    assert bench.oracle_errors(dict(final_cost=4.0), None, golden, 4) is None
+    m, n, N = 13_700, 4_500_000, 29_000_000
+    s = dict(hot_kernel_ms=0.5, matvec_ms=0.6)
+    r = bench.roofline(s, m, n, N, False, dict(hot_kernel_ms=1.0, matvec_ms=1.2))
+    alg = bench.hot_pass_algorithmic_bytes(n, N, 4)
+    assert r["bound"] == "hbm" and r["achieved"] == pytest.approx(alg / 0.5e-3 / 1e9)
+    assert r["frac"] == pytest.approx(r["achieved"] / 8000.0)
+    assert r["matvec_frac"] == pytest.approx(bench.matvec_algorithmic_bytes(m, n, N, 4) / 0.6e-3 / 8e12)
+    assert r["alu_peak_tflops"] == pytest.approx(78.6432)
+    assert r["fp64"]["frac"] == pytest.approx(bench.hot_pass_algorithmic_bytes(n, N, 8) / 1e-3 / 8e12)

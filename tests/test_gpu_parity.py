@@ -111,6 +111,7 @@ def assert_traces_match(tr, gpu, tol=1e-9, decisive=1e-10):
     assert gpu["iters_run"] == tr["iters_run"]
     assert abs(gpu["initial_cost"] - tr["initial_cost"]) <= 1e-13 * tr["initial_cost"]
     np.testing.assert_array_equal(gpu["pcg_iters"], tr["pcg_iters"])
+    np.testing.assert_array_equal(gpu["pcg_stop"], tr["pcg_stop"])
     prev = tr["initial_cost"]
     same_path = True
     for k in range(tr["iters_run"]):
@@ -154,6 +155,9 @@ def test_lm_rtol_mode_agrees(tiny):
             break
         assert gpu["accepted"][k] == tr["accepted"][k], k
         assert abs(int(gpu["pcg_iters"][k]) - int(tr["pcg_iters"][k])) <= 1, k
+        # a solve that stops short of the cap has met the residual test
+        stop = orc.PCG_CAP if gpu["pcg_iters"][k] >= 50 else orc.PCG_CONVERGED
+        assert gpu["pcg_stop"][k] == stop, k
         prev = tr["cost"][k]
     assert abs(gpu["final_cost"] - tr["final_cost"]) <= 1e-9 * tr["final_cost"]
 
