@@ -217,6 +217,26 @@ ba_status ba_cost_bwd_device(ba_problem *prob, int32_t dtype, const void *d_cams
                              const void *d_pts, double gout, void *d_grad_cams,
                              void *d_grad_pts, void *hip_stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the cost of
+ * ba_cost_fwd_device from caller device arrays, with no handle and no
+ * allocation.  F = 1/2 sum rho(|e|^2) over num_obs observations, written to
+ * the device double d_cost_f64, ordered on hip_stream (NULL = the default
+ * stream).  d_cams [m][9] and d_pts [n][3] are dtype arrays (0 = FP64, 1 =
+ * FP32; FP32 also computes the residuals in FP32, the sum is FP64);
+ * d_obs_camera, d_obs_point [N] int32 and d_obs_uv [N][2] FP64 are device
+ * arrays; huber_delta <= 0 selects the squared loss.  The reduction's only
+ * scratch is a fixed 2048-entry FP64 array in device memory, one per device
+ * for the life of the process, so any N is accepted; calls that overlap on
+ * one device share that array and race (order them on one stream).  An
+ * observation index out of range makes the result NaN.  Errors: BA_EINVAL
+ * (bad count, dtype, NULL array or NaN delta), BA_EDEVICE (launch failure). */
+ba_status ba_cost_device_noalloc(int32_t num_cameras, int32_t num_points, int64_t num_obs,
+                                 int32_t dtype, const void *d_cams, const void *d_pts,
+                                 const int32_t *d_obs_camera, const int32_t *d_obs_point,
+                                 const double *d_obs_uv, double huber_delta, double *d_cost_f64,
+                                 void *hip_stream);
+
 /* Bytes of device memory the handle holds. */
 ba_status ba_memory_bytes(const ba_problem *prob, int64_t *bytes);
 

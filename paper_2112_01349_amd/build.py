@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libba.so")
-SOURCES = ["api.hip", "build.hip", "schur.hip", "matvec.hip", "pcg.hip", "dense.hip"]
+SOURCES = ["api.hip", "build.hip", "schur.hip", "matvec.hip", "pcg.hip", "dense.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

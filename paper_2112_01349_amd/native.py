@@ -25,8 +25,8 @@ PCG_STOP_NAMES = ("converged", "cap", "breakdown", "fixed", "direct")
 DENSE_MAX_CAMERAS = 2048
 
 EXPORTED = ("ba_options_default", "ba_create", "ba_set_params", "ba_get_params", "ba_eval_cost_grad",
-            "ba_lm_solve", "ba_schur_matvec", "ba_cost_fwd_device", "ba_cost_bwd_device", "ba_memory_bytes", "ba_destroy",
-            "ba_status_str", "ba_last_error")
+            "ba_lm_solve", "ba_schur_matvec", "ba_cost_fwd_device", "ba_cost_bwd_device", "ba_cost_device_noalloc",
+            "ba_memory_bytes", "ba_destroy", "ba_status_str", "ba_last_error")
 
 
 class BAError(RuntimeError):
@@ -75,6 +75,8 @@ def lib():
         L.ba_schur_matvec.argtypes = [vp, C.c_double, C.c_int32, vp, vp]
         L.ba_cost_fwd_device.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
         L.ba_cost_bwd_device.argtypes = [vp, C.c_int32, vp, vp, C.c_double, vp, vp, vp]
+        L.ba_cost_device_noalloc.argtypes = [C.c_int32, C.c_int32, C.c_int64, C.c_int32, vp, vp, vp, vp, vp,
+                                             C.c_double, vp, vp]
         L.ba_memory_bytes.argtypes = [vp, C.POINTER(C.c_int64)]
         L.ba_destroy.argtypes = [vp]
         L.ba_destroy.restype = None
@@ -239,3 +241,13 @@ class Problem:
     def cost_bwd_device(self, dtype, cams_ptr, pts_ptr, gout, gcam_ptr, gpt_ptr, stream=None):
         self._check(lib().ba_cost_bwd_device(self._h, int(dtype), cams_ptr, pts_ptr, float(gout), gcam_ptr,
                                              gpt_ptr, stream))
+
+
+def cost_device_noalloc(m, n, N, dtype, cams_ptr, pts_ptr, oc_ptr, op_ptr, uv_ptr, huber_delta, cost_ptr,
+                        stream=None):
+    """ba_cost_device_noalloc: the robust cost from device arrays (pointers),
+    with no handle and no allocation; raises BAError on a bad argument."""
+    st = lib().ba_cost_device_noalloc(int(m), int(n), int(N), int(dtype), cams_ptr, pts_ptr, oc_ptr, op_ptr, uv_ptr,
+                                      float(huber_delta), cost_ptr, stream)
+    if st != BA_OK:
+        raise BAError(st, "ba_cost_device_noalloc")
