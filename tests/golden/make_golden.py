@@ -1,7 +1,7 @@
 """Writes the oracle's LM traces for the medium and large synthetic workloads.
 
 Calls only the FP64 CPU oracle (oracle/) and the seeded input generator.
-Usage: python tests/golden/make_golden.py {medium|large} [iters] [--permuted SEED]
+Usage: python tests/golden/make_golden.py {medium|large|synth_small} [iters] [--permuted SEED]
 
 Output: tests/golden/lm_trace_<name>.json with the generator digest, the
 solver options, the per-iteration trace (trial cost, cost, lambda,
@@ -12,8 +12,8 @@ camera, and a seeded sample of 10,000 points (indices and values).
 
 With --permuted SEED the oracle runs on the same problem with its
 observations in a seeded random order, replaying the stored trace's PCG
-counts, and writes tests/golden/order_spread_<name>.json: the per-iteration
-trace of that run.  Two FP64 runs that differ only in summation order
+counts, and writes tests/golden/order_spread_<name>_seed<SEED>.json: the
+per-iteration trace of that run.  Two FP64 runs that differ only in summation order
 measure how far rounding alone moves each iteration's costs; the parity
 tolerances for the GPU are set from this spread.
 """
@@ -34,7 +34,10 @@ from paper_2112_01349_amd import synth  # noqa: E402
 SETTINGS = {
     "medium": dict(huber_delta=0.0, max_pcg_iters=100, pcg_rtol=1e-6),
     "large": dict(huber_delta=1.0, max_pcg_iters=100, pcg_rtol=1e-6),
+    # the synthesised recipe at oracle size, as its GPU parity test runs it
+    "synth_small": dict(huber_delta=0.0, max_pcg_iters=30, pcg_rtol=1e-8),
 }
+DEFAULT_ITERS = {"synth_small": 4}
 POINT_SAMPLE = 10_000
 
 
@@ -57,7 +60,7 @@ def main():
         permuted = int(args[k + 1])
         del args[k:k + 2]
     name = args[0]
-    iters = int(args[1]) if len(args) > 1 else 20
+    iters = int(args[1]) if len(args) > 1 else DEFAULT_ITERS.get(name, 20)
     opts = SETTINGS[name]
     t0 = time.time()
     prob = synth.generate(name, seed=0)
@@ -88,7 +91,7 @@ def main():
                               "(numpy default_rng(%d).permutation), replaying the PCG counts of "
                               "lm_trace_%s.json; written by tests/golden/make_golden.py" % (permuted, name))
         out["permutation_seed"] = permuted
-        path = os.path.join(HERE, f"order_spread_{name}.json")
+        path = os.path.join(HERE, f"order_spread_{name}_seed{permuted}.json")
     else:
         path = os.path.join(HERE, f"lm_trace_{name}.json")
         idx = point_sample(prob.num_points)

@@ -42,3 +42,59 @@ def rel_err(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def order_spread(name):
+    """How far rounding alone moves the oracle's LM trace on workload `name`:
+    per iteration, the largest relative difference of the trial cost and of
+    the accepted cost between the oracle's stored run
+    (tests/golden/lm_trace_<name>.json) and its runs on the same problem with
+    the observations in seeded random orders, replaying the same PCG counts
+    (tests/golden/order_spread_<name>_seed*.json).  Both runs are FP64 and
+    differ only in summation order, as the GPU's run does.  None when the
+    files are missing."""
+    import glob
+    import json
+    import os
+
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    ref_path = os.path.join(here, f"lm_trace_{name}.json")
+    paths = sorted(glob.glob(os.path.join(here, f"order_spread_{name}_seed*.json")))
+    if not os.path.exists(ref_path) or not paths:
+        return None
+    ref = json.load(open(ref_path))
+    trial = np.zeros(ref["iters_run"])
+    cost = np.zeros(ref["iters_run"])
+    for p in paths:
+        g = json.load(open(p))
+        assert g["digest"] == ref["digest"] and g["pcg_iters"] == ref["pcg_iters"], p
+        t0, t1 = np.asarray(ref["trial_cost"]), np.asarray(g["trial_cost"])
+        c0, c1 = np.asarray(ref["cost"]), np.asarray(g["cost"])
+        trial = np.maximum(trial, np.abs(t1 - t0) / t0)
+        cost = np.maximum(cost, np.abs(c1 - c0) / c0)
+    return dict(trial=trial, cost=cost, runs=len(paths), trace=ref)
+
+
+def oracle_spread(arrays, trace, seeds=(1, 2, 3), **oracle_kw):
+    """order_spread for a small problem, measured on the spot: the oracle's
+    LM run on `arrays` with the observations in seeded random orders,
+    replaying trace's PCG counts (oracle_kw: the solver options of the run
+    that produced `trace`, as orc.lm_solve takes them).  Compared while the
+    accept/reject decisions agree."""
+    from oracle import oracle as orc
+
+    cams, pts, oc, op, uv = arrays[:5]
+    oc, op, uv = np.asarray(oc), np.asarray(op), np.asarray(uv)
+    kw = {k: v for k, v in oracle_kw.items() if k not in ("max_pcg_iters", "pcg_rtol", "pcg_schedule")}
+    n_it = trace["iters_run"]
+    trial, cost = np.zeros(n_it), np.zeros(n_it)
+    for sd in seeds:
+        perm = np.random.default_rng(sd).permutation(len(oc))
+        _, _, t2, _ = orc.lm_solve(cams, pts, oc[perm], op[perm], uv[perm], max_lm_iters=n_it,
+                                   pcg_schedule=trace["pcg_iters"], **kw)
+        for k in range(min(n_it, t2["iters_run"])):
+            trial[k] = max(trial[k], abs(t2["trial_cost"][k] - trace["trial_cost"][k]) / trace["trial_cost"][k])
+            cost[k] = max(cost[k], abs(t2["cost"][k] - trace["cost"][k]) / trace["cost"][k])
+            if t2["accepted"][k] != trace["accepted"][k]:
+                break
+    return dict(trial=trial, cost=cost, runs=len(seeds))

@@ -10,7 +10,7 @@ relative 1e-4 of the oracle's.
 import numpy as np
 import pytest
 
-from helpers import rel_err, small_zipf, with_edge_cases
+from helpers import oracle_spread, order_spread, rel_err, small_zipf, with_edge_cases
 from oracle import oracle as orc
 from paper_2112_01349_amd import FP32_MIXED, FP64, Problem, synth
 from paper_2112_01349_amd.native import PRECOND_SCHUR_JACOBI, SOLVER_DENSE
@@ -79,7 +79,7 @@ def test_edge_cases_cost_gradient_matvec():
     assert rel_err(prob.schur_matvec(x, lam), ref) <= 1e-10
 
 
-def lm_pair(src, delta=0.0, iters=10, max_pcg=50, rtol=1e-8, edge=False):
+def lm_pair(src, delta=0.0, iters=10, max_pcg=50, rtol=1e-8, spread=True):
     arrays = src if isinstance(src, tuple) else None
     if arrays is None:
         arrays = (src.cameras0, src.points0, src.obs_camera, src.obs_point, src.obs_uv)
@@ -87,42 +87,51 @@ def lm_pair(src, delta=0.0, iters=10, max_pcg=50, rtol=1e-8, edge=False):
     oc_, op_, tr, rc = orc.lm_solve(cams, pts, oc, op, uv, huber_delta=delta, max_lm_iters=iters,
                                     max_pcg_iters=max_pcg, pcg_rtol=rtol)
     assert rc == 0
+    if spread:
+        tr["spread"] = oracle_spread(arrays, tr, huber_delta=delta)
     prob, _ = make(arrays[:5], huber_delta=delta)
     gpu = prob.lm_solve(max_lm_iters=iters, pcg_schedule=tr["pcg_iters"], max_pcg_iters=max_pcg,
                         pcg_rtol=rtol)
     return tr, gpu, prob, (oc_, op_)
 
 
-def assert_traces_match(tr, gpu, tol=1e-9, decisive=1e-10):
-    """Per-iteration trial and accepted costs agree to `tol`.  Accept/reject
+# How far the GPU's trace may sit from the oracle's beyond the 1e-9 floor:
+# SPREAD_FACTOR times the oracle's own spread under a permuted observation
+# order (the GPU differs from the oracle only in summation order, and a
+# handful of permuted runs bounds that spread from below).
+SPREAD_FACTOR = 4.0
+
+
+def assert_traces_match(tr, gpu, tol=1e-9, decisive=1e-10, spread=None):
+    """Per-iteration trial and accepted costs agree to relative `tol`, or to
+    SPREAD_FACTOR times the oracle's own per-iteration spread under permuted
+    observation orders where that is given and larger.  Accept/reject
     decisions (and so lambda) must agree while the oracle's cost change is
-    above round-off (|F - F_trial| > decisive * F); once the solve has
-    converged the gain ratio is a ratio of rounding errors and either
-    decision is correct.  A trial point whose cost rises more than tenfold
-    lies far outside the step's linear model, near a camera's principal plane
-    where the cost amplifies rounding in the step: there the trial costs are
-    compared to 1e-5 and both sides must reject.  A step that removes most of
-    the cost (a near zero-residual problem) leaves a trial cost that is small
-    next to the rounding carried in from the step: a relative step error e
-    moves the trial residual by about e |r|, so F_trial by about
-    2 e sqrt(F F_trial); the bound is the larger of tol F_trial and
-    2 tol sqrt(F F_trial)."""
+    above round-off (|F - F_trial| > decisive * F, or above the spread
+    bound); once the solve has converged the gain ratio is a ratio of
+    rounding errors and either decision is correct.  A trial point whose
+    cost rises more than tenfold must be rejected by both sides."""
+    if spread is None:
+        spread = tr.get("spread")
     assert gpu["status"] == 0
     assert gpu["iters_run"] == tr["iters_run"]
     assert abs(gpu["initial_cost"] - tr["initial_cost"]) <= 1e-13 * tr["initial_cost"]
     np.testing.assert_array_equal(gpu["pcg_iters"], tr["pcg_iters"])
-    np.testing.assert_array_equal(gpu["pcg_stop"], tr["pcg_stop"])
+    # the oracle ran to its rtol (converged or cap) and the GPU replayed its counts
+    replayed = np.where(np.isin(tr["pcg_stop"], (orc.PCG_BREAKDOWN, orc.PCG_DIRECT)), tr["pcg_stop"], orc.PCG_FIXED)
+    np.testing.assert_array_equal(gpu["pcg_stop"], replayed)
     prev = tr["initial_cost"]
     same_path = True
     for k in range(tr["iters_run"]):
         ft = tr["trial_cost"][k]
+        rel = tol if spread is None else max(tol, SPREAD_FACTOR * spread["trial"][k])
+        crel = tol if spread is None else max(tol, SPREAD_FACTOR * spread["cost"][k])
         wild = ft > 10 * prev
-        bound = 1e-5 * ft if wild else tol * max(ft, 2.0 * np.sqrt(prev * ft))
-        assert abs(gpu["trial_cost"][k] - ft) <= bound, k
-        assert abs(gpu["cost"][k] - tr["cost"][k]) <= max(bound, tol * tr["cost"][k]), k
+        assert abs(gpu["trial_cost"][k] - ft) <= rel * ft, (k, gpu["trial_cost"][k], ft, rel)
+        assert abs(gpu["cost"][k] - tr["cost"][k]) <= max(rel * ft, crel * tr["cost"][k]), k
         if wild:
             assert not gpu["accepted"][k] and not tr["accepted"][k], k
-        if abs(prev - tr["trial_cost"][k]) > decisive * prev and same_path:
+        if abs(prev - ft) > max(decisive, 2 * rel) * prev and same_path:
             assert gpu["accepted"][k] == tr["accepted"][k], k
             assert abs(gpu["lambda"][k] - tr["lambda"][k]) <= 1e-6 * tr["lambda"][k], k
         else:
@@ -251,6 +260,7 @@ def test_autodiff_lm_trace_matches_oracle(tiny):
     _, _, tr, rc = orc.lm_solve(cams, pts, oc, op, uv, huber_delta=1.0, max_lm_iters=8, max_pcg_iters=50,
                                 pcg_rtol=1e-8)
     assert rc == 0
+    tr["spread"] = oracle_spread(arrays, tr, huber_delta=1.0)
     prob = Problem(cams, pts, oc, op, uv, huber_delta=1.0)
     gpu = prob.lm_solve(max_lm_iters=8, pcg_schedule=tr["pcg_iters"], max_pcg_iters=50, pcg_rtol=1e-8, jacobian=1)
     prob.close()
@@ -307,11 +317,12 @@ def test_synthesised_recipe_matches_oracle(hot, monkeypatch):
     """The synthesised recipe at oracle size (400 cameras, 1,600 points seen
     300 times each: every point spans five or six tiles), with the library's
     own choice of hot set and with all 400 cameras forced hot (every long
-    point walked twice).  Both give the oracle's product and FP64 LM trace.  The trace is compared
-    at 1e-8: the scene spans 0.025 rad of every camera's view, so the camera
-    blocks scaled to unit diagonal have smallest eigenvalues near 4e-5 (5e-3
-    on the tiny workload) and the PCG step carries about 1e-9 relative
-    rounding that varies between summation orders."""
+    point walked twice).  Both give the oracle's product and FP64 LM trace.
+    The problem has a zero-cost optimum: four iterations take the cost from
+    1.8e5 to 0.64, so the late trial costs are small next to the rounding
+    carried in the step, and the oracle's own trace moves by up to 5e-8
+    relative when only its summation order changes (stored permuted runs);
+    the trace is compared to that spread."""
     if hot is not None:
         monkeypatch.setenv("BA_HOT_CAMERAS", str(hot))
     prob = synth.generate("synth_small", seed=0)
@@ -327,8 +338,11 @@ def test_synthesised_recipe_matches_oracle(hot, monkeypatch):
         tol = 1e-10 if precision == FP64 else 1e-3
         assert rel_err(gpu.schur_matvec(x, lam), ref) <= tol, precision
         gpu.close()
-    tr, rep, _, _ = lm_pair(arrays, iters=4, max_pcg=30, rtol=1e-8)
-    assert_traces_match(tr, rep, tol=1e-8)
+    tr, rep, _, _ = lm_pair(arrays, iters=4, max_pcg=30, rtol=1e-8, spread=False)
+    spread = order_spread("synth_small")
+    assert spread is not None, "tests/golden/order_spread_synth_small_seed*.json missing"
+    np.testing.assert_array_equal(tr["trial_cost"], spread["trace"]["trial_cost"])  # the same oracle run
+    assert_traces_match(tr, rep, spread=spread)
 
 
 def test_mixed_point_at_camera_centre():
@@ -367,6 +381,7 @@ def dense_pair(arrays, delta=0.0, iters=6, precision=FP64):
     cams, pts, oc, op, uv = arrays[:5]
     _, _, tr, rc = orc.lm_solve(cams, pts, oc, op, uv, huber_delta=delta, max_lm_iters=iters, solver=1)
     assert rc == 0
+    tr["spread"] = oracle_spread(arrays, tr, huber_delta=delta, solver=1)
     prob, _ = make(arrays[:5], precision=precision, huber_delta=delta, solver=SOLVER_DENSE)
     gpu = prob.lm_solve(max_lm_iters=iters)
     return tr, gpu, prob
@@ -434,6 +449,7 @@ def schur_jacobi_pair(arrays, delta=0.0, iters=8, max_pcg=60, rtol=1e-8, precisi
     _, _, tr, rc = orc.lm_solve(cams, pts, oc, op, uv, huber_delta=delta, max_lm_iters=iters,
                                 max_pcg_iters=max_pcg, pcg_rtol=rtol, preconditioner=1)
     assert rc == 0
+    tr["spread"] = oracle_spread(arrays, tr, huber_delta=delta, preconditioner=1)
     prob, _ = make(arrays[:5], precision=precision, huber_delta=delta, preconditioner=PRECOND_SCHUR_JACOBI,
                    **opts)
     gpu = prob.lm_solve(max_lm_iters=iters, pcg_schedule=tr["pcg_iters"], max_pcg_iters=max_pcg, pcg_rtol=rtol)
