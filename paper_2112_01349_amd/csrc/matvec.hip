@@ -67,6 +67,61 @@ __device__ __forceinline__ T wave_sum(T v)
     return v;
 }
 
+// Lane shifts through DPP (data-parallel primitives: the shift rides on a
+// VALU move, with no LDS round trip).  CTRL: row_shr:n = 0x110 + n (within
+// rows of 16 lanes), row_bcast:15 = 0x142 (lane 15 of each row to the next
+// row), row_bcast:31 = 0x143 (lane 31 to rows 2 and 3), wave_shr:1 = 0x138.
+// Lanes without a source read 0; rows outside ROWMASK read 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_shift(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROWMASK, 0xf,
+                                                                 true));
+}
+
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_shift(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROWMASK, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROWMASK, 0xf, true);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// The value of lane - 1 (lane 0 reads `first`).
+__device__ __forceinline__ int32_t lane_before(int32_t v, int32_t first)
+{
+    return __builtin_amdgcn_update_dpp(first, v, 0x138, 0xf, 0xf, false);
+}
+
+// Inclusive sums of (a0, a1, a2) over each lane's run [seg_s, lane] of
+// contiguous lanes: within rows of 16 by shifts of 1, 2, 4 and 8, then the
+// last lane of row r into row r + 1 and lane 31 into rows 2 and 3 (the
+// row-carry form of a wave scan).  A step adds the shifted value times 1 where
+// its source lies in the lane's run and times 0 elsewhere (exactly an add or
+// nothing for finite values).
+template <typename T>
+__device__ __forceinline__ void run_prefix3(T& a0, T& a1, T& a2, int lane, int seg_s)
+{
+    const T m1 = lane - 1 >= seg_s ? (T)1 : (T)0;
+    const T m2 = lane - 2 >= seg_s ? (T)1 : (T)0;
+    const T m4 = lane - 4 >= seg_s ? (T)1 : (T)0;
+    const T m8 = lane - 8 >= seg_s ? (T)1 : (T)0;
+    const T m16 = (lane & ~15) - 1 >= seg_s ? (T)1 : (T)0;
+    const T m32 = (lane > 31 && seg_s <= 31) ? (T)1 : (T)0;
+#define BA_RUN_STEP(CTRL, ROWMASK, M)                 \
+    a0 = fma(dpp_shift<CTRL, ROWMASK>(a0), M, a0); \
+    a1 = fma(dpp_shift<CTRL, ROWMASK>(a1), M, a1); \
+    a2 = fma(dpp_shift<CTRL, ROWMASK>(a2), M, a2);
+    BA_RUN_STEP(0x111, 0xf, m1)
+    BA_RUN_STEP(0x112, 0xf, m2)
+    BA_RUN_STEP(0x114, 0xf, m4)
+    BA_RUN_STEP(0x118, 0xf, m8)
+    BA_RUN_STEP(0x142, 0xa, m16)
+    BA_RUN_STEP(0x143, 0xc, m32)
+#undef BA_RUN_STEP
+}
+
 // a = E_k^T x_j for one observation's 9x3 block.
 template <typename T>
 __device__ __forceinline__ void block_t_times_x(const T h[27], const T* __restrict__ xcam, int32_t j, T& a0, T& a1,
@@ -387,9 +442,21 @@ __device__ __forceinline__ void free_observation(int64_t k, const int32_t* __res
 template <typename T>
 struct FreeRow {
     int32_t b, len;  // segment start and length (uniform)
+    int32_t i0;      // point of the segment's first observation (uniform)
     int32_t j, i;
     T w;
 };
+
+// Element `e` of an array at a 32-bit byte offset from a wave-uniform base:
+// the load takes the base in scalar registers and one 32-bit vector offset,
+// with no 64-bit address arithmetic per lane.  Offsets stay below 4 GB: a
+// camera record times the camera count (checked when the problem is made),
+// or the records of the points inside one segment.
+template <typename E>
+__device__ __forceinline__ const E* at_bytes(const void* base, uint32_t off)
+{
+    return reinterpret_cast<const E*>(reinterpret_cast<const char*>(base) + off);
+}
 
 template <typename T>
 struct FreeData {
@@ -409,10 +476,11 @@ __device__ __forceinline__ void free_stream(const int2* __restrict__ sseg, int32
     const int2 be = sseg[q];
     r.b = __builtin_amdgcn_readfirstlane(be.x);
     r.len = __builtin_amdgcn_readfirstlane(be.y) - r.b;
-    const int64_t k = r.b + (lane < r.len ? lane : 0);
-    r.j = cam[k];
-    r.i = pt[k];
-    r.w = wobs[k];
+    const uint32_t l = (uint32_t)(lane < r.len ? lane : 0);
+    r.j = (cam + r.b)[l];
+    r.i = (pt + r.b)[l];
+    r.w = (wobs + r.b)[l];
+    r.i0 = __builtin_amdgcn_readfirstlane(r.i);  // lane 0 always holds an observation
 }
 
 template <typename T, int MODE>
@@ -421,24 +489,28 @@ __device__ __forceinline__ void free_gather(const FreeRow<T>& r, const double* _
                                             const T* __restrict__ cinv, const uint8_t* __restrict__ has_cold,
                                             const double* __restrict__ wpt, FreeData<T>& d)
 {
-    load_head<T>(ck, r.j, d.hd);
+    const uint32_t uj = (uint32_t)r.j, di = (uint32_t)(r.i - r.i0);
+    const T* h = at_bytes<T>(ck, uj * (uint32_t)sizeof(CamK<T>));
+#pragma unroll
+    for (int q = 0; q < kCamHead; ++q) d.hd[q] = h[q];
     if (MODE != 1) {
-        const T* x = xf + 12 * (int64_t)r.j;
+        const T* x = at_bytes<T>(xf, uj * (uint32_t)(12 * sizeof(T)));
 #pragma unroll
         for (int a = 0; a < 9; ++a) d.xv[a] = x[a];
     }
-    const double* X = pts + 3 * (int64_t)r.i;
+    const int64_t i0 = r.i0;
+    const double* X = at_bytes<double>(pts + 3 * i0, di * 24u);
 #pragma unroll
     for (int a = 0; a < 3; ++a) d.X[a] = (T)X[a];
-    const T* c6 = cinv + 6 * (int64_t)r.i;
+    const T* c6 = at_bytes<T>(cinv + 6 * i0, di * (uint32_t)(6 * sizeof(T)));
 #pragma unroll
     for (int a = 0; a < 6; ++a) d.c6[a] = c6[a];
     if (MODE != 0) {
-        const double* wv = wpt + 3 * (int64_t)r.i;
+        const double* wv = at_bytes<double>(wpt + 3 * i0, di * 24u);
 #pragma unroll
         for (int a = 0; a < 3; ++a) d.wv[a] = (T)wv[a];
     }
-    if (MODE != 2) d.hc = has_cold[r.i] != 0;
+    if (MODE != 2) d.hc = *at_bytes<uint8_t>(has_cold + i0, di) != 0;
 }
 
 // One short segment.  Mode 0 (product): E^T x per lane, a_i per point run
@@ -467,21 +539,13 @@ __device__ __forceinline__ void free_short(const FreeRow<T>& r, const FreeData<T
     } else {
         free_et_x<T>(o, d.hd, d.xv, r.w, a0, a1, a2);
         if (!valid) a0 = a1 = a2 = (T)0;
-        const int32_t prev = __shfl_up(r.i, 1, 64);
+        const int32_t prev = lane_before(r.i, -1);
         const bool head = valid && (lane == 0 || r.i != prev);
         const uint64_t hm = __ballot(head);
         const int seg_s = 63 - __clzll((hm & upto) | 1ull);
         const uint64_t above = hm & ~upto;
         seg_e = above ? __ffsll((unsigned long long)above) - 2 : r.len - 1;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const T u0 = __shfl_up(a0, off, 64), u1 = __shfl_up(a1, off, 64), u2 = __shfl_up(a2, off, 64);
-            if (lane - off >= seg_s) {
-                a0 += u0;
-                a1 += u1;
-                a2 += u2;
-            }
-        }
+        run_prefix3<T>(a0, a1, a2, lane, seg_s);
         a0 = __shfl(a0, seg_e, 64);
         a1 = __shfl(a1, seg_e, 64);
         a2 = __shfl(a2, seg_e, 64);
@@ -496,18 +560,21 @@ __device__ __forceinline__ void free_short(const FreeRow<T>& r, const FreeData<T
     const T b0 = d.c6[0] * a0 + d.c6[1] * a1 + d.c6[2] * a2;
     const T b1 = d.c6[1] * a0 + d.c6[3] * a1 + d.c6[4] * a2;
     const T b2 = d.c6[2] * a0 + d.c6[4] * a1 + d.c6[5] * a2;
+    const uint32_t di = (uint32_t)(r.i - r.i0);
     if (MODE == 2) {
         if (valid && lane == seg_e) {
-            dp[3 * (int64_t)r.i] = (double)b0;
-            dp[3 * (int64_t)r.i + 1] = (double)b1;
-            dp[3 * (int64_t)r.i + 2] = (double)b2;
+            double* o = const_cast<double*>(at_bytes<double>(dp + 3 * (int64_t)r.i0, di * 24u));
+            o[0] = (double)b0;
+            o[1] = (double)b1;
+            o[2] = (double)b2;
         }
         return;
     }
     if (valid && lane == seg_e && d.hc) {
-        bcold[kBcold * (int64_t)r.i] = b0;
-        bcold[kBcold * (int64_t)r.i + 1] = b1;
-        bcold[kBcold * (int64_t)r.i + 2] = b2;
+        T* o = const_cast<T*>(at_bytes<T>(bcold + kBcold * (int64_t)r.i0, di * (uint32_t)(kBcold * sizeof(T))));
+        o[0] = b0;
+        o[1] = b1;
+        o[2] = b2;
     }
     if (valid && r.j < K) free_add_hot<T>(cl, r.j, o, d.hd, r.w, b0, b1, b2);
 }
@@ -521,8 +588,17 @@ __device__ __forceinline__ void free_short(const FreeRow<T>& r, const FreeData<T
 // workgroup's LDS table as in k_schur_hot; b_i of points with cold
 // observations is stored for the cold pass, which reads its own stored
 // blocks.  Mode 2 has no camera side (K = 0).
+// Threads per workgroup of k_schur_free: the product and the right-hand side
+// run one workgroup per CU around the LDS table; the back-substitution has no
+// table, so it runs in workgroups of 256 (the same waves, four per group),
+// which lets the compiler keep it in registers without spilling.
 template <typename T, int MODE>
-__global__ __launch_bounds__(HotThreads<T>::value) void k_schur_free(
+struct FreeThreads {
+    static constexpr int value = MODE == 2 ? 256 : HotThreads<T>::value;
+};
+
+template <typename T, int MODE>
+__global__ __launch_bounds__((FreeThreads<T, MODE>::value)) void k_schur_free(
     const int32_t* __restrict__ frange, const int2* __restrict__ sseg, const int32_t* __restrict__ lrange,
     const int2* __restrict__ lseg, const int32_t* __restrict__ cam, const int32_t* __restrict__ pt,
     const T* __restrict__ wobs, const double* __restrict__ pts, const CamK<T>* __restrict__ ck,
@@ -530,7 +606,7 @@ __global__ __launch_bounds__(HotThreads<T>::value) void k_schur_free(
     const double* __restrict__ wpt, int32_t K, double* __restrict__ hot_part, T* __restrict__ bcold,
     const uint8_t* __restrict__ has_cold, double* __restrict__ dp, const PcgScalars* __restrict__ sc)
 {
-    constexpr int NT = HotThreads<T>::value;
+    constexpr int NT = FreeThreads<T, MODE>::value;
     if (MODE == 0 && sc->done) return;  // uniform over the grid
     extern __shared__ __align__(16) unsigned char smem[];
     double* cl = reinterpret_cast<double*>(smem);
@@ -1062,7 +1138,8 @@ hipError_t launch_backsub_free(const SchurPlan& sp, const PointMajor& pm, const 
                                const double* wpt, double* dp, hipStream_t s)
 {
     if (sp.num_wg <= 0) return hipGetLastError();
-    hipLaunchKernelGGL((k_schur_free<T, 2>), dim3(sp.num_wg), dim3(HotThreads<T>::value), 0, s, sp.frange, sp.sseg,
+    constexpr int NT = FreeThreads<T, 2>::value;  // the same waves as the product, NT / 64 per workgroup
+    hipLaunchKernelGGL((k_schur_free<T, 2>), dim3(sp.num_wg * (HotThreads<T>::value / NT)), dim3(NT), 0, s, sp.frange, sp.sseg,
                        sp.lrange, sp.lseg, pm.cam, pm.pt, ri.wobs, ri.pts, ri.ck, ri.ck64, ri.xf, cinv, wpt, 0, nullptr,
                        nullptr, sp.has_cold, dp, nullptr);
     return hipGetLastError();

@@ -108,54 +108,72 @@ hipError_t launch_pcg_reset(PcgScalars* sc, double rtol, int32_t max_iters, int3
 
 __host__ __device__ constexpr int tri2(int r, int c) { return r * (r + 1) / 2 + c; }
 
-// One thread per camera: (unless first) x += alpha p, r -= alpha q on its 9
-// entries, then z = (L L^T)^-1 r with the camera block's Cholesky factor.
-// The last block adds rho = r^T z and ||r||^2 over all blocks and takes the
-// decision the next matvec depends on: stop (converged or count reached) or
-// continue with beta = rho / rho_prev.
+// (Unless first) x += alpha p, r -= alpha q, then z = (L L^T)^-1 r with each
+// camera block's Cholesky factor.  A workgroup takes kStepCams cameras: their
+// vector entries and factors are read and written in contiguous runs through
+// LDS, and one lane per camera does the two triangular solves there.  The last
+// block adds rho = r^T z and ||r||^2 over all blocks and takes the decision
+// the next matvec depends on: stop (converged or count reached) or continue
+// with beta = rho / rho_prev.
+constexpr int kStepCams = 64;
+
 __global__ __launch_bounds__(kRedBlock) void k_pcg_step(int32_t m, int first, const double* __restrict__ lfac,
                                                         const double* __restrict__ p, const double* __restrict__ q,
                                                         double* __restrict__ x, double* __restrict__ r,
                                                         double* __restrict__ z, double* __restrict__ partials,
                                                         PcgScalars* __restrict__ sc)
 {
+    __shared__ double sl[kStepCams * 45];
+    __shared__ double sr[kStepCams * 9];
     if (sc->done) return;  // uniform: nobody writes `done` while this kernel runs
     const double alpha = first ? 0.0 : sc->alpha;
     double rz = 0.0, rr = 0.0;
-    for (int32_t j = blockIdx.x * kRedBlock + threadIdx.x; j < m; j += gridDim.x * kRedBlock) {
-        const double* L = lfac + 45 * (int64_t)j;
-        double rj[9], y[9];
-#pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            const int64_t t = 9 * (int64_t)j + a;
-            double v = r[t];
+    const int32_t groups = (m + kStepCams - 1) / kStepCams;
+    for (int32_t g = blockIdx.x; g < groups; g += gridDim.x) {
+        const int32_t j0 = g * kStepCams;
+        const int32_t nc = min(kStepCams, m - j0);
+        const int64_t e0 = 9 * (int64_t)j0;
+        for (int t = threadIdx.x; t < 9 * nc; t += kRedBlock) {
+            double v = r[e0 + t];
             if (!first) {
-                x[t] += alpha * p[t];
-                v -= alpha * q[t];
-                r[t] = v;
+                x[e0 + t] += alpha * p[e0 + t];
+                v -= alpha * q[e0 + t];
+                r[e0 + t] = v;
             }
-            rj[a] = v;
+            sr[t] = v;
         }
+        for (int t = threadIdx.x; t < 45 * nc; t += kRedBlock) sl[t] = lfac[45 * (int64_t)j0 + t];
+        __syncthreads();
+        if (threadIdx.x < nc) {
+            const double* L = sl + 45 * threadIdx.x;
+            double* rj = sr + 9 * threadIdx.x;
+            double rv[9], y[9];
 #pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            double v = rj[a];
+            for (int a = 0; a < 9; ++a) rv[a] = rj[a];
 #pragma unroll
-            for (int t = 0; t < a; ++t) v -= L[tri2(a, t)] * y[t];
-            y[a] = v / L[tri2(a, a)];
+            for (int a = 0; a < 9; ++a) {
+                double v = rv[a];
+#pragma unroll
+                for (int t = 0; t < a; ++t) v -= L[tri2(a, t)] * y[t];
+                y[a] = v / L[tri2(a, a)];
+            }
+#pragma unroll
+            for (int a = 8; a >= 0; --a) {
+                double v = y[a];
+#pragma unroll
+                for (int t = a + 1; t < 9; ++t) v -= L[tri2(t, a)] * y[t];
+                y[a] = v / L[tri2(a, a)];
+            }
+#pragma unroll
+            for (int a = 0; a < 9; ++a) {
+                rz += rv[a] * y[a];
+                rr += rv[a] * rv[a];
+                rj[a] = y[a];  // z replaces r in LDS
+            }
         }
-#pragma unroll
-        for (int a = 8; a >= 0; --a) {
-            double v = y[a];
-#pragma unroll
-            for (int t = a + 1; t < 9; ++t) v -= L[tri2(t, a)] * y[t];
-            y[a] = v / L[tri2(a, a)];
-        }
-#pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            z[9 * (int64_t)j + a] = y[a];
-            rz += rj[a] * y[a];
-            rr += rj[a] * rj[a];
-        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < 9 * nc; t += kRedBlock) z[e0 + t] = sr[t];
+        __syncthreads();
     }
     block_partials<2>(rz, rr, partials);
     if (!last_block_arrives(&sc->arrive[0])) return;
@@ -196,41 +214,55 @@ __global__ __launch_bounds__(kRedBlock) void k_pcg_step(int32_t m, int first, co
 hipError_t launch_pcg_step(int32_t m, bool first, const double* lfac, const double* p, const double* q, double* x,
                            double* r, double* z, double* partials, PcgScalars* sc, hipStream_t s)
 {
-    const int32_t b = reduce_blocks(m);
+    int32_t b = (m + kStepCams - 1) / kStepCams;
+    if (b > 2048) b = 2048;  // the partial sums hold 2048 blocks; larger m loops
+    if (b < 1) b = 1;
     hipLaunchKernelGGL(k_pcg_step, dim3(b), dim3(kRedBlock), 0, s, m, first ? 1 : 0, lfac, p, q, x, r, z, partials, sc);
     return hipGetLastError();
 }
 
 // p = z (first iteration) or z + beta p; pT = (T) p.  With xf set, also the
 // camera vectors the recomputing Schur product reads: [J_l p_w, p_t, p_f,
-// p_k1, p_k2] in T (12 words per camera, the last three unused).  One thread
-// per camera.
+// p_k1, p_k2] in T (12 words per camera, the last three unused).  A
+// workgroup takes kStepCams cameras; vectors are read and written in
+// contiguous runs, the new p passing through LDS for the J_l products.
 template <typename T>
-__global__ void k_pcg_direction(int32_t m, int force, const double* __restrict__ z, double* __restrict__ p,
-                                T* __restrict__ pT, const CamK<T>* __restrict__ ck, T* __restrict__ xf,
-                                const PcgScalars* __restrict__ sc)
+__global__ __launch_bounds__(kRedBlock) void k_pcg_direction(int32_t m, int force, const double* __restrict__ z,
+                                                             double* __restrict__ p, T* __restrict__ pT,
+                                                             const CamK<T>* __restrict__ ck, T* __restrict__ xf,
+                                                             const PcgScalars* __restrict__ sc)
 {
+    __shared__ double sv[kStepCams * 9];
     if (!force && sc->done) return;
     const bool first = force || sc->iters == 0;
     const double beta = first ? 0.0 : sc->beta;
-    for (int32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < m; j += gridDim.x * blockDim.x) {
-        double v[9];
-#pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            const int64_t t = 9 * (int64_t)j + a;
-            v[a] = first ? z[t] : z[t] + beta * p[t];
-            p[t] = v[a];
-            pT[t] = (T)v[a];
+    const int32_t groups = (m + kStepCams - 1) / kStepCams;
+    for (int32_t g = blockIdx.x; g < groups; g += gridDim.x) {
+        const int32_t j0 = g * kStepCams;
+        const int32_t nc = min(kStepCams, m - j0);
+        const int64_t e0 = 9 * (int64_t)j0;
+        for (int t = threadIdx.x; t < 9 * nc; t += kRedBlock) {
+            const double v = first ? z[e0 + t] : z[e0 + t] + beta * p[e0 + t];
+            p[e0 + t] = v;
+            pT[e0 + t] = (T)v;
+            sv[t] = v;
         }
         if (xf) {
-            const T* J = ck[j].Jl;
-            T* o = xf + 12 * (int64_t)j;
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-                o[a] = (T)((double)J[3 * a] * v[0] + (double)J[3 * a + 1] * v[1] + (double)J[3 * a + 2] * v[2]);
-#pragma unroll
-            for (int a = 3; a < 9; ++a) o[a] = (T)v[a];
+            __syncthreads();
+            for (int t = threadIdx.x; t < 12 * nc; t += kRedBlock) {
+                const int c = t / 12, a = t - 12 * c;
+                const double* v = sv + 9 * c;
+                T o = (T)0;
+                if (a < 3) {
+                    const T* J = ck[j0 + c].Jl;
+                    o = (T)((double)J[3 * a] * v[0] + (double)J[3 * a + 1] * v[1] + (double)J[3 * a + 2] * v[2]);
+                } else if (a < 9) {
+                    o = (T)v[a];
+                }
+                xf[12 * (int64_t)j0 + t] = o;
+            }
         }
+        __syncthreads();
     }
 }
 
@@ -238,10 +270,11 @@ template <typename T>
 hipError_t launch_pcg_direction(int32_t m, bool force, const double* z, double* p, T* pT, const CamK<T>* ck, T* xf,
                                 PcgScalars* sc, hipStream_t s)
 {
-    int32_t b = (m + 255) / 256;
+    int32_t b = (m + kStepCams - 1) / kStepCams;
+    if (b > 4096) b = 4096;
     if (b < 1) b = 1;
-    hipLaunchKernelGGL((k_pcg_direction<T>), dim3((unsigned)b), dim3(256), 0, s, m, force ? 1 : 0, z, p, pT, ck, xf,
-                       sc);
+    hipLaunchKernelGGL((k_pcg_direction<T>), dim3((unsigned)b), dim3(kRedBlock), 0, s, m, force ? 1 : 0, z, p, pT,
+                       ck, xf, sc);
     return hipGetLastError();
 }
 
