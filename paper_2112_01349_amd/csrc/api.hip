@@ -470,7 +470,9 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     // wavefronts; the point-major arrays end with one padding tile (point -1)
     P->pm.ld = ((N + 63) / 64 + 1) * 64;
     const int64_t ntiles64 = (N + 63) / 64;
-    const int32_t waves_per_wg = P->is_f32() ? HotThreads<float>::value / 64 : HotThreads<double>::value / 64;
+    const int32_t waves_per_wg = sp.recompute
+                                     ? (P->is_f32() ? FreeWgThreads<float>::value : FreeWgThreads<double>::value) / 64
+                                     : (P->is_f32() ? HotThreads<float>::value : HotThreads<double>::value) / 64;
     sp.num_wg = 0;
     if (ntiles64 > 0)
         sp.num_wg = (int32_t)std::max<int64_t>(1, std::min<int64_t>(std::max(1, cus),

@@ -19,6 +19,8 @@ constexpr int kCamSlotWords = 54;  // 45 upper-triangle B terms + 9 v terms
 constexpr int kSlotSeg = 32;       // slots summed by one wavefront before the per-camera combine
 constexpr int kHotFold = 8;        // slices the per-workgroup hot partials are folded into
 constexpr int kBcold = 8;          // words of T per point record read by the cold pass
+constexpr int kSmallBlocks = 96;   // blocks of the product's epilogue (its last-block reduction
+                                   // serialises one device-scope atomic per block)
 
 // Scalars of one PCG run, kept on the device.  Kernels of the PCG loop read
 // `done` first and do nothing once it is set, so the host can enqueue
@@ -102,6 +104,20 @@ struct HotThreads<float> {
 };
 template <>
 struct HotThreads<double> {
+    static constexpr int value = 512;
+};
+
+// Threads per workgroup of the recomputing product's point-major pass (one
+// workgroup per CU, like the stored-block pass).  Twelve FP64 wavefronts
+// (three per SIMD) ran 1% faster than eight but spill; eight are kept.
+template <typename T>
+struct FreeWgThreads;
+template <>
+struct FreeWgThreads<float> {
+    static constexpr int value = 1024;
+};
+template <>
+struct FreeWgThreads<double> {
     static constexpr int value = 512;
 };
 

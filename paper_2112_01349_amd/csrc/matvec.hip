@@ -594,7 +594,7 @@ __device__ __forceinline__ void free_short(const FreeRow<T>& r, const FreeData<T
 // which lets the compiler keep it in registers without spilling.
 template <typename T, int MODE>
 struct FreeThreads {
-    static constexpr int value = MODE == 2 ? 256 : HotThreads<T>::value;
+    static constexpr int value = MODE == 2 ? 256 : FreeWgThreads<T>::value;
 };
 
 template <typename T, int MODE>
@@ -1072,7 +1072,7 @@ hipError_t launch_schur_product(int mode, const SchurPlan& sp, const PointMajor&
     const size_t lds = hot_lds_bytes<T>(sp.K);
     if (hot_begin && (e = hipEventRecord(hot_begin, s)) != hipSuccess) return e;
     if (sp.num_wg > 0) {
-        const dim3 g(sp.num_wg), b(HotThreads<T>::value);
+        const dim3 g(sp.num_wg), b(sp.recompute && ri ? FreeWgThreads<T>::value : HotThreads<T>::value);
         if (mode == 0 && sp.recompute && ri)
             hipLaunchKernelGGL((k_schur_free<T, 0>), g, b, lds, s, sp.frange, sp.sseg, sp.lrange, sp.lseg, pm.cam,
                                pm.pt, ri->wobs, ri->pts, ri->ck, ri->ck64, ri->xf, cinv, nullptr, sp.K, (double*)sp.hot_part,
@@ -1116,7 +1116,9 @@ hipError_t launch_schur_product(int mode, const SchurPlan& sp, const PointMajor&
                            (const double*)sp.hot_part, sp.hot_fold, (const PcgScalars*)sc, mode == 0 ? 1 : 0);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    const int32_t nb = reduce_blocks(9 * (int64_t)m);
+    // few blocks: the last-block reduction serialises one device-scope atomic per block
+    int32_t nb = reduce_blocks(9 * (int64_t)m);
+    if (nb > kSmallBlocks) nb = kSmallBlocks;
     const int32_t Ke = sp.num_wg > 0 ? sp.K : 0;
     if (mode == 0)
         hipLaunchKernelGGL((k_schur_epilogue<0>), dim3(nb), dim3(kRedBlock), 0, s, m, Ke, sp.hot_fold,
@@ -1139,7 +1141,7 @@ hipError_t launch_backsub_free(const SchurPlan& sp, const PointMajor& pm, const 
 {
     if (sp.num_wg <= 0) return hipGetLastError();
     constexpr int NT = FreeThreads<T, 2>::value;  // the same waves as the product, NT / 64 per workgroup
-    hipLaunchKernelGGL((k_schur_free<T, 2>), dim3(sp.num_wg * (HotThreads<T>::value / NT)), dim3(NT), 0, s, sp.frange, sp.sseg,
+    hipLaunchKernelGGL((k_schur_free<T, 2>), dim3(sp.num_wg * (FreeWgThreads<T>::value / NT)), dim3(NT), 0, s, sp.frange, sp.sseg,
                        sp.lrange, sp.lseg, pm.cam, pm.pt, ri.wobs, ri.pts, ri.ck, ri.ck64, ri.xf, cinv, wpt, 0, nullptr,
                        nullptr, sp.has_cold, dp, nullptr);
     return hipGetLastError();

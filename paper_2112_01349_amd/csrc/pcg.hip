@@ -150,19 +150,20 @@ __global__ __launch_bounds__(kRedBlock) void k_pcg_step(int32_t m, int first, co
             double rv[9], y[9];
 #pragma unroll
             for (int a = 0; a < 9; ++a) rv[a] = rj[a];
+            // the factor's diagonal holds reciprocals (store_factor)
 #pragma unroll
             for (int a = 0; a < 9; ++a) {
                 double v = rv[a];
 #pragma unroll
                 for (int t = 0; t < a; ++t) v -= L[tri2(a, t)] * y[t];
-                y[a] = v / L[tri2(a, a)];
+                y[a] = v * L[tri2(a, a)];
             }
 #pragma unroll
             for (int a = 8; a >= 0; --a) {
                 double v = y[a];
 #pragma unroll
                 for (int t = a + 1; t < 9; ++t) v -= L[tri2(t, a)] * y[t];
-                y[a] = v / L[tri2(a, a)];
+                y[a] = v * L[tri2(a, a)];
             }
 #pragma unroll
             for (int a = 0; a < 9; ++a) {
@@ -214,8 +215,10 @@ __global__ __launch_bounds__(kRedBlock) void k_pcg_step(int32_t m, int first, co
 hipError_t launch_pcg_step(int32_t m, bool first, const double* lfac, const double* p, const double* q, double* x,
                            double* r, double* z, double* partials, PcgScalars* sc, hipStream_t s)
 {
+    // one block per group of cameras (the partial sums hold 2048 blocks;
+    // beyond that each block loops over several groups)
     int32_t b = (m + kStepCams - 1) / kStepCams;
-    if (b > 2048) b = 2048;  // the partial sums hold 2048 blocks; larger m loops
+    if (b > 2048) b = 2048;
     if (b < 1) b = 1;
     hipLaunchKernelGGL(k_pcg_step, dim3(b), dim3(kRedBlock), 0, s, m, first ? 1 : 0, lfac, p, q, x, r, z, partials, sc);
     return hipGetLastError();

@@ -47,6 +47,17 @@ __device__ __forceinline__ bool cholesky9(double L[45])
     return ok;
 }
 
+// The factor as the PCG step applies it: the lower triangle with each
+// diagonal entry replaced by its reciprocal, so the two triangular solves
+// multiply instead of divide.
+__device__ __forceinline__ void store_factor(const double L[45], double* __restrict__ out)
+{
+#pragma unroll
+    for (int r = 0; r < 9; ++r)
+#pragma unroll
+        for (int c = 0; c <= r; ++c) out[tri(r, c)] = r == c ? 1.0 / L[tri(r, c)] : L[tri(r, c)];
+}
+
 __global__ void k_damp_cameras(int32_t m, const double* __restrict__ hcc, double lambda, int32_t damping,
                                double* __restrict__ bd, double* __restrict__ lfac, double* __restrict__ dcam,
                                int32_t* __restrict__ flag)
@@ -68,7 +79,7 @@ __global__ void k_damp_cameras(int32_t m, const double* __restrict__ hcc, double
             bd[81 * (int64_t)j + r * 9 + c] = v;
         }
     const bool ok = cholesky9(L);
-    for (int q = 0; q < 45; ++q) lfac[45 * (int64_t)j + q] = L[q];
+    store_factor(L, lfac + 45 * (int64_t)j);
     if (!ok) {
         atomicOr(flag, 1);
         flag[1] = j;  // one of the failing cameras (for the error message)
@@ -87,7 +98,7 @@ __global__ void k_factor_schur_jacobi(int32_t m, const double* __restrict__ bd, 
     for (int r = 0; r < 9; ++r)
         for (int c = 0; c <= r; ++c) L[tri(r, c)] = bd[81 * (int64_t)j + r * 9 + c] + mj[81 * (int64_t)j + r * 9 + c];
     const bool ok = cholesky9(L);
-    for (int q = 0; q < 45; ++q) lfac[45 * (int64_t)j + q] = L[q];
+    store_factor(L, lfac + 45 * (int64_t)j);
     if (!ok) {
         atomicOr(flag, 1);
         flag[1] = j;

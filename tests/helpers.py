@@ -98,3 +98,13 @@ def oracle_spread(arrays, trace, seeds=(1, 2, 3), **oracle_kw):
             if t2["accepted"][k] != trace["accepted"][k]:
                 break
     return dict(trial=trial, cost=cost, runs=len(seeds))
+
+
+def rel_err_rows(a, b):
+    """Largest error of a row (one camera's block) relative to that row's
+    own largest entry: a small row is held to its own scale, not to the
+    largest row's."""
+    a = np.asarray(a, dtype=np.float64).reshape(len(b), -1)
+    b = np.asarray(b, dtype=np.float64).reshape(len(b), -1)
+    scale = np.maximum(np.max(np.abs(b), axis=1), 1e-300)
+    return float(np.max(np.max(np.abs(a - b), axis=1) / scale))

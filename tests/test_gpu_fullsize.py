@@ -34,11 +34,14 @@ def large():
 
 
 def sampled_cameras(d):
+    """The two most observed cameras, hot cameras of rank 20, 100 and 2000
+    (the product accumulates the 2,261 most observed ones in its LDS table),
+    the cold camera of rank 3000 and three random cold ones."""
     counts = np.diff(d["cam_csr"][0])
     order = np.argsort(-counts, kind="stable")
     rng = np.random.default_rng(5)
-    return [int(order[0]), int(order[1]), int(order[3000])] + [int(x) for x in
-                                                               rng.choice(order[2261:], 3, replace=False)]
+    return [int(order[r]) for r in (0, 1, 20, 100, 2000, 3000)] + [int(x) for x in
+                                                                 rng.choice(order[2261:], 3, replace=False)]
 
 
 def test_large_cost_gradient_fp64(large):
@@ -61,25 +64,42 @@ def test_large_cost_gradient_fp64(large):
         assert np.max(np.abs(gp[i] - ref)) <= 1e-10 * np.max(np.abs(ref)) + 1e-300, i
 
 
+@pytest.fixture(scope="module")
+def large_rows(large):
+    """The oracle's rows of the damped reduced system at lambda 1e-3 for the
+    sampled cameras (rank 20 and below), computed once from scratch."""
+    prob = large["prob"]
+    x = np.random.default_rng(7).normal(size=(prob.num_cameras, 9))
+    rows = sampled_cameras(large)[2:]
+    ref = orc.schur_rows(rows, *large["args"][:2], *large["args"][2:], x, 1e-3, DELTA,
+                         cam_csr=large["cam_csr"], pt_csr=large["pt_csr"])
+    return dict(x=x, rows=rows, ref=ref, lam=1e-3)
+
+
 @pytest.mark.parametrize("stored", [0, 1])
 @pytest.mark.parametrize("precision", [FP64, FP32_MIXED])
-def test_large_schur_rows(large, precision, stored, monkeypatch):
+def test_large_schur_rows(large, large_rows, precision, stored, monkeypatch):
     """Sampled rows of the reduced-system product at full size, from the
     recomputing product and from the stored-block one, against the oracle's
-    rows computed from scratch."""
+    rows computed from scratch: three hot cameras (their camera side goes
+    through the workgroups' LDS tables and the fold) and four cold ones
+    (the camera-major cold pass).  Each row is compared relative to its own
+    largest entry."""
     monkeypatch.setenv("BA_SCHUR_STORED", str(stored))
-    prob = large["prob"]
     gpu = Problem(*large["args"], precision=precision, huber_delta=DELTA)
-    lam = 1e-3
-    x = np.random.default_rng(7).normal(size=(prob.num_cameras, 9))
-    q = gpu.schur_matvec(x, lam)
+    q = gpu.schur_matvec(large_rows["x"], large_rows["lam"])
     gpu.close()
-    rows = sampled_cameras(large)[2:]   # the oracle's per-row cost grows with the camera's points
-    ref = orc.schur_rows(rows, *large["args"][:2], *large["args"][2:], x, lam, DELTA,
-                         cam_csr=large["cam_csr"], pt_csr=large["pt_csr"])
-    tol = 1e-9 if precision == FP64 else 2e-3
-    for t, j in enumerate(rows):
-        assert np.max(np.abs(q[j] - ref[t])) <= tol * np.max(np.abs(ref[t])), (j, q[j], ref[t])
+    counts = np.diff(large["cam_csr"][0])
+    order = np.argsort(-counts, kind="stable")
+    assert large_rows["rows"][:3] == [int(order[r]) for r in (20, 100, 2000)]   # hot (rank < 2261)
+    # FP32-mixed: float rounding through a row's thousands of points gives
+    # 2e-7 .. 3e-6; the bound is ten times that and more
+    tol = 1e-9 if precision == FP64 else 5e-5
+    errs = [np.max(np.abs(q[j] - large_rows["ref"][t])) / np.max(np.abs(large_rows["ref"][t]))
+            for t, j in enumerate(large_rows["rows"])]
+    print(f"precision {precision} stored {stored}: row errors " + " ".join(f"{e:.1e}" for e in errs))
+    for t, j in enumerate(large_rows["rows"]):
+        assert errs[t] <= tol, (j, q[j], large_rows["ref"][t])
 
 
 def load_golden(name):
@@ -142,14 +162,21 @@ def test_lm_trace_fp64_matches_oracle(name):
         prev = g["cost"][k]
 
 
-def test_lm_mixed_reaches_oracle_final_cost():
-    """The FP32-mixed solve (PCG rtol 1e-6, no replayed schedule) reaches the
-    oracle's 20-iteration FP64 final cost within relative 1e-4, within 30 LM
-    iterations, with non-increasing accepted costs.  The problem is far from
-    converged at 20 iterations (each one still lowers F by ~2e-4 relative) and
-    late PCG solves stop at their cap unconverged in both precisions, so the
-    FP32 and FP64 step sequences drift apart; after exactly 20 iterations the
-    mixed cost lands within a few 1e-4 of the oracle's on either side."""
+# How far above the oracle's 20-iteration cost the FP32-mixed solve may end
+# after the same 20 iterations: over repeated runs it ended between -4.8e-4
+# and +5.1e-4 of it (8 of 9 at or below +1e-4), so twice the worst excess.
+MIXED_20_MARGIN = 1e-3
+
+
+def test_lm_mixed_meets_oracle_final_cost():
+    """The FP32-mixed solve of the 29M workload (PCG rtol 1e-6, no replayed
+    schedule) against the oracle's 20-iteration FP64 cost.  After exactly 20
+    iterations its cost is at most MIXED_20_MARGIN above the oracle's: the
+    problem is still descending ~2e-4 per iteration, late PCG solves stop
+    at their cap or break down on the FP32 products' rounding, and a
+    rejected step costs an iteration, so the 20-iteration cost varies by a
+    few 1e-4 either side from run to run.  Within 30 iterations it reaches
+    the oracle's cost within 1e-4, with non-increasing accepted costs."""
     g = load_golden("large")
     prob = synth.generate("large", seed=0)
     gpu = Problem(prob.cameras0, prob.points0, prob.obs_camera, prob.obs_point, prob.obs_uv,
@@ -160,10 +187,11 @@ def test_lm_mixed_reaches_oracle_final_cost():
     assert rep["status"] == 0, (rep["error"], rep["lambda"].tolist(), rep["cost"].tolist())
     costs = np.concatenate([[rep["initial_cost"]], rep["cost"]])
     assert np.all(np.diff(costs) <= 0)
-    target = g["final_cost"] * (1 + 1e-4)
-    reached = np.nonzero(rep["cost"] <= target)[0]
-    print(f"mixed cost after 20 iterations: {rep['cost'][19] / g['final_cost'] - 1:+.2e} relative to the oracle; "
-          f"target reached at iteration {reached[0] + 1 if len(reached) else None}")
+    F20 = rep["cost"][19] / g["final_cost"] - 1
+    reached = np.nonzero(rep["cost"] <= g["final_cost"] * (1 + 1e-4))[0]
+    print(f"mixed cost after 20 iterations: {F20:+.2e} relative to the oracle; within 1e-4 from iteration "
+          f"{reached[0] + 1 if len(reached) else None}; PCG stops {rep['pcg_stop'].tolist()}")
+    assert F20 <= MIXED_20_MARGIN
     assert len(reached) > 0, (rep["final_cost"], g["final_cost"])
 
 
@@ -190,8 +218,10 @@ def test_stress_cost_gradient_and_schur_rows():
     x = np.random.default_rng(8).normal(size=(prob.num_cameras, 9))
     q = gpu.schur_matvec(x, 1e-3)
     ref = orc.schur_rows(rows, *args[:2], *args[2:], x, 1e-3, DELTA, cam_csr=cam_csr, pt_csr=pt_csr)
+    errs = [np.max(np.abs(q[j] - ref[t])) / np.max(np.abs(ref[t])) for t, j in enumerate(rows)]
+    print("60M FP32-mixed row errors " + " ".join(f"{e:.1e}" for e in errs))
     for t, j in enumerate(rows):
-        assert np.max(np.abs(q[j] - ref[t])) <= 2e-3 * np.max(np.abs(ref[t])), j
+        assert errs[t] <= 2e-3, j
     rep = gpu.lm_solve(max_lm_iters=2, max_pcg_iters=200, pcg_rtol=1e-6)
     gpu.close()
     assert rep["status"] == 0
@@ -230,8 +260,10 @@ def test_synthesised_20000_cost_gradient_and_schur_rows():
             assert np.max(np.abs(gp[i] - ref)) <= gtol * np.max(np.abs(ref)), (precision, i)
         q = gpu.schur_matvec(x, 1e-3)
         qtol = 1e-9 if precision == FP64 else 2e-3
+        errs = [np.max(np.abs(q[j] - ref_rows[t])) / np.max(np.abs(ref_rows[t])) for t, j in enumerate(cams)]
+        print(f"80M precision {precision}: row errors " + " ".join(f"{e:.1e}" for e in errs))
         for t, j in enumerate(cams):
-            assert np.max(np.abs(q[j] - ref_rows[t])) <= qtol * np.max(np.abs(ref_rows[t])), (precision, j)
+            assert errs[t] <= qtol, (precision, j)
         rep = gpu.lm_solve(max_lm_iters=2, max_pcg_iters=100, pcg_rtol=1e-6)
         gpu.close()
         assert rep["status"] == 0

@@ -10,12 +10,19 @@ relative 1e-4 of the oracle's.
 import numpy as np
 import pytest
 
-from helpers import oracle_spread, order_spread, rel_err, small_zipf, with_edge_cases
+from helpers import oracle_spread, order_spread, rel_err, rel_err_rows, small_zipf, with_edge_cases
 from oracle import oracle as orc
 from paper_2112_01349_amd import FP32_MIXED, FP64, Problem, synth
 from paper_2112_01349_amd.native import PRECOND_SCHUR_JACOBI, SOLVER_DENSE
 
 pytestmark = pytest.mark.gpu
+
+# The FP32-mixed reduced-system product against the FP64 oracle, per camera
+# row relative to the row's largest entry.  Float rounding (unit 6e-8) of the
+# Jacobian and of the per-point sums, carried through C~^-1 and the sum over
+# a camera's points, gives 1e-7 .. 5e-6 on these problems; the bound is about
+# 800 float units, ten times the largest seen.
+FP32_PRODUCT_TOL = 5e-5
 
 
 def make(prob_or_arrays, precision=FP64, **opts):
@@ -39,8 +46,8 @@ def test_cost_and_gradient(tiny, delta):
     F, gc, gp = prob.eval_cost_grad()
     Fo, gco, gpo = orc.gradient(cams, pts, oc, op, uv, delta)
     assert abs(F - Fo) <= 1e-13 * abs(Fo)
-    assert rel_err(gc, gco) <= 1e-10
-    assert rel_err(gp, gpo) <= 1e-10
+    assert rel_err_rows(gc, gco) <= 1e-10
+    assert rel_err_rows(gp, gpo) <= 1e-10
     c2, p2 = prob.get_params()
     np.testing.assert_array_equal(c2, cams)
     np.testing.assert_array_equal(p2, pts)
@@ -58,7 +65,7 @@ def test_schur_matvec(tiny, damping, stored, monkeypatch):
     x = np.random.default_rng(4).normal(size=(len(cams), 9))
     ref = orc.schur_matvec(oc, op, Bd, A["E"], Ci, x)
     q = prob.schur_matvec(x, lam, damping)
-    assert rel_err(q, ref) <= 1e-11
+    assert rel_err_rows(q, ref) <= 1e-11
 
 
 def test_edge_cases_cost_gradient_matvec():
@@ -68,7 +75,7 @@ def test_edge_cases_cost_gradient_matvec():
     F, gc, gp = prob.eval_cost_grad()
     Fo, gco, gpo = orc.gradient(cams, pts, oc, op, uv, 1.0)
     assert abs(F - Fo) <= 1e-13 * abs(Fo)
-    assert rel_err(gc, gco) <= 1e-10 and rel_err(gp, gpo) <= 1e-10
+    assert rel_err_rows(gc, gco) <= 1e-10 and rel_err_rows(gp, gpo) <= 1e-10
     assert np.all(gc[info["unseen_camera"]] == 0.0) and np.all(gp[info["unseen_point"]] == 0.0)
     lam = 1e-2
     A = orc.assemble(cams, pts, oc, op, uv, 1.0)
@@ -76,7 +83,7 @@ def test_edge_cases_cost_gradient_matvec():
     Ci = orc.invert_points(Cd)
     x = np.random.default_rng(5).normal(size=(len(cams), 9))
     ref = orc.schur_matvec(oc, op, Bd, A["E"], Ci, x)
-    assert rel_err(prob.schur_matvec(x, lam), ref) <= 1e-10
+    assert rel_err_rows(prob.schur_matvec(x, lam), ref) <= 1e-10
 
 
 def lm_pair(src, delta=0.0, iters=10, max_pcg=50, rtol=1e-8, spread=True):
@@ -212,8 +219,10 @@ def test_hot_cold_split_matches_oracle(hot, stored, monkeypatch):
         Ci = orc.invert_points(Cd)
         x = np.random.default_rng(hot).normal(size=(len(cams), 9))
         ref = orc.schur_matvec(oc, op, Bd, A["E"], Ci, x)
-        tol = 1e-10 if precision == FP64 else 1e-4
-        assert rel_err(prob.schur_matvec(x, lam), ref) <= tol, precision
+        tol = 1e-10 if precision == FP64 else FP32_PRODUCT_TOL
+        err = rel_err_rows(prob.schur_matvec(x, lam), ref)
+        print(f"hot {hot} stored {stored} precision {precision}: product error {err:.2e} of each row")
+        assert err <= tol, precision
         prob.close()
     tr, gpu, prob, _ = lm_pair(arrays, delta=1.0, iters=5, max_pcg=40, rtol=1e-8)
     assert_traces_match(tr, gpu)
@@ -239,17 +248,19 @@ def test_autodiff_jacobian_cost_gradient_matvec(tiny, edge):
     F, gc, gp = prob.eval_cost_grad()
     Fo, gco, gpo = orc.gradient(cams, pts, oc, op, uv, 1.0)
     assert abs(F - Fo) <= 1e-13 * abs(Fo)
-    assert rel_err(gc, gco) <= 1e-10 and rel_err(gp, gpo) <= 1e-10
+    assert rel_err_rows(gc, gco) <= 1e-10 and rel_err_rows(gp, gpo) <= 1e-10
     lam = 1e-2
     A = orc.assemble(cams, pts, oc, op, uv, 1.0)
     Bd, Cd, Dc, Dp = orc.damp(A["B"], A["C"], lam, 0)
     Ci = orc.invert_points(Cd)
     x = np.random.default_rng(5).normal(size=(len(cams), 9))
     ref = orc.schur_matvec(oc, op, Bd, A["E"], Ci, x)
-    assert rel_err(prob.schur_matvec(x, lam), ref) <= 1e-10
+    assert rel_err_rows(prob.schur_matvec(x, lam), ref) <= 1e-10
     prob.close()
     mixed = Problem(cams, pts, oc, op, uv, precision=FP32_MIXED, huber_delta=1.0, jacobian=1)
-    assert rel_err(mixed.schur_matvec(x, lam), ref) <= 2e-3
+    err = rel_err_rows(mixed.schur_matvec(x, lam), ref)
+    print(f"autodiff edge={edge}: FP32-mixed product error {err:.2e} of each row")
+    assert err <= FP32_PRODUCT_TOL
     mixed.close()
 
 
@@ -335,8 +346,10 @@ def test_synthesised_recipe_matches_oracle(hot, monkeypatch):
     ref = orc.schur_matvec(oc, op, Bd, A["E"], orc.invert_points(Cd), x)
     for precision in (FP64, FP32_MIXED):
         gpu, _ = make(arrays, precision=precision)
-        tol = 1e-10 if precision == FP64 else 1e-3
-        assert rel_err(gpu.schur_matvec(x, lam), ref) <= tol, precision
+        tol = 1e-10 if precision == FP64 else FP32_PRODUCT_TOL
+        err = rel_err_rows(gpu.schur_matvec(x, lam), ref)
+        print(f"synthesised recipe, hot {hot}, precision {precision}: product error {err:.2e} of each row")
+        assert err <= tol, precision
         gpu.close()
     tr, rep, _, _ = lm_pair(arrays, iters=4, max_pcg=30, rtol=1e-8, spread=False)
     spread = order_spread("synth_small")
@@ -349,8 +362,9 @@ def test_mixed_point_at_camera_centre():
     """A point within FP32 resolution of a camera's centre (LM can drift there
     when a point's other views are outliers: every projection is available
     from the centre) has a depth made of rounding in FP32.  The FP32-mixed
-    form gives that observation a zero Jacobian, so the blocks, the product
-    and the LM step stay finite; the FP64 form keeps its exact Jacobian."""
+    form forms that observation's geometry in FP64 from the FP64 camera
+    constants and point (and stores it in FP32), so the blocks, the product
+    and the LM step stay finite; the FP64 form needs no such step."""
     from scipy.spatial.transform import Rotation
 
     prob = synth.generate("tiny", seed=0)
