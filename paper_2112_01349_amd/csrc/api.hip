@@ -593,6 +593,10 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     sp.wrange = A.get<int32_t>((int64_t)wrange.size());
     sp.sseg = A.get<int2>(std::max<int64_t>(1, (int64_t)sseg.size()));
     sp.lseg = A.get<int2>(std::max<int64_t>(1, (int64_t)lseg.size()));
+    P->pm.sseg = sp.sseg;
+    P->pm.lseg = sp.lseg;
+    P->pm.num_short = sp.num_short;
+    P->pm.num_long = sp.num_long;
     sp.frange = A.get<int32_t>((int64_t)frange.size());
     sp.lrange = A.get<int32_t>((int64_t)lrange.size());
     P->wobs = A.get<char>(P->pm.ld * (int64_t)tsz);

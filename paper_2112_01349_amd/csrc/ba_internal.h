@@ -73,6 +73,11 @@ struct PointMajor {
     int32_t num_tiles;
     int64_t ld;        // stream length: N rounded up to 64 plus one padding tile
                        // (cam 0, pt -1), so tile t + 1 always exists; E holds 27 ld
+    // point-aligned segments as [begin, end) observation ranges: short ones
+    // (<= 64 observations of whole points) and long ones (one longer point)
+    const int2* sseg;
+    const int2* lseg;
+    int32_t num_short, num_long;
 };
 
 // Camera-major observation stream (sorted by camera, then point).

@@ -4,13 +4,13 @@
 //
 // Two passes over the observations, each with its own sorted copy of the
 // index and pixel streams:
-//   * point-major (k_build_points): one workgroup per point-aligned tile of
-//     <= 256 observations, one thread per observation.  Writes the coupling
-//     block E_k = w J_c^T J_p (tile-blocked, see eidx), and sums the
-//     point blocks C_i = sum w J_p^T J_p and w_i = -sum w J_p^T e over each
-//     point's run through LDS.
+//   * point-major (k_build_points): one wavefront per point-aligned segment
+//     of <= 64 observations, one lane per observation.  Writes the coupling
+//     block E_k = w J_c^T J_p (tile-blocked, see eidx) when E is stored, and
+//     sums the point blocks C_i = sum w J_p^T J_p and w_i = -sum w J_p^T e
+//     over each point's run of lanes by a segmented scan.
 //   * camera-major (k_build_cameras): one wavefront per contiguous chunk of
-//     2048 observations sorted by camera.  Lanes accumulate the camera terms
+//     2048 observations sorted by camera, its rows software-pipelined.  Lanes accumulate the camera terms
 //     B_j = sum w J_c^T J_c and v_j = -sum w J_c^T e in registers while the
 //     camera does not change and flush a wavefront-reduced partial sum into a
 //     slot when it does; slots of one camera are contiguous and are summed in
@@ -23,6 +23,7 @@
 //     at the damping of the current LM iteration.
 #include "ba_internal.h"
 #include "autodiff.h"
+#include "wave_ops.h"
 
 namespace ba {
 
@@ -135,136 +136,275 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Point-major build over point-aligned tiles of <= kTile observations (a
-// longer point is a tile alone).  One thread per observation computes its
-// residual and Jacobian, stores its IRLS weight and, when hcp is given,
-// E_k = w J_c^T J_p (27 coalesced streams);
-// its terms of C_i and w_i go to LDS (FP64), and the first thread of each
-// point sums the point's terms in stream order and stores C_i (upper 6) and
-// w_i in FP64.  GRAD_ONLY forms w_i only.
-template <typename T, bool GRAD_ONLY, bool AD>
-__global__ __launch_bounds__(kTile) void k_build_points(
-    const int32_t* __restrict__ tile, const int32_t* __restrict__ cam, const int32_t* __restrict__ pt,
-    const double* __restrict__ uvx, const double* __restrict__ uvy, const double* __restrict__ pts,
-    JacSource<T> js, T delta, int64_t ld, T* __restrict__ hcp, double* __restrict__ hpp,
-    double* __restrict__ wpt, T* __restrict__ wobs)
+// Point-major build, one wavefront per point-aligned segment.  A short
+// segment (up to 64 observations of whole points) has one observation per
+// lane: each lane computes its residual and Jacobian, stores its IRLS weight
+// and, when E is stored, E_k = w J_c^T J_p (27 coalesced rows); its terms of
+// C_i and w_i (FP64) are summed over each point's run of lanes by a
+// segmented scan, and the run's last lane stores C_i (upper 6) and w_i.  A
+// long segment (one point of more than 64 observations) is walked in rows of
+// 64 with per-lane partial sums reduced over the wavefront at the end.  Both
+// sums have a fixed order.  GRAD_ONLY forms w_i only; without STORE_E the
+// camera half of the Jacobian is never formed.
+template <typename T, bool GRAD_ONLY, bool AD, bool STORE_E>
+__global__ __launch_bounds__(256) void k_build_points(
+    int32_t num_short, const int2* __restrict__ sseg, int32_t num_long, const int2* __restrict__ lseg,
+    const int32_t* __restrict__ cam, const int32_t* __restrict__ pt, const double* __restrict__ uvx,
+    const double* __restrict__ uvy, const double* __restrict__ pts, JacSource<T> js, T delta,
+    T* __restrict__ hcp, double* __restrict__ hpp, double* __restrict__ wpt, T* __restrict__ wobs)
 {
     constexpr int R = GRAD_ONLY ? 3 : 9;  // terms kept: [C upper 6 |] w 3
-    __shared__ double sh[R][kTile];
-    __shared__ int32_t shpt[kTile];
-    __shared__ double red[R][kTile / 64];
-    const int tid = threadIdx.x;
-    const int32_t s = tile[blockIdx.x], e = tile[blockIdx.x + 1];
-    const int32_t len = e - s;
-    if (len <= kTile) {
-        const bool valid = tid < len;
-        int32_t i = -1;
-        if (valid) {
-            const int64_t k = s + tid;
+    const int lane = threadIdx.x & 63;
+    const int32_t w = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+    if (w < num_short) {
+        const int2 be = sseg[w];
+        const int32_t b = __builtin_amdgcn_readfirstlane(be.x);
+        const int32_t len = __builtin_amdgcn_readfirstlane(be.y) - b;
+        const bool valid = lane < len;
+        const int64_t k = b + (valid ? lane : 0);
+        T e0, e1, wt, Jc[18], Jp[6];
+        int32_t i;
+        observation<T, AD>(k, cam, pt, uvx, uvy, pts, js, delta, e0, e1, wt, Jc, Jp, i);
+        if (!GRAD_ONLY && valid) {
+            if (STORE_E) store_coupling_blocked<T>(k, Jc, Jp, wt, hcp);
+            wobs[k] = wt;
+        }
+        double v[9];
+        point_terms<T>(Jp, e0, e1, wt, v);
+        double a[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) a[q] = v[9 - R + q];
+        // runs of one point: lane 0 and every lane whose point differs from
+        // the lane before start one; lanes past the segment start none and
+        // only ever follow the valid ones
+        const int32_t prev = lane_before(i, -1);
+        const uint64_t heads = __ballot(valid && (lane == 0 || i != prev));
+        const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+        const int seg_s = 63 - __clzll((heads & upto) | 1ull);
+        run_prefix_sel<double, R>(a, lane, seg_s);
+        const bool last = valid && (lane == len - 1 || ((heads >> (lane + 1)) & 1ull));
+        if (last) {
+            if (!GRAD_ONLY)
+#pragma unroll
+                for (int q = 0; q < 6; ++q) hpp[6 * (int64_t)i + q] = a[q];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) wpt[3 * (int64_t)i + q] = a[R - 3 + q];
+        }
+    } else if (w < num_short + num_long) {
+        const int2 be = lseg[w - num_short];
+        const int32_t s0 = __builtin_amdgcn_readfirstlane(be.x), s1 = __builtin_amdgcn_readfirstlane(be.y);
+        const int32_t i = __builtin_amdgcn_readfirstlane(pt[s0]);
+        double acc[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) acc[q] = 0.0;
+        for (int64_t r = s0; r < s1; r += 64) {
+            const bool valid = r + lane < s1;
+            const int64_t k = valid ? r + lane : r;
             T e0, e1, wt, Jc[18], Jp[6];
-            observation<T, AD>(k, cam, pt, uvx, uvy, pts, js, delta, e0, e1, wt, Jc, Jp, i);
-            if (!GRAD_ONLY) {
-                if (hcp) store_coupling_blocked<T>(k, Jc, Jp, wt, hcp);
+            int32_t ii;
+            observation<T, AD>(k, cam, pt, uvx, uvy, pts, js, delta, e0, e1, wt, Jc, Jp, ii);
+            if (!GRAD_ONLY && valid) {
+                if (STORE_E) store_coupling_blocked<T>(k, Jc, Jp, wt, hcp);
                 wobs[k] = wt;
             }
             double v[9];
             point_terms<T>(Jp, e0, e1, wt, v);
+            if (valid)
 #pragma unroll
-            for (int q = 0; q < R; ++q) sh[q][tid] = v[9 - R + q];
+                for (int q = 0; q < R; ++q) acc[q] += v[9 - R + q];
         }
-        shpt[tid] = i;
-        __syncthreads();
-        if (valid && (tid == 0 || shpt[tid - 1] != i)) {
-            double acc[R];
 #pragma unroll
-            for (int q = 0; q < R; ++q) acc[q] = 0.0;
-            for (int u = tid; u < len && shpt[u] == i; ++u)
-#pragma unroll
-                for (int q = 0; q < R; ++q) acc[q] += sh[q][u];
+        for (int q = 0; q < R; ++q) acc[q] = wave_sum(acc[q]);
+        if (lane == 0) {
             if (!GRAD_ONLY)
 #pragma unroll
                 for (int q = 0; q < 6; ++q) hpp[6 * (int64_t)i + q] = acc[q];
 #pragma unroll
             for (int q = 0; q < 3; ++q) wpt[3 * (int64_t)i + q] = acc[R - 3 + q];
         }
-    } else {
-        // one point with more than kTile observations: strided partial sums,
-        // then a fixed-order reduction over the block
-        const int32_t i = pt[s];
-        double acc[R];
-#pragma unroll
-        for (int q = 0; q < R; ++q) acc[q] = 0.0;
-        for (int64_t k = s + tid; k < e; k += kTile) {
-            T e0, e1, wt, Jc[18], Jp[6];
-            int32_t ii;
-            observation<T, AD>(k, cam, pt, uvx, uvy, pts, js, delta, e0, e1, wt, Jc, Jp, ii);
-            if (!GRAD_ONLY) {
-                if (hcp) store_coupling_blocked<T>(k, Jc, Jp, wt, hcp);
-                wobs[k] = wt;
-            }
-            double v[9];
-            point_terms<T>(Jp, e0, e1, wt, v);
-#pragma unroll
-            for (int q = 0; q < R; ++q) acc[q] += v[9 - R + q];
-        }
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-            const double w = wave_sum(acc[q]);
-            if ((tid & 63) == 0) red[q][tid >> 6] = w;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            double tot[R];
-#pragma unroll
-            for (int q = 0; q < R; ++q) {
-                tot[q] = 0.0;
-                for (int w = 0; w < kTile / 64; ++w) tot[q] += red[q][w];
-            }
-            if (!GRAD_ONLY)
-#pragma unroll
-                for (int q = 0; q < 6; ++q) hpp[6 * (int64_t)i + q] = tot[q];
-#pragma unroll
-            for (int q = 0; q < 3; ++q) wpt[3 * (int64_t)i + q] = tot[R - 3 + q];
-        }
     }
 }
 
-template <typename T, bool G, bool A>
+template <typename T, bool G, bool A, bool S>
 static void build_points_variant(const PointMajor& pm, const double* pts, JacSource<T> js, T delta, T* hcp,
                                  double* hpp, double* wpt, T* wobs, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_build_points<T, G, A>), dim3((unsigned)pm.num_tiles), dim3(kTile), 0, s, pm.tile, pm.cam,
-                       pm.pt, pm.uvx, pm.uvy, pts, js, delta, pm.ld, hcp, hpp, wpt, wobs);
+    const int64_t waves = (int64_t)pm.num_short + pm.num_long;
+    hipLaunchKernelGGL((k_build_points<T, G, A, S>), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s,
+                       pm.num_short, pm.sseg, pm.num_long, pm.lseg, pm.cam, pm.pt, pm.uvx, pm.uvy, pts, js, delta,
+                       hcp, hpp, wpt, wobs);
 }
 
 template <typename T>
 hipError_t launch_build_points(const PointMajor& pm, double delta, bool grad_only, const double* pts,
                                JacSource<T> js, T* hcp, double* hpp, double* wpt, T* wobs, hipStream_t s)
 {
-    if (pm.num_tiles <= 0) return hipGetLastError();
+    if ((int64_t)pm.num_short + pm.num_long <= 0) return hipGetLastError();
     const bool ad = js.cams != nullptr;
     const T d = (T)delta;
     if (grad_only) {
-        if (ad) build_points_variant<T, true, true>(pm, pts, js, d, nullptr, nullptr, wpt, nullptr, s);
-        else build_points_variant<T, true, false>(pm, pts, js, d, nullptr, nullptr, wpt, nullptr, s);
+        if (ad) build_points_variant<T, true, true, false>(pm, pts, js, d, nullptr, nullptr, wpt, nullptr, s);
+        else build_points_variant<T, true, false, false>(pm, pts, js, d, nullptr, nullptr, wpt, nullptr, s);
+    } else if (hcp) {
+        if (ad) build_points_variant<T, false, true, true>(pm, pts, js, d, hcp, hpp, wpt, wobs, s);
+        else build_points_variant<T, false, false, true>(pm, pts, js, d, hcp, hpp, wpt, wobs, s);
     } else {
-        if (ad) build_points_variant<T, false, true>(pm, pts, js, d, hcp, hpp, wpt, wobs, s);
-        else build_points_variant<T, false, false>(pm, pts, js, d, hcp, hpp, wpt, wobs, s);
+        if (ad) build_points_variant<T, false, true, false>(pm, pts, js, d, nullptr, hpp, wpt, wobs, s);
+        else build_points_variant<T, false, false, false>(pm, pts, js, d, nullptr, hpp, wpt, wobs, s);
     }
     return hipGetLastError();
 }
 
 // ----------------------------------------------------- camera-major build
 
-// Wave sums of the W accumulated words into one slot.
+// Wave exchanges of the slot flush.  swap_add32(lo, hi): lanes 0-31 get
+// lo(l) + lo(l + 32), lanes 32-63 get hi(l - 32) + hi(l) (v_permlane32_swap
+// trades the upper half of its first operand for the lower half of its
+// second); swap_add16 does the same between rows 0|1 and 2|3 of 16 lanes
+// (v_permlane16_swap).  xor_step<M>: lanes with bit M clear get lo(l) +
+// lo(l ^ M), the others hi(l ^ M) + hi(l).
+__device__ __forceinline__ double pair_double(uint32_t lo, uint32_t hi)
+{
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ __forceinline__ double swap_add32(double lo, double hi)
+{
+    const uint64_t a = (uint64_t)__double_as_longlong(lo), b = (uint64_t)__double_as_longlong(hi);
+    const auto x = __builtin_amdgcn_permlane32_swap((uint32_t)a, (uint32_t)b, false, false);
+    const auto y = __builtin_amdgcn_permlane32_swap((uint32_t)(a >> 32), (uint32_t)(b >> 32), false, false);
+    return pair_double(x[0], y[0]) + pair_double(x[1], y[1]);
+}
+
+__device__ __forceinline__ double swap_add16(double lo, double hi)
+{
+    const uint64_t a = (uint64_t)__double_as_longlong(lo), b = (uint64_t)__double_as_longlong(hi);
+    const auto x = __builtin_amdgcn_permlane16_swap((uint32_t)a, (uint32_t)b, false, false);
+    const auto y = __builtin_amdgcn_permlane16_swap((uint32_t)(a >> 32), (uint32_t)(b >> 32), false, false);
+    return pair_double(x[0], y[0]) + pair_double(x[1], y[1]);
+}
+
+template <int M>
+__device__ __forceinline__ double xor_step(double lo, double hi, int lane)
+{
+    const bool up = (lane & M) != 0;
+    return (up ? hi : lo) + __shfl_xor(up ? lo : hi, M, 64);
+}
+
+// Sums each of the W accumulated words over the wavefront into word q of
+// the slot, then clears them.  Recursive halving: at each of the six
+// exchanges the lanes with the distance bit clear keep the lower half of the
+// words and the others the upper half, adding the partner's copy, so lane q
+// ends with word q (words from W on are zero).  63 pair exchanges replace
+// six shuffles per word, and the slot is written by one coalesced store.
 template <int W>
 __device__ __forceinline__ void flush_slot(double* acc, double* __restrict__ slots, int32_t slot, int lane)
 {
+    static_assert(W <= 64, "one word per lane");
+    double v32[32], v16[16], v8[8], v4[4], v2[2];
 #pragma unroll
-    for (int q = 0; q < W; ++q) {
-        const double v = wave_sum(acc[q]);
-        if (lane == 0) slots[(int64_t)slot * kCamSlotWords + q] = v;
-        acc[q] = 0.0;
+    for (int t = 0; t < 32; ++t) v32[t] = t < W ? swap_add32(acc[t], t + 32 < W ? acc[t + 32] : 0.0) : 0.0;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) v16[t] = t < W ? swap_add16(v32[t], v32[t + 16]) : 0.0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) v8[t] = t < W ? xor_step<8>(v16[t], v16[t + 8], lane) : 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) v4[t] = t < W ? xor_step<4>(v8[t], v8[t + 4], lane) : 0.0;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) v2[t] = xor_step<2>(v4[t], v4[t + 2], lane);
+    const double v = xor_step<1>(v2[0], v2[1], lane);
+    if (lane < W) slots[(int64_t)slot * kCamSlotWords + lane] = v;
+#pragma unroll
+    for (int q = 0; q < W; ++q) acc[q] = 0.0;
+}
+
+// One row (64 consecutive observations, one per lane) of a camera-major
+// chunk: the streamed words, then what they point at.  The chunk's rows are
+// software-pipelined: while row r is computed, the point and camera loads of
+// row r + 1 and the streamed words of row r + 2 are in flight, so one
+// wavefront per SIMD (the 54 FP64 accumulators leave no room for a second)
+// is not left waiting on a dependent gather every row.
+template <typename T>
+struct CmRow {
+    int32_t j, i;       // camera, point (lanes past the chunk's end: its first observation)
+    double u, v;        // pixel
+    double X[3];        // point (gathered)
+    T hd[kCamHead];     // camera constants R, t, f, k1, k2, small (gathered)
+    T Jl[9];            // camera left Jacobian (gathered)
+};
+
+template <typename T>
+__device__ __forceinline__ void cm_stream(int64_t start, int64_t end, int32_t row, int lane,
+                                          const int32_t* __restrict__ cam, const int32_t* __restrict__ pt,
+                                          const double* __restrict__ uvx, const double* __restrict__ uvy,
+                                          CmRow<T>& r)
+{
+    const int64_t k = start + (int64_t)row * 64 + lane;
+    const int64_t kk = k < end ? k : start;
+    r.j = cam[kk];
+    r.i = pt[kk];
+    r.u = uvx[kk];
+    r.v = uvy[kk];
+}
+
+template <typename T>
+__device__ __forceinline__ void cm_gather(const double* __restrict__ pts, const CamK<T>* __restrict__ ck, CmRow<T>& r)
+{
+    const double* X = pts + 3 * (int64_t)r.i;
+    r.X[0] = X[0];
+    r.X[1] = X[1];
+    r.X[2] = X[2];
+    const T* c = reinterpret_cast<const T*>(ck + r.j);
+#pragma unroll
+    for (int q = 0; q < kCamHead; ++q) r.hd[q] = c[q];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) r.Jl[q] = ck[r.j].Jl[q];
+}
+
+// Residual, Jacobian and IRLS weight of one gathered observation (the
+// analytic form from the constants, or forward-mode differentiation).
+template <typename T, bool AD>
+__device__ __forceinline__ void cm_observation(const CmRow<T>& r, const double* __restrict__ pts, JacSource<T> js,
+                                               T delta, T& e0, T& e1, T& wt, T Jc[18], T Jp[6])
+{
+    const T X0 = (T)r.X[0], X1 = (T)r.X[1], X2 = (T)r.X[2];
+    bool done = false;
+    if (AD) {
+        residual_jacobian_ad<T>(js.cams + 9 * (int64_t)r.j, X0, X1, X2, (T)r.u, (T)r.v, e0, e1, Jc, Jp);
+        // an unresolved FP32 depth: the analytic form from the FP64 geometry
+        done = sizeof(T) == 8 || depth_resolved<T>(r.hd[6] * X0 + r.hd[7] * X1 + r.hd[8] * X2, r.hd[11],
+                                                   r.hd[6] * X0 + r.hd[7] * X1 + r.hd[8] * X2 + r.hd[11]);
+    }
+    if (!done) {
+        ObsGeo<T> o;
+        if (!observation_geometry<T>(r.hd, X0, X1, X2, o) && js.ck64)
+            o = observation_geometry_f64<T>(js.ck64, r.j, pts + 3 * (int64_t)r.i);
+        jacobian_from_geometry<T>(r.hd, r.Jl, o, (T)r.u, (T)r.v, e0, e1, Jc, Jp);
+    }
+    wt = huber_weight<T>(e0 * e0 + e1 * e1, delta);
+}
+
+// Walks the rows of one camera-major chunk [start, end) through the
+// pipeline above and calls body(row, r) for each (uniform over the wave).
+template <typename T, class Body>
+__device__ __forceinline__ void cm_rows(int64_t start, int64_t end, int lane, const int32_t* __restrict__ cam,
+                                        const int32_t* __restrict__ pt, const double* __restrict__ uvx,
+                                        const double* __restrict__ uvy, const double* __restrict__ pts,
+                                        const CamK<T>* __restrict__ ck, Body&& body)
+{
+    const int32_t rows = (int32_t)((end - start + 63) >> 6);
+    CmRow<T> a, b;
+    cm_stream<T>(start, end, 0, lane, cam, pt, uvx, uvy, a);
+    cm_gather<T>(pts, ck, a);
+    if (rows > 1) cm_stream<T>(start, end, 1, lane, cam, pt, uvx, uvy, b);
+    for (int32_t row = 0; row < rows; ++row) {
+        const CmRow<T> c = a;
+        if (row + 1 < rows) {
+            a = b;
+            cm_gather<T>(pts, ck, a);
+        }
+        if (row + 2 < rows) cm_stream<T>(start, end, row + 2, lane, cam, pt, uvx, uvy, b);
+        body(row, c);
     }
 }
 
@@ -287,21 +427,16 @@ __global__ __launch_bounds__(256) void k_build_cameras(
     double acc[W];
 #pragma unroll
     for (int q = 0; q < W; ++q) acc[q] = 0.0;
-    for (int row = 0; row < kCmRows; ++row) {
+    cm_rows<T>(start, end, lane, cam, pt, uvx, uvy, pts, js.ck, [&](int32_t row, const CmRow<T>& r) {
         const int64_t k = start + (int64_t)row * 64 + lane;
-        if (start + (int64_t)row * 64 >= end) break;
         const bool valid = k < end;
-        T e0 = 0, e1 = 0, wt = 0, Jc[18], Jp[6];
-        int32_t j = 0x7fffffff;
-        if (valid) {
-            int32_t i;
-            j = cam[k];
-            observation<T, AD>(k, cam, pt, uvx, uvy, pts, js, delta, e0, e1, wt, Jc, Jp, i);
-            if (!GRAD_ONLY && k >= cold0) {
-                if (chcp) store_coupling<T>(k - cold0, Nc, Jc, Jp, wt, chcp);
-                if (cw) cw[k - cold0] = wt;
-            }
+        T e0, e1, wt, Jc[18], Jp[6];
+        cm_observation<T, AD>(r, pts, js, delta, e0, e1, wt, Jc, Jp);
+        if (!GRAD_ONLY && valid && k >= cold0) {
+            if (chcp) store_coupling<T>(k - cold0, Nc, Jc, Jp, wt, chcp);
+            if (cw) cw[k - cold0] = wt;
         }
+        const int32_t j = valid ? r.j : 0x7fffffff;
         while (true) {
             if (valid && j == cur) {
                 // FP64 products of the T-precision Jacobian (exact for
@@ -328,7 +463,7 @@ __global__ __launch_bounds__(256) void k_build_cameras(
             const int first = __ffsll((unsigned long long)more) - 1;
             cur = __shfl(j, first, 64);  // strictly larger: the loop ends
         }
-    }
+    });
     flush_slot<W>(acc, slots, slot, lane);
 }
 
@@ -436,7 +571,7 @@ __global__ __launch_bounds__(kRedBlock) void k_cost(int64_t N, const int32_t* __
     double acc = 0.0;
     for (int64_t k = blockIdx.x * (int64_t)kRedBlock + threadIdx.x; k < N; k += (int64_t)gridDim.x * kRedBlock) {
         const int32_t j = cam[k], i = pt[k];
-        const CamK<T> kk = ck[j];
+        const CamK<T>& kk = ck[j];  // only the words the residual reads
         T e0, e1;
         residual<T>(kk, (T)pts[3 * (int64_t)i], (T)pts[3 * (int64_t)i + 1], (T)pts[3 * (int64_t)i + 2], (T)uvx[k],
                     (T)uvy[k], e0, e1);
@@ -499,16 +634,12 @@ __global__ __launch_bounds__(256) void k_schur_jacobi_cameras(
     double acc[W];
 #pragma unroll
     for (int q = 0; q < W; ++q) acc[q] = 0.0;
-    for (int row = 0; row < kCmRows; ++row) {
+    cm_rows<T>(start, end, lane, cam, pt, uvx, uvy, pts, js.ck, [&](int32_t row, const CmRow<T>& r) {
         const int64_t k = start + (int64_t)row * 64 + lane;
-        if (start + (int64_t)row * 64 >= end) break;
         const bool valid = k < end;
-        T e0 = 0, e1 = 0, wt = 0, Jc[18], Jp[6];
-        int32_t j = 0x7fffffff, i = 0;
-        if (valid) {
-            j = cam[k];
-            observation<T, AD>(k, cam, pt, uvx, uvy, pts, js, delta, e0, e1, wt, Jc, Jp, i);
-        }
+        T e0, e1, wt, Jc[18], Jp[6];
+        cm_observation<T, AD>(r, pts, js, delta, e0, e1, wt, Jc, Jp);
+        const int32_t j = valid ? r.j : 0x7fffffff;
         while (true) {
             if (valid && j == cur) {
                 const double w = wt;
@@ -518,7 +649,7 @@ __global__ __launch_bounds__(256) void k_schur_jacobi_cameras(
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
                         E[a * 3 + c] = w * ((double)Jc[a] * (double)Jp[c] + (double)Jc[9 + a] * (double)Jp[3 + c]);
-                const T* c6 = cinv + 6 * (int64_t)i;
+                const T* c6 = cinv + 6 * (int64_t)r.i;
                 const double C[9] = {(double)c6[0], (double)c6[1], (double)c6[2], (double)c6[1], (double)c6[3],
                                      (double)c6[4], (double)c6[2], (double)c6[4], (double)c6[5]};
 #pragma unroll
@@ -540,7 +671,7 @@ __global__ __launch_bounds__(256) void k_schur_jacobi_cameras(
             const int first = __ffsll((unsigned long long)more) - 1;
             cur = __shfl(j, first, 64);
         }
-    }
+    });
     flush_slot<W>(acc, slots, slot, lane);
 }
 

@@ -196,10 +196,10 @@ __device__ __forceinline__ void observation_geometry_checked(const T* hd, const 
 }
 
 // Residual and Jacobians from the geometry: Jc row-major 2x9, Jp row-major
-// 2x3.
+// 2x3.  R: the camera's rotation (row-major), Jl: its left Jacobian.
 template <typename T>
-__device__ __forceinline__ void jacobian_from_geometry(const CamK<T>& k, const ObsGeo<T>& o, T u, T v, T& e0, T& e1,
-                                                       T Jc[18], T Jp[6])
+__device__ __forceinline__ void jacobian_from_geometry(const T* R, const T* Jl, const ObsGeo<T>& o, T u, T v, T& e0,
+                                                       T& e1, T Jc[18], T Jp[6])
 {
     e0 = o.fd * o.px - u;
     e1 = o.fd * o.py - v;
@@ -209,10 +209,10 @@ __device__ __forceinline__ void jacobian_from_geometry(const CamK<T>& k, const O
     const T y10 = o.a1 * D[5] - o.a2 * D[4], y11 = o.a2 * D[3] - o.a0 * D[5], y12 = o.a0 * D[4] - o.a1 * D[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        Jc[c] = y00 * k.Jl[c] + y01 * k.Jl[3 + c] + y02 * k.Jl[6 + c];
-        Jc[9 + c] = y10 * k.Jl[c] + y11 * k.Jl[3 + c] + y12 * k.Jl[6 + c];
-        Jp[c] = D[0] * k.R[c] + D[1] * k.R[3 + c] + D[2] * k.R[6 + c];
-        Jp[3 + c] = D[3] * k.R[c] + D[4] * k.R[3 + c] + D[5] * k.R[6 + c];
+        Jc[c] = y00 * Jl[c] + y01 * Jl[3 + c] + y02 * Jl[6 + c];
+        Jc[9 + c] = y10 * Jl[c] + y11 * Jl[3 + c] + y12 * Jl[6 + c];
+        Jp[c] = D[0] * R[c] + D[1] * R[3 + c] + D[2] * R[6 + c];
+        Jp[3 + c] = D[3] * R[c] + D[4] * R[3 + c] + D[5] * R[6 + c];
     }
     Jc[3] = D[0]; Jc[4] = D[1]; Jc[5] = D[2];
     Jc[12] = D[3]; Jc[13] = D[4]; Jc[14] = D[5];
@@ -222,6 +222,13 @@ __device__ __forceinline__ void jacobian_from_geometry(const CamK<T>& k, const O
     Jc[16] = o.fr2 * o.py;
     Jc[8] = o.fr4 * o.px;
     Jc[17] = o.fr4 * o.py;
+}
+
+template <typename T>
+__device__ __forceinline__ void jacobian_from_geometry(const CamK<T>& k, const ObsGeo<T>& o, T u, T v, T& e0, T& e1,
+                                                       T Jc[18], T Jp[6])
+{
+    jacobian_from_geometry<T>(k.R, k.Jl, o, u, v, e0, e1, Jc, Jp);
 }
 
 template <typename T>
