@@ -438,13 +438,25 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     }
     SchurPlan& sp = P->sp;
     {
-        int32_t kmax = P->is_f32() ? hot_max_cameras<float>((size_t)lds_limit)
-                                   : hot_max_cameras<double>((size_t)lds_limit);
+        const char* stored = std::getenv("BA_SCHUR_STORED");
+        sp.recompute = !(stored && std::atoi(stored) != 0);
+        // recomputing product: the LDS holds the records of cameras [0, Kc)
+        // and the hot table in the rest.  At 29M observations (Zipf) the
+        // point-major pass ran 0.370 / 0.351 / 0.342 ms (FP32) with 120 / 260 /
+        // 880 records, while the cold pass shrinks as the table grows; 256
+        // records and the rest for the table gave the shortest PCG iteration
+        // in both precisions.
+        const size_t rec = P->is_f32() ? kCamRecBytes<float>() : kCamRecBytes<double>();
+        const char* env_c = std::getenv("BA_CACHE_CAMERAS");
+        if (!sp.recompute) sp.Kc = 0;
+        else sp.Kc = std::max(0, std::min(m, env_c ? std::atoi(env_c) : kCacheCameras));
+        if (sp.Kc > 0 && (size_t)sp.Kc * rec + 1040 > (size_t)lds_limit)
+            sp.Kc = (int32_t)(((size_t)lds_limit - 1040) / rec);
+        int32_t kmax = P->is_f32() ? hot_max_cameras<float>((size_t)lds_limit, sp.Kc)
+                                   : hot_max_cameras<double>((size_t)lds_limit, sp.Kc);
         const char* env = std::getenv("BA_HOT_CAMERAS");
         if (env) kmax = std::min(kmax, std::max(0, std::atoi(env)));
         sp.K = std::max(0, std::min(m, kmax));
-        const char* stored = std::getenv("BA_SCHUR_STORED");
-        sp.recompute = !(stored && std::atoi(stored) != 0);
         if (sp.K > 0 && !env) {
             // Keep the hot set only when it costs fewer observation visits per
             // product than none: N + rewalk + cold < 2N.  With a hot set, a long
@@ -701,7 +713,8 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     if (e == hipSuccess) e = up(sp.cold.chunk_slot, cold_chunk_slot.data(), sizeof(int32_t) * cold_chunk_slot.size());
     if (e == hipSuccess) e = up(sp.cold.cam_slot, cold_cam_slot.data(), sizeof(int32_t) * cold_cam_slot.size());
     if (e == hipSuccess)
-        e = P->is_f32() ? prepare_schur_kernels<float>(sp.K) : prepare_schur_kernels<double>(sp.K);
+        e = P->is_f32() ? prepare_schur_kernels<float>(sp.K, sp.Kc, sp.recompute)
+                        : prepare_schur_kernels<double>(sp.K, sp.Kc, sp.recompute);
     if (e == hipSuccess) e = hipMemset(P->hpp, 0, 6 * (size_t)(n > 0 ? n : 1) * sizeof(double));
     if (e == hipSuccess) e = hipMemset(P->wpt, 0, 3 * (size_t)(n > 0 ? n : 1) * sizeof(double));
     if (e == hipSuccess) e = hipMemset(P->sc, 0, sizeof(PcgScalars));

@@ -100,6 +100,16 @@ struct CameraMajor {
     uint32_t* arrive;     // [m] arrival counters (zero between calls)
 };
 
+// Words of the camera record the recomputing product keeps in LDS for its
+// hot cameras: the head of CamK and the 12-word direction record.
+constexpr int kCamRec = kCamHead + 12;
+constexpr int kCacheCameras = 256;  // records kept (most observed cameras first)
+template <typename T>
+constexpr size_t kCamRecBytes()
+{
+    return kCamRec * sizeof(T);
+}
+
 // Threads per workgroup of the hot-camera Schur pass (one workgroup per CU).
 template <typename T>
 struct HotThreads;
@@ -143,6 +153,8 @@ struct ColdStream {
 // Schedule of the implicit Schur product (see matvec.hip).
 struct SchurPlan {
     int32_t K = 0;                  // hot cameras: internal ids [0, K)
+    int32_t Kc = 0;                 // recomputing product: cameras [0, Kc) whose records the
+                                    // point-major pass keeps in LDS
     int32_t num_wg = 0;             // persistent workgroups of the hot pass
     int32_t* wrange = nullptr;      // [num_wg * waves per workgroup + 1] ranges of 64-observation
                                     // tiles per wavefront
@@ -271,12 +283,15 @@ hipError_t launch_schur_product(int mode, const SchurPlan& sp, const PointMajor&
 template <typename T>
 hipError_t launch_backsub_free(const SchurPlan& sp, const PointMajor& pm, const RecomputeInputs<T>& ri, const T* cinv,
                                const double* wpt, double* dp, hipStream_t s);
+// LDS of the point-major pass for K hot cameras: their FP64 table, and with
+// the recomputing product the records of cameras [0, Kc).
 template <typename T>
-size_t hot_lds_bytes(int32_t K);
+size_t hot_lds_bytes(int32_t K, int32_t Kc);
+// The largest hot set whose table fits beside Kc camera records.
 template <typename T>
-int32_t hot_max_cameras(size_t lds_limit);
+int32_t hot_max_cameras(size_t lds_limit, int32_t Kc);
 template <typename T>
-hipError_t prepare_schur_kernels(int32_t K);
+hipError_t prepare_schur_kernels(int32_t K, int32_t Kc, bool recompute);
 
 hipError_t launch_zero(double* p, int64_t count, hipStream_t s);
 hipError_t launch_sum_partials(const double* partials, int32_t count, int32_t stride, int32_t ncols,

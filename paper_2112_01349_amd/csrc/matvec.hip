@@ -312,6 +312,68 @@ __device__ __forceinline__ void load_head(const CamK<T>* __restrict__ ck, int32_
     for (int q = 0; q < kCamHead; ++q) hd[q] = src[q];
 }
 
+// Element `e` of an array at a 32-bit byte offset from a wave-uniform base:
+// the load takes the base in scalar registers and one 32-bit vector offset,
+// with no 64-bit address arithmetic per lane.  Offsets stay below 4 GB: a
+// camera record times the camera count (checked when the problem is made),
+// or the records of the points inside one segment.
+template <typename E>
+__device__ __forceinline__ const E* at_bytes(const void* base, uint32_t off)
+{
+    return reinterpret_cast<const E*>(reinterpret_cast<const char*>(base) + off);
+}
+
+// The camera record the product reads per observation, kept in LDS for the
+// hot cameras: the first kCamHead words of CamK (R, t, f, k1, k2, small) and
+// the camera's direction record from launch_pcg_direction (12 words, 9 used).
+// Reading these from memory costs seven L1 line lookups per observation (one
+// per 16-byte load, each lane on its own camera), which bounds the pass
+// (the L1 serves about one line lookup per CU per cycle); an LDS copy takes
+// them off that path for the most observed cameras (85% of the observations
+// of the 29M-observation workload come from its 900 most observed cameras).
+
+template <typename T>
+using Vec16 = T __attribute__((ext_vector_type(16 / sizeof(T))));
+
+// N words from a 16-byte aligned address: 16 bytes per load, then the
+// remainder one word at a time (a load never writes registers it does not
+// fill, which would make it wait for older loads into them).
+template <typename T, int N>
+__device__ __forceinline__ void load_words16(const T* __restrict__ src, T* dst)
+{
+    constexpr int P = 16 / sizeof(T);
+    const Vec16<T>* s = reinterpret_cast<const Vec16<T>*>(src);
+#pragma unroll
+    for (int c = 0; c < N / P; ++c) {
+        const Vec16<T> v = s[c];
+#pragma unroll
+        for (int e = 0; e < P; ++e) dst[c * P + e] = v[e];
+    }
+#pragma unroll
+    for (int e = N / P * P; e < N; ++e) dst[e] = src[e];
+}
+
+// Camera j's head and (XV) direction words: from the workgroup's LDS copy
+// when j < Kc, else from memory.  The LDS reads are issued first: both
+// branches fill the same registers, so the memory loads of the other lanes
+// wait only for those short reads, never the reverse.
+template <typename T, bool XV>
+__device__ __forceinline__ void camera_inputs(int32_t j, int32_t Kc, const T* cache, const CamK<T>* __restrict__ ck,
+                                              const T* __restrict__ xf, T hd[kCamHead], T xv[9])
+{
+    if (j < Kc) {
+        const T* c = cache + kCamRec * j;
+        load_words16<T, kCamHead>(c, hd);
+        if (XV) load_words16<T, 9>(c + kCamHead, xv);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (j >= Kc) {
+        const uint32_t uj = (uint32_t)j;
+        load_words16<T, kCamHead>(at_bytes<T>(ck, uj * (uint32_t)sizeof(CamK<T>)), hd);
+        if (XV) load_words16<T, 9>(at_bytes<T>(xf, uj * (uint32_t)(12 * sizeof(T))), xv);
+    }
+}
+
 // E_k^T x for one observation (3 values in the point's frame).
 template <typename T>
 __device__ __forceinline__ void free_et_x(const ObsGeo<T>& o, const T hd[kCamHead], const T xv[9], T w, T& e0,
@@ -366,20 +428,18 @@ __device__ __forceinline__ void free_add_hot(double* __restrict__ cl, int32_t j,
 
 // Everything one observation needs: its camera's constants and vector, its
 // point and its weight.
-template <typename T>
+template <typename T, bool XV>
 __device__ __forceinline__ void free_observation(int64_t k, const int32_t* __restrict__ cam,
                                                  const int32_t* __restrict__ pt, const T* __restrict__ wobs,
                                                  const double* __restrict__ pts, const CamK<T>* __restrict__ ck,
                                                  const CamK<double>* __restrict__ ck64, const T* __restrict__ xf,
-                                                 int32_t& j, int32_t& i, T& w, T hd[kCamHead], T xv[9], ObsGeo<T>& o)
+                                                 int32_t Kc, const T* cache, int32_t& j, int32_t& i, T& w,
+                                                 T hd[kCamHead], T xv[9], ObsGeo<T>& o)
 {
     j = cam[k];
     i = pt[k];
     w = wobs[k];
-    load_head<T>(ck, j, hd);
-    const T* x = xf + 12 * (int64_t)j;
-#pragma unroll
-    for (int a = 0; a < 9; ++a) xv[a] = x[a];
+    camera_inputs<T, XV>(j, Kc, cache, ck, xf, hd, xv);
     observation_geometry_checked<T>(hd, ck64, j, pts + 3 * (int64_t)i, o);
 }
 
@@ -393,16 +453,6 @@ struct FreeRow {
     T w;
 };
 
-// Element `e` of an array at a 32-bit byte offset from a wave-uniform base:
-// the load takes the base in scalar registers and one 32-bit vector offset,
-// with no 64-bit address arithmetic per lane.  Offsets stay below 4 GB: a
-// camera record times the camera count (checked when the problem is made),
-// or the records of the points inside one segment.
-template <typename E>
-__device__ __forceinline__ const E* at_bytes(const void* base, uint32_t off)
-{
-    return reinterpret_cast<const E*>(reinterpret_cast<const char*>(base) + off);
-}
 
 template <typename T>
 struct FreeData {
@@ -432,18 +482,12 @@ __device__ __forceinline__ void free_stream(const int2* __restrict__ sseg, int32
 template <typename T, int MODE>
 __device__ __forceinline__ void free_gather(const FreeRow<T>& r, const double* __restrict__ pts,
                                             const CamK<T>* __restrict__ ck, const T* __restrict__ xf,
-                                            const T* __restrict__ cinv, const uint8_t* __restrict__ has_cold,
-                                            const double* __restrict__ wpt, FreeData<T>& d)
+                                            int32_t Kc, const T* cache, const T* __restrict__ cinv,
+                                            const uint8_t* __restrict__ has_cold, const double* __restrict__ wpt,
+                                            FreeData<T>& d)
 {
-    const uint32_t uj = (uint32_t)r.j, di = (uint32_t)(r.i - r.i0);
-    const T* h = at_bytes<T>(ck, uj * (uint32_t)sizeof(CamK<T>));
-#pragma unroll
-    for (int q = 0; q < kCamHead; ++q) d.hd[q] = h[q];
-    if (MODE != 1) {
-        const T* x = at_bytes<T>(xf, uj * (uint32_t)(12 * sizeof(T)));
-#pragma unroll
-        for (int a = 0; a < 9; ++a) d.xv[a] = x[a];
-    }
+    const uint32_t di = (uint32_t)(r.i - r.i0);
+    camera_inputs<T, MODE != 1>(r.j, Kc, cache, ck, xf, d.hd, d.xv);
     const int64_t i0 = r.i0;
     const double* X = at_bytes<double>(pts + 3 * i0, di * 24u);
 #pragma unroll
@@ -533,15 +577,20 @@ __device__ __forceinline__ void free_short(const FreeRow<T>& r, const FreeData<T
 // each wavefront has a range of each kind.  Hot cameras accumulate in the
 // workgroup's LDS table as in k_schur_hot; b_i of points with cold
 // observations is stored for the cold pass, which reads its own stored
-// blocks.  Mode 2 has no camera side (K = 0).
-// Threads per workgroup of k_schur_free: the product and the right-hand side
-// run one workgroup per CU around the LDS table; the back-substitution has no
-// table, so it runs in workgroups of 256 (the same waves, four per group),
-// which lets the compiler keep it in registers without spilling.
+// blocks.  Mode 2 has no camera side (K = 0).  Every mode keeps an LDS copy
+// of the camera records of cameras [0, Kc) (kCamRec words each, after the
+// hot table), so all three run one workgroup per CU.
 template <typename T, int MODE>
 struct FreeThreads {
-    static constexpr int value = MODE == 2 ? 256 : FreeWgThreads<T>::value;
+    static constexpr int value = FreeWgThreads<T>::value;
 };
+
+// Bytes of the hot table (K cameras, FP64), rounded to 16 for the records
+// after it.
+__host__ __device__ __forceinline__ size_t free_table_bytes(int32_t K)
+{
+    return ((size_t)K * 9 * sizeof(double) + 15) & ~(size_t)15;
+}
 
 template <typename T, int MODE>
 __global__ __launch_bounds__((FreeThreads<T, MODE>::value)) void k_schur_free(
@@ -549,7 +598,7 @@ __global__ __launch_bounds__((FreeThreads<T, MODE>::value)) void k_schur_free(
     const int2* __restrict__ lseg, const int32_t* __restrict__ cam, const int32_t* __restrict__ pt,
     const T* __restrict__ wobs, const double* __restrict__ pts, const CamK<T>* __restrict__ ck,
     const CamK<double>* __restrict__ ck64, const T* __restrict__ xf, const T* __restrict__ cinv,
-    const double* __restrict__ wpt, int32_t K, double* __restrict__ hot_part, T* __restrict__ bcold,
+    const double* __restrict__ wpt, int32_t K, int32_t Kc, double* __restrict__ hot_part, T* __restrict__ bcold,
     const uint8_t* __restrict__ has_cold, double* __restrict__ dp, const PcgScalars* __restrict__ sc)
 {
     constexpr int NT = FreeThreads<T, MODE>::value;
@@ -557,6 +606,18 @@ __global__ __launch_bounds__((FreeThreads<T, MODE>::value)) void k_schur_free(
     extern __shared__ __align__(16) unsigned char smem[];
     double* cl = reinterpret_cast<double*>(smem);
     for (int q = threadIdx.x; q < K * 9; q += NT) cl[q] = 0.0;
+    // the hot cameras' records, 16 bytes per thread and step (the right-hand
+    // side reads no direction words)
+    T* cache = reinterpret_cast<T*>(smem + free_table_bytes(K));
+    {
+        constexpr int RC = kCamRec * (int)sizeof(T) / 16, HC = kCamHead * (int)sizeof(T) / 16;
+        uint4* dst = reinterpret_cast<uint4*>(cache);
+        for (int q = threadIdx.x; q < Kc * RC; q += NT) {
+            const int32_t j = q / RC, c = q - j * RC;
+            if (c < HC) dst[q] = reinterpret_cast<const uint4*>(ck + j)[c];
+            else if (MODE != 1) dst[q] = reinterpret_cast<const uint4*>(xf + 12 * (int64_t)j)[c - HC];
+        }
+    }
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int32_t gw = __builtin_amdgcn_readfirstlane(blockIdx.x * (NT / 64) + (threadIdx.x >> 6));
@@ -565,7 +626,9 @@ __global__ __launch_bounds__((FreeThreads<T, MODE>::value)) void k_schur_free(
         // Batches of NB short segments: the loads of all of them are issued
         // before any is computed (one index prefetch a batch ahead was 1.6%
         // faster in FP32 and 5% slower in FP64 at 29M observations).
-        constexpr int NB = 2;  // three spill in FP32 and gain nothing in FP64
+        // (the back-substitution takes one at a time in FP32, to stay within
+        // the registers of sixteen wavefronts per CU)
+        constexpr int NB = MODE == 2 && sizeof(T) == 4 ? 1 : 2;  // three spill in FP32 and gain nothing in FP64
         const int32_t S0 = frange[gw], S1 = frange[gw + 1];
         const int32_t nbat = (S1 - S0) / NB;
         for (int32_t bt = 0; bt < nbat; ++bt) {
@@ -575,7 +638,7 @@ __global__ __launch_bounds__((FreeThreads<T, MODE>::value)) void k_schur_free(
             for (int u = 0; u < NB; ++u) free_stream<T>(sseg, S0 + NB * bt + u, lane, cam, pt, wobs, r[u]);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int u = 0; u < NB; ++u) free_gather<T, MODE>(r[u], pts, ck, xf, cinv, has_cold, wpt, d[u]);
+            for (int u = 0; u < NB; ++u) free_gather<T, MODE>(r[u], pts, ck, xf, Kc, cache, cinv, has_cold, wpt, d[u]);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int u = 0; u < NB; ++u) free_short<T, MODE>(r[u], d[u], lane, upto, K, cl, bcold, dp, pts, ck64);
@@ -584,7 +647,7 @@ __global__ __launch_bounds__((FreeThreads<T, MODE>::value)) void k_schur_free(
             FreeRow<T> r;
             FreeData<T> d;
             free_stream<T>(sseg, q, lane, cam, pt, wobs, r);
-            free_gather<T, MODE>(r, pts, ck, xf, cinv, has_cold, wpt, d);
+            free_gather<T, MODE>(r, pts, ck, xf, Kc, cache, cinv, has_cold, wpt, d);
             free_short<T, MODE>(r, d, lane, upto, K, cl, bcold, dp, pts, ck64);
         }
     }
@@ -601,7 +664,7 @@ __global__ __launch_bounds__((FreeThreads<T, MODE>::value)) void k_schur_free(
                 int32_t j, ii;
                 T w, hd[kCamHead], xv[9];
                 ObsGeo<T> o;
-                free_observation<T>(k, cam, pt, wobs, pts, ck, ck64, xf, j, ii, w, hd, xv, o);
+                free_observation<T, MODE != 1>(k, cam, pt, wobs, pts, ck, ck64, xf, Kc, cache, j, ii, w, hd, xv, o);
                 T e0, e1, e2;
                 free_et_x<T>(o, hd, xv, w, e0, e1, e2);
                 if (!valid) e0 = e1 = e2 = (T)0;
@@ -639,7 +702,7 @@ __global__ __launch_bounds__((FreeThreads<T, MODE>::value)) void k_schur_free(
                 int32_t j, ii;
                 T w, hd[kCamHead], xv[9];
                 ObsGeo<T> o;
-                free_observation<T>(k, cam, pt, wobs, pts, ck, ck64, xf, j, ii, w, hd, xv, o);
+                free_observation<T, MODE != 1>(k, cam, pt, wobs, pts, ck, ck64, xf, Kc, cache, j, ii, w, hd, xv, o);
                 if (valid && j < K) free_add_hot<T>(cl, j, o, hd, w, b0, b1, b2);
             }
     }
@@ -955,27 +1018,32 @@ __global__ __launch_bounds__(kRedBlock) void k_schur_epilogue(
 }
 
 template <typename T>
-size_t hot_lds_bytes(int32_t K)
+size_t hot_lds_bytes(int32_t K, int32_t Kc)
 {
-    return (size_t)K * 9 * sizeof(double);
+    return free_table_bytes(K) + (size_t)Kc * kCamRec * sizeof(T);
 }
 
 template <typename T>
-int32_t hot_max_cameras(size_t lds_limit)
+int32_t hot_max_cameras(size_t lds_limit, int32_t Kc)
 {
-    if (lds_limit <= 1024) return 0;
-    return (int32_t)((lds_limit - 1024) / (9 * sizeof(double)));
+    const size_t rec = (size_t)Kc * kCamRec * sizeof(T) + 1024 + 16;
+    if (lds_limit <= rec) return 0;
+    return (int32_t)((lds_limit - rec) / (9 * sizeof(double)));
 }
 
 template <typename T>
-hipError_t prepare_schur_kernels(int32_t K)
+hipError_t prepare_schur_kernels(int32_t K, int32_t Kc, bool recompute)
 {
-    const int bytes = (int)hot_lds_bytes<T>(K);
-    hipError_t e = hipFuncSetAttribute((const void*)k_schur_hot<T>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)k_schur_free<T, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)k_schur_free<T, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    const int bytes = (int)hot_lds_bytes<T>(K, recompute ? Kc : 0);
+    hipError_t e;
+    if (recompute) {
+        e = hipFuncSetAttribute((const void*)k_schur_free<T, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e != hipSuccess) return e;
+        e = hipFuncSetAttribute((const void*)k_schur_free<T, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e != hipSuccess) return e;
+        return hipFuncSetAttribute((const void*)k_schur_free<T, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    }
+    e = hipFuncSetAttribute((const void*)k_schur_hot<T>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void*)k_schur_rhs<T>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
@@ -1015,17 +1083,17 @@ hipError_t launch_schur_product(int mode, const SchurPlan& sp, const PointMajor&
                                 hipEvent_t hot_end, hipStream_t s)
 {
     hipError_t e;
-    const size_t lds = hot_lds_bytes<T>(sp.K);
+    const size_t lds = hot_lds_bytes<T>(sp.K, sp.recompute && ri ? sp.Kc : 0);
     if (hot_begin && (e = hipEventRecord(hot_begin, s)) != hipSuccess) return e;
     if (sp.num_wg > 0) {
         const dim3 g(sp.num_wg), b(sp.recompute && ri ? FreeWgThreads<T>::value : HotThreads<T>::value);
         if (mode == 0 && sp.recompute && ri)
             hipLaunchKernelGGL((k_schur_free<T, 0>), g, b, lds, s, sp.frange, sp.sseg, sp.lrange, sp.lseg, pm.cam,
-                               pm.pt, ri->wobs, ri->pts, ri->ck, ri->ck64, ri->xf, cinv, nullptr, sp.K, (double*)sp.hot_part,
+                               pm.pt, ri->wobs, ri->pts, ri->ck, ri->ck64, ri->xf, cinv, nullptr, sp.K, sp.Kc, (double*)sp.hot_part,
                                (T*)sp.bcold, sp.has_cold, nullptr, sc);
         else if (mode == 1 && sp.recompute && ri)
             hipLaunchKernelGGL((k_schur_free<T, 1>), g, b, lds, s, sp.frange, sp.sseg, sp.lrange, sp.lseg, pm.cam,
-                               pm.pt, ri->wobs, ri->pts, ri->ck, ri->ck64, nullptr, cinv, wpt, sp.K, (double*)sp.hot_part,
+                               pm.pt, ri->wobs, ri->pts, ri->ck, ri->ck64, nullptr, cinv, wpt, sp.K, sp.Kc, (double*)sp.hot_part,
                                (T*)sp.bcold, sp.has_cold, nullptr, nullptr);
         else if (mode == 0)
             hipLaunchKernelGGL((k_schur_hot<T>), g, b, lds, s, sp.wrange, N, pm.cam, pm.pt, hcp, cinv, xcam,
@@ -1075,21 +1143,23 @@ hipError_t launch_schur_product(int mode, const SchurPlan& sp, const PointMajor&
     return hipGetLastError();
 }
 
-template size_t hot_lds_bytes<float>(int32_t);
-template size_t hot_lds_bytes<double>(int32_t);
-template int32_t hot_max_cameras<float>(size_t);
-template int32_t hot_max_cameras<double>(size_t);
-template hipError_t prepare_schur_kernels<float>(int32_t);
-template hipError_t prepare_schur_kernels<double>(int32_t);
+template size_t hot_lds_bytes<float>(int32_t, int32_t);
+template size_t hot_lds_bytes<double>(int32_t, int32_t);
+template int32_t hot_max_cameras<float>(size_t, int32_t);
+template int32_t hot_max_cameras<double>(size_t, int32_t);
+template hipError_t prepare_schur_kernels<float>(int32_t, int32_t, bool);
+template hipError_t prepare_schur_kernels<double>(int32_t, int32_t, bool);
 template <typename T>
 hipError_t launch_backsub_free(const SchurPlan& sp, const PointMajor& pm, const RecomputeInputs<T>& ri, const T* cinv,
                                const double* wpt, double* dp, hipStream_t s)
 {
     if (sp.num_wg <= 0) return hipGetLastError();
     constexpr int NT = FreeThreads<T, 2>::value;  // the same waves as the product, NT / 64 per workgroup
-    hipLaunchKernelGGL((k_schur_free<T, 2>), dim3(sp.num_wg * (FreeWgThreads<T>::value / NT)), dim3(NT), 0, s, sp.frange, sp.sseg,
-                       sp.lrange, sp.lseg, pm.cam, pm.pt, ri.wobs, ri.pts, ri.ck, ri.ck64, ri.xf, cinv, wpt, 0, nullptr,
-                       nullptr, sp.has_cold, dp, nullptr);
+    // no hot table (K = 0), the same camera records
+    const size_t lds = hot_lds_bytes<T>(0, sp.Kc);
+    hipLaunchKernelGGL((k_schur_free<T, 2>), dim3(sp.num_wg * (FreeWgThreads<T>::value / NT)), dim3(NT), lds, s,
+                       sp.frange, sp.sseg, sp.lrange, sp.lseg, pm.cam, pm.pt, ri.wobs, ri.pts, ri.ck, ri.ck64, ri.xf,
+                       cinv, wpt, 0, sp.Kc, nullptr, nullptr, sp.has_cold, dp, nullptr);
     return hipGetLastError();
 }
 

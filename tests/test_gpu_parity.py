@@ -200,14 +200,17 @@ def test_lm_monotone_and_state_consistent(tiny):
 
 
 @pytest.mark.parametrize("stored", [0, 1])
-@pytest.mark.parametrize("hot", [0, 3, 7])
-def test_hot_cold_split_matches_oracle(hot, stored, monkeypatch):
+@pytest.mark.parametrize("hot,cached", [(0, 0), (3, 5), (7, 2), (0, 15), (7, 15)])
+def test_hot_cold_split_matches_oracle(hot, cached, stored, monkeypatch):
     """The Schur product splits cameras into an LDS-held hot set and a
-    camera-major cold stream; every split gives the oracle's product and LM
-    trace (with a point longer than one tile in the problem), both for the
-    product that recomputes E from the Jacobian and for the one that reads
-    the stored blocks."""
+    camera-major cold stream, and the recomputing product reads the camera
+    records of its first `cached` cameras from an LDS copy and the others
+    from memory; every split gives the oracle's product and LM trace (with a
+    point longer than one tile in the problem), both for the product that
+    recomputes E from the Jacobian and for the one that reads the stored
+    blocks (which keeps no camera records)."""
     monkeypatch.setenv("BA_HOT_CAMERAS", str(hot))
+    monkeypatch.setenv("BA_CACHE_CAMERAS", str(cached))
     monkeypatch.setenv("BA_SCHUR_STORED", str(stored))
     arrays = with_edge_cases(small_zipf(seed=13, m=14, n=300, N=1500))
     cams, pts, oc, op, uv, _ = arrays
@@ -221,7 +224,7 @@ def test_hot_cold_split_matches_oracle(hot, stored, monkeypatch):
         ref = orc.schur_matvec(oc, op, Bd, A["E"], Ci, x)
         tol = 1e-10 if precision == FP64 else FP32_PRODUCT_TOL
         err = rel_err_rows(prob.schur_matvec(x, lam), ref)
-        print(f"hot {hot} stored {stored} precision {precision}: product error {err:.2e} of each row")
+        print(f"hot {hot} cached {cached} stored {stored} precision {precision}: product error {err:.2e} of each row")
         assert err <= tol, precision
         prob.close()
     tr, gpu, prob, _ = lm_pair(arrays, delta=1.0, iters=5, max_pcg=40, rtol=1e-8)
