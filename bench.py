@@ -181,6 +181,13 @@ def oracle_errors(rep, params, golden, steps):
         out["cameras_rel_err"] = float(np.linalg.norm(cams - gp["cameras"]) / np.linalg.norm(gp["cameras"]))
         out["points_rel_err"] = float(np.linalg.norm(pts[sel] - gp["points"]) / np.linalg.norm(gp["points"]))
         out["points_sampled"] = int(len(sel))
+        # per point and per camera: a few weakly constrained points (depth
+        # along a narrow baseline) can dominate the 2-norm above
+        for name, a, b in (("cameras", cams, gp["cameras"]), ("points", pts[sel], gp["points"])):
+            e = np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-300)
+            out[f"{name}_rel_err_median"] = float(np.median(e))
+            out[f"{name}_rel_err_p99"] = float(np.quantile(e, 0.99))
+            out[f"{name}_rel_err_max"] = float(e.max())
     return out
 
 

@@ -609,6 +609,7 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     P->pm.lseg = sp.lseg;
     P->pm.num_short = sp.num_short;
     P->pm.num_long = sp.num_long;
+    P->pm.num_cameras = m;
     sp.frange = A.get<int32_t>((int64_t)frange.size());
     sp.lrange = A.get<int32_t>((int64_t)lrange.size());
     P->wobs = A.get<char>(P->pm.ld * (int64_t)tsz);
@@ -715,6 +716,7 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     if (e == hipSuccess)
         e = P->is_f32() ? prepare_schur_kernels<float>(sp.K, sp.Kc, sp.recompute)
                         : prepare_schur_kernels<double>(sp.K, sp.Kc, sp.recompute);
+    if (e == hipSuccess) e = prepare_cost_kernels();
     if (e == hipSuccess) e = hipMemset(P->hpp, 0, 6 * (size_t)(n > 0 ? n : 1) * sizeof(double));
     if (e == hipSuccess) e = hipMemset(P->wpt, 0, 3 * (size_t)(n > 0 ? n : 1) * sizeof(double));
     if (e == hipSuccess) e = hipMemset(P->sc, 0, sizeof(PcgScalars));

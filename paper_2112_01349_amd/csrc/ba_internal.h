@@ -78,7 +78,15 @@ struct PointMajor {
     const int2* sseg;
     const int2* lseg;
     int32_t num_short, num_long;
+    int32_t num_cameras;
 };
+
+// Workgroups of the persistent streaming kernels (the cost pass):
+// one per CU of the MI355X.
+constexpr int kPersistentBlocks = 256;
+// Sets the dynamic LDS limits of the cost kernels (once per process
+// is enough; called when a problem is made).
+hipError_t prepare_cost_kernels();
 
 // Camera-major observation stream (sorted by camera, then point).
 struct CameraMajor {

@@ -23,6 +23,7 @@
 //     at the damping of the current LM iteration.
 #include "ba_internal.h"
 #include "autodiff.h"
+#include "camera_cache.h"
 #include "wave_ops.h"
 
 namespace ba {
@@ -560,20 +561,31 @@ hipError_t launch_build_cameras(const CameraMajor& cm, int32_t m, int64_t N, con
 }
 
 // -------------------------------------------------------------- FP64 cost
+// Persistent workgroups of kCostThreads over the point-major stream; the
+// camera heads of the most observed cameras are read from an LDS copy.
+constexpr int kCostThreads = 1024;
+constexpr int kCostCacheCameras = 1024;
+
 template <typename T>
-__global__ __launch_bounds__(kRedBlock) void k_cost(int64_t N, const int32_t* __restrict__ cam,
-                                                    const int32_t* __restrict__ pt, const double* __restrict__ uvx,
-                                                    const double* __restrict__ uvy, const double* __restrict__ pts,
-                                                    const CamK<T>* __restrict__ ck, T delta,
-                                                    double* __restrict__ partials)
+__global__ __launch_bounds__(kCostThreads) void k_cost(int64_t N, const int32_t* __restrict__ cam,
+                                                       const int32_t* __restrict__ pt, const double* __restrict__ uvx,
+                                                       const double* __restrict__ uvy, const double* __restrict__ pts,
+                                                       const CamK<T>* __restrict__ ck, T delta, int32_t Kc,
+                                                       double* __restrict__ partials)
 {
-    __shared__ double sh[kRedBlock / 64];
+    constexpr int S = sizeof(CamK<T>) / sizeof(T);
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* cache = reinterpret_cast<T*>(smem);
+    __shared__ double sh[kCostThreads / 64];
+    fill_camera_cache<T, kCamHead, S, kCostThreads>(reinterpret_cast<const T*>(ck), Kc, cache);
+    __syncthreads();
     double acc = 0.0;
-    for (int64_t k = blockIdx.x * (int64_t)kRedBlock + threadIdx.x; k < N; k += (int64_t)gridDim.x * kRedBlock) {
+    for (int64_t k = blockIdx.x * (int64_t)kCostThreads + threadIdx.x; k < N;
+         k += (int64_t)gridDim.x * kCostThreads) {
         const int32_t j = cam[k], i = pt[k];
-        const CamK<T>& kk = ck[j];  // only the words the residual reads
-        T e0, e1;
-        residual<T>(kk, (T)pts[3 * (int64_t)i], (T)pts[3 * (int64_t)i + 1], (T)pts[3 * (int64_t)i + 2], (T)uvx[k],
+        T hd[kCamHead], e0, e1;
+        camera_words<T, kCamHead, kCamHead, S>(j, Kc, cache, reinterpret_cast<const T*>(ck), hd);
+        residual<T>(hd, (T)pts[3 * (int64_t)i], (T)pts[3 * (int64_t)i + 1], (T)pts[3 * (int64_t)i + 2], (T)uvx[k],
                     (T)uvy[k], e0, e1);
         acc += 0.5 * (double)huber_rho<T>(e0 * e0 + e1 * e1, delta);
     }
@@ -582,7 +594,7 @@ __global__ __launch_bounds__(kRedBlock) void k_cost(int64_t N, const int32_t* __
     __syncthreads();
     if (threadIdx.x == 0) {
         double t = 0.0;
-        for (int w = 0; w < kRedBlock / 64; ++w) t += sh[w];
+        for (int w = 0; w < kCostThreads / 64; ++w) t += sh[w];
         partials[blockIdx.x] = t;
     }
 }
@@ -599,11 +611,24 @@ template <typename T>
 hipError_t launch_cost_t(const PointMajor& pm, int64_t N, const double* pts, const CamK<T>* ck, double delta,
                          double* partials, int32_t* nblocks, hipStream_t s)
 {
-    const int32_t b = reduce_blocks(N);
-    *nblocks = b;
-    hipLaunchKernelGGL((k_cost<T>), dim3(b), dim3(kRedBlock), 0, s, N, pm.cam, pm.pt, pm.uvx, pm.uvy, pts, ck,
-                       (T)delta, partials);
+    int64_t b = (N + kCostThreads - 1) / kCostThreads;
+    if (b > kPersistentBlocks) b = kPersistentBlocks;
+    if (b < 1) b = 1;
+    *nblocks = (int32_t)b;
+    const int32_t Kc = pm.num_cameras < kCostCacheCameras ? pm.num_cameras : kCostCacheCameras;
+    hipLaunchKernelGGL((k_cost<T>), dim3((unsigned)b), dim3(kCostThreads), (size_t)Kc * kCamHead * sizeof(T), s, N,
+                       pm.cam, pm.pt, pm.uvx, pm.uvy, pts, ck, (T)delta, Kc, partials);
     return hipGetLastError();
+}
+
+// Dynamic LDS beyond the default limit for the cost kernels above.
+hipError_t prepare_cost_kernels()
+{
+    hipError_t e = hipFuncSetAttribute((const void*)k_cost<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(kCostCacheCameras * kCamHead * sizeof(double)));
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)k_cost<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(kCostCacheCameras * kCamHead * sizeof(float)));
 }
 
 hipError_t launch_cost(const PointMajor& pm, int64_t N, const double* pts, const CamK<double>* ck, double delta,

@@ -80,18 +80,24 @@ __host__ __device__ inline void camera_constants(const double* c, CamK<T>& k)
     for (int q = 0; q < 7; ++q) k.pad[q] = (T)0;
 }
 
-// Residual only.
+// Residual only, from the first 15 words of CamK (R, t, f, k1, k2).
+template <typename T>
+__device__ __forceinline__ void residual(const T* hd, T X0, T X1, T X2, T u, T v, T& e0, T& e1)
+{
+    const T P0 = hd[0] * X0 + hd[1] * X1 + hd[2] * X2 + hd[9];
+    const T P1 = hd[3] * X0 + hd[4] * X1 + hd[5] * X2 + hd[10];
+    const T P2 = hd[6] * X0 + hd[7] * X1 + hd[8] * X2 + hd[11];
+    const T px = -(P0 / P2), py = -(P1 / P2);
+    const T r2 = px * px + py * py;
+    const T fd = hd[12] * ((T)1 + hd[13] * r2 + hd[14] * (r2 * r2));
+    e0 = fd * px - u;
+    e1 = fd * py - v;
+}
+
 template <typename T>
 __device__ __forceinline__ void residual(const CamK<T>& k, T X0, T X1, T X2, T u, T v, T& e0, T& e1)
 {
-    const T P0 = k.R[0] * X0 + k.R[1] * X1 + k.R[2] * X2 + k.t[0];
-    const T P1 = k.R[3] * X0 + k.R[4] * X1 + k.R[5] * X2 + k.t[1];
-    const T P2 = k.R[6] * X0 + k.R[7] * X1 + k.R[8] * X2 + k.t[2];
-    const T px = -(P0 / P2), py = -(P1 / P2);
-    const T r2 = px * px + py * py;
-    const T fd = k.f * ((T)1 + k.k1 * r2 + k.k2 * (r2 * r2));
-    e0 = fd * px - u;
-    e1 = fd * py - v;
+    residual<T>(k.R, X0, X1, X2, u, v, e0, e1);
 }
 
 // What the Jacobian of one observation is built from: de/dP (2x3), the

@@ -27,6 +27,7 @@
 //     the workgroup partials (hot) or the slots (cold) in a fixed order and
 //     forms q or g.
 #include "ba_internal.h"
+#include "camera_cache.h"
 #include "wave_ops.h"
 
 namespace ba {
@@ -324,34 +325,9 @@ __device__ __forceinline__ const E* at_bytes(const void* base, uint32_t off)
 }
 
 // The camera record the product reads per observation, kept in LDS for the
-// hot cameras: the first kCamHead words of CamK (R, t, f, k1, k2, small) and
-// the camera's direction record from launch_pcg_direction (12 words, 9 used).
-// Reading these from memory costs seven L1 line lookups per observation (one
-// per 16-byte load, each lane on its own camera), which bounds the pass
-// (the L1 serves about one line lookup per CU per cycle); an LDS copy takes
-// them off that path for the most observed cameras (85% of the observations
-// of the 29M-observation workload come from its 900 most observed cameras).
-
-template <typename T>
-using Vec16 = T __attribute__((ext_vector_type(16 / sizeof(T))));
-
-// N words from a 16-byte aligned address: 16 bytes per load, then the
-// remainder one word at a time (a load never writes registers it does not
-// fill, which would make it wait for older loads into them).
-template <typename T, int N>
-__device__ __forceinline__ void load_words16(const T* __restrict__ src, T* dst)
-{
-    constexpr int P = 16 / sizeof(T);
-    const Vec16<T>* s = reinterpret_cast<const Vec16<T>*>(src);
-#pragma unroll
-    for (int c = 0; c < N / P; ++c) {
-        const Vec16<T> v = s[c];
-#pragma unroll
-        for (int e = 0; e < P; ++e) dst[c * P + e] = v[e];
-    }
-#pragma unroll
-    for (int e = N / P * P; e < N; ++e) dst[e] = src[e];
-}
+// hot cameras (camera_cache.h): the first kCamHead words of CamK (R, t, f,
+// k1, k2, small) and the camera's direction record from
+// launch_pcg_direction (12 words, 9 used).
 
 // Camera j's head and (XV) direction words: from the workgroup's LDS copy
 // when j < Kc, else from memory.  The LDS reads are issued first: both

@@ -87,6 +87,9 @@ def test_oracle_errors_and_roofline_fractions():
     e = bench.oracle_errors(dict(final_cost=2.002), (cams, pts), golden, 3)
     assert e["final_cost_rel_err"] == pytest.approx(1e-3)
     assert e["cameras_rel_err"] == pytest.approx(1.0) and e["points_rel_err"] == 0.0
+    # per camera: camera 0 is off by 6/3 = 2 of its own norm, the others exact
+    assert e["cameras_rel_err_max"] == pytest.approx(2.0) and e["cameras_rel_err_median"] == 0.0
+    assert e["points_rel_err_max"] == 0.0
     assert bench.oracle_errors(dict(final_cost=4.0), None, golden, 2)["final_cost_rel_err"] == 0.0
     assert bench.oracle_errors(dict(final_cost=4.0), None, golden, 4) is None
     m, n, N = 13_700, 4_500_000, 29_000_000
