@@ -139,7 +139,9 @@ __device__ __forceinline__ bool observation_geometry(const T* hd, T X0, T X1, T 
     T P0 = RX0 + hd[9], P1 = RX1 + hd[10];
     const T P2 = RX2 + hd[11];
     const T f = hd[12], k1 = hd[13], k2 = hd[14];
-    T iz = (T)1 / P2;
+    // FP32: the hardware reciprocal (1 ulp) in place of a correctly rounded
+    // division, well inside the form's own rounding
+    T iz = sizeof(T) == 4 ? (T)__builtin_amdgcn_rcpf((float)P2) : (T)1 / P2;
     const bool resolved = depth_resolved<T>(RX2, hd[11], P2);
     if (!resolved) P0 = P1 = iz = (T)0;  // all derivatives vanish
     const T px = -(P0 * iz), py = -(P1 * iz);

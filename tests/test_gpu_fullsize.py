@@ -221,7 +221,7 @@ def test_stress_cost_gradient_and_schur_rows():
     errs = [np.max(np.abs(q[j] - ref[t])) / np.max(np.abs(ref[t])) for t, j in enumerate(rows)]
     print("60M FP32-mixed row errors " + " ".join(f"{e:.1e}" for e in errs))
     for t, j in enumerate(rows):
-        assert errs[t] <= 2e-3, j
+        assert errs[t] <= 5e-5, j  # float rounding: 2e-7 .. 2.4e-6 measured
     rep = gpu.lm_solve(max_lm_iters=2, max_pcg_iters=200, pcg_rtol=1e-6)
     gpu.close()
     assert rep["status"] == 0
@@ -259,7 +259,7 @@ def test_synthesised_20000_cost_gradient_and_schur_rows():
             ref = -orc.subset_sums(order[off[i]:off[i + 1]], *args, 0.0)["w"]
             assert np.max(np.abs(gp[i] - ref)) <= gtol * np.max(np.abs(ref)), (precision, i)
         q = gpu.schur_matvec(x, 1e-3)
-        qtol = 1e-9 if precision == FP64 else 2e-3
+        qtol = 1e-9 if precision == FP64 else 5e-5  # FP32-mixed: 1e-9 .. 7e-8 measured
         errs = [np.max(np.abs(q[j] - ref_rows[t])) / np.max(np.abs(ref_rows[t])) for t, j in enumerate(cams)]
         print(f"80M precision {precision}: row errors " + " ".join(f"{e:.1e}" for e in errs))
         for t, j in enumerate(cams):
