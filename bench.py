@@ -35,6 +35,8 @@ FP32_UNPACKED_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # wavefront VALU instructions the chip can issue per second: 256 CUs x 4 SIMDs,
 # one wave64 instruction per SIMD every 4 cycles at 2.4 GHz
 VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4
+# L1 (TCP) cache-line lookups per second: about one per CU per cycle
+L1_LOOKUPS_PER_S = 256 * 2.4e9
 WORKLOADS = {  # name -> synth config and solver settings
     "large": dict(config="large", huber_delta=1.0, max_pcg_iters=100, pcg_rtol=1e-6),
     "medium": dict(config="medium", huber_delta=0.0, max_pcg_iters=100, pcg_rtol=1e-6),
@@ -82,6 +84,9 @@ def schur_product_kind():
 
 COUNTER_FILES = {"k_schur_hot<float>": "schur_hot_stored_29M_hbm_counters.md",
                  "k_schur_free<float>": "schur_free_29M_counters.md"}
+# the sources the point-major product kernels are built from (their hash
+# dates a counter summary)
+COUNTER_SOURCES = ("matvec.hip", "ba_internal.h", "camera_model.h", "camera_cache.h", "wave_ops.h")
 
 
 def counted(kernel):
@@ -100,8 +105,11 @@ def counted(kernel):
         if sep:
             fields[key] = val
     h = hashlib.sha256()
-    for f in ("matvec.hip", "ba_internal.h", "camera_model.h"):
-        h.update(open(os.path.join(ROOT, "paper_2112_01349_amd", "csrc", f), "rb").read())
+    for f in COUNTER_SOURCES:
+        path = os.path.join(ROOT, "paper_2112_01349_amd", "csrc", f)
+        if not os.path.exists(path):
+            return {}
+        h.update(open(path, "rb").read())
     if fields.get("kernel") != kernel or fields.get("source_sha256") != h.hexdigest()[:16]:
         return {}
     return {k: float(v) for k, v in fields.items() if k.endswith("_per_launch")}
@@ -138,11 +146,15 @@ def roofline(s32, m, n, N, counters_apply, s64=None):
         flops = free_pass_algorithmic_flops(n, N)
         tflops = flops / (ms * 1e-3) / 1e12
         insts = c.get("valu_insts_per_launch")
+        lookups = c.get("l1_lookups_per_launch")
         out.update(alu_flops_per_launch=flops, alu_tflops=tflops, alu_peak_tflops=FP32_UNPACKED_PEAK_TFLOPS,
                    alu_frac=tflops / FP32_UNPACKED_PEAK_TFLOPS,
                    valu_issue_frac=(insts / VALU_ISSUE_PER_S) / (ms * 1e-3) if insts else None,
+                   # L1 line lookups against one per CU per cycle (the limit of per-lane gathers)
+                   l1_lookup_frac=(lookups / L1_LOOKUPS_PER_S) / (ms * 1e-3) if lookups else None,
                    note="E is formed again from the Jacobian, so the algorithmic bytes bound a design that "
-                        "stores E, not this kernel (frac can pass 1); its limit is VALU issue")
+                        "stores E, not this kernel (frac can pass 1); its limits are VALU issue and L1 line "
+                        "lookups of the per-lane camera gathers")
     if s64 is not None:
         alg64 = hot_pass_algorithmic_bytes(n, N, 8)
         mv64 = matvec_algorithmic_bytes(m, n, N, 8)

@@ -212,10 +212,13 @@ ba_status ba_cost_fwd_device(ba_problem *prob, int32_t dtype, const void *d_cams
                              const void *d_pts, void *d_cost_f64, void *hip_stream);
 
 /* d_grad_cams [m][9], d_grad_pts [n][3] (dtype, caller order) receive
- * gout * sum rho'(|e|^2) J^T e at (d_cams, d_pts); either may be NULL. */
+ * s * sum rho'(|e|^2) J^T e at (d_cams, d_pts), s = gout times the device
+ * double *d_gout when d_gout is not NULL (read on the stream, so a caller
+ * holding the upstream gradient on the device need not synchronise); either
+ * output may be NULL. */
 ba_status ba_cost_bwd_device(ba_problem *prob, int32_t dtype, const void *d_cams,
-                             const void *d_pts, double gout, void *d_grad_cams,
-                             void *d_grad_pts, void *hip_stream);
+                             const void *d_pts, double gout, const double *d_gout,
+                             void *d_grad_cams, void *d_grad_pts, void *hip_stream);
 
 /* For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): the cost of

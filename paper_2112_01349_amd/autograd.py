@@ -2,6 +2,7 @@
 
 forward(cams [m,9], pts [n,3]) -> F = 1/2 sum rho(|e|^2)   (FP64 scalar)
 backward(dF)                     -> dF * sum rho' J_c^T e, dF * sum rho' J_p^T e
+                                    (dF read on the device: no host synchronisation)
 
 Both directions run in libba's HIP kernels through the device-pointer calls
 (ba_cost_fwd_device / ba_cost_bwd_device): the backward kernels recompute the
@@ -47,10 +48,13 @@ class HuberReprojCost(torch.autograd.Function):
         problem = ctx.problem
         gc = torch.empty_like(cams) if ctx.needs_input_grad[0] else None
         gp = torch.empty_like(pts) if ctx.needs_input_grad[1] else None
-        scale = float(gout.item())
-        problem.cost_bwd_device(_DTYPES[cams.dtype], cams.data_ptr(), pts.data_ptr(), scale,
+        # the upstream gradient stays on the device: the kernels read it on the
+        # stream, so backward never waits for the GPU (a temporary copy is
+        # reused by torch's allocator only in the order of that stream)
+        g = gout.to(device=cams.device, dtype=torch.float64).contiguous()
+        problem.cost_bwd_device(_DTYPES[cams.dtype], cams.data_ptr(), pts.data_ptr(), 1.0,
                                 None if gc is None else gc.data_ptr(),
-                                None if gp is None else gp.data_ptr(), _stream())
+                                None if gp is None else gp.data_ptr(), _stream(), gout_ptr=g.data_ptr())
         return gc, gp, None
 
 

@@ -1138,7 +1138,7 @@ extern "C" ba_status ba_eval_cost_grad(ba_problem* P, double* cost, double* grad
     if (grad_cameras || grad_points) {
         if ((st = grad_into<double>(P, P->cams, P->pts, P->ck64, nullptr, s)) != BA_OK) return st;
         // gradients land in cams_t / pts_t (caller order), then to the host
-        BA_TRY(P, launch_scatter_grad(P->m, P->n, 0, 1.0, P->vcam, P->wpt, P->d_old_of_new,
+        BA_TRY(P, launch_scatter_grad(P->m, P->n, 0, 1.0, nullptr, P->vcam, P->wpt, P->d_old_of_new,
                                       grad_cameras ? (void*)P->cams_t : nullptr,
                                       grad_points ? (void*)P->pts_t : nullptr, s));
         BA_TRY(P, hipStreamSynchronize(s));
@@ -1152,7 +1152,7 @@ extern "C" ba_status ba_eval_cost_grad(ba_problem* P, double* cost, double* grad
 
 template <typename T>
 static ba_status device_form(ba_problem* P, int32_t dtype, const void* d_cams, const void* d_pts, bool backward,
-                             double gout, void* d_cost, void* d_gc, void* d_gp, hipStream_t s)
+                             double gout, const double* d_gout, void* d_cost, void* d_gc, void* d_gp, hipStream_t s)
 {
     BA_TRY(P, launch_gather_cameras(P->m, dtype, d_cams, P->d_old_of_new, P->cams_t, s));
     BA_TRY(P, launch_convert_points(P->n, dtype, d_pts, P->pts_t, s));
@@ -1172,7 +1172,8 @@ static ba_status device_form(ba_problem* P, int32_t dtype, const void* d_cams, c
     }
     if ((st = grad_into<T>(P, P->cams_t, P->pts_t, ck, sizeof(T) == 4 ? P->ck64_t : nullptr, s)) != BA_OK)
         return st;
-    BA_TRY(P, launch_scatter_grad(P->m, P->n, dtype, gout, P->vcam, P->wpt, P->d_old_of_new, d_gc, d_gp, s));
+    BA_TRY(P, launch_scatter_grad(P->m, P->n, dtype, gout, d_gout, P->vcam, P->wpt, P->d_old_of_new, d_gc, d_gp,
+                                  s));
     return BA_OK;
 }
 
@@ -1184,21 +1185,24 @@ extern "C" ba_status ba_cost_fwd_device(ba_problem* P, int32_t dtype, const void
         return BA_EINVAL;
     }
     hipStream_t s = hip_stream ? (hipStream_t)hip_stream : P->stream;
-    return dtype == 0 ? device_form<double>(P, dtype, d_cams, d_pts, false, 0.0, d_cost_f64, nullptr, nullptr, s)
-                      : device_form<float>(P, dtype, d_cams, d_pts, false, 0.0, d_cost_f64, nullptr, nullptr, s);
+    return dtype == 0
+               ? device_form<double>(P, dtype, d_cams, d_pts, false, 0.0, nullptr, d_cost_f64, nullptr, nullptr, s)
+               : device_form<float>(P, dtype, d_cams, d_pts, false, 0.0, nullptr, d_cost_f64, nullptr, nullptr, s);
 }
 
 extern "C" ba_status ba_cost_bwd_device(ba_problem* P, int32_t dtype, const void* d_cams, const void* d_pts,
-                                        double gout, void* d_grad_cams, void* d_grad_pts, void* hip_stream)
+                                        double gout, const double* d_gout, void* d_grad_cams, void* d_grad_pts,
+                                        void* hip_stream)
 {
     if (!P || (dtype != 0 && dtype != 1) || !d_cams || (P->n > 0 && !d_pts) || !std::isfinite(gout)) {
         if (P) P->last_error = "invalid argument";
         return BA_EINVAL;
     }
     hipStream_t s = hip_stream ? (hipStream_t)hip_stream : P->stream;
-    return dtype == 0
-               ? device_form<double>(P, dtype, d_cams, d_pts, true, gout, nullptr, d_grad_cams, d_grad_pts, s)
-               : device_form<float>(P, dtype, d_cams, d_pts, true, gout, nullptr, d_grad_cams, d_grad_pts, s);
+    return dtype == 0 ? device_form<double>(P, dtype, d_cams, d_pts, true, gout, d_gout, nullptr, d_grad_cams,
+                                            d_grad_pts, s)
+                      : device_form<float>(P, dtype, d_cams, d_pts, true, gout, d_gout, nullptr, d_grad_cams,
+                                           d_grad_pts, s);
 }
 
 // ------------------------------------------------ reduced-system operator

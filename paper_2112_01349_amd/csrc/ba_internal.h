@@ -333,9 +333,10 @@ hipError_t launch_pred(int32_t m, int32_t n, const double* dc, const double* dca
 hipError_t launch_gather_cameras(int32_t m, int dtype, const void* src, const int32_t* old_of_new, double* dst,
                                  hipStream_t s);
 hipError_t launch_convert_points(int32_t n, int dtype, const void* src, double* dst, hipStream_t s);
-hipError_t launch_scatter_grad(int32_t m, int32_t n, int dtype, double scale, const double* vcam,
-                               const double* wpt, const int32_t* old_of_new, void* gcam, void* gpt,
-                               hipStream_t s);
+// scale (times *dscale when dscale is set) times -v and -w into caller order
+hipError_t launch_scatter_grad(int32_t m, int32_t n, int dtype, double scale, const double* dscale,
+                               const double* vcam, const double* wpt, const int32_t* old_of_new, void* gcam,
+                               void* gpt, hipStream_t s);
 hipError_t launch_store_cost(const double* sum, double* out, hipStream_t s);
 
 int32_t reduce_blocks(int64_t count);

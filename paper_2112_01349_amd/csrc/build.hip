@@ -182,7 +182,9 @@ __global__ __launch_bounds__(256) void k_build_points(
         const uint64_t heads = __ballot(valid && (lane == 0 || i != prev));
         const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
         const int seg_s = 63 - __clzll((heads & upto) | 1ull);
-        run_prefix_sel<double, R>(a, lane, seg_s);
+        // (a non-finite term spreads to the other points of its segment, whose
+        // blocks the solve then rejects as it rejects that point's)
+        run_prefix<double, R>(a, lane, seg_s);
         const bool last = valid && (lane == len - 1 || ((heads >> (lane + 1)) & 1ull));
         if (last) {
             if (!GRAD_ONLY)

@@ -380,10 +380,12 @@ hipError_t launch_convert_points(int32_t n, int dtype, const void* src, double* 
 }
 
 // grad = -scale * [v; w] scattered to caller order (v, w hold -J^T W e)
-__global__ void k_scatter_grad(int64_t lc, int64_t lp, int dtype, double scale, const double* __restrict__ vcam,
-                               const double* __restrict__ wpt, const int32_t* __restrict__ old_of_new,
-                               void* __restrict__ gcam, void* __restrict__ gpt)
+__global__ void k_scatter_grad(int64_t lc, int64_t lp, int dtype, double gout, const double* __restrict__ dscale,
+                               const double* __restrict__ vcam, const double* __restrict__ wpt,
+                               const int32_t* __restrict__ old_of_new, void* __restrict__ gcam,
+                               void* __restrict__ gpt)
 {
+    const double scale = dscale ? gout * dscale[0] : gout;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < lc + lp; t += (int64_t)gridDim.x * blockDim.x) {
         if (t < lc) {
             if (!gcam) continue;
@@ -403,14 +405,15 @@ __global__ void k_scatter_grad(int64_t lc, int64_t lp, int dtype, double scale, 
     }
 }
 
-hipError_t launch_scatter_grad(int32_t m, int32_t n, int dtype, double scale, const double* vcam, const double* wpt,
-                               const int32_t* old_of_new, void* gcam, void* gpt, hipStream_t s)
+hipError_t launch_scatter_grad(int32_t m, int32_t n, int dtype, double scale, const double* dscale,
+                               const double* vcam, const double* wpt, const int32_t* old_of_new, void* gcam, void* gpt,
+                               hipStream_t s)
 {
     const int64_t lc = 9 * (int64_t)m, lp = 3 * (int64_t)n;
     int64_t b = (lc + lp + 255) / 256;
     if (b > 8192) b = 8192;
     if (b < 1) b = 1;
-    hipLaunchKernelGGL(k_scatter_grad, dim3((unsigned)b), dim3(256), 0, s, lc, lp, dtype, scale, vcam, wpt,
+    hipLaunchKernelGGL(k_scatter_grad, dim3((unsigned)b), dim3(256), 0, s, lc, lp, dtype, scale, dscale, vcam, wpt,
                        old_of_new, gcam, gpt);
     return hipGetLastError();
 }

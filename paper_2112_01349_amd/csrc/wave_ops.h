@@ -63,18 +63,19 @@ __device__ __forceinline__ void run_prefix3(T& a0, T& a1, T& a2, int lane, int s
 }
 
 // Inclusive sums of the NV values a[] over each lane's run [seg_s, lane],
-// as run_prefix3 but with the shifted value selected (not multiplied) into
-// the sum, so a non-finite value in one run never reaches another.
+// in the same steps as run_prefix3 (an add or nothing for finite values; a
+// non-finite value can reach the other runs of its wavefront).
 template <typename T, int NV>
-__device__ __forceinline__ void run_prefix_sel(T* a, int lane, int seg_s)
+__device__ __forceinline__ void run_prefix(T* a, int lane, int seg_s)
 {
-    const bool m1 = lane - 1 >= seg_s, m2 = lane - 2 >= seg_s, m4 = lane - 4 >= seg_s, m8 = lane - 8 >= seg_s;
-    const bool m16 = (lane & ~15) - 1 >= seg_s, m32 = lane > 31 && seg_s <= 31;
+    const T m1 = lane - 1 >= seg_s ? (T)1 : (T)0;
+    const T m2 = lane - 2 >= seg_s ? (T)1 : (T)0;
+    const T m4 = lane - 4 >= seg_s ? (T)1 : (T)0;
+    const T m8 = lane - 8 >= seg_s ? (T)1 : (T)0;
+    const T m16 = (lane & ~15) - 1 >= seg_s ? (T)1 : (T)0;
+    const T m32 = (lane > 31 && seg_s <= 31) ? (T)1 : (T)0;
 #define BA_RUN_STEP(CTRL, ROWMASK, M)                                      \
-    _Pragma("unroll") for (int q = 0; q < NV; ++q) {                     \
-        const T sh = dpp_shift<CTRL, ROWMASK>(a[q]);                     \
-        a[q] += M ? sh : (T)0;                                           \
-    }
+    _Pragma("unroll") for (int q = 0; q < NV; ++q) a[q] = fma(dpp_shift<CTRL, ROWMASK>(a[q]), M, a[q]);
     BA_RUN_STEP(0x111, 0xf, m1)
     BA_RUN_STEP(0x112, 0xf, m2)
     BA_RUN_STEP(0x114, 0xf, m4)

@@ -74,7 +74,7 @@ def lib():
         L.ba_lm_solve.argtypes = [vp, C.POINTER(Options), C.POINTER(Report)]
         L.ba_schur_matvec.argtypes = [vp, C.c_double, C.c_int32, vp, vp]
         L.ba_cost_fwd_device.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
-        L.ba_cost_bwd_device.argtypes = [vp, C.c_int32, vp, vp, C.c_double, vp, vp, vp]
+        L.ba_cost_bwd_device.argtypes = [vp, C.c_int32, vp, vp, C.c_double, vp, vp, vp, vp]
         L.ba_cost_device_noalloc.argtypes = [C.c_int32, C.c_int32, C.c_int64, C.c_int32, vp, vp, vp, vp, vp,
                                              C.c_double, vp, vp]
         L.ba_memory_bytes.argtypes = [vp, C.POINTER(C.c_int64)]
@@ -238,9 +238,9 @@ class Problem:
     def cost_fwd_device(self, dtype, cams_ptr, pts_ptr, cost_ptr, stream=None):
         self._check(lib().ba_cost_fwd_device(self._h, int(dtype), cams_ptr, pts_ptr, cost_ptr, stream))
 
-    def cost_bwd_device(self, dtype, cams_ptr, pts_ptr, gout, gcam_ptr, gpt_ptr, stream=None):
-        self._check(lib().ba_cost_bwd_device(self._h, int(dtype), cams_ptr, pts_ptr, float(gout), gcam_ptr,
-                                             gpt_ptr, stream))
+    def cost_bwd_device(self, dtype, cams_ptr, pts_ptr, gout, gcam_ptr, gpt_ptr, stream=None, gout_ptr=None):
+        self._check(lib().ba_cost_bwd_device(self._h, int(dtype), cams_ptr, pts_ptr, float(gout), gout_ptr,
+                                             gcam_ptr, gpt_ptr, stream))
 
 
 def cost_device_noalloc(m, n, N, dtype, cams_ptr, pts_ptr, oc_ptr, op_ptr, uv_ptr, huber_delta, cost_ptr,

@@ -44,7 +44,7 @@ def test_counter_summary_is_read_only_for_matching_sources(tmp_path, monkeypatch
     (fake / "profiles").mkdir(parents=True)
     csrc = fake / "paper_2112_01349_amd" / "csrc"
     csrc.mkdir(parents=True)
-    for f in ("matvec.hip", "ba_internal.h", "camera_model.h"):
+    for f in bench.COUNTER_SOURCES:
         shutil.copy(os.path.join(ROOT, "paper_2112_01349_amd", "csrc", f), csrc / f)
     shutil.copy(summary, fake / "profiles" / os.path.basename(summary))
     monkeypatch.setattr(bench, "ROOT", str(fake))
