@@ -131,8 +131,10 @@ struct HotThreads<double> {
 };
 
 // Threads per workgroup of the recomputing product's point-major pass (one
-// workgroup per CU, like the stored-block pass).  Twelve FP64 wavefronts
-// (three per SIMD) ran 1% faster than eight but spill; eight are kept.
+// workgroup per CU, like the stored-block pass): sixteen wavefronts in both
+// precisions.  FP64 takes one segment at a time to fit them (at 29M
+// observations 0.524 ms per pass, against 0.554 ms for eight wavefronts
+// with two segments in flight and 0.533 ms for twelve with one).
 template <typename T>
 struct FreeWgThreads;
 template <>
@@ -141,7 +143,7 @@ struct FreeWgThreads<float> {
 };
 template <>
 struct FreeWgThreads<double> {
-    static constexpr int value = 512;
+    static constexpr int value = 1024;
 };
 
 // Observations on cameras outside the hot set, in camera-major order.

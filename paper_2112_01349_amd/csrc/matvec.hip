@@ -17,7 +17,7 @@
 //     over shuffles (a point that runs on into the next tile is finished from
 //     the prefetched registers) and b_i is formed in registers; contributions
 //     to the K hottest cameras accumulate in a per-workgroup LDS copy of their
-//     9-vectors (K sized to fill the 160 KB LDS), written out once at the
+//     9-vectors (K sized to fill the LDS), written out once at the
 //     end.  b_i of points that also have observations on colder cameras is
 //     stored.
 //   pass 2 (k_schur_cold): the observations on cameras >= K, from their own
@@ -26,6 +26,12 @@
 //   fold + epilogue (k_hot_fold, k_schur_epilogue): per camera entry, sums
 //     the workgroup partials (hot) or the slots (cold) in a fixed order and
 //     forms q or g.
+//
+// That is the stored-block design.  The default product stores no E: its
+// point-major pass (k_schur_free) and cold pass (k_schur_cold_free) form
+// each block again from the Jacobian's geometry, and the point-major pass
+// shares its LDS between the hot table and a copy of the most observed
+// cameras' records (camera_cache.h).
 #include "ba_internal.h"
 #include "camera_cache.h"
 #include "wave_ops.h"
@@ -602,9 +608,9 @@ __global__ __launch_bounds__((FreeThreads<T, MODE>::value)) void k_schur_free(
         // Batches of NB short segments: the loads of all of them are issued
         // before any is computed (one index prefetch a batch ahead was 1.6%
         // faster in FP32 and 5% slower in FP64 at 29M observations).
-        // (the back-substitution takes one at a time in FP32, to stay within
+        // (FP64 and the back-substitution take one at a time, to stay within
         // the registers of sixteen wavefronts per CU)
-        constexpr int NB = MODE == 2 && sizeof(T) == 4 ? 1 : 2;  // three spill in FP32 and gain nothing in FP64
+        constexpr int NB = MODE == 2 || sizeof(T) == 8 ? 1 : 2;  // three spill in FP32
         const int32_t S0 = frange[gw], S1 = frange[gw + 1];
         const int32_t nbat = (S1 - S0) / NB;
         for (int32_t bt = 0; bt < nbat; ++bt) {

@@ -34,13 +34,17 @@ def large():
 
 
 def sampled_cameras(d):
-    """The two most observed cameras, hot cameras of rank 20, 100 and 2000
-    (the product accumulates the 2,261 most observed ones in its LDS table),
-    the cold camera of rank 3000 and three random cold ones."""
+    """The two most observed cameras; hot cameras of rank 20 and 100 (in the
+    LDS hot-camera table, and among the 256 whose records the recomputing
+    product reads from LDS) and 1000 (in the table, record read from
+    memory); the camera of rank 3000 and three random ones of rank 2261 and
+    beyond, cold in every product (the recomputing product's table holds the
+    1,862 most observed cameras in FP32, 1,464 in FP64; the stored-block
+    product's 2,261)."""
     counts = np.diff(d["cam_csr"][0])
     order = np.argsort(-counts, kind="stable")
     rng = np.random.default_rng(5)
-    return [int(order[r]) for r in (0, 1, 20, 100, 2000, 3000)] + [int(x) for x in
+    return [int(order[r]) for r in (0, 1, 20, 100, 1000, 3000)] + [int(x) for x in
                                                                  rng.choice(order[2261:], 3, replace=False)]
 
 
@@ -82,8 +86,8 @@ def test_large_schur_rows(large, large_rows, precision, stored, monkeypatch):
     """Sampled rows of the reduced-system product at full size, from the
     recomputing product and from the stored-block one, against the oracle's
     rows computed from scratch: three hot cameras (their camera side goes
-    through the workgroups' LDS tables and the fold) and four cold ones
-    (the camera-major cold pass).  Each row is compared relative to its own
+    through the workgroups' LDS tables and the fold; two of them with their
+    records read from LDS) and four cold ones (the camera-major cold pass).  Each row is compared relative to its own
     largest entry."""
     monkeypatch.setenv("BA_SCHUR_STORED", str(stored))
     gpu = Problem(*large["args"], precision=precision, huber_delta=DELTA)
@@ -91,7 +95,7 @@ def test_large_schur_rows(large, large_rows, precision, stored, monkeypatch):
     gpu.close()
     counts = np.diff(large["cam_csr"][0])
     order = np.argsort(-counts, kind="stable")
-    assert large_rows["rows"][:3] == [int(order[r]) for r in (20, 100, 2000)]   # hot (rank < 2261)
+    assert large_rows["rows"][:3] == [int(order[r]) for r in (20, 100, 1000)]   # hot (rank < 1464)
     # FP32-mixed: float rounding through a row's thousands of points gives
     # 2e-7 .. 3e-6; the bound is ten times that and more
     tol = 1e-9 if precision == FP64 else 5e-5
@@ -136,10 +140,14 @@ def test_lm_trace_fp64_matches_oracle(name):
     3.4e19 against 1.3e8 by putting observations near a camera's principal
     plane), the step carries that rounding into the cost.  Where the trial
     cost rises more than tenfold both sides must reject."""
-    g, rep = replay(name)
     spread = order_spread(name)
     if spread is None:
         pytest.skip(f"tests/golden/order_spread_{name}_seed*.json not written yet")
+    # where the spread, not the 1e-9 floor, sets a bound, one permuted run is
+    # too small a sample of it: the largest of several is taken
+    if spread["runs"] < 3 and np.any(SPREAD_FACTOR * spread["trial"] > 1e-9):
+        pytest.skip(f"{spread['runs']} stored permuted run(s) of {name}; the spread bound needs three")
+    g, rep = replay(name)
     assert rep["status"] == 0 and rep["iters_run"] == g["iters_run"]
     assert abs(rep["initial_cost"] - g["initial_cost"]) <= 1e-12 * g["initial_cost"]
     prev = g["initial_cost"]
