@@ -62,6 +62,34 @@ __device__ __forceinline__ void run_prefix3(T& a0, T& a1, T& a2, int lane, int s
 #undef BA_RUN_STEP
 }
 
+// FP32: each step is one v_fmac_f32 with the shifted value as its DPP
+// source (a += shift(a) * m), where the compiler would emit a DPP move and an
+// FMA; the same arithmetic, a third fewer instructions.  s_nop 1 gives the
+// two wait states a DPP read needs after the VALU write of its source.
+#define BA_FMAC3_DPP(A0, A1, A2, M, DPP)                                                   \
+    asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %0, %3 " DPP "\n\tv_fmac_f32_dpp %1, %1, %3 " DPP \
+                 "\n\tv_fmac_f32_dpp %2, %2, %3 " DPP                                       \
+                 : "+v"(A0), "+v"(A1), "+v"(A2)                                            \
+                 : "v"(M))
+
+template <>
+__device__ __forceinline__ void run_prefix3<float>(float& a0, float& a1, float& a2, int lane, int seg_s)
+{
+    const float m1 = lane - 1 >= seg_s ? 1.0f : 0.0f;
+    const float m2 = lane - 2 >= seg_s ? 1.0f : 0.0f;
+    const float m4 = lane - 4 >= seg_s ? 1.0f : 0.0f;
+    const float m8 = lane - 8 >= seg_s ? 1.0f : 0.0f;
+    const float m16 = (lane & ~15) - 1 >= seg_s ? 1.0f : 0.0f;
+    const float m32 = (lane > 31 && seg_s <= 31) ? 1.0f : 0.0f;
+    BA_FMAC3_DPP(a0, a1, a2, m1, "row_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1");
+    BA_FMAC3_DPP(a0, a1, a2, m2, "row_shr:2 row_mask:0xf bank_mask:0xf bound_ctrl:1");
+    BA_FMAC3_DPP(a0, a1, a2, m4, "row_shr:4 row_mask:0xf bank_mask:0xf bound_ctrl:1");
+    BA_FMAC3_DPP(a0, a1, a2, m8, "row_shr:8 row_mask:0xf bank_mask:0xf bound_ctrl:1");
+    BA_FMAC3_DPP(a0, a1, a2, m16, "row_bcast:15 row_mask:0xa bank_mask:0xf");
+    BA_FMAC3_DPP(a0, a1, a2, m32, "row_bcast:31 row_mask:0xc bank_mask:0xf");
+}
+#undef BA_FMAC3_DPP
+
 // Inclusive sums of the NV values a[] over each lane's run [seg_s, lane],
 // in the same steps as run_prefix3 (an add or nothing for finite values; a
 // non-finite value can reach the other runs of its wavefront).
