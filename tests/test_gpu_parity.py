@@ -231,6 +231,29 @@ def test_hot_cold_split_matches_oracle(hot, cached, stored, monkeypatch):
     assert_traces_match(tr, gpu)
 
 
+@pytest.mark.parametrize("precision", [FP64, FP32_MIXED])
+def test_without_hot_table_runs_are_bitwise_repeatable(precision, monkeypatch):
+    """With no LDS hot table (BA_HOT_CAMERAS=0) every sum of the solve runs in
+    a fixed order (segmented scans, fixed slots, ordered last-block and slot
+    reductions), so two solves from the same state give the same bits: the
+    deterministic mode.  The table's LDS atomics are the only order the
+    hardware chooses."""
+    monkeypatch.setenv("BA_HOT_CAMERAS", "0")
+    arrays = with_edge_cases(small_zipf(seed=17, m=16, n=400, N=2500))
+    runs = []
+    for _ in range(2):
+        prob, _ = make(arrays[:5], precision=precision, huber_delta=1.0)
+        rep = prob.lm_solve(max_lm_iters=5, max_pcg_iters=40, pcg_rtol=1e-8)
+        assert rep["status"] == 0
+        runs.append((rep, prob.get_params()))
+        prob.close()
+    (r0, p0), (r1, p1) = runs
+    for key in ("cost", "trial_cost", "lambda", "pcg_iters", "accepted"):
+        np.testing.assert_array_equal(r0[key], r1[key], err_msg=key)
+    np.testing.assert_array_equal(p0[0], p1[0])
+    np.testing.assert_array_equal(p0[1], p1[1])
+
+
 def zero_rotation_variant(arrays):
     """The same problem with camera 0's angle-axis set to exactly zero (the
     first-order branch of the rotation)."""
