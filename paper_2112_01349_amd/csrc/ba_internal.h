@@ -150,7 +150,7 @@ struct FreeWgThreads<double> {
 struct ColdStream {
     int64_t N = 0;
     int32_t* cam = nullptr;         // [N]
-    int32_t* pt = nullptr;          // [N]
+    int32_t* pt = nullptr;          // [N] the observation's point record (crec)
     void* hcp = nullptr;            // [27][N] of T (stored-block product)
     void* w = nullptr;              // [N] of T: IRLS weights (recomputing product)
     int32_t* chunk_slot = nullptr;  // [num_chunks + 1]
@@ -168,11 +168,15 @@ struct SchurPlan {
     int32_t num_wg = 0;             // persistent workgroups of the hot pass
     int32_t* wrange = nullptr;      // [num_wg * waves per workgroup + 1] ranges of 64-observation
                                     // tiles per wavefront
-    uint8_t* has_cold = nullptr;    // [n] point has an observation in the cold stream
+    int32_t* crec = nullptr;        // [n] the point's record in bcold, -1 when it has no cold
+                                    // observation (the stored-block design: the point's own index;
+                                    // the recomputing one: records in order of first use by the
+                                    // camera-major cold stream, so they are read mostly in sequence)
     void* hot_part = nullptr;       // [num_wg][K][9] FP64
     double* hot_fold = nullptr;     // [kHotFold][K][9] FP64
     void* bcold = nullptr;          // [n][kBcold] of T: b_i for the cold pass, and (recomputing
-                                    // product) the point cast to T, one record per point
+                                    // product) the point cast to T and its index, one record per
+                                    // point with a cold observation (crec)
     ColdStream cold;
     // the recomputing product (mode 0 when set): point-aligned segments, short
     // (<= 64 observations of whole points) and long (one longer point), as

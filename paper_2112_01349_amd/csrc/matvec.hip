@@ -113,7 +113,7 @@ __global__ __launch_bounds__(HotThreads<T>::value) void k_schur_hot(
     const int32_t* __restrict__ wrange, int64_t N, const int32_t* __restrict__ cam,
     const int32_t* __restrict__ pt, const T* __restrict__ hcp, const T* __restrict__ cinv,
     const T* __restrict__ xcam, int32_t K, double* __restrict__ hot_part, T* __restrict__ bcold,
-    const uint8_t* __restrict__ has_cold, const PcgScalars* __restrict__ sc)
+    const int32_t* __restrict__ crec, const PcgScalars* __restrict__ sc)
 {
     constexpr int NT = HotThreads<T>::value;
     if (sc->done) return;  // uniform over the grid
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(HotThreads<T>::value) void k_schur_hot(
             for (int a = 0; a < 9; ++a) x[a] = xcam[9 * (int64_t)cj + a];
 #pragma unroll
             for (int a = 0; a < 6; ++a) c6[a] = cinv[6 * ii + a];
-            const bool hc = has_cold[ii] != 0;
+            const bool hc = crec[ii] >= 0;  // (this design's records are indexed by point)
             __builtin_amdgcn_sched_barrier(0);
             int32_t nj, ni;
             T nh[27];
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(HotThreads<T>::value) void k_schur_hot(
                         const T s0 = q6[0] * p0 + q6[1] * p1 + q6[2] * p2;
                         const T s1 = q6[1] * p0 + q6[3] * p1 + q6[4] * p2;
                         const T s2 = q6[2] * p0 + q6[4] * p1 + q6[5] * p2;
-                        if (lane == 0 && has_cold[s_pt]) {
+                        if (lane == 0 && crec[s_pt] >= 0) {
                             bcold[kBcold * (int64_t)s_pt] = s0;
                             bcold[kBcold * (int64_t)s_pt + 1] = s1;
                             bcold[kBcold * (int64_t)s_pt + 2] = s2;
@@ -443,7 +443,7 @@ struct FreeData {
     T X[3];
     T c6[6];
     T wv[3];   // w_i, modes 1 and 2
-    bool hc;   // modes 0 and 1
+    int32_t rec;  // the point's cold-pass record or -1 (modes 0 and 1)
 };
 
 template <typename T>
@@ -465,7 +465,7 @@ template <typename T, int MODE>
 __device__ __forceinline__ void free_gather(const FreeRow<T>& r, const double* __restrict__ pts,
                                             const CamK<T>* __restrict__ ck, const T* __restrict__ xf,
                                             int32_t Kc, const T* cache, const T* __restrict__ cinv,
-                                            const uint8_t* __restrict__ has_cold, const double* __restrict__ wpt,
+                                            const int32_t* __restrict__ crec, const double* __restrict__ wpt,
                                             FreeData<T>& d)
 {
     const uint32_t di = (uint32_t)(r.i - r.i0);
@@ -482,7 +482,7 @@ __device__ __forceinline__ void free_gather(const FreeRow<T>& r, const double* _
 #pragma unroll
         for (int a = 0; a < 3; ++a) d.wv[a] = (T)wv[a];
     }
-    if (MODE != 2) d.hc = *at_bytes<uint8_t>(has_cold + i0, di) != 0;
+    if (MODE != 2) d.rec = *at_bytes<int32_t>(crec + i0, di * 4u);
 }
 
 // One short segment.  Mode 0 (product): E^T x per lane, a_i per point run
@@ -542,8 +542,8 @@ __device__ __forceinline__ void free_short(const FreeRow<T>& r, const FreeData<T
         }
         return;
     }
-    if (valid && lane == seg_e && d.hc) {
-        T* o = const_cast<T*>(at_bytes<T>(bcold + kBcold * (int64_t)r.i0, di * (uint32_t)(kBcold * sizeof(T))));
+    if (valid && lane == seg_e && d.rec >= 0) {
+        T* o = bcold + kBcold * (int64_t)d.rec;
         o[0] = b0;
         o[1] = b1;
         o[2] = b2;
@@ -581,7 +581,7 @@ __global__ __launch_bounds__((FreeThreads<T, MODE>::value)) void k_schur_free(
     const T* __restrict__ wobs, const double* __restrict__ pts, const CamK<T>* __restrict__ ck,
     const CamK<double>* __restrict__ ck64, const T* __restrict__ xf, const T* __restrict__ cinv,
     const double* __restrict__ wpt, int32_t K, int32_t Kc, double* __restrict__ hot_part, T* __restrict__ bcold,
-    const uint8_t* __restrict__ has_cold, double* __restrict__ dp, const PcgScalars* __restrict__ sc)
+    const int32_t* __restrict__ crec, double* __restrict__ dp, const PcgScalars* __restrict__ sc)
 {
     constexpr int NT = FreeThreads<T, MODE>::value;
     if (MODE == 0 && sc->done) return;  // uniform over the grid
@@ -620,7 +620,7 @@ __global__ __launch_bounds__((FreeThreads<T, MODE>::value)) void k_schur_free(
             for (int u = 0; u < NB; ++u) free_stream<T>(sseg, S0 + NB * bt + u, lane, cam, pt, wobs, r[u]);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int u = 0; u < NB; ++u) free_gather<T, MODE>(r[u], pts, ck, xf, Kc, cache, cinv, has_cold, wpt, d[u]);
+            for (int u = 0; u < NB; ++u) free_gather<T, MODE>(r[u], pts, ck, xf, Kc, cache, cinv, crec, wpt, d[u]);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int u = 0; u < NB; ++u) free_short<T, MODE>(r[u], d[u], lane, upto, K, cl, bcold, dp, pts, ck64);
@@ -629,7 +629,7 @@ __global__ __launch_bounds__((FreeThreads<T, MODE>::value)) void k_schur_free(
             FreeRow<T> r;
             FreeData<T> d;
             free_stream<T>(sseg, q, lane, cam, pt, wobs, r);
-            free_gather<T, MODE>(r, pts, ck, xf, Kc, cache, cinv, has_cold, wpt, d);
+            free_gather<T, MODE>(r, pts, ck, xf, Kc, cache, cinv, crec, wpt, d);
             free_short<T, MODE>(r, d, lane, upto, K, cl, bcold, dp, pts, ck64);
         }
     }
@@ -672,10 +672,11 @@ __global__ __launch_bounds__((FreeThreads<T, MODE>::value)) void k_schur_free(
             }
             continue;
         }
-        if (lane == 0 && has_cold[i]) {
-            bcold[kBcold * (int64_t)i] = b0;
-            bcold[kBcold * (int64_t)i + 1] = b1;
-            bcold[kBcold * (int64_t)i + 2] = b2;
+        const int32_t rec = crec[i];
+        if (lane == 0 && rec >= 0) {
+            bcold[kBcold * (int64_t)rec] = b0;
+            bcold[kBcold * (int64_t)rec + 1] = b1;
+            bcold[kBcold * (int64_t)rec + 2] = b2;
         }
         if (K > 0)
             for (int32_t r = s0; r < s1; r += 64) {
@@ -714,7 +715,7 @@ __global__ __launch_bounds__(HotThreads<T>::value) void k_schur_rhs(
     const int32_t* __restrict__ wrange, int64_t N, const int32_t* __restrict__ cam,
     const int32_t* __restrict__ pt, const T* __restrict__ hcp, const T* __restrict__ cinv,
     const double* __restrict__ wpt, int32_t K, double* __restrict__ hot_part, T* __restrict__ bcold,
-    const uint8_t* __restrict__ has_cold)
+    const int32_t* __restrict__ crec)
 {
     constexpr int NT = HotThreads<T>::value;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -735,7 +736,7 @@ __global__ __launch_bounds__(HotThreads<T>::value) void k_schur_rhs(
             const T b0 = c6[0] * w0 + c6[1] * w1 + c6[2] * w2;
             const T b1 = c6[1] * w0 + c6[3] * w1 + c6[4] * w2;
             const T b2 = c6[2] * w0 + c6[4] * w1 + c6[5] * w2;
-            if ((lane == 0 || prev != i) && has_cold[i]) {
+            if ((lane == 0 || prev != i) && crec[i] >= 0) {
                 bcold[kBcold * (int64_t)i] = b0;
                 bcold[kBcold * (int64_t)i + 1] = b1;
                 bcold[kBcold * (int64_t)i + 2] = b2;
@@ -811,6 +812,21 @@ __global__ __launch_bounds__(256) void k_schur_cold(int64_t Nc, int32_t num_chun
 // formed from the camera constants, the point and the observation's weight
 // (cw, in cold-stream order).  The camera is uniform over a slot, so J_l^T of
 // the rotation part is applied once per slot.
+// Word 7 of a cold-pass record: the point's index, as bits of T.
+template <typename T>
+__device__ __forceinline__ T record_id(int32_t i)
+{
+    if constexpr (sizeof(T) == 4) return __builtin_bit_cast(float, i);
+    else return __builtin_bit_cast(double, (int64_t)i);
+}
+
+template <typename T>
+__device__ __forceinline__ int32_t record_point(const T* rec)
+{
+    if constexpr (sizeof(T) == 4) return __builtin_bit_cast(int32_t, rec[7]);
+    else return (int32_t)__builtin_bit_cast(int64_t, rec[7]);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_schur_cold_free(int64_t Nc, int32_t num_chunks,
                                                          const int32_t* __restrict__ ccam,
@@ -884,6 +900,7 @@ __global__ __launch_bounds__(256) void k_schur_cold_free(int64_t Nc, int32_t num
                 b[u][a] = bp[a];
                 X[u][a] = bp[4 + a];
             }
+            i[u] = record_point<T>(bp);  // the point itself (for an unresolved FP32 depth)
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -1030,26 +1047,30 @@ hipError_t prepare_schur_kernels(int32_t K, int32_t Kc, bool recompute)
     return hipFuncSetAttribute((const void*)k_schur_rhs<T>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
-// The point half of the cold pass's per-point records: the point cast to T,
-// for points with a cold observation.  Points change only with the state, so
-// this runs with the build; the product passes write the b_i half.
+// The point half of the cold pass's per-point records: the point cast to T
+// (words 4-6) and its index (word 7, as bits), for points with a cold
+// observation.  Points change only with the state, so this runs with the
+// build; the product passes write the b_i half.
 template <typename T>
-__global__ void k_cold_points(int32_t n, const double* __restrict__ pts, const uint8_t* __restrict__ has_cold,
+__global__ void k_cold_points(int32_t n, const double* __restrict__ pts, const int32_t* __restrict__ crec,
                               T* __restrict__ bcold)
 {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || !has_cold[i]) return;
-    T* rec = bcold + kBcold * (int64_t)i;
+    if (i >= n) return;
+    const int32_t r = crec[i];
+    if (r < 0) return;
+    T* rec = bcold + kBcold * (int64_t)r;
     rec[4] = (T)pts[3 * (int64_t)i];
     rec[5] = (T)pts[3 * (int64_t)i + 1];
     rec[6] = (T)pts[3 * (int64_t)i + 2];
+    rec[7] = record_id<T>(i);
 }
 
 template <typename T>
 hipError_t launch_cold_points(const SchurPlan& sp, int32_t n, const double* pts, hipStream_t s)
 {
     if (n > 0 && sp.cold.N > 0)
-        hipLaunchKernelGGL((k_cold_points<T>), dim3((n + 255) / 256), dim3(256), 0, s, n, pts, sp.has_cold,
+        hipLaunchKernelGGL((k_cold_points<T>), dim3((n + 255) / 256), dim3(256), 0, s, n, pts, sp.crec,
                            (T*)sp.bcold);
     return hipGetLastError();
 }
@@ -1072,17 +1093,17 @@ hipError_t launch_schur_product(int mode, const SchurPlan& sp, const PointMajor&
         if (mode == 0 && sp.recompute && ri)
             hipLaunchKernelGGL((k_schur_free<T, 0>), g, b, lds, s, sp.frange, sp.sseg, sp.lrange, sp.lseg, pm.cam,
                                pm.pt, ri->wobs, ri->pts, ri->ck, ri->ck64, ri->xf, cinv, nullptr, sp.K, sp.Kc, (double*)sp.hot_part,
-                               (T*)sp.bcold, sp.has_cold, nullptr, sc);
+                               (T*)sp.bcold, sp.crec, nullptr, sc);
         else if (mode == 1 && sp.recompute && ri)
             hipLaunchKernelGGL((k_schur_free<T, 1>), g, b, lds, s, sp.frange, sp.sseg, sp.lrange, sp.lseg, pm.cam,
                                pm.pt, ri->wobs, ri->pts, ri->ck, ri->ck64, nullptr, cinv, wpt, sp.K, sp.Kc, (double*)sp.hot_part,
-                               (T*)sp.bcold, sp.has_cold, nullptr, nullptr);
+                               (T*)sp.bcold, sp.crec, nullptr, nullptr);
         else if (mode == 0)
             hipLaunchKernelGGL((k_schur_hot<T>), g, b, lds, s, sp.wrange, N, pm.cam, pm.pt, hcp, cinv, xcam,
-                               sp.K, (double*)sp.hot_part, (T*)sp.bcold, sp.has_cold, sc);
+                               sp.K, (double*)sp.hot_part, (T*)sp.bcold, sp.crec, sc);
         else
             hipLaunchKernelGGL((k_schur_rhs<T>), g, b, lds, s, sp.wrange, N, pm.cam, pm.pt, hcp, cinv, wpt,
-                               sp.K, (double*)sp.hot_part, (T*)sp.bcold, sp.has_cold);
+                               sp.K, (double*)sp.hot_part, (T*)sp.bcold, sp.crec);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (hot_end && (e = hipEventRecord(hot_end, s)) != hipSuccess) return e;
@@ -1141,7 +1162,7 @@ hipError_t launch_backsub_free(const SchurPlan& sp, const PointMajor& pm, const 
     const size_t lds = hot_lds_bytes<T>(0, sp.Kc);
     hipLaunchKernelGGL((k_schur_free<T, 2>), dim3(sp.num_wg * (FreeWgThreads<T>::value / NT)), dim3(NT), lds, s,
                        sp.frange, sp.sseg, sp.lrange, sp.lseg, pm.cam, pm.pt, ri.wobs, ri.pts, ri.ck, ri.ck64, ri.xf,
-                       cinv, wpt, 0, sp.Kc, nullptr, nullptr, sp.has_cold, dp, nullptr);
+                       cinv, wpt, 0, sp.Kc, nullptr, nullptr, sp.crec, dp, nullptr);
     return hipGetLastError();
 }
 

@@ -99,6 +99,11 @@ def lm_pair(src, delta=0.0, iters=10, max_pcg=50, rtol=1e-8, spread=True):
     prob, _ = make(arrays[:5], huber_delta=delta)
     gpu = prob.lm_solve(max_lm_iters=iters, pcg_schedule=tr["pcg_iters"], max_pcg_iters=max_pcg,
                         pcg_rtol=rtol)
+    if len(arrays) > 5 and "unseen_point" in arrays[5]:
+        # a point with no observation never moves (its step is zero in the
+        # oracle, and the device must not leave it to whatever memory held)
+        u = arrays[5]["unseen_point"]
+        np.testing.assert_array_equal(prob.get_params()[1][u], pts[u])
     return tr, gpu, prob, (oc_, op_)
 
 
