@@ -19,7 +19,8 @@ constexpr int kCamSlotWords = 54;  // 45 upper-triangle B terms + 9 v terms
 constexpr int kSlotSeg = 32;       // slots summed by one wavefront before the per-camera combine
 constexpr int kHotFold = 8;        // slices the per-workgroup hot partials are folded into
 constexpr int kBcold = 8;          // words of T per point record read by the cold pass
-constexpr int kSmallBlocks = 96;   // blocks of the product's epilogue (its last-block reduction
+constexpr int kEpiThreads = 1024;  // threads of the product's epilogue blocks
+constexpr int kSmallBlocks = 192;  // at most this many epilogue blocks (its last-block reduction
                                    // serialises one device-scope atomic per block)
 
 // Scalars of one PCG run, kept on the device.  Kernels of the PCG loop read

@@ -941,18 +941,18 @@ __global__ __launch_bounds__(256) void k_hot_fold(int32_t K9, int32_t G, const d
 // mode 0: p^T q, then alpha = rho / p^T q and the matvec count (or a breakdown
 // when p^T q <= 0); mode 1: ||b||^2.
 template <int MODE>
-__global__ __launch_bounds__(kRedBlock) void k_schur_epilogue(
+__global__ __launch_bounds__(kEpiThreads) void k_schur_epilogue(
     int32_t m, int32_t K, const double* __restrict__ hot_fold, const int32_t* __restrict__ cold_cam_slot,
     const double* __restrict__ cold_slots, const double* __restrict__ bd,
     const double* __restrict__ pvec, const double* __restrict__ vcam, double* __restrict__ out,
     double* __restrict__ xvec, double* __restrict__ rvec, double* __restrict__ partials,
     PcgScalars* __restrict__ sc)
 {
-    __shared__ double sh[kRedBlock / 64];
+    __shared__ double sh[kEpiThreads / 64];
     if (MODE == 0 && sc->done) return;  // uniform over the grid
     double acc = 0.0;
     const int64_t len = 9 * (int64_t)m;
-    for (int64_t t = blockIdx.x * (int64_t)kRedBlock + threadIdx.x; t < len; t += (int64_t)gridDim.x * kRedBlock) {
+    for (int64_t t = blockIdx.x * (int64_t)kEpiThreads + threadIdx.x; t < len; t += (int64_t)gridDim.x * kEpiThreads) {
         const int64_t j = t / 9;
         const int a = (int)(t - 9 * j);
         double c = 0.0;
@@ -985,19 +985,19 @@ __global__ __launch_bounds__(kRedBlock) void k_schur_epilogue(
     __syncthreads();
     if (threadIdx.x == 0) {
         double s = 0.0;
-        for (int w = 0; w < kRedBlock / 64; ++w) s += sh[w];
+        for (int w = 0; w < kEpiThreads / 64; ++w) s += sh[w];
         partials[blockIdx.x] = s;
     }
     if (!last_block_arrives(&sc->arrive[MODE == 0 ? 1 : 2])) return;
     double tot = 0.0;
-    for (int32_t b = threadIdx.x; b < (int32_t)gridDim.x; b += kRedBlock) tot += partials[b];
+    for (int32_t b = threadIdx.x; b < (int32_t)gridDim.x; b += kEpiThreads) tot += partials[b];
     tot = wave_sum(tot);
     __syncthreads();
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = tot;
     __syncthreads();
     if (threadIdx.x == 0) {
         double s = 0.0;
-        for (int w = 0; w < kRedBlock / 64; ++w) s += sh[w];
+        for (int w = 0; w < kEpiThreads / 64; ++w) s += sh[w];
         if (MODE == 0) {
             sc->pq = s;
             if (!(s > 0.0) || !isfinite(s)) {
@@ -1133,15 +1133,16 @@ hipError_t launch_schur_product(int mode, const SchurPlan& sp, const PointMajor&
                            (const double*)sp.hot_part, sp.hot_fold, (const PcgScalars*)sc, mode == 0 ? 1 : 0);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    // few blocks: the last-block reduction serialises one device-scope atomic per block
-    int32_t nb = reduce_blocks(9 * (int64_t)m);
-    if (nb > kSmallBlocks) nb = kSmallBlocks;
+    // one entry per thread where the blocks allow; few blocks, since the
+    // last-block reduction serialises one device-scope atomic per block
+    int64_t nb64 = (9 * (int64_t)m + kEpiThreads - 1) / kEpiThreads;
+    const int32_t nb = (int32_t)(nb64 < 1 ? 1 : (nb64 > kSmallBlocks ? kSmallBlocks : nb64));
     const int32_t Ke = sp.num_wg > 0 ? sp.K : 0;
     if (mode == 0)
-        hipLaunchKernelGGL((k_schur_epilogue<0>), dim3(nb), dim3(kRedBlock), 0, s, m, Ke, sp.hot_fold,
+        hipLaunchKernelGGL((k_schur_epilogue<0>), dim3(nb), dim3(kEpiThreads), 0, s, m, Ke, sp.hot_fold,
                            sp.cold.cam_slot, sp.cold.slots, bd, pvec, vcam, out, xvec, rvec, partials, sc);
     else
-        hipLaunchKernelGGL((k_schur_epilogue<1>), dim3(nb), dim3(kRedBlock), 0, s, m, Ke, sp.hot_fold,
+        hipLaunchKernelGGL((k_schur_epilogue<1>), dim3(nb), dim3(kEpiThreads), 0, s, m, Ke, sp.hot_fold,
                            sp.cold.cam_slot, sp.cold.slots, bd, pvec, vcam, out, xvec, rvec, partials, sc);
     return hipGetLastError();
 }

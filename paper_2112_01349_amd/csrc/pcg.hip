@@ -129,20 +129,51 @@ __global__ __launch_bounds__(kRedBlock) void k_pcg_step(int32_t m, int first, co
     const double alpha = first ? 0.0 : sc->alpha;
     double rz = 0.0, rr = 0.0;
     const int32_t groups = (m + kStepCams - 1) / kStepCams;
+    // entries of the group's vectors and factors per thread; every load of a
+    // group is issued before any is used (indices past the group's end read
+    // its first entry and are not used)
+    constexpr int UV = (9 * kStepCams + kRedBlock - 1) / kRedBlock;
+    constexpr int UL = (45 * kStepCams + kRedBlock - 1) / kRedBlock;
     for (int32_t g = blockIdx.x; g < groups; g += gridDim.x) {
         const int32_t j0 = g * kStepCams;
         const int32_t nc = min(kStepCams, m - j0);
         const int64_t e0 = 9 * (int64_t)j0;
-        for (int t = threadIdx.x; t < 9 * nc; t += kRedBlock) {
-            double v = r[e0 + t];
+        const int nv = 9 * nc, nl = 45 * nc;
+        double rv[UV], xv[UV], pv[UV], qv[UV], lv[UL];
+#pragma unroll
+        for (int u = 0; u < UV; ++u) {
+            const int t = threadIdx.x + u * kRedBlock;
+            const int64_t e = e0 + (t < nv ? t : 0);
+            rv[u] = r[e];
             if (!first) {
-                x[e0 + t] += alpha * p[e0 + t];
-                v -= alpha * q[e0 + t];
-                r[e0 + t] = v;
+                xv[u] = x[e];
+                pv[u] = p[e];
+                qv[u] = q[e];
             }
-            sr[t] = v;
         }
-        for (int t = threadIdx.x; t < 45 * nc; t += kRedBlock) sl[t] = lfac[45 * (int64_t)j0 + t];
+#pragma unroll
+        for (int u = 0; u < UL; ++u) {
+            const int t = threadIdx.x + u * kRedBlock;
+            lv[u] = lfac[45 * (int64_t)j0 + (t < nl ? t : 0)];
+        }
+#pragma unroll
+        for (int u = 0; u < UV; ++u) {
+            const int t = threadIdx.x + u * kRedBlock;
+            if (t < nv) {
+                double v = rv[u];
+                if (!first) {
+                    x[e0 + t] = xv[u] + alpha * pv[u];
+                    v -= alpha * qv[u];
+                    r[e0 + t] = v;
+                }
+                sr[t] = v;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UL; ++u) {
+            const int t = threadIdx.x + u * kRedBlock;
+            if (t < nl) sl[t] = lv[u];
+        }
         __syncthreads();
         if (threadIdx.x < nc) {
             const double* L = sl + 45 * threadIdx.x;
@@ -173,7 +204,11 @@ __global__ __launch_bounds__(kRedBlock) void k_pcg_step(int32_t m, int first, co
             }
         }
         __syncthreads();
-        for (int t = threadIdx.x; t < 9 * nc; t += kRedBlock) z[e0 + t] = sr[t];
+#pragma unroll
+        for (int u = 0; u < UV; ++u) {
+            const int t = threadIdx.x + u * kRedBlock;
+            if (t < nv) z[e0 + t] = sr[t];
+        }
         __syncthreads();
     }
     block_partials<2>(rz, rr, partials);
@@ -240,29 +275,59 @@ __global__ __launch_bounds__(kRedBlock) void k_pcg_direction(int32_t m, int forc
     const bool first = force || sc->iters == 0;
     const double beta = first ? 0.0 : sc->beta;
     const int32_t groups = (m + kStepCams - 1) / kStepCams;
+    // loads of a group issued before any is used, as in k_pcg_step
+    constexpr int UV = (9 * kStepCams + kRedBlock - 1) / kRedBlock;
+    constexpr int UX = (12 * kStepCams + kRedBlock - 1) / kRedBlock;
     for (int32_t g = blockIdx.x; g < groups; g += gridDim.x) {
         const int32_t j0 = g * kStepCams;
         const int32_t nc = min(kStepCams, m - j0);
         const int64_t e0 = 9 * (int64_t)j0;
-        for (int t = threadIdx.x; t < 9 * nc; t += kRedBlock) {
-            const double v = first ? z[e0 + t] : z[e0 + t] + beta * p[e0 + t];
-            p[e0 + t] = v;
-            pT[e0 + t] = (T)v;
-            sv[t] = v;
+        const int nv = 9 * nc, nx = 12 * nc;
+        double zv[UV], pv[UV];
+#pragma unroll
+        for (int u = 0; u < UV; ++u) {
+            const int t = threadIdx.x + u * kRedBlock;
+            const int64_t e = e0 + (t < nv ? t : 0);
+            zv[u] = z[e];
+            pv[u] = first ? 0.0 : p[e];
+        }
+#pragma unroll
+        for (int u = 0; u < UV; ++u) {
+            const int t = threadIdx.x + u * kRedBlock;
+            if (t < nv) {
+                const double v = first ? zv[u] : zv[u] + beta * pv[u];
+                p[e0 + t] = v;
+                pT[e0 + t] = (T)v;
+                sv[t] = v;
+            }
         }
         if (xf) {
+            // J_l rows of the lanes that form J_l p_w (a < 3), loaded before the barrier
+            T J[UX][3];
+#pragma unroll
+            for (int u = 0; u < UX; ++u) {
+                const int t = threadIdx.x + u * kRedBlock;
+                const int tt = t < nx ? t : 0;
+                const int c = tt / 12, a = tt - 12 * c;
+                const T* Jr = ck[j0 + c].Jl + 3 * (a < 3 ? a : 0);
+                J[u][0] = Jr[0];
+                J[u][1] = Jr[1];
+                J[u][2] = Jr[2];
+            }
             __syncthreads();
-            for (int t = threadIdx.x; t < 12 * nc; t += kRedBlock) {
-                const int c = t / 12, a = t - 12 * c;
-                const double* v = sv + 9 * c;
-                T o = (T)0;
-                if (a < 3) {
-                    const T* J = ck[j0 + c].Jl;
-                    o = (T)((double)J[3 * a] * v[0] + (double)J[3 * a + 1] * v[1] + (double)J[3 * a + 2] * v[2]);
-                } else if (a < 9) {
-                    o = (T)v[a];
+#pragma unroll
+            for (int u = 0; u < UX; ++u) {
+                const int t = threadIdx.x + u * kRedBlock;
+                if (t < nx) {
+                    const int c = t / 12, a = t - 12 * c;
+                    const double* v = sv + 9 * c;
+                    T o = (T)0;
+                    if (a < 3)
+                        o = (T)((double)J[u][0] * v[0] + (double)J[u][1] * v[1] + (double)J[u][2] * v[2]);
+                    else if (a < 9)
+                        o = (T)v[a];
+                    xf[12 * (int64_t)j0 + t] = o;
                 }
-                xf[12 * (int64_t)j0 + t] = o;
             }
         }
         __syncthreads();
