@@ -115,7 +115,8 @@ typedef struct {
                                       iteration; overrides pcg_fixed_iters and pcg_rtol */
     double lambda_init;            /* initial LM damping, default 1e-4 */
     double min_relative_decrease;  /* accept a step iff gain ratio > this, default 1e-3 */
-    int32_t time_kernels;          /* != 0: time every Schur matvec with HIP events */
+    int32_t time_kernels;          /* != 0: time every 8th Schur matvec of each PCG solve with
+                                      HIP events (the events lengthen the matvecs they bracket) */
     int32_t solver;                /* ba_solver; fixed at ba_create.  With BA_SOLVER_DENSE
                                       the PCG fields are ignored and pcg_iters reports 0;
                                       a reduced system that is not positive definite

@@ -866,6 +866,9 @@ static ba_status build_system(ba_problem* P)
     return BA_OK;
 }
 
+// With time_kernels, the PCG loop brackets every kTimedStride-th matvec with events.
+constexpr int32_t kTimedStride = 8;
+
 struct PcgTimer {
     std::vector<hipEvent_t> ev;
     size_t used = 0;
@@ -907,15 +910,22 @@ static ba_status run_pcg(ba_problem* P, const ba_options& o, int32_t fixed, int3
                                       &ri, m, P->bd, nullptr, P->vcam, P->g, P->x, P->r, P->partials, P->sc,
                                       nullptr, nullptr, s));
     BA_TRY(P, launch_pcg_step(m, true, P->lfac, P->p, P->q, P->x, P->r, P->z, P->partials, P->sc, s));
-    std::vector<std::array<hipEvent_t, 4>> marks;
+    // timed matvecs: every kTimedStride-th (each event marker costs the stream
+    // a few microseconds: timing all of them made a PCG iteration 3% longer)
+    struct Mark {
+        int32_t iter;
+        std::array<hipEvent_t, 4> ev;
+    };
+    std::vector<Mark> marks;
     const int32_t batch = fixed > 0 ? std::max(1, cap) : 8;
     int32_t enqueued = 0;
     while (enqueued < cap) {
         const int32_t nb = std::min(batch, cap - enqueued);
         for (int32_t b = 0; b < nb; ++b) {
             BA_TRY(P, launch_pcg_direction<T>(m, false, P->z, P->p, (T*)P->pT, ri.ck, xf, P->sc, s));
+            const bool timed = tm && enqueued % kTimedStride == 0;
             std::array<hipEvent_t, 4> ev{nullptr, nullptr, nullptr, nullptr};
-            if (tm) {
+            if (timed) {
                 BA_TRY(P, tm->next(&ev[0], &ev[1]));
                 BA_TRY(P, tm->next(&ev[2], &ev[3]));
                 BA_TRY(P, hipEventRecord(ev[0], s));
@@ -923,9 +933,9 @@ static ba_status run_pcg(ba_problem* P, const ba_options& o, int32_t fixed, int3
             BA_TRY(P, launch_schur_product<T>(0, P->sp, P->pm, P->N, (const T*)P->hcp, (const T*)P->cinv, P->wpt,
                                               (const T*)P->pT, &ri, m, P->bd, P->p, nullptr, P->q, nullptr, nullptr,
                                               P->partials, P->sc, ev[2], ev[3], s));
-            if (tm) {
+            if (timed) {
                 BA_TRY(P, hipEventRecord(ev[1], s));
-                marks.push_back(ev);
+                marks.push_back(Mark{enqueued, ev});
             }
             BA_TRY(P, launch_pcg_step(m, false, P->lfac, P->p, P->q, P->x, P->r, P->z, P->partials, P->sc, s));
             ++enqueued;
@@ -946,11 +956,11 @@ static ba_status run_pcg(ba_problem* P, const ba_options& o, int32_t fixed, int3
         *stop = h->iters >= o.max_pcg_iters ? BA_PCG_CAP : BA_PCG_CONVERGED;
     // A breakdown (p^T q <= 0 or non-finite) stops the loop before that
     // update, so x holds the last iterate: it is used as the step (truncated CG).
-    // matvecs run in order: the first `iters` marks timed real work
-    for (size_t u = 0; u < marks.size() && (int32_t)u < h->iters; ++u) {
+    // matvecs run in order: those enqueued before the count reached did real work
+    for (size_t u = 0; u < marks.size() && marks[u].iter < h->iters; ++u) {
         float ms = 0.0f, hms = 0.0f;
-        BA_TRY(P, hipEventElapsedTime(&ms, marks[u][0], marks[u][1]));
-        BA_TRY(P, hipEventElapsedTime(&hms, marks[u][2], marks[u][3]));
+        BA_TRY(P, hipEventElapsedTime(&ms, marks[u].ev[0], marks[u].ev[1]));
+        BA_TRY(P, hipEventElapsedTime(&hms, marks[u].ev[2], marks[u].ev[3]));
         *matvec_ms += ms;
         *hot_ms += hms;
         *launches += 1;
