@@ -443,15 +443,16 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
         const char* stored = std::getenv("BA_SCHUR_STORED");
         sp.recompute = !(stored && std::atoi(stored) != 0);
         // recomputing product: the LDS holds the records of cameras [0, Kc)
-        // and the hot table in the rest.  At 29M observations (Zipf) the
-        // point-major pass ran 0.370 / 0.351 / 0.342 ms (FP32) with 120 / 260 /
-        // 880 records, while the cold pass shrinks as the table grows; 256
-        // records and the rest for the table gave the shortest PCG iteration
-        // in both precisions.
+        // and the hot table in the rest.  More records shorten the
+        // point-major pass and fewer hot cameras lengthen the cold pass; at
+        // 29M observations (Zipf) the PCG iteration took 0.462 / 0.444 /
+        // 0.441 / 0.441 ms FP32 and 0.636 / 0.636 / 0.639 / 0.654 ms FP64
+        // with 128 / 256 / 384 / 512 records.
         const size_t rec = P->is_f32() ? kCamRecBytes<float>() : kCamRecBytes<double>();
         const char* env_c = std::getenv("BA_CACHE_CAMERAS");
+        const int32_t kc_default = P->is_f32() ? kCacheCamerasF32 : kCacheCamerasF64;
         if (!sp.recompute) sp.Kc = 0;
-        else sp.Kc = std::max(0, std::min(m, env_c ? std::atoi(env_c) : kCacheCameras));
+        else sp.Kc = std::max(0, std::min(m, env_c ? std::atoi(env_c) : kc_default));
         if (sp.Kc > 0 && (size_t)sp.Kc * rec + 1040 > (size_t)lds_limit)
             sp.Kc = (int32_t)(((size_t)lds_limit - 1040) / rec);
         int32_t kmax = P->is_f32() ? hot_max_cameras<float>((size_t)lds_limit, sp.Kc)

@@ -112,7 +112,9 @@ struct CameraMajor {
 // Words of the camera record the recomputing product keeps in LDS for its
 // hot cameras: the head of CamK and the 12-word direction record.
 constexpr int kCamRec = kCamHead + 12;
-constexpr int kCacheCameras = 256;  // records kept (most observed cameras first)
+// records kept (most observed cameras first), FP32-mixed / FP64
+constexpr int kCacheCamerasF32 = 512;
+constexpr int kCacheCamerasF64 = 256;
 template <typename T>
 constexpr size_t kCamRecBytes()
 {
