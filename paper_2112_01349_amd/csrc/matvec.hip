@@ -551,6 +551,15 @@ __device__ __forceinline__ void free_short(const FreeRow<T>& r, const FreeData<T
     if (valid && r.j < K) free_add_hot<T>(cl, r.j, o, d.hd, r.w, b0, b1, b2);
 }
 
+// A unit of the workgroup's shared work list for the calling wavefront
+// (wave-uniform; every lane must be active).
+__device__ __forceinline__ int32_t grab_unit(int32_t* counter, int lane)
+{
+    int32_t v = 0;
+    if (lane == 0) v = atomicAdd(counter, 1);
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
 // The point-major pass without stored blocks, in the three modes of
 // free_short (0: product, 1: reduced right-hand side, 2: back-substitution).
 // Work units are point-aligned segments: short ones (up to 64 observations of
@@ -586,6 +595,7 @@ __global__ __launch_bounds__((FreeThreads<T, MODE>::value)) void k_schur_free(
     constexpr int NT = FreeThreads<T, MODE>::value;
     if (MODE == 0 && sc->done) return;  // uniform over the grid
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int32_t next_unit[2];  // next short batch, next long segment of the workgroup
     double* cl = reinterpret_cast<double*>(smem);
     for (int q = threadIdx.x; q < K * 9; q += NT) cl[q] = 0.0;
     // the hot cameras' records, 16 bytes per thread and step (the right-hand
@@ -600,20 +610,90 @@ __global__ __launch_bounds__((FreeThreads<T, MODE>::value)) void k_schur_free(
             else if (MODE != 1) dst[q] = reinterpret_cast<const uint4*>(xf + 12 * (int64_t)j)[c - HC];
         }
     }
+    if (threadIdx.x == 0) {
+        next_unit[0] = 0;
+        next_unit[1] = 0;
+    }
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    const int32_t gw = __builtin_amdgcn_readfirstlane(blockIdx.x * (NT / 64) + (threadIdx.x >> 6));
     const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+    // The workgroup's segments (the host's split over its wavefronts, taken
+    // together) are handed out to its wavefronts one unit at a time from LDS
+    // counters: the SIMDs issue their oldest wavefront first, so equal static
+    // shares ended 270 us (first of four per SIMD) to 370 us (last) into a
+    // 29M-observation pass, the last ones at low occupancy.  Long segments
+    // (the largest units) go first.
+    constexpr int WPG = NT / 64;
+    const int32_t wg = blockIdx.x;
+    {
+        const int32_t L0 = lrange[wg * WPG], L1 = lrange[(wg + 1) * WPG];
+        for (int32_t q = L0 + grab_unit(&next_unit[1], lane); q < L1; q = L0 + grab_unit(&next_unit[1], lane)) {
+            const int2 be = lseg[q];
+            const int32_t s0 = __builtin_amdgcn_readfirstlane(be.x), s1 = __builtin_amdgcn_readfirstlane(be.y);
+            const int32_t i = __builtin_amdgcn_readfirstlane(pt[s0]);
+            T s_0 = (T)0, s_1 = (T)0, s_2 = (T)0;
+            if (MODE != 1)
+                for (int32_t r = s0; r < s1; r += 64) {
+                    const bool valid = r + lane < s1;
+                    const int64_t k = valid ? r + lane : r;
+                    int32_t j, ii;
+                    T w, hd[kCamHead], xv[9];
+                    ObsGeo<T> o;
+                    free_observation<T, MODE != 1>(k, cam, pt, wobs, pts, ck, ck64, xf, Kc, cache, j, ii, w, hd, xv, o);
+                    T e0, e1, e2;
+                    free_et_x<T>(o, hd, xv, w, e0, e1, e2);
+                    if (!valid) e0 = e1 = e2 = (T)0;
+                    s_0 += wave_sum(e0);
+                    s_1 += wave_sum(e1);
+                    s_2 += wave_sum(e2);
+                }
+            if (MODE != 0) {
+                const T w0 = (T)wpt[3 * (int64_t)i], w1 = (T)wpt[3 * (int64_t)i + 1], w2 = (T)wpt[3 * (int64_t)i + 2];
+                s_0 = MODE == 1 ? w0 : w0 - s_0;
+                s_1 = MODE == 1 ? w1 : w1 - s_1;
+                s_2 = MODE == 1 ? w2 : w2 - s_2;
+            }
+            const T* c6 = cinv + 6 * (int64_t)i;
+            const T b0 = c6[0] * s_0 + c6[1] * s_1 + c6[2] * s_2;
+            const T b1 = c6[1] * s_0 + c6[3] * s_1 + c6[4] * s_2;
+            const T b2 = c6[2] * s_0 + c6[4] * s_1 + c6[5] * s_2;
+            if (MODE == 2) {
+                if (lane == 0) {
+                    dp[3 * (int64_t)i] = (double)b0;
+                    dp[3 * (int64_t)i + 1] = (double)b1;
+                    dp[3 * (int64_t)i + 2] = (double)b2;
+                }
+                continue;
+            }
+            const int32_t rec = crec[i];
+            if (lane == 0 && rec >= 0) {
+                bcold[kBcold * (int64_t)rec] = b0;
+                bcold[kBcold * (int64_t)rec + 1] = b1;
+                bcold[kBcold * (int64_t)rec + 2] = b2;
+            }
+            if (K > 0)
+                for (int32_t r = s0; r < s1; r += 64) {
+                    const bool valid = r + lane < s1;
+                    const int64_t k = valid ? r + lane : r;
+                    int32_t j, ii;
+                    T w, hd[kCamHead], xv[9];
+                    ObsGeo<T> o;
+                    free_observation<T, MODE != 1>(k, cam, pt, wobs, pts, ck, ck64, xf, Kc, cache, j, ii, w, hd, xv, o);
+                    if (valid && j < K) free_add_hot<T>(cl, j, o, hd, w, b0, b1, b2);
+                }
+        }
+    }
     {
         // Batches of NB short segments: the loads of all of them are issued
-        // before any is computed (one index prefetch a batch ahead was 1.6%
-        // faster in FP32 and 5% slower in FP64 at 29M observations).
-        // (FP64 and the back-substitution take one at a time, to stay within
-        // the registers of sixteen wavefronts per CU)
+        // before any is computed; the next batch is claimed before this one
+        // is computed.  (FP64 and the back-substitution take one at a time,
+        // to stay within the registers of sixteen wavefronts per CU)
         constexpr int NB = MODE == 2 || sizeof(T) == 8 ? 1 : 2;  // three spill in FP32
-        const int32_t S0 = frange[gw], S1 = frange[gw + 1];
+        const int32_t S0 = frange[wg * WPG], S1 = frange[(wg + 1) * WPG];
         const int32_t nbat = (S1 - S0) / NB;
-        for (int32_t bt = 0; bt < nbat; ++bt) {
+        int32_t bt = grab_unit(&next_unit[0], lane);
+        while (bt < nbat) {
+            const int32_t next = grab_unit(&next_unit[0], lane);
             FreeRow<T> r[NB];
             FreeData<T> d[NB];
 #pragma unroll
@@ -624,69 +704,16 @@ __global__ __launch_bounds__((FreeThreads<T, MODE>::value)) void k_schur_free(
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int u = 0; u < NB; ++u) free_short<T, MODE>(r[u], d[u], lane, upto, K, cl, bcold, dp, pts, ck64);
+            bt = next;
         }
-        for (int32_t q = S0 + NB * nbat; q < S1; ++q) {
-            FreeRow<T> r;
-            FreeData<T> d;
-            free_stream<T>(sseg, q, lane, cam, pt, wobs, r);
-            free_gather<T, MODE>(r, pts, ck, xf, Kc, cache, cinv, crec, wpt, d);
-            free_short<T, MODE>(r, d, lane, upto, K, cl, bcold, dp, pts, ck64);
-        }
-    }
-    const int32_t L0 = lrange[gw], L1 = lrange[gw + 1];
-    for (int32_t q = L0; q < L1; ++q) {
-        const int2 be = lseg[q];
-        const int32_t s0 = __builtin_amdgcn_readfirstlane(be.x), s1 = __builtin_amdgcn_readfirstlane(be.y);
-        const int32_t i = __builtin_amdgcn_readfirstlane(pt[s0]);
-        T s_0 = (T)0, s_1 = (T)0, s_2 = (T)0;
-        if (MODE != 1)
-            for (int32_t r = s0; r < s1; r += 64) {
-                const bool valid = r + lane < s1;
-                const int64_t k = valid ? r + lane : r;
-                int32_t j, ii;
-                T w, hd[kCamHead], xv[9];
-                ObsGeo<T> o;
-                free_observation<T, MODE != 1>(k, cam, pt, wobs, pts, ck, ck64, xf, Kc, cache, j, ii, w, hd, xv, o);
-                T e0, e1, e2;
-                free_et_x<T>(o, hd, xv, w, e0, e1, e2);
-                if (!valid) e0 = e1 = e2 = (T)0;
-                s_0 += wave_sum(e0);
-                s_1 += wave_sum(e1);
-                s_2 += wave_sum(e2);
-            }
-        if (MODE != 0) {
-            const T w0 = (T)wpt[3 * (int64_t)i], w1 = (T)wpt[3 * (int64_t)i + 1], w2 = (T)wpt[3 * (int64_t)i + 2];
-            s_0 = MODE == 1 ? w0 : w0 - s_0;
-            s_1 = MODE == 1 ? w1 : w1 - s_1;
-            s_2 = MODE == 1 ? w2 : w2 - s_2;
-        }
-        const T* c6 = cinv + 6 * (int64_t)i;
-        const T b0 = c6[0] * s_0 + c6[1] * s_1 + c6[2] * s_2;
-        const T b1 = c6[1] * s_0 + c6[3] * s_1 + c6[4] * s_2;
-        const T b2 = c6[2] * s_0 + c6[4] * s_1 + c6[5] * s_2;
-        if (MODE == 2) {
-            if (lane == 0) {
-                dp[3 * (int64_t)i] = (double)b0;
-                dp[3 * (int64_t)i + 1] = (double)b1;
-                dp[3 * (int64_t)i + 2] = (double)b2;
-            }
-            continue;
-        }
-        const int32_t rec = crec[i];
-        if (lane == 0 && rec >= 0) {
-            bcold[kBcold * (int64_t)rec] = b0;
-            bcold[kBcold * (int64_t)rec + 1] = b1;
-            bcold[kBcold * (int64_t)rec + 2] = b2;
-        }
-        if (K > 0)
-            for (int32_t r = s0; r < s1; r += 64) {
-                const bool valid = r + lane < s1;
-                const int64_t k = valid ? r + lane : r;
-                int32_t j, ii;
-                T w, hd[kCamHead], xv[9];
-                ObsGeo<T> o;
-                free_observation<T, MODE != 1>(k, cam, pt, wobs, pts, ck, ck64, xf, Kc, cache, j, ii, w, hd, xv, o);
-                if (valid && j < K) free_add_hot<T>(cl, j, o, hd, w, b0, b1, b2);
+        // the segments past the last whole batch go to the wavefront that claims batch nbat
+        if (bt == nbat)
+            for (int32_t q = S0 + NB * nbat; q < S1; ++q) {
+                FreeRow<T> r;
+                FreeData<T> d;
+                free_stream<T>(sseg, q, lane, cam, pt, wobs, r);
+                free_gather<T, MODE>(r, pts, ck, xf, Kc, cache, cinv, crec, wpt, d);
+                free_short<T, MODE>(r, d, lane, upto, K, cl, bcold, dp, pts, ck64);
             }
     }
     __syncthreads();
