@@ -491,7 +491,7 @@ __device__ __forceinline__ void free_gather(const FreeRow<T>& r, const double* _
 // camera side.  Mode 2 (back-substitution): a_i as in mode 0, then
 // dp_i = C~_i^-1 (w_i - a_i).
 template <typename T, int MODE>
-__device__ __forceinline__ void free_short(const FreeRow<T>& r, const FreeData<T>& d, int lane, uint64_t upto,
+__device__ __forceinline__ void free_short(const FreeRow<T>& r, const FreeData<T>& d, int lane,
                                            int32_t K, double* __restrict__ cl, T* __restrict__ bcold,
                                            double* __restrict__ dp, const double* __restrict__ pts,
                                            const CamK<double>* __restrict__ ck64)
@@ -514,9 +514,11 @@ __device__ __forceinline__ void free_short(const FreeRow<T>& r, const FreeData<T
         const int32_t prev = lane_before(r.i, -1);
         const bool head = valid && (lane == 0 || r.i != prev);
         const uint64_t hm = __ballot(head);
-        const int seg_s = 63 - __clzll((hm & upto) | 1ull);
-        const uint64_t above = hm & ~upto;
-        seg_e = above ? __ffsll((unsigned long long)above) - 2 : r.len - 1;
+        // the run's first lane: the highest head at or below this lane (lane
+        // 0 is always one); its last: the lane before the next head above
+        const int seg_s = lane - __clzll((hm | 1ull) << (63 - lane));
+        const uint64_t above = lane < 63 ? hm >> (lane + 1) : 0ull;
+        seg_e = above ? __ffsll((unsigned long long)above) + lane - 1 : r.len - 1;
         run_prefix3<T>(a0, a1, a2, lane, seg_s);
         a0 = __shfl(a0, seg_e, 64);
         a1 = __shfl(a1, seg_e, 64);
@@ -616,7 +618,6 @@ __global__ __launch_bounds__((FreeThreads<T, MODE>::value)) void k_schur_free(
     }
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
     // The workgroup's segments (the host's split over its wavefronts, taken
     // together) are handed out to its wavefronts one unit at a time from LDS
     // counters: the SIMDs issue their oldest wavefront first, so equal static
@@ -703,7 +704,7 @@ __global__ __launch_bounds__((FreeThreads<T, MODE>::value)) void k_schur_free(
             for (int u = 0; u < NB; ++u) free_gather<T, MODE>(r[u], pts, ck, xf, Kc, cache, cinv, crec, wpt, d[u]);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int u = 0; u < NB; ++u) free_short<T, MODE>(r[u], d[u], lane, upto, K, cl, bcold, dp, pts, ck64);
+            for (int u = 0; u < NB; ++u) free_short<T, MODE>(r[u], d[u], lane, K, cl, bcold, dp, pts, ck64);
             bt = next;
         }
         // the segments past the last whole batch go to the wavefront that claims batch nbat
@@ -713,7 +714,7 @@ __global__ __launch_bounds__((FreeThreads<T, MODE>::value)) void k_schur_free(
                 FreeData<T> d;
                 free_stream<T>(sseg, q, lane, cam, pt, wobs, r);
                 free_gather<T, MODE>(r, pts, ck, xf, Kc, cache, cinv, crec, wpt, d);
-                free_short<T, MODE>(r, d, lane, upto, K, cl, bcold, dp, pts, ck64);
+                free_short<T, MODE>(r, d, lane, K, cl, bcold, dp, pts, ck64);
             }
     }
     __syncthreads();
