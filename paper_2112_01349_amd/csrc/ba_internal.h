@@ -188,8 +188,10 @@ struct SchurPlan {
     int32_t num_short = 0, num_long = 0;
     int2* sseg = nullptr;           // [num_short]
     int2* lseg = nullptr;           // [num_long]
-    int32_t* frange = nullptr;      // [num_wg * waves per workgroup + 1] short-segment ranges
-    int32_t* lrange = nullptr;      // [num_wg * waves per workgroup + 1] long-segment ranges
+    int32_t* frange = nullptr;      // [num_wg * waves per workgroup + 1] short-segment ranges, split
+                                    // by observation count; a workgroup's share runs from its first
+                                    // wavefront's start to the next workgroup's
+    int32_t* lrange = nullptr;      // [num_wg * waves per workgroup + 1] long-segment ranges, alike
 };
 
 // What the recomputing product reads besides the streams of PointMajor.

@@ -567,12 +567,12 @@ __device__ __forceinline__ int32_t grab_unit(int32_t* counter, int lane)
 // Work units are point-aligned segments: short ones (up to 64 observations of
 // whole points, one per lane) and long ones (one point of more than 64
 // observations, in rows of 64, walked a second time for its camera side);
-// each wavefront has a range of each kind.  Hot cameras accumulate in the
-// workgroup's LDS table as in k_schur_hot; b_i of points with cold
-// observations is stored for the cold pass, which reads its own stored
-// blocks.  Mode 2 has no camera side (K = 0).  Every mode keeps an LDS copy
-// of the camera records of cameras [0, Kc) (kCamRec words each, after the
-// hot table), so all three run one workgroup per CU.
+// each workgroup has a range of each kind, which its wavefronts share.  Hot
+// cameras accumulate in the workgroup's LDS table as in k_schur_hot; b_i of
+// points with cold observations goes into their cold-pass records
+// (k_schur_cold_free).  Mode 2 has no camera side (K = 0).  Every mode keeps
+// an LDS copy of the camera records of cameras [0, Kc) (kCamRec words each,
+// after the hot table), so all three run one workgroup per CU.
 template <typename T, int MODE>
 struct FreeThreads {
     static constexpr int value = FreeWgThreads<T>::value;
