@@ -627,6 +627,7 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     P->wobs = A.get<char>(P->pm.ld * (int64_t)tsz);
     P->xf = A.get<char>(12 * (int64_t)m * (int64_t)tsz);
     sp.crec = A.get<int32_t>(std::max<int64_t>(1, n));
+    sp.rec_pt = A.get<int32_t>(std::max<int64_t>(1, n));
     sp.hot_part = A.get<double>((int64_t)sp.num_wg * sp.K * 9);
     sp.hot_fold = A.get<double>((int64_t)kHotFold * sp.K * 9);
     sp.bcold = A.get<char>(kBcold * (int64_t)n * (int64_t)tsz);
@@ -728,6 +729,12 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     if (e == hipSuccess) e = hipMemset(P->wobs, 0, (size_t)P->pm.ld * tsz);
     if (e == hipSuccess) e = hipMemset(P->xf, 0, 12 * (size_t)m * tsz);
     if (e == hipSuccess && n > 0) e = up(sp.crec, crec.data(), sizeof(int32_t) * (size_t)n);
+    if (e == hipSuccess && n > 0) {
+        std::vector<int32_t> rec_pt((size_t)n, 0);
+        for (int32_t i = 0; i < n; ++i)
+            if (crec[(size_t)i] >= 0) rec_pt[(size_t)crec[(size_t)i]] = i;
+        e = up(sp.rec_pt, rec_pt.data(), sizeof(int32_t) * (size_t)n);
+    }
     if (e == hipSuccess) e = up(sp.cold.cam, h_cold_cam.data(), sizeof(int32_t) * h_cold_cam.size());
     if (e == hipSuccess) e = up(sp.cold.pt, h_cold_pt.data(), sizeof(int32_t) * h_cold_pt.size());
     if (e == hipSuccess) e = up(sp.cold.chunk_slot, cold_chunk_slot.data(), sizeof(int32_t) * cold_chunk_slot.size());

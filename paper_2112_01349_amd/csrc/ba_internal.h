@@ -18,7 +18,7 @@ constexpr int kRedBlock = 256;  // threads of reduction blocks
 constexpr int kCamSlotWords = 54;  // 45 upper-triangle B terms + 9 v terms
 constexpr int kSlotSeg = 32;       // slots summed by one wavefront before the per-camera combine
 constexpr int kHotFold = 8;        // slices the per-workgroup hot partials are folded into
-constexpr int kBcold = 8;          // words of T per point record read by the cold pass
+constexpr int kBcold = 6;          // words of T per point record read by the cold pass
 constexpr int kEpiThreads = 1024;  // threads of the product's epilogue blocks
 constexpr int kSmallBlocks = 192;  // at most this many epilogue blocks (its last-block reduction
                                    // serialises one device-scope atomic per block)
@@ -177,9 +177,10 @@ struct SchurPlan {
                                     // camera-major cold stream, so they are read mostly in sequence)
     void* hot_part = nullptr;       // [num_wg][K][9] FP64
     double* hot_fold = nullptr;     // [kHotFold][K][9] FP64
-    void* bcold = nullptr;          // [n][kBcold] of T: b_i for the cold pass, and (recomputing
-                                    // product) the point cast to T and its index, one record per
-                                    // point with a cold observation (crec)
+    void* bcold = nullptr;          // [n][kBcold] of T: b_i for the cold pass (words 0-2), and
+                                    // (recomputing product) the point cast to T (words 3-5), one
+                                    // record per point with a cold observation (crec)
+    int32_t* rec_pt = nullptr;      // recomputing product: the point of each record
     ColdStream cold;
     // the recomputing product (mode 0 when set): point-aligned segments, short
     // (<= 64 observations of whole points) and long (one longer point), as

@@ -840,21 +840,6 @@ __global__ __launch_bounds__(256) void k_schur_cold(int64_t Nc, int32_t num_chun
 // formed from the camera constants, the point and the observation's weight
 // (cw, in cold-stream order).  The camera is uniform over a slot, so J_l^T of
 // the rotation part is applied once per slot.
-// Word 7 of a cold-pass record: the point's index, as bits of T.
-template <typename T>
-__device__ __forceinline__ T record_id(int32_t i)
-{
-    if constexpr (sizeof(T) == 4) return __builtin_bit_cast(float, i);
-    else return __builtin_bit_cast(double, (int64_t)i);
-}
-
-template <typename T>
-__device__ __forceinline__ int32_t record_point(const T* rec)
-{
-    if constexpr (sizeof(T) == 4) return __builtin_bit_cast(int32_t, rec[7]);
-    else return (int32_t)__builtin_bit_cast(int64_t, rec[7]);
-}
-
 template <typename T>
 __global__ __launch_bounds__(256) void k_schur_cold_free(int64_t Nc, int32_t num_chunks,
                                                          const int32_t* __restrict__ ccam,
@@ -863,6 +848,7 @@ __global__ __launch_bounds__(256) void k_schur_cold_free(int64_t Nc, int32_t num
                                                          const CamK<T>* __restrict__ ck,
                                                          const CamK<double>* __restrict__ ck64,
                                                          const T* __restrict__ bcold,
+                                                         const int32_t* __restrict__ rec_pt,
                                                          const int32_t* __restrict__ chunk_slot,
                                                          double* __restrict__ slots, const PcgScalars* __restrict__ sc,
                                                          int skip_if_done, int32_t cold_blocks, int32_t K9,
@@ -926,16 +912,16 @@ __global__ __launch_bounds__(256) void k_schur_cold_free(int64_t Nc, int32_t num
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 b[u][a] = bp[a];
-                X[u][a] = bp[4 + a];
+                X[u][a] = bp[3 + a];
             }
-            i[u] = record_point<T>(bp);  // the point itself (for an unresolved FP32 depth)
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             ObsGeo<T> o;
+            // an unresolved FP32 depth: the geometry from the FP64 point of the record
             if (!observation_geometry<T>(hd[u], X[u][0], X[u][1], X[u][2], o) && ck64)
-                o = observation_geometry_f64<T>(ck64, j[u], pts + 3 * (int64_t)i[u]);
+                o = observation_geometry_f64<T>(ck64, j[u], pts + 3 * (int64_t)rec_pt[i[u]]);
             T c[9];
             free_camera_side<T>(o, hd[u], w[u], b[u][0], b[u][1], b[u][2], c);
             const int32_t jj = valid[u] ? j[u] : 0x7fffffff;
@@ -1076,9 +1062,9 @@ hipError_t prepare_schur_kernels(int32_t K, int32_t Kc, bool recompute)
 }
 
 // The point half of the cold pass's per-point records: the point cast to T
-// (words 4-6) and its index (word 7, as bits), for points with a cold
-// observation.  Points change only with the state, so this runs with the
-// build; the product passes write the b_i half.
+// (words 3-5), for points with a cold observation.  Points change only with
+// the state, so this runs with the build; the product passes write the b_i
+// half (words 0-2).
 template <typename T>
 __global__ void k_cold_points(int32_t n, const double* __restrict__ pts, const int32_t* __restrict__ crec,
                               T* __restrict__ bcold)
@@ -1088,10 +1074,9 @@ __global__ void k_cold_points(int32_t n, const double* __restrict__ pts, const i
     const int32_t r = crec[i];
     if (r < 0) return;
     T* rec = bcold + kBcold * (int64_t)r;
-    rec[4] = (T)pts[3 * (int64_t)i];
-    rec[5] = (T)pts[3 * (int64_t)i + 1];
-    rec[6] = (T)pts[3 * (int64_t)i + 2];
-    rec[7] = record_id<T>(i);
+    rec[3] = (T)pts[3 * (int64_t)i];
+    rec[4] = (T)pts[3 * (int64_t)i + 1];
+    rec[5] = (T)pts[3 * (int64_t)i + 2];
 }
 
 template <typename T>
@@ -1145,7 +1130,7 @@ hipError_t launch_schur_product(int mode, const SchurPlan& sp, const PointMajor&
             const int32_t fold_blocks = fold ? (K9 + 255) / 256 * kHotFold : 0;
             hipLaunchKernelGGL((k_schur_cold_free<T>), dim3(cold_blocks + fold_blocks), dim3(256), 0, s, sp.cold.N,
                                sp.cold.num_chunks, sp.cold.cam, sp.cold.pt, (const T*)sp.cold.w, ri->pts, ri->ck,
-                               ri->ck64, (const T*)sp.bcold, sp.cold.chunk_slot, sp.cold.slots,
+                               ri->ck64, (const T*)sp.bcold, sp.rec_pt, sp.cold.chunk_slot, sp.cold.slots,
                                (const PcgScalars*)sc, mode == 0 ? 1 : 0, cold_blocks, K9, sp.num_wg,
                                (const double*)sp.hot_part, sp.hot_fold);
             folded = fold;
