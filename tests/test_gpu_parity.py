@@ -389,13 +389,18 @@ def test_synthesised_recipe_matches_oracle(hot, monkeypatch):
     assert_traces_match(tr, rep, spread=spread)
 
 
-def test_mixed_point_at_camera_centre():
+def test_mixed_point_at_camera_centre(monkeypatch):
     """A point within FP32 resolution of a camera's centre (LM can drift there
     when a point's other views are outliers: every projection is available
     from the centre) has a depth made of rounding in FP32.  The FP32-mixed
     form forms that observation's geometry in FP64 from the FP64 camera
     constants and point (and stores it in FP32), so the blocks, the product
-    and the LM step stay finite; the FP64 form needs no such step."""
+    and the LM step stay finite; the FP64 form needs no such step.  With no
+    hot cameras the observation goes through the camera-major cold pass,
+    which finds the point through its record: its mixed product matches the
+    point-major pass's.  (Against the FP64 product the mixed rows of the two
+    cameras that see this point differ by ~1e-2: their terms reach 1e7 times
+    the others' and cancel, so float rounding of the geometry shows there.)"""
     from scipy.spatial.transform import Rotation
 
     prob = synth.generate("tiny", seed=0)
@@ -409,15 +414,23 @@ def test_mixed_point_at_camera_centre():
     op = np.concatenate([prob.obs_point, [i, i]]).astype(np.int32)
     uv = np.vstack([prob.obs_uv, [[12.0, -7.0], orc.project(cams[1], X) + 0.3]])
     x = np.random.default_rng(2).normal(size=(len(cams), 9))
-    for precision in (FP64, FP32_MIXED):
+    q = {}
+    for precision, hot in ((FP64, None), (FP32_MIXED, None), (FP32_MIXED, 0)):
+        if hot is not None:
+            monkeypatch.setenv("BA_HOT_CAMERAS", str(hot))
         gpu, _ = make((cams, pts, oc, op, uv), precision=precision, huber_delta=1.0)
         F, gc, gp = gpu.eval_cost_grad()
         assert np.isfinite(F) and np.all(np.isfinite(gc)) and np.all(np.isfinite(gp)), precision
-        assert np.all(np.isfinite(gpu.schur_matvec(x, 1e-3))), precision
+        q[precision, hot] = gpu.schur_matvec(x, 1e-3)
+        assert np.all(np.isfinite(q[precision, hot])), precision
         rep = gpu.lm_solve(max_lm_iters=3, max_pcg_iters=30, pcg_rtol=1e-6)
         assert rep["status"] == 0, (precision, rep["error"])
         assert np.all(np.diff(np.concatenate([[rep["initial_cost"]], rep["cost"]])) <= 0)
         gpu.close()
+    err = rel_err_rows(q[FP32_MIXED, 0], q[FP32_MIXED, None])
+    far = rel_err_rows(q[FP32_MIXED, None], q[FP64, None])
+    print(f"cold pass against point-major pass (mixed): {err:.2e} of each row; mixed against FP64 {far:.1e}")
+    assert err <= FP32_PRODUCT_TOL
 
 
 def dense_pair(arrays, delta=0.0, iters=6, precision=FP64):
