@@ -245,9 +245,9 @@ ba_status ba_memory_bytes(const ba_problem* prob, int64_t* bytes)
 }  // extern "C"
 
 // ------------------------------------------------------------------ set-up
-// Partial-sum slots of a camera-sorted stream cut into wave chunks of
-// `chunk` observations: one slot per (chunk, camera run); a camera's slots
-// are contiguous.  Returns the slot count.
+// Partial-sum slots of a camera-sorted stream (observations, or rows of one
+// camera each) cut into wave chunks of `chunk` entries: one slot per (chunk,
+// camera run); a camera's slots are contiguous.  Returns the slot count.
 static int32_t plan_slots(const std::vector<int32_t>& cam_sorted, int32_t m, int32_t chunk,
                           std::vector<int32_t>& chunk_slot, std::vector<int32_t>& cam_slot)
 {
@@ -414,8 +414,19 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
             h_cm_uvy[(size_t)d] = h_uvy[(size_t)t];
         }
     }
+    // rows of <= 64 observations that never span two cameras (a camera's
+    // last row may be short), so a camera changes only between rows
+    std::vector<int32_t> h_cm_row;
+    for (int32_t j = 0; j < m; ++j)
+        for (int64_t t = coff[j]; t < coff[(size_t)j + 1]; t += 64) h_cm_row.push_back((int32_t)t);
+    h_cm_row.push_back((int32_t)N);
+    P->cm.num_rows = (int32_t)h_cm_row.size() - 1;
     std::vector<int32_t> chunk_slot, cam_slot;
-    P->cm.num_slots = plan_slots(h_cm_cam, m, kCmChunk, chunk_slot, cam_slot);
+    {
+        std::vector<int32_t> row_cam((size_t)P->cm.num_rows);
+        for (int32_t r = 0; r < P->cm.num_rows; ++r) row_cam[(size_t)r] = h_cm_cam[(size_t)h_cm_row[(size_t)r]];
+        P->cm.num_slots = plan_slots(row_cam, m, kCmRows, chunk_slot, cam_slot);
+    }
     const int32_t num_chunks = (int32_t)chunk_slot.size() - 1;
     P->cm.num_chunks = num_chunks;
     std::vector<int32_t> seg_cam, seg_slot, cam_seg((size_t)m + 1, 0);
@@ -593,6 +604,7 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     P->cm.pt = A.get<int32_t>(N);
     P->cm.uvx = A.get<double>(N);
     P->cm.uvy = A.get<double>(N);
+    P->cm.row = A.get<int32_t>((int64_t)P->cm.num_rows + 1);
     P->cm.chunk_slot = A.get<int32_t>((int64_t)num_chunks + 1);
     P->cm.cam_slot = A.get<int32_t>((int64_t)m + 1);
     P->cm.slots = A.get<double>((int64_t)P->cm.num_slots * kCamSlotWords);
@@ -693,6 +705,7 @@ extern "C" ba_status ba_create(int32_t m, int32_t n, int64_t N, const double* ca
     if (e == hipSuccess) e = up(P->cm.pt, h_cm_pt.data(), sizeof(int32_t) * N);
     if (e == hipSuccess) e = up(P->cm.uvx, h_cm_uvx.data(), sizeof(double) * N);
     if (e == hipSuccess) e = up(P->cm.uvy, h_cm_uvy.data(), sizeof(double) * N);
+    if (e == hipSuccess) e = up(P->cm.row, h_cm_row.data(), sizeof(int32_t) * h_cm_row.size());
     if (e == hipSuccess) e = up(P->cm.chunk_slot, chunk_slot.data(), sizeof(int32_t) * chunk_slot.size());
     if (e == hipSuccess) e = up(P->cm.cam_slot, cam_slot.data(), sizeof(int32_t) * cam_slot.size());
     if (e == hipSuccess) e = up(P->cm.seg_cam, seg_cam.data(), sizeof(int32_t) * seg_cam.size());

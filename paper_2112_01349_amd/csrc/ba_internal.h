@@ -10,8 +10,7 @@
 namespace ba {
 
 constexpr int kTile = 256;      // observations per point-aligned tile (one workgroup)
-constexpr int kCmRows = 32;     // rows of 64 observations per camera-major wave chunk
-constexpr int kCmChunk = 64 * kCmRows;
+constexpr int kCmRows = 32;     // rows of <= 64 observations of one camera per camera-major wave chunk
 constexpr int kColdRows = 8;    // rows of 64 observations per cold-stream wave chunk
 constexpr int kColdChunk = 64 * kColdRows;
 constexpr int kRedBlock = 256;  // threads of reduction blocks
@@ -95,7 +94,9 @@ struct CameraMajor {
     int32_t* pt;          // [N]
     double* uvx;          // [N]
     double* uvy;          // [N]
-    int32_t* chunk_slot;  // [num_chunks + 1] first partial-sum slot of each wave chunk
+    int32_t* row;         // [num_rows + 1] first observation of each row: <= 64 of one camera
+    int32_t num_rows;
+    int32_t* chunk_slot;  // [num_chunks + 1] first partial-sum slot of each wave chunk (kCmRows rows)
     int32_t* cam_slot;    // [m + 1] slots of each camera (contiguous)
     int32_t num_chunks;
     int32_t num_slots;

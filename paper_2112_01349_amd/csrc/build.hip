@@ -9,12 +9,14 @@
 //     block E_k = w J_c^T J_p (tile-blocked, see eidx) when E is stored, and
 //     sums the point blocks C_i = sum w J_p^T J_p and w_i = -sum w J_p^T e
 //     over each point's run of lanes by a segmented scan.
-//   * camera-major (k_build_cameras): one wavefront per contiguous chunk of
-//     2048 observations sorted by camera, its rows software-pipelined.  Lanes accumulate the camera terms
+//   * camera-major (k_build_cameras): one wavefront per chunk of 32 rows of
+//     the camera-sorted stream, each row up to 64 observations of one camera,
+//     software-pipelined.  Lanes accumulate the camera terms
 //     B_j = sum w J_c^T J_c and v_j = -sum w J_c^T e in registers while the
 //     camera does not change and flush a wavefront-reduced partial sum into a
-//     slot when it does; slots of one camera are contiguous and are summed in
-//     a fixed order by k_reduce_slots, so the result is deterministic.  This
+//     slot at the first row of the next; slots of one camera are contiguous
+//     and are summed in a fixed order by k_reduce_slots, so the result is
+//     deterministic.  This
 //     balances the Zipf-skewed camera segments (the most-seen camera holds
 //     about 60% of all points) over the whole chip, as the paper's equal-edge
 //     partition (Sec. 4.1) does over GPUs.
@@ -321,15 +323,16 @@ __device__ __forceinline__ void flush_slot(double* acc, double* __restrict__ slo
     for (int q = 0; q < W; ++q) acc[q] = 0.0;
 }
 
-// One row (64 consecutive observations, one per lane) of a camera-major
-// chunk: the streamed words, then what they point at.  The chunk's rows are
-// software-pipelined: while row r is computed, the point and camera loads of
-// row r + 1 and the streamed words of row r + 2 are in flight, so one
-// wavefront per SIMD (the 54 FP64 accumulators leave no room for a second)
-// is not left waiting on a dependent gather every row.
+// One row (up to 64 consecutive observations of one camera, one per lane)
+// of a camera-major chunk: the streamed words, then what they point at.  The
+// chunk's rows are software-pipelined: while row r is computed, the point and
+// camera loads of row r + 1 and the streamed words of row r + 2 are in
+// flight, so one wavefront per SIMD (the 54 FP64 accumulators leave no room
+// for a second) is not left waiting on a dependent gather every row.
 template <typename T>
 struct CmRow {
-    int32_t j, i;       // camera, point (lanes past the chunk's end: its first observation)
+    int32_t k0, len;    // first observation and length (uniform)
+    int32_t j, i;       // camera, point (lanes past the row's end: its first observation)
     double u, v;        // pixel
     double X[3];        // point (gathered)
     T hd[kCamHead];     // camera constants R, t, f, k1, k2, small (gathered)
@@ -337,13 +340,14 @@ struct CmRow {
 };
 
 template <typename T>
-__device__ __forceinline__ void cm_stream(int64_t start, int64_t end, int32_t row, int lane,
+__device__ __forceinline__ void cm_stream(const int32_t* __restrict__ rows, int32_t row, int lane,
                                           const int32_t* __restrict__ cam, const int32_t* __restrict__ pt,
                                           const double* __restrict__ uvx, const double* __restrict__ uvy,
                                           CmRow<T>& r)
 {
-    const int64_t k = start + (int64_t)row * 64 + lane;
-    const int64_t kk = k < end ? k : start;
+    r.k0 = __builtin_amdgcn_readfirstlane(rows[row]);
+    r.len = __builtin_amdgcn_readfirstlane(rows[row + 1]) - r.k0;
+    const int64_t kk = r.k0 + (lane < r.len ? lane : 0);
     r.j = cam[kk];
     r.i = pt[kk];
     r.u = uvx[kk];
@@ -387,84 +391,84 @@ __device__ __forceinline__ void cm_observation(const CmRow<T>& r, const double* 
     wt = huber_weight<T>(e0 * e0 + e1 * e1, delta);
 }
 
-// Walks the rows of one camera-major chunk [start, end) through the
-// pipeline above and calls body(row, r) for each (uniform over the wave).
+// Walks the rows [r0, r1) of one camera-major chunk through the pipeline
+// above and calls body(r) for each (uniform over the wave).
 template <typename T, class Body>
-__device__ __forceinline__ void cm_rows(int64_t start, int64_t end, int lane, const int32_t* __restrict__ cam,
-                                        const int32_t* __restrict__ pt, const double* __restrict__ uvx,
-                                        const double* __restrict__ uvy, const double* __restrict__ pts,
-                                        const CamK<T>* __restrict__ ck, Body&& body)
+__device__ __forceinline__ void cm_rows(int32_t r0, int32_t r1, int lane, const int32_t* __restrict__ rows,
+                                        const int32_t* __restrict__ cam, const int32_t* __restrict__ pt,
+                                        const double* __restrict__ uvx, const double* __restrict__ uvy,
+                                        const double* __restrict__ pts, const CamK<T>* __restrict__ ck, Body&& body)
 {
-    const int32_t rows = (int32_t)((end - start + 63) >> 6);
     CmRow<T> a, b;
-    cm_stream<T>(start, end, 0, lane, cam, pt, uvx, uvy, a);
+    cm_stream<T>(rows, r0, lane, cam, pt, uvx, uvy, a);
     cm_gather<T>(pts, ck, a);
-    if (rows > 1) cm_stream<T>(start, end, 1, lane, cam, pt, uvx, uvy, b);
-    for (int32_t row = 0; row < rows; ++row) {
+    if (r0 + 1 < r1) cm_stream<T>(rows, r0 + 1, lane, cam, pt, uvx, uvy, b);
+    for (int32_t row = r0; row < r1; ++row) {
         const CmRow<T> c = a;
-        if (row + 1 < rows) {
+        if (row + 1 < r1) {
             a = b;
             cm_gather<T>(pts, ck, a);
         }
-        if (row + 2 < rows) cm_stream<T>(start, end, row + 2, lane, cam, pt, uvx, uvy, b);
-        body(row, c);
+        if (row + 2 < r1) cm_stream<T>(rows, row + 2, lane, cam, pt, uvx, uvy, b);
+        body(c);
     }
 }
 
 template <typename T, bool GRAD_ONLY, bool AD>
 __global__ __launch_bounds__(256) void k_build_cameras(
-    int64_t N, int32_t num_chunks, const int32_t* __restrict__ cam, const int32_t* __restrict__ pt,
-    const double* __restrict__ uvx, const double* __restrict__ uvy, const double* __restrict__ pts,
-    JacSource<T> js, T delta, const int32_t* __restrict__ chunk_slot, double* __restrict__ slots,
-    int64_t Nc, T* __restrict__ chcp, T* __restrict__ cw)
+    int64_t N, int32_t num_rows, const int32_t* __restrict__ rows, const int32_t* __restrict__ cam,
+    const int32_t* __restrict__ pt, const double* __restrict__ uvx, const double* __restrict__ uvy,
+    const double* __restrict__ pts, JacSource<T> js, T delta, const int32_t* __restrict__ chunk_slot,
+    double* __restrict__ slots, int64_t Nc, T* __restrict__ chcp, T* __restrict__ cw)
 {
     constexpr int W = GRAD_ONLY ? 9 : kCamSlotWords;
     const int64_t cold0 = N - Nc;  // the cold cameras' observations are the stream's tail
     const int lane = threadIdx.x & 63;
-    const int32_t chunk = (int32_t)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
-    if (chunk >= num_chunks) return;  // whole wavefront leaves together
-    const int64_t start = (int64_t)chunk * kCmChunk;
-    const int64_t end = start + kCmChunk < N ? start + kCmChunk : N;
+    const int32_t chunk = __builtin_amdgcn_readfirstlane((int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    const int32_t r0 = chunk * kCmRows;
+    if (r0 >= num_rows) return;  // whole wavefront leaves together
+    const int32_t r1 = min(r0 + kCmRows, num_rows);
     int32_t slot = chunk_slot[chunk];
-    int32_t cur = cam[start];
+    int32_t cur = cam[rows[r0]];
     double acc[W];
 #pragma unroll
     for (int q = 0; q < W; ++q) acc[q] = 0.0;
-    cm_rows<T>(start, end, lane, cam, pt, uvx, uvy, pts, js.ck, [&](int32_t row, const CmRow<T>& r) {
-        const int64_t k = start + (int64_t)row * 64 + lane;
-        const bool valid = k < end;
+    cm_rows<T>(r0, r1, lane, rows, cam, pt, uvx, uvy, pts, js.ck, [&](const CmRow<T>& r) {
+        const int64_t k = (int64_t)r.k0 + lane;
+        const bool valid = lane < r.len;
         T e0, e1, wt, Jc[18], Jp[6];
         cm_observation<T, AD>(r, pts, js, delta, e0, e1, wt, Jc, Jp);
         if (!GRAD_ONLY && valid && k >= cold0) {
             if (chcp) store_coupling<T>(k - cold0, Nc, Jc, Jp, wt, chcp);
             if (cw) cw[k - cold0] = wt;
         }
-        const int32_t j = valid ? r.j : 0x7fffffff;
-        while (true) {
-            if (valid && j == cur) {
-                // FP64 products of the T-precision Jacobian (exact for
-                // float), as in point_terms: B_j stays a Gram matrix
-                const double w = wt, r0 = e0, r1 = e1;
-                double jc[18];
-#pragma unroll
-                for (int a = 0; a < 18; ++a) jc[a] = Jc[a];
-                int q = 0;
-                if (!GRAD_ONLY) {
-#pragma unroll
-                    for (int a = 0; a < 9; ++a)
-#pragma unroll
-                        for (int b = a; b < 9; ++b) acc[q++] += w * (jc[a] * jc[b] + jc[9 + a] * jc[9 + b]);
-                }
-#pragma unroll
-                for (int a = 0; a < 9; ++a) acc[q++] += -w * (jc[a] * r0 + jc[9 + a] * r1);
-            }
-            // lanes not yet consumed hold larger camera ids (the chunk is sorted)
-            const uint64_t more = __ballot(valid && j > cur);
-            if (more == 0) break;
+        // a row holds one camera: the previous camera's sums leave at its first row
+        const int32_t jr = __builtin_amdgcn_readfirstlane(r.j);
+        if (jr != cur) {
             flush_slot<W>(acc, slots, slot, lane);
             ++slot;
-            const int first = __ffsll((unsigned long long)more) - 1;
-            cur = __shfl(j, first, 64);  // strictly larger: the loop ends
+            cur = jr;
+        }
+        if (valid) {
+            // FP64 terms: the weighted Jacobian entry w J_c[r][a] (exact for
+            // float operands) times J_c[r][b], fused into the accumulator
+            const double w = wt, re0 = e0, re1 = e1;
+            double jc[18];
+#pragma unroll
+            for (int a = 0; a < 18; ++a) jc[a] = Jc[a];
+            int q = 0;
+#pragma unroll
+            for (int a = 0; a < 9; ++a) {
+                const double w0 = w * jc[a], w1 = w * jc[9 + a];
+                if (!GRAD_ONLY) {
+#pragma unroll
+                    for (int b = a; b < 9; ++b) {
+                        acc[q] = fma(w0, jc[b], fma(w1, jc[9 + b], acc[q]));
+                        ++q;
+                    }
+                }
+                acc[W - 9 + a] = fma(-w0, re0, fma(-w1, re1, acc[W - 9 + a]));
+            }
         }
     });
     flush_slot<W>(acc, slots, slot, lane);
@@ -530,8 +534,8 @@ template <typename T, bool G, bool A>
 static void build_cameras_variant(const CameraMajor& cm, int64_t N, const double* pts, JacSource<T> js, T delta,
                                   int64_t Nc, T* chcp, T* cw, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_build_cameras<T, G, A>), dim3((cm.num_chunks + 3) / 4), dim3(256), 0, s, N, cm.num_chunks,
-                       cm.cam, cm.pt, cm.uvx, cm.uvy, pts, js, delta, cm.chunk_slot, cm.slots, Nc, chcp, cw);
+    hipLaunchKernelGGL((k_build_cameras<T, G, A>), dim3((cm.num_chunks + 3) / 4), dim3(256), 0, s, N, cm.num_rows,
+                       cm.row, cm.cam, cm.pt, cm.uvx, cm.uvy, pts, js, delta, cm.chunk_slot, cm.slots, Nc, chcp, cw);
 }
 
 template <typename T>
@@ -645,58 +649,54 @@ hipError_t launch_cost(const PointMajor& pm, int64_t N, const double* pts, const
 // Products in FP64 from the T-precision Jacobian.
 template <typename T, bool AD>
 __global__ __launch_bounds__(256) void k_schur_jacobi_cameras(
-    int64_t N, int32_t num_chunks, const int32_t* __restrict__ cam, const int32_t* __restrict__ pt,
-    const double* __restrict__ uvx, const double* __restrict__ uvy, const double* __restrict__ pts,
-    JacSource<T> js, T delta, const T* __restrict__ cinv, const int32_t* __restrict__ chunk_slot,
-    double* __restrict__ slots)
+    int32_t num_rows, const int32_t* __restrict__ rows, const int32_t* __restrict__ cam,
+    const int32_t* __restrict__ pt, const double* __restrict__ uvx, const double* __restrict__ uvy,
+    const double* __restrict__ pts, JacSource<T> js, T delta, const T* __restrict__ cinv,
+    const int32_t* __restrict__ chunk_slot, double* __restrict__ slots)
 {
     constexpr int W = 45;
     const int lane = threadIdx.x & 63;
-    const int32_t chunk = (int32_t)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
-    if (chunk >= num_chunks) return;  // whole wavefront leaves together
-    const int64_t start = (int64_t)chunk * kCmChunk;
-    const int64_t end = start + kCmChunk < N ? start + kCmChunk : N;
+    const int32_t chunk = __builtin_amdgcn_readfirstlane((int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    const int32_t r0 = chunk * kCmRows;
+    if (r0 >= num_rows) return;  // whole wavefront leaves together
+    const int32_t r1 = min(r0 + kCmRows, num_rows);
     int32_t slot = chunk_slot[chunk];
-    int32_t cur = cam[start];
+    int32_t cur = cam[rows[r0]];
     double acc[W];
 #pragma unroll
     for (int q = 0; q < W; ++q) acc[q] = 0.0;
-    cm_rows<T>(start, end, lane, cam, pt, uvx, uvy, pts, js.ck, [&](int32_t row, const CmRow<T>& r) {
-        const int64_t k = start + (int64_t)row * 64 + lane;
-        const bool valid = k < end;
+    cm_rows<T>(r0, r1, lane, rows, cam, pt, uvx, uvy, pts, js.ck, [&](const CmRow<T>& r) {
+        const bool valid = lane < r.len;
         T e0, e1, wt, Jc[18], Jp[6];
         cm_observation<T, AD>(r, pts, js, delta, e0, e1, wt, Jc, Jp);
-        const int32_t j = valid ? r.j : 0x7fffffff;
-        while (true) {
-            if (valid && j == cur) {
-                const double w = wt;
-                double E[27], Tm[27];
-#pragma unroll
-                for (int a = 0; a < 9; ++a)
-#pragma unroll
-                    for (int c = 0; c < 3; ++c)
-                        E[a * 3 + c] = w * ((double)Jc[a] * (double)Jp[c] + (double)Jc[9 + a] * (double)Jp[3 + c]);
-                const T* c6 = cinv + 6 * (int64_t)r.i;
-                const double C[9] = {(double)c6[0], (double)c6[1], (double)c6[2], (double)c6[1], (double)c6[3],
-                                     (double)c6[4], (double)c6[2], (double)c6[4], (double)c6[5]};
-#pragma unroll
-                for (int a = 0; a < 9; ++a)
-#pragma unroll
-                    for (int c = 0; c < 3; ++c)
-                        Tm[a * 3 + c] = E[a * 3] * C[c] + E[a * 3 + 1] * C[3 + c] + E[a * 3 + 2] * C[6 + c];
-                int q = 0;
-#pragma unroll
-                for (int a = 0; a < 9; ++a)
-#pragma unroll
-                    for (int b = a; b < 9; ++b)
-                        acc[q++] -= Tm[a * 3] * E[b * 3] + Tm[a * 3 + 1] * E[b * 3 + 1] + Tm[a * 3 + 2] * E[b * 3 + 2];
-            }
-            const uint64_t more = __ballot(valid && j > cur);
-            if (more == 0) break;
+        const int32_t jr = __builtin_amdgcn_readfirstlane(r.j);
+        if (jr != cur) {
             flush_slot<W>(acc, slots, slot, lane);
             ++slot;
-            const int first = __ffsll((unsigned long long)more) - 1;
-            cur = __shfl(j, first, 64);
+            cur = jr;
+        }
+        if (valid) {
+            const double w = wt;
+            double E[27], Tm[27];
+#pragma unroll
+            for (int a = 0; a < 9; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    E[a * 3 + c] = w * ((double)Jc[a] * (double)Jp[c] + (double)Jc[9 + a] * (double)Jp[3 + c]);
+            const T* c6 = cinv + 6 * (int64_t)r.i;
+            const double C[9] = {(double)c6[0], (double)c6[1], (double)c6[2], (double)c6[1], (double)c6[3],
+                                 (double)c6[4], (double)c6[2], (double)c6[4], (double)c6[5]};
+#pragma unroll
+            for (int a = 0; a < 9; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    Tm[a * 3 + c] = E[a * 3] * C[c] + E[a * 3 + 1] * C[3 + c] + E[a * 3 + 2] * C[6 + c];
+            int q = 0;
+#pragma unroll
+            for (int a = 0; a < 9; ++a)
+#pragma unroll
+                for (int b = a; b < 9; ++b)
+                    acc[q++] -= Tm[a * 3] * E[b * 3] + Tm[a * 3 + 1] * E[b * 3 + 1] + Tm[a * 3 + 2] * E[b * 3 + 2];
         }
     });
     flush_slot<W>(acc, slots, slot, lane);
@@ -709,10 +709,10 @@ hipError_t launch_schur_jacobi_terms(const CameraMajor& cm, int64_t N, const dou
     if (cm.num_chunks > 0) {
         const dim3 grid((cm.num_chunks + 3) / 4);
         if (js.cams)
-            hipLaunchKernelGGL((k_schur_jacobi_cameras<T, true>), grid, dim3(256), 0, s, N, cm.num_chunks, cm.cam,
+            hipLaunchKernelGGL((k_schur_jacobi_cameras<T, true>), grid, dim3(256), 0, s, cm.num_rows, cm.row, cm.cam,
                                cm.pt, cm.uvx, cm.uvy, pts, js, (T)delta, cinv, cm.chunk_slot, cm.slots);
         else
-            hipLaunchKernelGGL((k_schur_jacobi_cameras<T, false>), grid, dim3(256), 0, s, N, cm.num_chunks, cm.cam,
+            hipLaunchKernelGGL((k_schur_jacobi_cameras<T, false>), grid, dim3(256), 0, s, cm.num_rows, cm.row, cm.cam,
                                cm.pt, cm.uvx, cm.uvy, pts, js, (T)delta, cinv, cm.chunk_slot, cm.slots);
     }
     if (cm.num_segs > 0)
