@@ -703,8 +703,9 @@ __global__ __launch_bounds__(256) void k_schur_jacobi_cameras(
 }
 
 template <typename T>
-hipError_t launch_schur_jacobi_terms(const CameraMajor& cm, int64_t N, const double* pts, JacSource<T> js,
-                                     double delta, const T* cinv, double* mj, hipStream_t s)
+hipError_t launch_schur_jacobi_terms(const CameraMajor& cm, int64_t /* N: the rows bound the stream */,
+                                     const double* pts, JacSource<T> js, double delta, const T* cinv, double* mj,
+                                     hipStream_t s)
 {
     if (cm.num_chunks > 0) {
         const dim3 grid((cm.num_chunks + 3) / 4);
