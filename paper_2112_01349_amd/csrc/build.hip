@@ -327,16 +327,17 @@ __device__ __forceinline__ void flush_slot(double* acc, double* __restrict__ slo
 // of a camera-major chunk: the streamed words, then what they point at.  The
 // chunk's rows are software-pipelined: while row r is computed, the point and
 // camera loads of row r + 1 and the streamed words of row r + 2 are in
-// flight, so one wavefront per SIMD (the 54 FP64 accumulators leave no room
-// for a second) is not left waiting on a dependent gather every row.
+// flight.  A row holds one camera: its index is wave-uniform.
 template <typename T>
 struct CmRow {
     int32_t k0, len;    // first observation and length (uniform)
-    int32_t j, i;       // camera, point (lanes past the row's end: its first observation)
+    int32_t j;          // the row's camera (uniform)
+    int32_t jv;         // the same, loaded per lane (FP32: the camera gathers stay vector loads)
+    int32_t i;          // point (lanes past the row's end: the row's first observation's)
     double u, v;        // pixel
     double X[3];        // point (gathered)
-    T hd[kCamHead];     // camera constants R, t, f, k1, k2, small (gathered)
-    T Jl[9];            // camera left Jacobian (gathered)
+    T hd[kCamHead];     // camera constants R, t, f, k1, k2, small
+    T Jl[9];            // camera left Jacobian
 };
 
 template <typename T>
@@ -348,7 +349,8 @@ __device__ __forceinline__ void cm_stream(const int32_t* __restrict__ rows, int3
     r.k0 = __builtin_amdgcn_readfirstlane(rows[row]);
     r.len = __builtin_amdgcn_readfirstlane(rows[row + 1]) - r.k0;
     const int64_t kk = r.k0 + (lane < r.len ? lane : 0);
-    r.j = cam[kk];
+    r.j = __builtin_amdgcn_readfirstlane(cam[r.k0]);
+    if (sizeof(T) == 4) r.jv = cam[kk];
     r.i = pt[kk];
     r.u = uvx[kk];
     r.v = uvy[kk];
@@ -361,11 +363,15 @@ __device__ __forceinline__ void cm_gather(const double* __restrict__ pts, const 
     r.X[0] = X[0];
     r.X[1] = X[1];
     r.X[2] = X[2];
-    const T* c = reinterpret_cast<const T*>(ck + r.j);
+    // FP64: scalar loads of the uniform camera (fewer vector registers: two
+    // wavefronts per SIMD); FP32: per-lane loads (the scalar form's 42
+    // registers of camera words for two rows overflow the scalar file)
+    const int32_t j = sizeof(T) == 8 ? r.j : r.jv;
+    const T* c = reinterpret_cast<const T*>(ck + j);
 #pragma unroll
     for (int q = 0; q < kCamHead; ++q) r.hd[q] = c[q];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) r.Jl[q] = ck[r.j].Jl[q];
+    for (int q = 0; q < 9; ++q) r.Jl[q] = ck[j].Jl[q];
 }
 
 // Residual, Jacobian and IRLS weight of one gathered observation (the
@@ -443,11 +449,10 @@ __global__ __launch_bounds__(256) void k_build_cameras(
             if (cw) cw[k - cold0] = wt;
         }
         // a row holds one camera: the previous camera's sums leave at its first row
-        const int32_t jr = __builtin_amdgcn_readfirstlane(r.j);
-        if (jr != cur) {
+        if (r.j != cur) {
             flush_slot<W>(acc, slots, slot, lane);
             ++slot;
-            cur = jr;
+            cur = r.j;
         }
         if (valid) {
             // FP64 terms: the weighted Jacobian entry w J_c[r][a] (exact for
@@ -669,11 +674,10 @@ __global__ __launch_bounds__(256) void k_schur_jacobi_cameras(
         const bool valid = lane < r.len;
         T e0, e1, wt, Jc[18], Jp[6];
         cm_observation<T, AD>(r, pts, js, delta, e0, e1, wt, Jc, Jp);
-        const int32_t jr = __builtin_amdgcn_readfirstlane(r.j);
-        if (jr != cur) {
+        if (r.j != cur) {
             flush_slot<W>(acc, slots, slot, lane);
             ++slot;
-            cur = jr;
+            cur = r.j;
         }
         if (valid) {
             const double w = wt;
