@@ -68,6 +68,44 @@ def test_schur_matvec(tiny, damping, stored, monkeypatch):
     assert rel_err_rows(q, ref) <= 1e-11
 
 
+@pytest.mark.parametrize("hot", [12, 3, 0])
+def test_camera_rows_at_row_and_chunk_boundaries(hot, monkeypatch):
+    """The camera-side build cuts the camera-sorted stream into rows of at
+    most 64 observations of one camera and gives each wavefront 32 rows, a
+    camera's terms leaving in one partial sum per chunk it touches.  Cameras
+    seen 4097, 2049, 2048, 2047, 130 ... 127, 65, 64, 63 and 1 times end
+    before, at and after row and chunk boundaries (and the cold stream, the
+    tail of that order, starts inside a chunk when only 3 cameras are hot):
+    B_j through the Schur product and v_j through the gradient match the
+    oracle's, in both precisions."""
+    monkeypatch.setenv("BA_HOT_CAMERAS", str(hot))
+    base = small_zipf(seed=21, m=12, n=4200, N=9000, vmax=8)
+    counts = [4097, 2049, 2048, 2047, 130, 129, 128, 127, 65, 64, 63, 1]
+    rng = np.random.default_rng(8)
+    n = len(base.points0)
+    oc = np.concatenate([np.full(c, j, np.int32) for j, c in enumerate(counts)])
+    op = np.concatenate([rng.choice(n, size=c, replace=False) for c in counts]).astype(np.int32)
+    uv = rng.normal(0, 20, size=(len(oc), 2))
+    arrays = (base.cameras0, base.points0, oc, op, uv)
+    Fo, gco, gpo = orc.gradient(*arrays, 0.0)
+    lam = 1e-3
+    A = orc.assemble(*arrays)
+    Bd, Cd, Dc, Dp = orc.damp(A["B"], A["C"], lam, 0)
+    Ci = orc.invert_points(Cd)
+    x = np.random.default_rng(9).normal(size=(len(counts), 9))
+    ref = orc.schur_matvec(oc, op, Bd, A["E"], Ci, x)
+    for precision in (FP64, FP32_MIXED):
+        prob, _ = make(arrays, precision=precision)
+        if precision == FP64:
+            F, gc, gp = prob.eval_cost_grad()
+            assert abs(F - Fo) <= 1e-13 * abs(Fo)
+            assert rel_err_rows(gc, gco) <= 1e-10 and rel_err_rows(gp, gpo) <= 1e-10
+        err = rel_err_rows(prob.schur_matvec(x, lam), ref)
+        print(f"hot {hot} precision {precision}: product error {err:.2e} of each row")
+        assert err <= (1e-10 if precision == FP64 else FP32_PRODUCT_TOL), precision
+        prob.close()
+
+
 def test_edge_cases_cost_gradient_matvec():
     arrays = with_edge_cases(small_zipf(seed=7))
     cams, pts, oc, op, uv, info = arrays
